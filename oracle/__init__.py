@@ -1,0 +1,129 @@
+"""CPU oracle for the one-sided implicit Hari-Zimmermann GSVD.
+
+TEST INFRASTRUCTURE ONLY: this package may be imported by the tests, the smoke
+check and the benchmark's CPU-baseline leg, never by the GPU library.  It
+wraps ``hz_oracle.c`` (plain C, double / double complex, unblocked) through
+ctypes.  The C file shares no code with the GPU path; see its header for the
+algorithm, the paper passages it follows and the readings taken where the
+paper is ambiguous.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hz_oracle.c")
+_LIB = os.path.join(_HERE, "libhzoracle.so")
+
+ORD_ROWCYCLIC, ORD_MM, ORD_RR = 0, 1, 2
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (IEEE double, no contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        i64, dp = ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+        sig = [i64, i64, i64, dp, i64, dp, i64, dp, i64, dp, dp, dp,
+               ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+               ctypes.POINTER(ctypes.c_int64)]
+        for name in ("hzo_dgsvd", "hzo_zgsvd"):
+            f = getattr(lib, name)
+            f.argtypes = sig
+            f.restype = ctypes.c_int
+        lib.hzo_real_2x2.argtypes = [ctypes.c_double] * 4 + [dp, ctypes.POINTER(ctypes.c_int)]
+        lib.hzo_real_2x2.restype = None
+        lib.hzo_cplx_2x2_v.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp, dp,
+                                       ctypes.POINTER(ctypes.c_int)]
+        lib.hzo_cplx_2x2_v.restype = None
+        lib.hzo_ordering.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        lib.hzo_ordering.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def gsvd(F, G, *, ordering=ORD_ROWCYCLIC, tol=0.0, max_sweeps=30, sort=True, threads=0):
+    """GSVD of the pair (F, G) by the unblocked oracle.
+
+    Returns a dict with U, V, Z (Fortran-ordered), sigma, sigma_f, sigma_g
+    (descending in sigma), sweeps, rot_all, rot_big, converged, status.
+    tol <= 0 selects sqrt(n)*eps.  F and G are copied, not modified.
+    """
+    lib = _load()
+    is_c = np.iscomplexobj(F) or np.iscomplexobj(G)
+    dt = np.complex128 if is_c else np.float64
+    U = np.array(F, dtype=dt, order="F", copy=True)
+    V = np.array(G, dtype=dt, order="F", copy=True)
+    m_f, n = U.shape
+    m_g, n2 = V.shape
+    if n != n2:
+        raise ValueError("F and G must have the same number of columns")
+    Z = np.zeros((n, n), dtype=dt, order="F")
+    s = np.zeros(n)
+    sf = np.zeros(n)
+    sg = np.zeros(n)
+    info = np.zeros(4, dtype=np.int64)
+    fn = lib.hzo_zgsvd if is_c else lib.hzo_dgsvd
+    st = fn(m_f, m_g, n, _dptr(U), m_f, _dptr(V), m_g, _dptr(Z), n,
+            _dptr(s), _dptr(sf), _dptr(sg), int(ordering), float(tol), int(max_sweeps),
+            1 if sort else 0, int(threads), info.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if st < 0:
+        raise ValueError("oracle rejected the arguments")
+    return dict(U=U, V=V, Z=Z, sigma=s, sigma_f=sf, sigma_g=sg, sweeps=int(info[0]),
+                rot_all=int(info[1]), rot_big=int(info[2]), converged=bool(info[3]), status=st)
+
+
+def real_2x2(aii, ajj, aij, x):
+    """The oracle's real 2x2 transformation (Section 2.1.2) as a 2x2 array."""
+    lib = _load()
+    z = np.zeros(4)
+    e = ctypes.c_int(0)
+    lib.hzo_real_2x2(aii, ajj, aij, x, _dptr(z), ctypes.byref(e))
+    return z.reshape(2, 2, order="F"), bool(e.value)
+
+
+def cplx_2x2(aii, ajj, aij, b):
+    """The oracle's complex 2x2 transformation (Section 2.1.1)."""
+    lib = _load()
+    a = np.array([complex(aij).real, complex(aij).imag])
+    bb = np.array([complex(b).real, complex(b).imag])
+    z = np.zeros(8)
+    e = ctypes.c_int(0)
+    lib.hzo_cplx_2x2_v(aii, ajj, _dptr(a), _dptr(bb), _dptr(z), ctypes.byref(e))
+    zc = z[0::2] + 1j * z[1::2]
+    return zc.reshape(2, 2, order="F"), bool(e.value)
+
+
+def ordering(kind: int, n: int) -> np.ndarray:
+    """The oracle's ordering table: array (steps, pairs_per_step, 2)."""
+    lib = _load()
+    N = n + (n & 1)
+    if kind == ORD_ROWCYCLIC:
+        steps, pp = n * (n - 1) // 2, 1
+    else:
+        steps, pp = (N if kind == ORD_MM else N - 1), N // 2
+    t = np.zeros(steps * pp * 2, dtype=np.int32)
+    got = lib.hzo_ordering(kind, n, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    assert got == steps
+    return t.reshape(steps, pp, 2)

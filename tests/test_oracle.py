@@ -1,0 +1,331 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these tests retypes the oracle's formulas: the 2x2 transformations are
+checked through the congruence properties they must have (Section 2.1), whole
+solves through the GSVD output contract (Section 1), the GEVD link, brute-force
+generalized eigenvalues, high-precision singular values of F G^{-1}, the worked
+example printed in Appendix G and the n = 1 closed form's defining properties.
+"""
+
+import json
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+import scipy.linalg as sl
+
+import gsvd_inputs as gi
+import oracle
+
+EPS = np.finfo(np.float64).eps
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- helpers
+
+def check_contract(F, G, r, tol_res=1e-13, tol_orth=1e-13):
+    """Section 1: F Z = U Sigma_F, G Z = V Sigma_G, U^*U = V^*V = I,
+    Sigma_F^2 + Sigma_G^2 = I, Sigma = Sigma_F / Sigma_G sorted descending,
+    and the GEVD link F^*F Z = G^*G Z Sigma^2."""
+    U, V, Z = r["U"], r["V"], r["Z"]
+    sf, sg, s = r["sigma_f"], r["sigma_g"], r["sigma"]
+    n = Z.shape[0]
+    rf = np.linalg.norm(F @ Z - U * sf) / (np.linalg.norm(F) * np.linalg.norm(Z))
+    rg = np.linalg.norm(G @ Z - V * sg) / (np.linalg.norm(G) * np.linalg.norm(Z))
+    assert rf < tol_res and rg < tol_res, (rf, rg)
+    assert np.linalg.norm(U.conj().T @ U - np.eye(n)) < tol_orth * n
+    assert np.linalg.norm(V.conj().T @ V - np.eye(n)) < tol_orth * n
+    assert np.max(np.abs(sf * sf + sg * sg - 1.0)) < 8 * EPS
+    assert np.all(sf > 0) and np.all(sg > 0)
+    np.testing.assert_allclose(s, sf / sg, rtol=8 * EPS)
+    assert np.all(np.diff(s) <= 0), "sigma not sorted descending"
+    A = F.conj().T @ F
+    B = G.conj().T @ G
+    lhs = A @ Z
+    rhs = B @ Z * (s * s)
+    gev = np.linalg.norm(lhs - rhs, axis=0) / (np.linalg.norm(A) * np.linalg.norm(Z, axis=0)
+                                               * np.maximum(1.0, s * s))
+    assert np.max(gev) < 1e-12, np.max(gev)
+
+
+def rel_err(a, b):
+    return np.max(np.abs(a - b) / np.abs(b))
+
+
+# ------------------------------------------------------- 2x2 (Section 2.1)
+
+def _spd(rng, cplx=False):
+    a = rng.standard_normal((2, 2))
+    if cplx:
+        a = a + 1j * rng.standard_normal((2, 2))
+    return a @ a.conj().T
+
+
+def _check_2x2(A, B, Z, cplx=False):
+    """Z^* B Z = I and Z^* A Z diagonal (Section 2.1), with diagonal entries
+    equal to the generalized eigenvalues of the pencil (A, B)."""
+    H = (lambda M: M.conj().T) if cplx else (lambda M: M.T)
+    kB = np.linalg.cond(B)
+    N = H(Z) @ B @ Z
+    M = H(Z) @ A @ Z
+    zn = np.linalg.norm(Z) ** 2
+    assert np.max(np.abs(N - np.eye(2))) < 64 * EPS * kB, N
+    assert abs(M[0, 1]) < 64 * EPS * np.linalg.norm(A) * zn, M
+    assert abs(M[1, 0]) < 64 * EPS * np.linalg.norm(A) * zn, M
+    lam = sl.eigh(A, B, eigvals_only=True)
+    got = np.sort(np.real(np.diag(M)))
+    assert np.allclose(got, lam, rtol=1e-10 * kB, atol=64 * EPS * np.linalg.norm(A) * zn), (got, lam)
+    # 0 <= phi, psi < pi/2 means the scaled cosines on the diagonal are positive.
+    assert np.real(Z[0, 0]) > 0 and np.real(Z[1, 1]) > 0
+    if cplx:
+        assert abs(np.imag(Z[0, 0])) == 0.0 and abs(np.imag(Z[1, 1])) == 0.0
+
+
+def test_2x2_real_random():
+    rng = np.random.default_rng(11)
+    for _ in range(5000):
+        A = _spd(rng)
+        x = rng.uniform(-0.99, 0.99)
+        Z, exc = oracle.real_2x2(A[0, 0], A[1, 1], A[0, 1], x)
+        assert not exc
+        _check_2x2(A, np.array([[1.0, x], [x, 1.0]]), Z)
+
+
+@pytest.mark.parametrize("x", [0.6, -0.6, 0.0, 1e-9, -0.95])
+def test_2x2_real_exception(x):
+    # A' proportional to B' (Section 2.1.2, the exception), also for x < 0.
+    a = 2.5
+    A = a * np.array([[1.0, x], [x, 1.0]])
+    Z, exc = oracle.real_2x2(A[0, 0], A[1, 1], A[0, 1], x)
+    assert exc
+    _check_2x2(A, np.array([[1.0, x], [x, 1.0]]), Z)
+
+
+@pytest.mark.parametrize("case", ["equal_diag", "zero_b", "zero_a12", "diag_A"])
+def test_2x2_real_special(case):
+    x = 0.3
+    if case == "equal_diag":
+        A = np.array([[2.0, 0.7], [0.7, 2.0]])        # h = 0, cot(2 theta) = 0
+    elif case == "zero_b":
+        x = 0.0
+        A = np.array([[3.0, 0.5], [0.5, 1.0]])        # an ordinary Jacobi rotation
+    elif case == "zero_a12":
+        A = np.array([[3.0, 0.0], [0.0, 1.0]])
+    else:
+        A = np.array([[1.0, 0.9 * 0.3], [0.9 * 0.3, 2.0]])
+    Z, _ = oracle.real_2x2(A[0, 0], A[1, 1], A[0, 1], x)
+    _check_2x2(A, np.array([[1.0, x], [x, 1.0]]), Z)
+
+
+def test_2x2_real_zero_b_is_rotation():
+    # With B' = I the transformation must be orthogonal (a Jacobi rotation).
+    A = np.array([[3.0, 0.5], [0.5, 1.0]])
+    Z, _ = oracle.real_2x2(3.0, 1.0, 0.5, 0.0)
+    assert np.allclose(Z.T @ Z, np.eye(2), atol=4 * EPS)
+
+
+def test_2x2_complex_random():
+    rng = np.random.default_rng(12)
+    for _ in range(3000):
+        A = _spd(rng, True)
+        b = complex(rng.uniform(-0.69, 0.69), rng.uniform(-0.69, 0.69))
+        Z, exc = oracle.cplx_2x2(A[0, 0].real, A[1, 1].real, A[0, 1], b)
+        assert not exc
+        B = np.array([[1.0, b], [np.conj(b), 1.0]])
+        _check_2x2(A, B, Z, cplx=True)
+
+
+def test_2x2_complex_exception():
+    # v = h = 0: arg(b) = arg(a12) and a11 = a22 (Section 2.1.1, the exception).
+    b = 0.4 * np.exp(1j * 0.7)
+    a12 = 1.3 * np.exp(1j * 0.7)
+    A = np.array([[2.0, a12], [np.conj(a12), 2.0]])
+    Z, exc = oracle.cplx_2x2(2.0, 2.0, a12, b)
+    assert exc
+    _check_2x2(A, np.array([[1.0, b], [np.conj(b), 1.0]]), Z, cplx=True)
+
+
+@pytest.mark.parametrize("sgn", [1.0, -1.0])
+def test_2x2_complex_h_zero(sgn):
+    # h = 0 with v != 0 of either sign: tan(gamma) is infinite.
+    b = 0.3 + 0.0j
+    a12 = 0.8 + sgn * 0.5j
+    A = np.array([[1.5, a12], [np.conj(a12), 1.5]])
+    Z, exc = oracle.cplx_2x2(1.5, 1.5, a12, b)
+    assert not exc
+    _check_2x2(A, np.array([[1.0, b], [np.conj(b), 1.0]]), Z, cplx=True)
+
+
+def test_2x2_complex_reduces_to_real():
+    # Real data through the complex formulas diagonalizes the same pencil.
+    rng = np.random.default_rng(13)
+    for _ in range(500):
+        A = _spd(rng)
+        x = rng.uniform(-0.9, 0.9)
+        Zc, _ = oracle.cplx_2x2(A[0, 0], A[1, 1], A[0, 1], x)
+        _check_2x2(A.astype(complex), np.array([[1.0, x], [x, 1.0]], dtype=complex), Zc, cplx=True)
+
+
+# -------------------------------------------------- orderings (Section 2.2)
+
+@pytest.mark.parametrize("n", [2, 4, 6, 8, 32, 64])
+def test_mm_ordering(n):
+    t = oracle.ordering(oracle.ORD_MM, n)
+    assert t.shape == (n, n // 2, 2)
+    seen = {}
+    for k, step in enumerate(t):
+        idx = step.reshape(-1)
+        assert sorted(idx.tolist()) == list(range(n)), "step is not a perfect matching"
+        for p, q in step:
+            assert p < q
+            seen[(p, q)] = seen.get((p, q), 0) + 1
+    assert len(seen) == n * (n - 1) // 2, "a pair is missing from the sweep"
+    rep = sorted(pq for pq, c in seen.items() if c > 1)
+    assert rep == [(p, p + n // 2) for p in range(n // 2)] or n == 2
+    assert sum(seen.values()) == n * n // 2      # quasi-cyclic, s = n
+
+
+@pytest.mark.parametrize("n", [2, 4, 6, 8, 32, 64])
+def test_rr_ordering(n):
+    t = oracle.ordering(oracle.ORD_RR, n)
+    assert t.shape == (n - 1, n // 2, 2)
+    pairs = set()
+    for step in t:
+        assert sorted(step.reshape(-1).tolist()) == list(range(n))
+        for p, q in step:
+            assert p < q
+            pairs.add((p, q))
+    assert len(pairs) == n * (n - 1) // 2           # cyclic, s = n - 1
+
+
+def test_rowcyclic_ordering():
+    t = oracle.ordering(oracle.ORD_ROWCYCLIC, 5)
+    got = [tuple(p) for p in t[:, 0, :].tolist()]
+    assert got == [(i, j) for i in range(5) for j in range(i + 1, 5)]
+
+
+# ------------------------------------------------------- whole solves
+
+def test_constructed_pair_config1():
+    F, G, s = gi.config_pair(1)
+    r = oracle.gsvd(F, G, tol=32 * EPS)
+    assert r["converged"]
+    assert rel_err(r["sigma"], s) < 1e-12
+    check_contract(F, G, r)
+
+
+@pytest.mark.parametrize("kind", [oracle.ORD_ROWCYCLIC, oracle.ORD_MM, oracle.ORD_RR])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_constructed_pairs(kind, cplx):
+    F, G, s = gi.custom_pair(60, 45, 28, kappa=30.0, is_complex=cplx, seed=7)
+    r = oracle.gsvd(F, G, ordering=kind, threads=2)
+    assert r["converged"] and r["status"] == 0
+    assert rel_err(r["sigma"], s) < 1e-12
+    check_contract(F, G, r)
+
+
+@pytest.mark.parametrize("n", [3, 5, 17])
+def test_odd_n(n):
+    F, G, s = gi.custom_pair(n + 4, n + 1, n, seed=n)
+    for kind in (oracle.ORD_ROWCYCLIC, oracle.ORD_MM, oracle.ORD_RR):
+        r = oracle.gsvd(F, G, ordering=kind)
+        assert rel_err(r["sigma"], s) < 1e-12
+        check_contract(F, G, r)
+
+
+def test_threads_do_not_change_result():
+    F, G, _ = gi.custom_pair(70, 60, 32, seed=9)
+    r1 = oracle.gsvd(F, G, ordering=oracle.ORD_MM, threads=1)
+    r4 = oracle.gsvd(F, G, ordering=oracle.ORD_MM, threads=4)
+    for k in ("U", "V", "Z", "sigma"):
+        assert np.array_equal(r1[k], r4[k])
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_n1_closed_form(cplx):
+    rng = np.random.default_rng(5)
+    F = rng.standard_normal((7, 1)) + (1j * rng.standard_normal((7, 1)) if cplx else 0)
+    G = rng.standard_normal((4, 1)) + (1j * rng.standard_normal((4, 1)) if cplx else 0)
+    r = oracle.gsvd(F, G)
+    check_contract(F, G, r)
+    # The single generalized eigenvalue of (F^*F, G^*G) is sigma^2.
+    lam = (np.vdot(F, F) / np.vdot(G, G)).real
+    assert abs(r["sigma"][0] ** 2 - lam) < 4 * EPS * lam
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_bruteforce_tiny(seed):
+    # sigma^2 are the generalized eigenvalues of (F^*F, G^*G) (Section 1);
+    # safe to compute this way because B is well conditioned here.
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(2, 9))
+    cplx = bool(seed % 2)
+    F = rng.standard_normal((n + 3, n))
+    G = rng.standard_normal((n + 2, n)) + 2 * np.eye(n + 2, n)
+    if cplx:
+        F = F + 1j * rng.standard_normal(F.shape)
+        G = G + 1j * rng.standard_normal(G.shape)
+    A, B = F.conj().T @ F, G.conj().T @ G
+    assert np.linalg.cond(B) < 1e3
+    lam = sl.eigh(A, B, eigvals_only=True)[::-1]
+    r = oracle.gsvd(F, G)
+    assert rel_err(r["sigma"] ** 2, lam) < 1e-12
+    check_contract(F, G, r)
+
+
+def _mp_gsv(F, G, dps=40):
+    mp.mp.dps = dps
+    Fm = mp.matrix(F.tolist())
+    Gm = mp.matrix(G.tolist())
+    s = mp.svd_r(Fm * mp.inverse(Gm), compute_uv=False)
+    return np.array(sorted((float(v) for v in s), reverse=True))
+
+
+@pytest.mark.parametrize("kappa_g", [1e1, 1e4, 1e8, 1e12])
+def test_square_graded_high_precision(kappa_g):
+    # For square nonsingular G the generalized singular values are the
+    # singular values of F G^{-1} (Appendix G, the 32-digit comparison),
+    # and the GSVD keeps them relatively accurate as kappa(G) grows.
+    rng = np.random.default_rng(int(np.log10(kappa_g)))
+    n = 10
+    F = rng.standard_normal((n, n))
+    G = rng.standard_normal((n, n)) @ np.diag(np.geomspace(1.0, 1.0 / kappa_g, n))
+    ref = _mp_gsv(F, G)
+    r = oracle.gsvd(F, G)
+    assert r["converged"]
+    assert rel_err(r["sigma"], ref) < 1e-12, (r["sigma"], ref)
+
+
+def test_appendix_g_example():
+    with open(os.path.join(GOLD, "appendix_g.json")) as fh:
+        gold = json.load(fh)
+    F = np.array(gold["F"], dtype=float)
+    G = np.array(gold["G_without_g11"], dtype=float)
+    G[0, 0] = gold["g11"]
+    r = oracle.gsvd(F, G)
+    printed = np.array(gold["sigma_printed_desc"])
+    # The printed values carry 16 significant digits.
+    assert rel_err(r["sigma"], printed) < 2e-15
+    lam = np.array(gold["lambda_exact_desc"])
+    assert rel_err(r["sigma"] ** 2, lam) < 4e-15
+    ref = _mp_gsv(F, G, dps=50)
+    assert rel_err(r["sigma"], ref) < 4 * EPS
+
+
+def test_no_sort_still_valid():
+    F, G, s = gi.custom_pair(40, 40, 16, seed=21)
+    r = oracle.gsvd(F, G, sort=False)
+    assert rel_err(r["sigma"], s) < 1e-12
+    check_contract(F, G, r)
+
+
+def test_sweep_cap_reports_not_converged():
+    F, G, _ = gi.custom_pair(40, 40, 16, seed=22)
+    r = oracle.gsvd(F, G, max_sweeps=1)
+    assert r["status"] == 1 and not r["converged"] and r["sweeps"] == 1
+
+
+def test_bad_arguments_rejected():
+    with pytest.raises(ValueError):
+        oracle.gsvd(np.ones((3, 4)), np.ones((5, 4)))      # m_F < n
