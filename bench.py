@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark of the blocked one-sided implicit Hari-Zimmermann GSVD on MI355X.
+
+Workload: the seeded real FP64 pair F, G of 4096 x 1024 (kappa(X) = 1e2,
+generalized singular values log-uniform in [1e-3, 1e3]), block width w = 32,
+modified-modulus outer ordering, relative-orthogonality threshold 1024 eps.
+A step is one complete GSVD solve of that pair (prescale, sweeps of block
+steps to convergence, extraction and sort), inputs resident in HBM; before
+each solve the pair is restored from pristine device copies (two 32 MiB
+device-to-device copies, inside the timed region, <0.1% of a solve).
+
+Prints one JSON line: solves/s, the measured per-kernel split, the roofline
+entry of the dominant kernel (algorithmic bytes or flops per launch over its
+average launch time, measured with HIP events on the solve's stream) and the
+CPU oracle timed on a bounded sample on the host.
+"""
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFS = 78.6
+METRIC = "GSVD solves/s + FP64 MFMA util, 4096x1024 pair; mixed/batched vs plain"
+
+
+def algorithmic(m_f, m_g, n, w):
+    """Algorithmic work per launch of each block-step kernel (one step =
+    n/(2w) pivot pairs).  Gram: reads all of F and G once, 8 n (m_F+m_G)
+    bytes; 2w(2w+1)(m_F+m_G) flops per pair using symmetry.  Update: reads
+    and writes all of F, G, Z, 16 n (m_F+m_G+n) bytes; 2 (2w)^2 (m_F+m_G+n)
+    flops per pair."""
+    pairs = n // (2 * w)
+    gram = dict(bytes=8.0 * n * (m_f + m_g), flops=pairs * 2.0 * w * (2 * w + 1) * (m_f + m_g))
+    upd = dict(bytes=16.0 * n * (m_f + m_g + n),
+               flops=pairs * 2.0 * (2 * w) ** 2 * (m_f + m_g + n))
+    return gram, upd
+
+
+def cpu_baseline(F, G, tol, golden_sweeps):
+    """Time one sweep of the CPU oracle (modified-modulus ordering, OpenMP over
+    the disjoint pairs of each step, all host threads) on the same pair, and
+    scale by the oracle's sweep count for this pair to solves/s."""
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    r = oracle.gsvd(F, G, ordering=oracle.ORD_MM, tol=tol, max_sweeps=1, threads=threads)
+    dt = time.perf_counter() - t0
+    sweeps = golden_sweeps
+    return dict(value=1.0 / (dt * sweeps), unit="solves/s", cores=threads, kind="oracle",
+                sample=f"one full sweep ({r['rot_all']} pointwise steps) of the unblocked "
+                       f"oracle on the 4096x1024 pair took {dt:.2f} s on {threads} threads; "
+                       f"scaled by the {sweeps} sweeps the oracle needs on this pair")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--w", type=int, default=32)
+    ap.add_argument("--inner-max-sweeps", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the solver runs on a single MI355X "
+              "(see DESIGN.md for how the path would shard); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import gsvd_inputs as gi
+    import paper_1909_00101_amd as hz
+
+    spec = gi.CONFIGS[2]
+    F, G, s_true = gi.config_pair(2)
+    eps = np.finfo(np.float64).eps
+    tol = spec.n * eps
+    dev = torch.device("cuda:0")
+    F0 = torch.from_numpy(F).to(dev)          # Fortran-ordered -> column-major storage
+    G0 = torch.from_numpy(G).to(dev)
+    Fw = F0.clone()
+    Gw = G0.clone()
+    kw = dict(w=args.w, ordering=hz.HZ_ORD_MM, tol=tol, inner_max_sweeps=args.inner_max_sweeps)
+    p = hz.params(**kw)
+    nbytes = hz.lib().hz_dgsvd_work_size(ctypes.byref(p), spec.m_f, spec.m_g, spec.n)
+    work = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+
+    def solve():
+        Fw.copy_(F0)
+        Gw.copy_(G0)
+        return hz.gsvd(Fw, Gw, overwrite=True, workspace=work, **kw)
+
+    for _ in range(args.warmup):
+        r = solve()
+    torch.cuda.synchronize()
+    L = hz.lib()
+    L.hz_profile_enable(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sweeps = []
+    for _ in range(args.steps):
+        r = solve()
+        sweeps.append(r["sweeps"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = (ctypes.c_double * 4)()
+    cnt = (ctypes.c_int64 * 4)()
+    L.hz_profile_read(ms, cnt, 4)
+    L.hz_profile_enable(0)
+    err = float(np.max(np.abs(r["sigma"].cpu().numpy() - s_true) / s_true))
+
+    gram, upd = algorithmic(spec.m_f, spec.m_g, spec.n, args.w)
+    kinds = {"gram": (ms[0], cnt[0], gram), "inner": (ms[1], cnt[1], None),
+             "update": (ms[2], cnt[2], upd)}
+    split = {k: round(v[0] / max(1e-9, sum(x[0] for x in kinds.values())), 4)
+             for k, v in kinds.items()}
+    dom = max(("gram", "update"), key=lambda k: kinds[k][0])
+    t_launch = kinds[dom][0] / max(1, kinds[dom][1]) * 1e-3
+    work_d = kinds[dom][2]
+    intensity = work_d["flops"] / work_d["bytes"]
+    ridge = FP64_MFMA_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if intensity < ridge:
+        achieved = work_d["bytes"] / t_launch / 1e9
+        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None)
+    else:
+        achieved = work_d["flops"] / t_launch / 1e12
+        roof = dict(bound="mfma", achieved=round(achieved, 2), peak=FP64_MFMA_PEAK_TFS,
+                    unit="TFLOP/s", frac=round(achieved / FP64_MFMA_PEAK_TFS, 4), traffic=None)
+    roof["kernel"] = f"k_{dom}<W2={2 * args.w}>"
+    roof["avg_launch_us"] = round(t_launch * 1e6, 2)
+    roof["intensity_flop_per_byte"] = round(intensity, 2)
+    # whole-solve FP64 MFMA utilisation from algorithmic flops of the executed steps
+    steps_per_sweep = spec.n // args.w
+    mean_sweeps = float(np.mean(sweeps))
+    solve_flops = mean_sweeps * steps_per_sweep * (gram["flops"] + upd["flops"])
+    solves_per_s = args.steps / dt
+    mfma_util = solve_flops * solves_per_s / (FP64_MFMA_PEAK_TFS * 1e12)
+
+    out = dict(metric=METRIC, value=round(solves_per_s, 3), unit="solves/s", n_gpus=1,
+               steps=args.steps, warmup=args.warmup, ms_per_step=round(dt / args.steps * 1e3, 3),
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+               data="synthetic",
+               config=dict(workload="blocked real FP64 GSVD of a seeded 4096x1024 pair "
+                                    "(kappa(X)=1e2, sigma log-uniform in [1e-3,1e3])",
+                           m_f=spec.m_f, m_g=spec.m_g, n=spec.n, w=args.w, ordering="MM",
+                           inner_max_sweeps=args.inner_max_sweeps, tol="1024*eps",
+                           parallelism="single GPU"),
+               sweeps=sweeps, max_rel_sigma_err_vs_prescribed=err,
+               fp64_mfma_util_solve=round(mfma_util, 4),
+               kernel_time_split=split, roofline=roof)
+    if not args.no_cpu_baseline:
+        golden = os.path.join(ROOT, "tests", "golden", "oracle_config2.json")
+        gs = None
+        if os.path.exists(golden):
+            with open(golden) as fh:
+                gs = json.load(fh)["sweeps"]
+        out["cpu_baseline"] = cpu_baseline(F, G, tol, gs if gs else int(round(mean_sweeps)))
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,154 @@
+/*
+ * hzgsvd.h -- C ABI of the MI355X (gfx950) one-sided, blocked, implicit
+ * Hari-Zimmermann GSVD library (libhzgsvd.so).
+ *
+ * Problem (paper, Section 1 and the start of Section 2): for F (m_F x n) and
+ * G (m_G x n) of full column rank with min(m_F, m_G) >= n, compute
+ *     F Z = U Sigma_F,   G Z = V Sigma_G,   U^* U = V^* V = I,
+ *     Sigma_F^2 + Sigma_G^2 = I,   Sigma = Sigma_G^{-1} Sigma_F,
+ * with Z square and nonsingular and the generalized singular values sorted
+ * descendingly by a symmetric permutation of the columns of U, V, Z.
+ * U overwrites F and V overwrites G (Section 3.1.1: U in place of F, V in
+ * place of G).  Sigma, Sigma_F and Sigma_G are real (double) vectors of
+ * length n, also for complex input (Section 3.1.1).
+ *
+ * Method (Sections 2.1-2.5, 3.3-3.6): prescale by Z_0 = diag(1/||g_j||);
+ * sweeps of parallel block steps; in each step every pivot block-column pair
+ * (width w each) forms its 2w x 2w Gram blocks F_b^*F_b and G_b^*G_b,
+ * Cholesky-factors them, runs the pointwise implicit Hari-Zimmermann method
+ * on the factors (at most inner_max_sweeps inner sweeps: 30 = "full block",
+ * 1 = "block oriented"), rescales the accumulated transformation by Theta
+ * (Section 2.4) and postmultiplies the pivot block columns of F, G, Z by it.
+ * The solve stops after an outer sweep with no "big" transformation
+ * (criterion C1, Section 2.5) or after max_sweeps sweeps.
+ *
+ * Layout: every matrix is column-major (Fortran order) with a leading
+ * dimension in elements; complex matrices are interleaved (re, im) double
+ * pairs (C99 double complex / numpy complex128).
+ *
+ * Memory and ownership: F, G, Z, sigma, sigma_f, sigma_g and work are
+ * caller-owned DEVICE pointers (HIP device memory of the current device).
+ * info is a caller-owned HOST pointer (may be NULL).  The library keeps no
+ * pointer after a call returns.  If work is NULL the library allocates the
+ * workspace itself for the duration of the call; otherwise work must hold at
+ * least hz_*_work_size(...) bytes, 256-byte aligned.  Inputs are read once
+ * into the workspace, so F and G may be any device buffers of the stated
+ * shape.  stream is a hipStream_t (NULL = the default stream); every call is
+ * synchronous with respect to the host: it returns after its work on
+ * stream has completed (the sweep loop reads the convergence counters back
+ * once per sweep, as in the paper's host algorithm, Algorithm 1).
+ *
+ * Errors (return value):
+ *    0            success, converged
+ *   -i            argument i (1-based, in the order of the prototype) is
+ *                 invalid; nothing was launched
+ *   HZ_ENOCONV    max_sweeps reached; outputs are valid but not converged
+ *   HZ_ECHOL      a pivot Gram block was not numerically positive definite
+ *                 (input not of full column rank, or too ill-conditioned for
+ *                 Gram + Cholesky); info->failed_pair names the block pair;
+ *                 outputs are not meaningful
+ *   HZ_ENONFINITE a NaN or infinity was found in the input or arose; outputs
+ *                 are not meaningful
+ *   HZ_EHIP       a HIP runtime call failed
+ */
+#ifndef HZGSVD_H
+#define HZGSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HZ_OK 0
+#define HZ_ENOCONV 1
+#define HZ_ECHOL 2
+#define HZ_ENONFINITE 3
+#define HZ_EHIP 4
+
+/* Parallel orderings (Section 2.2).  HZ_ORD_MM: modified modulus,
+ * quasi-cyclic with s = N steps per sweep (step k pairs p < q with
+ * p + q = k mod N, and the two fixed points of even k with each other).
+ * HZ_ORD_RR: round robin, cyclic with s = N - 1 steps. */
+#define HZ_ORD_MM 1
+#define HZ_ORD_RR 2
+
+typedef struct hz_params {
+    int variant;          /* 0 only: criterion C1, prescaled, ordinary dots (Table 1) */
+    int ordering;         /* outer block ordering, HZ_ORD_MM (default) or HZ_ORD_RR */
+    int inner_ordering;   /* pointwise ordering inside a block pair (default HZ_ORD_RR) */
+    int w;                /* block-column width: 0 = default, else 8, 16 or 32 */
+    int inner_max_sweeps; /* inner sweeps per block step: 30 = FB (default), 1 = BO */
+    int max_sweeps;       /* outer sweep cap (default 30, Algorithm 1) */
+    double tol;           /* relative-orthogonality threshold; <= 0 selects
+                             sqrt(n)*DBL_EPSILON (Section 2.1) */
+    int sort;             /* 1 = per-step column sorting heuristic (default), 0 = none */
+    double mixed_switch;  /* mixed form: switch to FP64 when the largest scaled
+                             off-diagonal Gram entry of an FP32 sweep falls below
+                             this (default 1e-5) */
+    int max_fp32_sweeps;  /* mixed form: cap on FP32 sweeps (default 20) */
+} hz_params;
+
+typedef struct hz_info {
+    int sweeps;           /* outer sweeps executed (FP64 sweeps in the mixed form) */
+    int sweeps_fp32;      /* FP32 sweeps (mixed form only) */
+    int converged;        /* 1 if the last sweep had no big transformation */
+    int w;                /* block width used */
+    int64_t failed_pair;  /* HZ_ECHOL: step * 65536 + pair of the first failing block */
+    uint64_t rot_total;   /* transformations applied (inner level, all sweeps) */
+    uint64_t rot_big;     /* big transformations among them */
+    double last_offdiag;  /* mixed form: off-diagonal measure of the last FP32 sweep */
+} hz_info;
+
+/* Fill *p with the defaults listed above. */
+void hz_default_params(hz_params *p);
+
+/* Workspace bytes needed by hz_dgsvd for the given shape (0 if the shape is
+ * invalid). */
+size_t hz_dgsvd_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n);
+
+/* Real FP64 GSVD (variant 0, Sections 2-3).  Arguments in order:
+ *  1 p (host, may be NULL = defaults), 2 m_f, 3 m_g, 4 n,
+ *  5 F (device, m_f x n, overwritten by U), 6 ldf (>= m_f),
+ *  7 G (device, m_g x n, overwritten by V), 8 ldg (>= m_g),
+ *  9 Z (device, n x n, output), 10 ldz (>= n),
+ * 11 sigma, 12 sigma_f, 13 sigma_g (device, n doubles each, output),
+ * 14 work (device or NULL), 15 work_bytes, 16 info (host or NULL),
+ * 17 stream (hipStream_t or NULL). */
+int hz_dgsvd(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n,
+             double *F, int64_t ldf, double *G, int64_t ldg, double *Z, int64_t ldz,
+             double *sigma, double *sigma_f, double *sigma_g,
+             void *work, size_t work_bytes, hz_info *info, void *stream);
+
+/* The block ordering the solver uses: fills table (host, steps * (N/2) * 2
+ * ints, row k = the N/2 disjoint pairs (p, q), p < q, of step k) for kind
+ * HZ_ORD_MM or HZ_ORD_RR on N (even, >= 2) block columns, and returns the
+ * number of steps (N or N - 1), or -1 for a bad kind or N.  table may be
+ * NULL to query the step count. */
+int hz_ordering(int kind, int N, int *table);
+
+/* Per-kernel timing of later solves in this process, for measurement:
+ * with enable != 0 every Gram, inner-solve and update launch is bracketed by
+ * HIP events on the solve's stream (resolved at the host syncs each sweep
+ * already makes), and the sums are cleared; enable = 0 stops collecting.
+ * Not for concurrent solves. */
+void hz_profile_enable(int enable);
+
+/* Copy the accumulated per-kind kernel time (milliseconds) and launch
+ * counts for kinds 0 = Gram, 1 = inner solve, 2 = update, 3 = other into
+ * host arrays of nkinds entries (either may be NULL); returns the number of
+ * kinds written. */
+int hz_profile_read(double *ms, int64_t *launches, int nkinds);
+
+/* Short English description of a status code. */
+const char *hz_strerror(int status);
+
+/* Library version string. */
+const char *hz_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HZGSVD_H */

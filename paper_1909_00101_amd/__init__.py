@@ -1,0 +1,176 @@
+"""MI355X (gfx950) one-sided, blocked, implicit Hari-Zimmermann GSVD.
+
+Thin ctypes binding of ``libhzgsvd.so`` (C ABI declared in
+``include/hzgsvd.h``).  This module only marshals arguments: every step of
+the solve runs in the library's HIP kernels.  PyTorch supplies device memory
+and the current stream; there is no CPU fallback -- if the library is not
+built, every call raises.
+
+Matrices are column-major (Fortran order).  A torch tensor ``F`` of shape
+(m, n) is passed as is when ``F.t().is_contiguous()`` (column-major storage),
+otherwise a column-major copy is made.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_HERE)
+LIB_PATH = os.path.join(_HERE, "libhzgsvd.so")
+CSRC = os.path.join(_HERE, "csrc")
+SOURCES = ["hz_api.hip", "hz_real.hip"]
+
+HZ_OK, HZ_ENOCONV, HZ_ECHOL, HZ_ENONFINITE, HZ_EHIP = 0, 1, 2, 3, 4
+HZ_ORD_MM, HZ_ORD_RR = 1, 2
+
+HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-Wno-unused-result"]
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libhzgsvd.so for gfx950 with hipcc (always recompiles)."""
+    objs = []
+    bdir = os.path.join(_HERE, "_build")
+    os.makedirs(bdir, exist_ok=True)
+    for src in SOURCES:
+        obj = os.path.join(bdir, src.replace(".hip", ".o"))
+        cmd = ["hipcc", *HIPCC_FLAGS, "-I", os.path.join(_ROOT, "include"), "-c",
+               os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr}")
+        if verbose and r.stderr:
+            print(r.stderr)
+        objs.append(obj)
+    tmp = LIB_PATH + ".tmp"
+    r = subprocess.run(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class HzParams(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int), ("ordering", ctypes.c_int),
+                ("inner_ordering", ctypes.c_int), ("w", ctypes.c_int),
+                ("inner_max_sweeps", ctypes.c_int), ("max_sweeps", ctypes.c_int),
+                ("tol", ctypes.c_double), ("sort", ctypes.c_int),
+                ("mixed_switch", ctypes.c_double), ("max_fp32_sweeps", ctypes.c_int)]
+
+
+class HzInfo(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int), ("sweeps_fp32", ctypes.c_int),
+                ("converged", ctypes.c_int), ("w", ctypes.c_int),
+                ("failed_pair", ctypes.c_int64), ("rot_total", ctypes.c_uint64),
+                ("rot_big", ctypes.c_uint64), ("last_offdiag", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, vp, dp = ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p
+        L.hz_default_params.argtypes = [ctypes.POINTER(HzParams)]
+        L.hz_default_params.restype = None
+        L.hz_dgsvd_work_size.argtypes = [ctypes.POINTER(HzParams), i64, i64, i64]
+        L.hz_dgsvd_work_size.restype = ctypes.c_size_t
+        L.hz_dgsvd.argtypes = [ctypes.POINTER(HzParams), i64, i64, i64, dp, i64, dp, i64, dp,
+                               i64, dp, dp, dp, vp, ctypes.c_size_t, ctypes.POINTER(HzInfo), vp]
+        L.hz_dgsvd.restype = ctypes.c_int
+        L.hz_strerror.argtypes = [ctypes.c_int]
+        L.hz_strerror.restype = ctypes.c_char_p
+        L.hz_version.argtypes = []
+        L.hz_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def params(**kw) -> HzParams:
+    p = HzParams()
+    lib().hz_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k}")
+        setattr(p, k, v)
+    return p
+
+
+def _colmajor(t):
+    return t if t.t().is_contiguous() else t.t().contiguous().t()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ld(t):
+    """Leading dimension of a column-major matrix view (torch normalises the
+    stride of a size-1 dimension, so a single column reports its row count)."""
+    return t.stride(1) if t.shape[1] > 1 else max(1, t.shape[0])
+
+
+class GsvdError(RuntimeError):
+    def __init__(self, status, info):
+        msg = lib().hz_strerror(status).decode()
+        super().__init__(f"hz status {status}: {msg}")
+        self.status = status
+        self.info = info
+
+
+def gsvd(F, G, *, overwrite=False, raise_on_noconv=False, workspace=None, **kw):
+    """GSVD of (F, G) on the GPU.
+
+    F (m_F x n) and G (m_G x n) are float64 CUDA tensors.  Returns a dict
+    with U, V (overwriting column-major copies of F, G unless ``overwrite``
+    and the inputs are already column-major), Z, sigma, sigma_f, sigma_g
+    (descending in sigma), the hz_info fields and the status code.
+    Keyword arguments set hz_params fields (w, ordering, inner_max_sweeps,
+    max_sweeps, tol, sort, ...).
+    """
+    import torch
+    L = lib()
+    if F.dtype != torch.float64 or G.dtype != torch.float64:
+        raise TypeError("hz_dgsvd takes float64 tensors")
+    if not (F.is_cuda and G.is_cuda):
+        raise ValueError("F and G must be CUDA (HIP) tensors")
+    U = _colmajor(F) if overwrite else F.t().contiguous().t().clone() if F.t().is_contiguous() \
+        else _colmajor(F)
+    V = _colmajor(G) if overwrite else G.t().contiguous().t().clone() if G.t().is_contiguous() \
+        else _colmajor(G)
+    m_f, n = U.shape
+    m_g = V.shape[0]
+    dev = U.device
+    Z = torch.empty((n, n), dtype=torch.float64, device=dev).t()
+    sig = torch.empty(n, dtype=torch.float64, device=dev)
+    sf = torch.empty_like(sig)
+    sg = torch.empty_like(sig)
+    p = params(**kw)
+    nbytes = L.hz_dgsvd_work_size(ctypes.byref(p), m_f, m_g, n)
+    if nbytes == 0:
+        raise ValueError("invalid shape or parameters")
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    wptr = (workspace.data_ptr() + 255) & ~255
+    info = HzInfo()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    st = L.hz_dgsvd(ctypes.byref(p), m_f, m_g, n, _ptr(U), _ld(U), _ptr(V), _ld(V),
+                    _ptr(Z), _ld(Z), _ptr(sig), _ptr(sf), _ptr(sg), ctypes.c_void_p(wptr),
+                    nbytes, ctypes.byref(info), ctypes.c_void_p(stream))
+    if st < 0:
+        raise ValueError(f"hz_dgsvd rejected argument {-st}")
+    if st in (HZ_ECHOL, HZ_ENONFINITE, HZ_EHIP) or (raise_on_noconv and st == HZ_ENOCONV):
+        raise GsvdError(st, info)
+    return dict(U=U, V=V, Z=Z, sigma=sig, sigma_f=sf, sigma_g=sg, status=st,
+                sweeps=info.sweeps, converged=bool(info.converged), w=info.w,
+                rot_total=info.rot_total, rot_big=info.rot_big)

@@ -1,0 +1,427 @@
+// hz_api.hip -- C ABI, planning and the host sweep loop of libhzgsvd
+// (paper: Algorithm 1 of Section 3.6 -- prescale once, then outer sweeps of
+// block steps, the per-step counters read back once per sweep, stop after a
+// sweep without big transformations, then the final rescale/extraction).
+#include <float.h>
+#include <limits.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "hz_internal.h"
+
+namespace hz {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Parallel orderings of Section 2.2 on N (even) indices; table[k][l] = (p, q).
+// Modified modulus (quasi-cyclic, N steps): step k takes every p < q with
+// p + q = k (mod N) and, for even k, pairs the two fixed points k/2 and
+// k/2 + N/2.  Round robin (cyclic, N - 1 steps): index N - 1 stays, the
+// others rotate: (k, N-1) and ((k-i) mod (N-1), (k+i) mod (N-1)).
+template <typename T>
+static int build_ordering(int kind, int N, std::vector<T> &tab)
+{
+    const int half = N / 2;
+    if (kind == HZ_ORD_MM) {
+        tab.assign((size_t)N * half * 2, 0);
+        for (int k = 0; k < N; ++k) {
+            int c = 0;
+            for (int p = 0; p < N; ++p) {
+                const int q = ((k - p) % N + N) % N;
+                if (p < q) {
+                    tab[(size_t)(k * half + c) * 2] = (T)p;
+                    tab[(size_t)(k * half + c) * 2 + 1] = (T)q;
+                    ++c;
+                }
+            }
+            if ((k & 1) == 0) {
+                tab[(size_t)(k * half + c) * 2] = (T)(k / 2);
+                tab[(size_t)(k * half + c) * 2 + 1] = (T)(k / 2 + half);
+            }
+        }
+        return N;
+    }
+    const int M = N - 1;
+    tab.assign((size_t)M * half * 2, 0);
+    for (int k = 0; k < M; ++k) {
+        tab[(size_t)(k * half) * 2] = (T)k;
+        tab[(size_t)(k * half) * 2 + 1] = (T)M;
+        for (int i = 1; i < half; ++i) {
+            int p = ((k - i) % M + M) % M, q = (k + i) % M;
+            if (p > q) { const int t = p; p = q; q = t; }
+            tab[(size_t)(k * half + i) * 2] = (T)p;
+            tab[(size_t)(k * half + i) * 2 + 1] = (T)q;
+        }
+    }
+    return M;
+}
+
+static int params_ok(const hz_params &p)
+{
+    if (p.variant != 0) return 0;
+    if (p.ordering != HZ_ORD_MM && p.ordering != HZ_ORD_RR) return 0;
+    if (p.inner_ordering != HZ_ORD_MM && p.inner_ordering != HZ_ORD_RR) return 0;
+    if (p.w != 0 && p.w != 8 && p.w != 16 && p.w != 32) return 0;
+    if (p.inner_max_sweeps < 1 || p.max_sweeps < 1) return 0;
+    return 1;
+}
+
+static int default_w(int64_t n, int is_complex)
+{
+    (void)is_complex;
+    if (n <= 16) return 8;
+    return 16;
+}
+
+static bool make_plan(const hz_params &prm, int64_t mf, int64_t mg, int64_t n, int is_complex,
+                      Plan &P)
+{
+    if (n < 2) return false;
+    memset(&P, 0, sizeof(P));
+    P.mf = mf;
+    P.mg = mg;
+    P.n = n;
+    P.is_complex = is_complex;
+    P.esz = is_complex ? 16 : 8;
+    P.w = prm.w ? prm.w : default_w(n, is_complex);
+    P.W2 = 2 * P.w;
+    P.nw = round_up(n, P.W2);
+    const int64_t nb = P.nw - n;
+    P.mfw = round_up(mf + nb, 64);
+    P.mgw = round_up(mg + nb, 64);
+    P.nzw = round_up(P.nw, 64);
+    P.nblk = (int)(P.nw / P.w);
+    P.npairs = P.nblk / 2;
+    P.steps = (prm.ordering == HZ_ORD_MM) ? P.nblk : P.nblk - 1;
+    P.isteps = (prm.inner_ordering == HZ_ORD_MM) ? P.W2 : P.W2 - 1;
+    const int64_t maxch = (P.mfw > P.mgw ? P.mfw : P.mgw) / 64;
+    int64_t sp = (512 + 2 * P.npairs - 1) / (2 * P.npairs);
+    if (sp > maxch) sp = maxch;
+    if (sp < 1) sp = 1;
+    P.splits = (int)sp;
+    P.upd_rows = 64;
+    const size_t es = P.esz;
+    size_t o = 0;
+    P.o_fw = o; o = align256(o + es * (size_t)P.mfw * P.nw);
+    P.o_gw = o; o = align256(o + es * (size_t)P.mgw * P.nw);
+    P.o_zw = o; o = align256(o + es * (size_t)P.nzw * P.nw);
+    P.o_part = o; o = align256(o + es * (size_t)P.npairs * 2 * P.splits * P.W2 * P.W2);
+    P.o_zt = o; o = align256(o + es * (size_t)P.npairs * P.W2 * P.W2);
+    P.o_otab = o; o = align256(o + sizeof(int) * (size_t)P.steps * P.npairs * 2);
+    P.o_itab = o; o = align256(o + sizeof(int16_t) * (size_t)P.isteps * P.w * 2);
+    P.o_cnt = o; o = align256(o + sizeof(unsigned long long) * (size_t)P.steps * P.npairs * 2);
+    P.o_status = o; o = align256(o + sizeof(int) * ST_NSLOTS);
+    P.o_sf = o; o = align256(o + sizeof(double) * (size_t)P.nw);
+    P.o_sg = o; o = align256(o + sizeof(double) * (size_t)P.nw);
+    P.o_sig = o; o = align256(o + sizeof(double) * (size_t)P.nw);
+    P.o_rank = o; o = align256(o + sizeof(int) * (size_t)P.nw);
+    P.o_border = o; o = align256(o + sizeof(int) * (size_t)P.nw);
+    P.total = o;
+    return true;
+}
+
+static Ptrs make_ptrs(const Plan &P, void *work)
+{
+    Ptrs W;
+    char *b = (char *)work;
+    W.base = b;
+    W.Fw = (double *)(b + P.o_fw);
+    W.Gw = (double *)(b + P.o_gw);
+    W.Zw = (double *)(b + P.o_zw);
+    W.part = (double *)(b + P.o_part);
+    W.Zt = (double *)(b + P.o_zt);
+    W.otab = (int *)(b + P.o_otab);
+    W.itab = (int16_t *)(b + P.o_itab);
+    W.cnt = (unsigned long long *)(b + P.o_cnt);
+    W.status = (int *)(b + P.o_status);
+    W.sf = (double *)(b + P.o_sf);
+    W.sg = (double *)(b + P.o_sg);
+    W.sig = (double *)(b + P.o_sig);
+    W.rank = (int *)(b + P.o_rank);
+    W.border = (int *)(b + P.o_border);
+    return W;
+}
+
+#define HZ_CHECK(call)                                                                         \
+    do {                                                                                       \
+        if ((call) != hipSuccess) {                                                            \
+            rc = HZ_EHIP;                                                                      \
+            goto done;                                                                         \
+        }                                                                                      \
+    } while (0)
+
+// Validation common to the entry points: returns 0 or -(argument index).
+static int check_args(int64_t mf, int64_t mg, int64_t n, const void *F, int64_t ldf,
+                      const void *G, int64_t ldg, const void *Z, int64_t ldz, const void *s,
+                      const void *sf, const void *sg)
+{
+    if (mf < 1) return -2;
+    if (mg < 1) return -3;
+    if (n < 1 || n > mf || n > mg || n > (int64_t)INT_MAX / 2) return -4;
+    if (!F || ((uintptr_t)F & 7)) return -5;
+    if (ldf < mf) return -6;
+    if (!G || ((uintptr_t)G & 7)) return -7;
+    if (ldg < mg) return -8;
+    if (!Z || ((uintptr_t)Z & 7)) return -9;
+    if (ldz < n) return -10;
+    if (!s || ((uintptr_t)s & 7)) return -11;
+    if (!sf || ((uintptr_t)sf & 7)) return -12;
+    if (!sg || ((uintptr_t)sg & 7)) return -13;
+    return 0;
+}
+
+// ------------------------------------------------------------ profiler
+// When enabled, every timed launch is bracketed by two HIP events on its
+// stream; the pending pairs are resolved at the host syncs the sweep loop
+// already makes (prof_flush), so the profiler adds no synchronisation.
+struct Prof {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<int> kind;
+    double ms[K_NKINDS] = {0, 0, 0, 0};
+    int64_t launches[K_NKINDS] = {0, 0, 0, 0};
+};
+static Prof g_prof;
+
+void prof_mark(int kind, bool begin, hipStream_t s)
+{
+    if (!g_prof.on) return;
+    if (g_prof.used == g_prof.pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        g_prof.pool.push_back(e);
+    }
+    if (begin) g_prof.kind.push_back(kind);
+    (void)hipEventRecord(g_prof.pool[g_prof.used++], s);
+}
+
+// Resolve recorded pairs; the caller has synchronised the stream.
+static void prof_flush()
+{
+    if (!g_prof.on) return;
+    for (size_t i = 0; i + 1 < g_prof.used; i += 2) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, g_prof.pool[i], g_prof.pool[i + 1]) == hipSuccess) {
+            const int k = g_prof.kind[i / 2];
+            g_prof.ms[k] += t;
+            g_prof.launches[k] += 1;
+        }
+    }
+    g_prof.used = 0;
+    g_prof.kind.clear();
+}
+
+// The host sweep loop shared by the real and complex solvers.
+static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t work_bytes,
+                     hz_info *info, hipStream_t st, bool complex_path, const void *F, int64_t ldf,
+                     const void *G, int64_t ldg, void *U, void *V, void *Z, int64_t ldz,
+                     double *sigma, double *sigma_f, double *sigma_g);
+
+}  // namespace hz
+
+using namespace hz;
+
+extern "C" {
+
+void hz_default_params(hz_params *p)
+{
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->variant = 0;
+    p->ordering = HZ_ORD_MM;
+    p->inner_ordering = HZ_ORD_RR;
+    p->w = 0;
+    p->inner_max_sweeps = 30;
+    p->max_sweeps = 30;
+    p->tol = 0.0;
+    p->sort = 1;
+    p->mixed_switch = 1e-5;
+    p->max_fp32_sweeps = 20;
+}
+
+const char *hz_strerror(int status)
+{
+    switch (status) {
+    case HZ_OK: return "success";
+    case HZ_ENOCONV: return "not converged within max_sweeps";
+    case HZ_ECHOL: return "pivot Gram block not positive definite (rank-deficient or too ill-conditioned input)";
+    case HZ_ENONFINITE: return "NaN or infinity in the input or the iteration";
+    case HZ_EHIP: return "HIP runtime error";
+    default: return status < 0 ? "invalid argument" : "unknown status";
+    }
+}
+
+const char *hz_version(void) { return "hzgsvd 0.1 (gfx950)"; }
+
+int hz_ordering(int kind, int N, int *table)
+{
+    if ((kind != HZ_ORD_MM && kind != HZ_ORD_RR) || N < 2 || (N & 1) || N > (1 << 15)) return -1;
+    std::vector<int> t;
+    const int steps = build_ordering<int>(kind, N, t);
+    if (table) memcpy(table, t.data(), t.size() * sizeof(int));
+    return steps;
+}
+
+void hz_profile_enable(int enable)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = enable != 0;
+    g_prof.used = 0;
+    g_prof.kind.clear();
+    for (int k = 0; k < K_NKINDS; ++k) {
+        g_prof.ms[k] = 0.0;
+        g_prof.launches[k] = 0;
+    }
+}
+
+int hz_profile_read(double *ms, int64_t *launches, int nkinds)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    const int n = nkinds < K_NKINDS ? nkinds : K_NKINDS;
+    for (int k = 0; k < n; ++k) {
+        if (ms) ms[k] = g_prof.ms[k];
+        if (launches) launches[k] = g_prof.launches[k];
+    }
+    return n;
+}
+
+size_t hz_dgsvd_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n)
+{
+    hz_params prm;
+    if (p) prm = *p; else hz_default_params(&prm);
+    if (!params_ok(prm) || m_f < n || m_g < n || n < 1) return 0;
+    if (n == 1) return 256;
+    Plan P;
+    if (!make_plan(prm, m_f, m_g, n, 0, P)) return 0;
+    return P.total;
+}
+
+int hz_dgsvd(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, double *F, int64_t ldf,
+             double *G, int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
+             double *sigma_g, void *work, size_t work_bytes, hz_info *info, void *stream)
+{
+    hz_params prm;
+    if (p) prm = *p; else hz_default_params(&prm);
+    if (!params_ok(prm)) return -1;
+    const int a = check_args(m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g);
+    if (a) return a;
+    if (work && ((uintptr_t)work & 255)) return -14;
+    hipStream_t st = (hipStream_t)stream;
+    if (info) memset(info, 0, sizeof(*info));
+    if (n == 1) {
+        int rc = HZ_OK;
+        int *status = nullptr;
+        int hs[ST_NSLOTS] = {0};
+        bool own = false;
+        if (work && work_bytes >= 256) status = (int *)work;
+        else { if (hipMalloc(&status, 256) != hipSuccess) return HZ_EHIP; own = true; }
+        HZ_CHECK(hipMemsetAsync(status, 0, sizeof(int) * ST_NSLOTS, st));
+        launch_n1_real(m_f, m_g, F, G, Z, sigma, sigma_f, sigma_g, status, st);
+        HZ_CHECK(hipGetLastError());
+        HZ_CHECK(hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, st));
+        HZ_CHECK(hipStreamSynchronize(st));
+        if (hs[ST_FLAGS] & FLAG_NONFINITE) rc = HZ_ENONFINITE;
+        if (info) { info->converged = 1; info->w = 1; }
+    done:
+        if (own) (void)hipFree(status);
+        return rc;
+    }
+    Plan P;
+    if (!make_plan(prm, m_f, m_g, n, 0, P)) return -4;
+    if (work && work_bytes < P.total) return -15;
+    return run_solve(prm, P, work, work_bytes, info, st, false, F, ldf, G, ldg, F, G, Z, ldz,
+                     sigma, sigma_f, sigma_g);
+}
+
+}  // extern "C"
+
+namespace hz {
+
+static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t work_bytes,
+                     hz_info *info, hipStream_t st, bool complex_path, const void *F, int64_t ldf,
+                     const void *G, int64_t ldg, void *U, void *V, void *Z, int64_t ldz,
+                     double *sigma, double *sigma_f, double *sigma_g)
+{
+    (void)work_bytes;
+    int rc = HZ_OK;
+    bool own = false;
+    if (!work) {
+        if (hipMalloc(&work, P.total) != hipSuccess) return HZ_EHIP;
+        own = true;
+    }
+    {
+        const Ptrs W = make_ptrs(P, work);
+        const double tol = (prm.tol > 0.0) ? prm.tol : sqrt((double)P.n) * DBL_EPSILON;
+        std::vector<int> otab;
+        std::vector<int16_t> itab;
+        build_ordering<int>(prm.ordering, P.nblk, otab);
+        build_ordering<int16_t>(prm.inner_ordering, P.W2, itab);
+        std::vector<unsigned long long> hc((size_t)P.steps * P.npairs * 2);
+        int hs[ST_NSLOTS] = {0, INT_MAX, 0, 0};
+        uint64_t tot_all = 0, tot_big = 0;
+        int sweeps = 0, converged = 0;
+        HZ_CHECK(hipMemcpyAsync(W.otab, otab.data(), otab.size() * sizeof(int),
+                                hipMemcpyHostToDevice, st));
+        HZ_CHECK(hipMemcpyAsync(W.itab, itab.data(), itab.size() * sizeof(int16_t),
+                                hipMemcpyHostToDevice, st));
+        HZ_CHECK(hipMemcpyAsync(W.status, hs, sizeof(hs), hipMemcpyHostToDevice, st));
+        if (complex_path) { rc = HZ_EHIP; goto done; }
+        launch_prescale_real(P, W, (const double *)F, ldf, (const double *)G, ldg, st);
+        HZ_CHECK(hipGetLastError());
+        for (int sw = 0; sw < prm.max_sweeps; ++sw) {
+            for (int k = 0; k < P.steps; ++k) launch_step_real(P, W, k, prm, tol, st);
+            HZ_CHECK(hipGetLastError());
+            HZ_CHECK(hipMemcpyAsync(hc.data(), W.cnt, hc.size() * sizeof(unsigned long long),
+                                    hipMemcpyDeviceToHost, st));
+            HZ_CHECK(hipMemcpyAsync(hs, W.status, sizeof(hs), hipMemcpyDeviceToHost, st));
+            HZ_CHECK(hipStreamSynchronize(st));
+            prof_flush();
+            ++sweeps;
+            uint64_t s_all = 0, s_big = 0;
+            for (size_t i = 0; i < hc.size(); i += 2) {
+                s_all += hc[i];
+                s_big += hc[i + 1];
+            }
+            tot_all += s_all;
+            tot_big += s_big;
+            if (hs[ST_FLAGS]) break;
+            if (s_big == 0) {
+                converged = 1;
+                break;
+            }
+        }
+        if (!(hs[ST_FLAGS] & FLAG_CHOL)) {
+            launch_finish_real(P, W, (double *)U, ldf, (double *)V, ldg, (double *)Z, ldz, sigma,
+                               sigma_f, sigma_g, st);
+            HZ_CHECK(hipGetLastError());
+            HZ_CHECK(hipMemcpyAsync(hs, W.status, sizeof(hs), hipMemcpyDeviceToHost, st));
+        }
+        HZ_CHECK(hipStreamSynchronize(st));
+        if (hs[ST_FLAGS] & FLAG_NONFINITE) rc = HZ_ENONFINITE;
+        else if (hs[ST_FLAGS] & FLAG_CHOL) rc = HZ_ECHOL;
+        else if (!converged) rc = HZ_ENOCONV;
+        if (info) {
+            info->sweeps = sweeps;
+            info->converged = converged;
+            info->w = P.w;
+            info->failed_pair = (hs[ST_FLAGS] & FLAG_CHOL) ? hs[ST_FAILPAIR] : -1;
+            info->rot_total = tot_all;
+            info->rot_big = tot_big;
+        }
+    }
+done:
+    if (own) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(work);
+    }
+    return rc;
+}
+
+}  // namespace hz

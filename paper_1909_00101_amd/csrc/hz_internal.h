@@ -1,0 +1,66 @@
+// hz_internal.h -- host-side plan and kernel-launch interface of libhzgsvd.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/hzgsvd.h"
+
+namespace hz {
+
+// Geometry and workspace layout of one solve.  The working copies Fw, Gw,
+// Zw are column-major with leading dimension equal to their (64-padded) row
+// count; columns n .. nw-1 are the bordering columns of the paper's data
+// layout (Section 3.1): a unit in a fresh row of F and of G, zeros elsewhere.
+struct Plan {
+    int64_t mf, mg, n;        // caller shape
+    int64_t nw;               // columns after bordering, multiple of 2w
+    int64_t mfw, mgw, nzw;    // padded row counts of Fw, Gw, Zw (multiples of 64)
+    int w, W2;                // block width and pivot block order 2w
+    int nblk;                 // N = nw / w block columns
+    int npairs;               // N / 2 block pairs per step
+    int steps;                // outer steps per sweep
+    int isteps;               // inner steps per inner sweep
+    int splits;               // row splits of the Gram kernel
+    int upd_rows;             // rows per wave in the update kernel
+    int is_complex;
+    size_t esz;               // bytes per matrix element (8 or 16)
+    // workspace offsets (bytes)
+    size_t o_fw, o_gw, o_zw, o_part, o_zt, o_otab, o_itab, o_cnt, o_status;
+    size_t o_sf, o_sg, o_sig, o_rank, o_border, total;
+};
+
+struct Ptrs {
+    char *base;
+    double *Fw, *Gw, *Zw, *part, *Zt;
+    int *otab;
+    int16_t *itab;
+    unsigned long long *cnt;
+    int *status;
+    double *sf, *sg, *sig;
+    int *rank, *border;
+};
+
+// status[] slots written by kernels (integer atomics only)
+enum { ST_FLAGS = 0, ST_FAILPAIR = 1, ST_NSLOTS = 4 };
+enum { FLAG_NONFINITE = 1, FLAG_CHOL = 2 };
+
+// Kernel kinds timed by the optional per-launch profiler.
+enum { K_GRAM = 0, K_INNER = 1, K_UPDATE = 2, K_OTHER = 3, K_NKINDS = 4 };
+
+// Per-launch event hook: called before (begin=true) and after each timed
+// launch on stream s when profiling is enabled; no-op otherwise.
+void prof_mark(int kind, bool begin, hipStream_t s);
+
+// launchers (real FP64), hz_real.hip
+void launch_prescale_real(const Plan &P, const Ptrs &W, const double *F, int64_t ldf,
+                          const double *G, int64_t ldg, hipStream_t s);
+void launch_step_real(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
+                      hipStream_t s);
+void launch_finish_real(const Plan &P, const Ptrs &W, double *F, int64_t ldf, double *G,
+                        int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
+                        double *sigma_g, hipStream_t s);
+void launch_n1_real(int64_t mf, int64_t mg, double *F, double *G, double *Z, double *sigma,
+                    double *sigma_f, double *sigma_g, int *status, hipStream_t s);
+
+}  // namespace hz

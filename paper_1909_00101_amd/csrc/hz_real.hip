@@ -1,0 +1,622 @@
+// hz_real.hip -- FP64 kernels of the blocked one-sided implicit
+// Hari-Zimmermann GSVD on gfx950 (CDNA4).
+//
+// Per solve:  prescale/copy-in  ->  sweeps of block steps
+//             (Gram -> inner solve -> update)  ->  norms -> rank -> scatter.
+// Every reduction has a fixed association order and no floating-point
+// atomics are used, so reruns on the same input are bitwise identical.
+#include "hz_device.h"
+#include "hz_internal.h"
+
+namespace hz {
+
+// ------------------------------------------------------------------------
+// Prescale and copy-in (paper: Section 2, Z_0 = diag(1/||g_j||), and the
+// initFGZ kernel of Section 3.3), fused with the bordering of Section 3.1.
+// One wave per working column j < nw.  Columns j < n: d_j = 1/||g_j||,
+// Fw(:,j) = d_j F(:,j), Gw(:,j) = d_j G(:,j), Zw(:,j) = d_j e_j.  Columns
+// j >= n (bordering): unit entries at rows mf + (j-n) of Fw and mg + (j-n)
+// of Gw, Zw(:,j) = e_j.  Rows beyond the data are zero.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_prescale_copy(
+    int64_t mf, int64_t mg, int64_t n, const double *__restrict__ F, int64_t ldf,
+    const double *__restrict__ G, int64_t ldg, int64_t nw, int64_t mfw, int64_t mgw,
+    int64_t nzw, double *__restrict__ Fw, double *__restrict__ Gw, double *__restrict__ Zw,
+    int *__restrict__ status)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= nw) return;
+    double *fw = Fw + j * mfw, *gw = Gw + j * mgw, *zw = Zw + j * nzw;
+    if (j < n) {
+        const double *f = F + j * ldf, *g = G + j * ldg;
+        double s = 0.0;
+        for (int64_t r = lane; r < mg; r += 64) s = fma(g[r], g[r], s);
+        s = wave_sum(s);
+        const double d = 1.0 / sqrt(s);
+        bool bad = !(s > 0.0) || !isfinite(s);
+        for (int64_t r = lane; r < mfw; r += 64) {
+            const double v = (r < mf) ? f[r] * d : 0.0;
+            bad |= !isfinite(v);
+            fw[r] = v;
+        }
+        for (int64_t r = lane; r < mgw; r += 64) gw[r] = (r < mg) ? g[r] * d : 0.0;
+        for (int64_t r = lane; r < nzw; r += 64) zw[r] = (r == j) ? d : 0.0;
+        if (bad) atomicOr(status + ST_FLAGS, FLAG_NONFINITE);
+    } else {
+        const int64_t k = j - n;
+        for (int64_t r = lane; r < mfw; r += 64) fw[r] = (r == mf + k) ? 1.0 : 0.0;
+        for (int64_t r = lane; r < mgw; r += 64) gw[r] = (r == mg + k) ? 1.0 : 0.0;
+        for (int64_t r = lane; r < nzw; r += 64) zw[r] = (r == j) ? 1.0 : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Pivot Gram blocks (paper: Section 2.3, A_hat = [F_p F_q]^T [F_p F_q] and
+// B_hat likewise; Section 3.5.1 computes both triangles).  FP64 MFMA
+// 16x16x4.  Grid (splits, pairs, 2): each workgroup sums the rows of its
+// split (64-row chunks staged in LDS, next chunk prefetched into registers)
+// into a full W2 x W2 partial Gram; the 4 waves take interleaved k-steps
+// and are summed in LDS in wave order.  Output part[pair][mat][split] is
+// column-major W2 x W2; the inner kernel adds the splits in split order.
+// ------------------------------------------------------------------------
+template <int W2>
+__global__ __launch_bounds__(256) void k_gram(const double *__restrict__ Fw,
+                                              const double *__restrict__ Gw, int64_t mfw,
+                                              int64_t mgw, const int *__restrict__ pairs,
+                                              int splits, double *__restrict__ part)
+{
+    constexpr int W = W2 / 2, NB = W2 / 16, LDT = 66, NLD = W2 / 8;
+    __shared__ double tile[W2 * LDT];
+    const int split = blockIdx.x, pr = blockIdx.y, mat = blockIdx.z;
+    const double *Y = mat ? Gw : Fw;
+    const int64_t m = mat ? mgw : mfw;
+    const int p = pairs[2 * pr], q = pairs[2 * pr + 1];
+    const int64_t nch = m / 64;
+    const int64_t c0 = nch * split / splits, c1 = nch * (split + 1) / splits;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lrow = 2 * (tid & 31), lcol = tid >> 5;
+
+    d4 acc[NB][NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const double *colp[NLD];
+#pragma unroll
+    for (int t = 0; t < NLD; ++t) {
+        const int cc = lcol + 8 * t;
+        const int gc = (cc < W) ? p * W + cc : q * W + (cc - W);
+        colp[t] = Y + (int64_t)gc * m + lrow;
+    }
+    d2 buf[NLD];
+    if (c0 < c1) {
+#pragma unroll
+        for (int t = 0; t < NLD; ++t) buf[t] = *(const d2 *)(colp[t] + c0 * 64);
+    }
+    for (int64_t c = c0; c < c1; ++c) {
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < NLD; ++t) *(d2 *)(tile + (lcol + 8 * t) * LDT + lrow) = buf[t];
+        __syncthreads();
+        if (c + 1 < c1) {
+#pragma unroll
+            for (int t = 0; t < NLD; ++t) buf[t] = *(const d2 *)(colp[t] + (c + 1) * 64);
+        }
+#pragma unroll
+        for (int s = wave; s < 16; s += 4) {
+            double fr[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                fr[b] = tile[(16 * b + (lane & 15)) * LDT + 4 * s + (lane >> 4)];
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) acc[a][b] = mfma16(fr[a], fr[b], acc[a][b]);
+        }
+    }
+    // Sum the four waves' partial tiles in wave order (tile reused, ld W2).
+    for (int wv = 0; wv < 4; ++wv) {
+        __syncthreads();
+        if (wave == wv) {
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int gi = 16 * a + 4 * r + (lane >> 4), gj = 16 * b + (lane & 15);
+                        double *dst = tile + gj * W2 + gi;
+                        *dst = (wv == 0) ? acc[a][b][r] : *dst + acc[a][b][r];
+                    }
+        }
+    }
+    __syncthreads();
+    double *out = part + ((size_t)(pr * 2 + mat) * splits + split) * (W2 * W2);
+    for (int e = tid; e < W2 * W2; e += 256) out[e] = tile[e];
+}
+
+// ------------------------------------------------------------------------
+// Inner solve of one pivot block pair (paper: Section 2.3 factorization,
+// Section 2.1 pointwise method on the factors, Section 2.4 Theta rescale,
+// Section 2.5 counters; Sections 3.5.2-3.5.3 for the shared-memory flow).
+// One workgroup per block pair.  Steps:
+//  1. A_hat, B_hat = sum of the Gram partials (split order).
+//  2. Cholesky A_hat = F_hat^T F_hat, B_hat = G_hat^T G_hat (F_hat, G_hat
+//     upper triangular), one lane per row, the current column of L
+//     broadcast through LDS; a non-positive pivot flags HZ_ECHOL.
+//  3. Z_hat = diag(1/||g_hat_j||), F_hat, G_hat scaled by it.
+//  4. Inner sweeps (<= inner_max, stop after a sweep without
+//     transformations): each step, LP lanes per column pair form a_ii,
+//     a_jj, a_ij, b_ij, apply the skip test, the 2x2 transformation, the
+//     C1 classification and the sorting swap to the columns of F_hat,
+//     G_hat, Z_hat in LDS.
+//  5. Z_tilde = Z_hat Theta, Theta_jj = (||f_hat_j||^2+||g_hat_j||^2)^-1/2.
+// ------------------------------------------------------------------------
+template <int W2, int NT>
+__global__ __launch_bounds__(NT) void k_inner(
+    const double *__restrict__ part, int splits, int npairs, int step,
+    const int16_t *__restrict__ itab, int isteps, int inner_max, double tol, int sort,
+    double *__restrict__ Zt, unsigned long long *__restrict__ cnt, int *__restrict__ status)
+{
+    constexpr int W = W2 / 2;         // column pairs per inner step
+    constexpr int LP = NT / W;        // lanes per column pair
+    constexpr int RPL = W2 / LP;      // rows per lane
+    constexpr int LDI = W2 + 2;
+    static_assert(LP * W == NT && RPL * LP == W2 && LP <= 64, "bad inner geometry");
+    __shared__ double sF[W2 * LDI], sG[W2 * LDI], sZ[W2 * LDI];
+    __shared__ int16_t stab[W2 * W2];
+    __shared__ double lbuf[2][64];
+    __shared__ int s_fail;
+
+    const int pr = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // 1. sum the partial Grams
+    {
+        const double *pa = part + (size_t)(pr * 2) * splits * (W2 * W2);
+        const double *pb = pa + (size_t)splits * (W2 * W2);
+        for (int e = tid; e < W2 * W2; e += NT) {
+            double a = 0.0, b = 0.0;
+            for (int s = 0; s < splits; ++s) {
+                a += pa[(size_t)s * (W2 * W2) + e];
+                b += pb[(size_t)s * (W2 * W2) + e];
+            }
+            const int col = e / W2, row = e % W2;
+            sF[col * LDI + row] = a;
+            sG[col * LDI + row] = b;
+        }
+        for (int e = tid; e < isteps * W * 2; e += NT) stab[e] = itab[e];
+        if (tid == 0) s_fail = 0;
+    }
+    __syncthreads();
+
+    // 2. Cholesky factorizations, lane = row.
+    {
+        const bool big = (W2 == 64);
+        const int mat = big ? wave : (lane >> 5);
+        const int i = big ? lane : (lane & 31);
+        const bool active = (big ? (wave < 2) : (wave == 0)) && i < W2;
+        if (active) {
+            double *M = mat ? sG : sF;
+            double *lb = lbuf[mat];
+            const int base = big ? 0 : 32 * mat;
+            double a[W2];
+#pragma unroll
+            for (int k = 0; k < W2; ++k) a[k] = M[k * LDI + i];
+            bool ok = true;
+#pragma unroll
+            for (int j = 0; j < W2; ++j) {
+                const double djj = __shfl(a[j], base + j, 64);
+                ok = ok && (djj > 0.0) && isfinite(djj);
+                const double inv = 1.0 / sqrt(djj);
+                const double l = (i >= j) ? a[j] * inv : 0.0;
+                a[j] = l;
+                lb[i] = l;
+                wave_fence();
+#pragma unroll
+                for (int k = j + 1; k < W2; ++k) a[k] = fma(-l, lb[k], a[k]);
+                wave_fence();
+            }
+            // F_hat = L^T: column i of F_hat is row i of L.
+#pragma unroll
+            for (int k = 0; k < W2; ++k) M[i * LDI + k] = (k <= i) ? a[k] : 0.0;
+            if (!ok) atomicOr(&s_fail, 1);
+        }
+    }
+    __syncthreads();
+    if (s_fail) {
+        double *zt = Zt + (size_t)pr * (W2 * W2);
+        for (int e = tid; e < W2 * W2; e += NT) zt[e] = (e % W2 == e / W2) ? 1.0 : 0.0;
+        if (tid == 0) {
+            cnt[((size_t)step * npairs + pr) * 2 + 0] = 0;
+            cnt[((size_t)step * npairs + pr) * 2 + 1] = 0;
+            atomicOr(status + ST_FLAGS, FLAG_CHOL);
+            atomicMin(status + ST_FAILPAIR, step * 65536 + pr);
+        }
+        return;
+    }
+
+    const int grp = tid / LP, gl = tid % LP, r0 = gl * RPL;
+    // 3. prescale the factor pair: columns 2*grp and 2*grp+1 per group.
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = 2 * grp + h;
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const double g = sG[c * LDI + r0 + r];
+            s = fma(g, g, s);
+        }
+        s = group_sum<LP>(s);
+        const double d = 1.0 / sqrt(s);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            sF[c * LDI + r0 + r] *= d;
+            sG[c * LDI + r0 + r] *= d;
+            sZ[c * LDI + r0 + r] = (r0 + r == c) ? d : 0.0;
+        }
+    }
+    __syncthreads();
+
+    // 4. inner sweeps
+    unsigned my_all = 0, my_big = 0;
+    for (int sw = 0; sw < inner_max; ++sw) {
+        unsigned sw_all = 0, sw_big = 0;
+        for (int st = 0; st < isteps; ++st) {
+            const int ci = stab[(st * W + grp) * 2], cj = stab[(st * W + grp) * 2 + 1];
+            double fi[RPL], fj[RPL], gi[RPL], gj[RPL], zi[RPL], zj[RPL];
+            double aii = 0.0, ajj = 0.0, aij = 0.0, bij = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                fi[r] = sF[ci * LDI + r0 + r];
+                fj[r] = sF[cj * LDI + r0 + r];
+                gi[r] = sG[ci * LDI + r0 + r];
+                gj[r] = sG[cj * LDI + r0 + r];
+                zi[r] = sZ[ci * LDI + r0 + r];
+                zj[r] = sZ[cj * LDI + r0 + r];
+                aii = fma(fi[r], fi[r], aii);
+                ajj = fma(fj[r], fj[r], ajj);
+                aij = fma(fi[r], fj[r], aij);
+                bij = fma(gi[r], gj[r], bij);
+            }
+            aii = group_sum<LP>(aii);
+            ajj = group_sum<LP>(ajj);
+            aij = group_sum<LP>(aij);
+            bij = group_sum<LP>(bij);
+            double z11 = 1.0, z21 = 0.0, z12 = 0.0, z22 = 1.0;
+            bool swap = false;
+            const bool orth = fabs(aij) < sqrt(aii) * sqrt(ajj) * tol && fabs(bij) < tol;
+            if (orth) {
+                swap = sort && (aii < ajj);
+            } else {
+                hz_real_2x2(aii, ajj, aij, bij, z11, z21, z12, z22);
+                sw_all += 1;
+                if (!(z11 == 1.0 && z22 == 1.0)) sw_big += 1;
+                if (sort) {
+                    const double a11 = z11 * z11 * aii + 2.0 * z11 * z21 * aij + z21 * z21 * ajj;
+                    const double a22 = z12 * z12 * aii + 2.0 * z22 * z12 * aij + z22 * z22 * ajj;
+                    swap = a11 < a22;
+                }
+            }
+            if (!orth || swap) {
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) {
+                    double nfi = fma(fj[r], z21, fi[r] * z11), nfj = fma(fi[r], z12, fj[r] * z22);
+                    double ngi = fma(gj[r], z21, gi[r] * z11), ngj = fma(gi[r], z12, gj[r] * z22);
+                    double nzi = fma(zj[r], z21, zi[r] * z11), nzj = fma(zi[r], z12, zj[r] * z22);
+                    if (swap) {
+                        double t;
+                        t = nfi; nfi = nfj; nfj = t;
+                        t = ngi; ngi = ngj; ngj = t;
+                        t = nzi; nzi = nzj; nzj = t;
+                    }
+                    sF[ci * LDI + r0 + r] = nfi;
+                    sF[cj * LDI + r0 + r] = nfj;
+                    sG[ci * LDI + r0 + r] = ngi;
+                    sG[cj * LDI + r0 + r] = ngj;
+                    sZ[ci * LDI + r0 + r] = nzi;
+                    sZ[cj * LDI + r0 + r] = nzj;
+                }
+            }
+            __syncthreads();
+        }
+        my_all += sw_all;
+        my_big += sw_big;
+        const int any = __syncthreads_count(gl == 0 && sw_all > 0);
+        if (any == 0) break;
+    }
+
+    // 5. Theta rescale and write Z_tilde (column-major W2 x W2).
+    double *zt = Zt + (size_t)pr * (W2 * W2);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = 2 * grp + h;
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const double f = sF[c * LDI + r0 + r], g = sG[c * LDI + r0 + r];
+            s = fma(f, f, s);
+            s = fma(g, g, s);
+        }
+        s = group_sum<LP>(s);
+        const double th = 1.0 / sqrt(s);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) zt[c * W2 + r0 + r] = sZ[c * LDI + r0 + r] * th;
+    }
+    // counters: sum the groups' totals in group order through LDS
+    __syncthreads();
+    unsigned *cbuf = (unsigned *)lbuf;   // 2*W <= 128 slots
+    if (gl == 0) {
+        cbuf[2 * grp] = my_all;
+        cbuf[2 * grp + 1] = my_big;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long ta = 0, tb = 0;
+        for (int g = 0; g < W; ++g) {
+            ta += cbuf[2 * g];
+            tb += cbuf[2 * g + 1];
+        }
+        cnt[((size_t)step * npairs + pr) * 2 + 0] = ta;
+        cnt[((size_t)step * npairs + pr) * 2 + 1] = tb;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Block update (paper: Section 2.3, [F_p F_q] <- [F_p F_q] Z_tilde and the
+// same for G and Z; Section 3.5.4 does it in place with one read and one
+// write of the block columns).  FP64 MFMA: each wave holds Z_tilde^T as
+// MFMA A-fragments in registers and streams 16-row tiles X of the block
+// column pair: D' = Z_tilde^T X^T, so both the loads of X and the stores of
+// D' = (X Z_tilde)^T are 128-byte column segments.  A wave reads all W2
+// columns of its 16 rows before writing them: in place without races.
+// Grid (row tiles of Fw | Gw | Zw, pairs), 4 waves x rows_per_wave rows.
+// ------------------------------------------------------------------------
+template <int W2>
+__global__ __launch_bounds__(256) void k_update(double *__restrict__ Fw, double *__restrict__ Gw,
+                                                double *__restrict__ Zw, int64_t mfw,
+                                                int64_t mgw, int64_t nzw,
+                                                const int *__restrict__ pairs,
+                                                const double *__restrict__ Zt, int tiles_f,
+                                                int tiles_g, int rows_per_wave)
+{
+    constexpr int W = W2 / 2, NB = W2 / 16, KS = W2 / 4;
+    const int pr = blockIdx.y;
+    const int p = pairs[2 * pr], q = pairs[2 * pr + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t t = blockIdx.x;
+    double *Y;
+    int64_t m;
+    if (t < tiles_f) {
+        Y = Fw;
+        m = mfw;
+    } else if (t < tiles_f + tiles_g) {
+        Y = Gw;
+        m = mgw;
+        t -= tiles_f;
+    } else {
+        Y = Zw;
+        m = nzw;
+        t -= tiles_f + tiles_g;
+    }
+    const int64_t rb = (t * 4 + wave) * rows_per_wave;
+    if (rb >= m) return;
+    const int64_t re = (rb + rows_per_wave < m) ? rb + rows_per_wave : m;
+    const double *zt = Zt + (size_t)pr * (W2 * W2);
+    double za[NB][KS];
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) za[jb][s] = zt[(16 * jb + (lane & 15)) * W2 + 4 * s + (lane >> 4)];
+    double *xcol[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int c = 4 * s + (lane >> 4);
+        const int gc = (c < W) ? p * W + c : q * W + (c - W);
+        xcol[s] = Y + (int64_t)gc * m + (lane & 15);
+    }
+    for (int64_t r0 = rb; r0 < re; r0 += 16) {
+        double xb[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) xb[s] = xcol[s][r0];
+        d4 acc[NB];
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) acc[jb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) acc[jb] = mfma16(za[jb][s], xb[s], acc[jb]);
+        // element r of acc[jb] in lane l is output column 16jb + 4r + l/16, row l%16
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = 16 * jb + 4 * r + (lane >> 4);
+                const int gc = (c < W) ? p * W + c : q * W + (c - W);
+                Y[(int64_t)gc * m + r0 + (lane & 15)] = acc[jb][r];
+            }
+    }
+}
+
+// ------------------------------------------------------------------------
+// Final extraction (paper: Section 2.4 post-iterative phase and the rescale
+// kernel of Section 3.4) and descending sort (Section 1).
+// k_colnorms: one wave per working column: ||f_j||, ||g_j||, sigma_j =
+//   ||f_j|| / ||g_j||, and whether the column is a bordering column (its Z
+//   column is nonzero only in rows >= n).
+// k_rank: stable descending rank of sigma among the non-bordering columns.
+// k_scatter: U(:,rank) = f_j/||f_j||, V(:,rank) = g_j/||g_j||,
+//   Z(:,rank) = theta_j z_j, Sigma_F = theta ||f_j||, Sigma_G = theta ||g_j||.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_colnorms(const double *__restrict__ Fw,
+                                                  const double *__restrict__ Gw,
+                                                  const double *__restrict__ Zw, int64_t mfw,
+                                                  int64_t mgw, int64_t nzw, int64_t n,
+                                                  int64_t nw, double *__restrict__ sf,
+                                                  double *__restrict__ sg,
+                                                  double *__restrict__ sig,
+                                                  int *__restrict__ border,
+                                                  int *__restrict__ status)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= nw) return;
+    const double *f = Fw + j * mfw, *g = Gw + j * mgw, *z = Zw + j * nzw;
+    double a = 0.0, b = 0.0;
+    for (int64_t r = lane; r < mfw; r += 64) a = fma(f[r], f[r], a);
+    for (int64_t r = lane; r < mgw; r += 64) b = fma(g[r], g[r], b);
+    int bz = 0;
+    for (int64_t r = n + lane; r < nw; r += 64) bz |= (z[r] != 0.0);
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int isb = __any(bz) ? 1 : 0;
+    if (lane == 0) {
+        const double x = sqrt(a), y = sqrt(b);
+        sf[j] = x;
+        sg[j] = y;
+        sig[j] = x / y;
+        border[j] = isb;
+        if (!isb && !(isfinite(x / y) && x > 0.0 && y > 0.0)) atomicOr(status + ST_FLAGS, FLAG_NONFINITE);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rank(const double *__restrict__ sig,
+                                              const int *__restrict__ border, int64_t nw,
+                                              int *__restrict__ rank)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nw) return;
+    if (border[j]) {
+        rank[j] = -1;
+        return;
+    }
+    const double s = sig[j];
+    int64_t r = 0;
+    for (int64_t k = 0; k < nw; ++k) {
+        if (border[k]) continue;
+        const double t = sig[k];
+        r += (t > s) || (t == s && k < j);
+    }
+    rank[j] = (int)r;
+}
+
+__global__ __launch_bounds__(256) void k_scatter(
+    const double *__restrict__ Fw, const double *__restrict__ Gw, const double *__restrict__ Zw,
+    int64_t mfw, int64_t mgw, int64_t nzw, int64_t mf, int64_t mg, int64_t n, int64_t nw,
+    const double *__restrict__ sf, const double *__restrict__ sg, const int *__restrict__ rank,
+    double *__restrict__ U, int64_t ldu, double *__restrict__ V, int64_t ldv,
+    double *__restrict__ Z, int64_t ldz, double *__restrict__ sigma,
+    double *__restrict__ sigma_f, double *__restrict__ sigma_g)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= nw) return;
+    const int rk = rank[j];
+    if (rk < 0 || rk >= n) return;
+    const double x = sf[j], y = sg[j];
+    const double th = 1.0 / sqrt(x * x + y * y);
+    const double ix = 1.0 / x, iy = 1.0 / y;
+    const double *f = Fw + j * mfw, *g = Gw + j * mgw, *z = Zw + j * nzw;
+    double *u = U + (int64_t)rk * ldu, *v = V + (int64_t)rk * ldv, *zo = Z + (int64_t)rk * ldz;
+    for (int64_t r = lane; r < mf; r += 64) u[r] = f[r] * ix;
+    for (int64_t r = lane; r < mg; r += 64) v[r] = g[r] * iy;
+    for (int64_t r = lane; r < n; r += 64) zo[r] = z[r] * th;
+    if (lane == 0) {
+        sigma[rk] = x / y;
+        sigma_f[rk] = x * th;
+        sigma_g[rk] = y * th;
+    }
+}
+
+// n = 1 closed form (paper, Section 2).  One wave.
+__global__ __launch_bounds__(64) void k_n1(int64_t mf, int64_t mg, double *__restrict__ F,
+                                           double *__restrict__ G, double *__restrict__ Z,
+                                           double *__restrict__ sigma,
+                                           double *__restrict__ sigma_f,
+                                           double *__restrict__ sigma_g,
+                                           int *__restrict__ status)
+{
+    const int lane = threadIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int64_t r = lane; r < mf; r += 64) a = fma(F[r], F[r], a);
+    for (int64_t r = lane; r < mg; r += 64) b = fma(G[r], G[r], b);
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const double nf = sqrt(a), ng = sqrt(b), rr = sqrt(a + b);
+    for (int64_t r = lane; r < mf; r += 64) F[r] = F[r] / nf;
+    for (int64_t r = lane; r < mg; r += 64) G[r] = G[r] / ng;
+    if (lane == 0) {
+        Z[0] = 1.0 / rr;
+        sigma[0] = nf / ng;
+        sigma_f[0] = nf / rr;
+        sigma_g[0] = ng / rr;
+        if (!(isfinite(nf / ng) && nf > 0.0 && ng > 0.0)) atomicOr(status + ST_FLAGS, FLAG_NONFINITE);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+void launch_prescale_real(const Plan &P, const Ptrs &W, const double *F, int64_t ldf,
+                          const double *G, int64_t ldg, hipStream_t s)
+{
+    const unsigned nb = (unsigned)((P.nw + 3) / 4);
+    hipLaunchKernelGGL(k_prescale_copy, dim3(nb), dim3(256), 0, s, P.mf, P.mg, P.n, F, ldf, G,
+                       ldg, P.nw, P.mfw, P.mgw, P.nzw, W.Fw, W.Gw, W.Zw, W.status);
+}
+
+template <int W2>
+static void step_impl(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
+                      hipStream_t s)
+{
+    const int *pairs = W.otab + (size_t)step * P.npairs * 2;
+    prof_mark(K_GRAM, true, s);
+    hipLaunchKernelGGL(k_gram<W2>, dim3(P.splits, P.npairs, 2), dim3(256), 0, s, W.Fw, W.Gw,
+                       P.mfw, P.mgw, pairs, P.splits, W.part);
+    prof_mark(K_GRAM, false, s);
+    constexpr int NT = (W2 == 64) ? 512 : (W2 == 32 ? 128 : 64);
+    prof_mark(K_INNER, true, s);
+    hipLaunchKernelGGL((k_inner<W2, NT>), dim3(P.npairs), dim3(NT), 0, s, W.part, P.splits,
+                       P.npairs, step, W.itab, P.isteps, prm.inner_max_sweeps, tol, prm.sort,
+                       W.Zt, W.cnt, W.status);
+    prof_mark(K_INNER, false, s);
+    const int64_t rpt = 4 * (int64_t)P.upd_rows;
+    const int tf = (int)((P.mfw + rpt - 1) / rpt), tg = (int)((P.mgw + rpt - 1) / rpt),
+              tz = (int)((P.nzw + rpt - 1) / rpt);
+    prof_mark(K_UPDATE, true, s);
+    hipLaunchKernelGGL(k_update<W2>, dim3(tf + tg + tz, P.npairs), dim3(256), 0, s, W.Fw, W.Gw,
+                       W.Zw, P.mfw, P.mgw, P.nzw, pairs, W.Zt, tf, tg, P.upd_rows);
+    prof_mark(K_UPDATE, false, s);
+}
+
+void launch_step_real(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
+                      hipStream_t s)
+{
+    switch (P.W2) {
+    case 16: step_impl<16>(P, W, step, prm, tol, s); break;
+    case 32: step_impl<32>(P, W, step, prm, tol, s); break;
+    default: step_impl<64>(P, W, step, prm, tol, s); break;
+    }
+}
+
+void launch_finish_real(const Plan &P, const Ptrs &W, double *F, int64_t ldf, double *G,
+                        int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
+                        double *sigma_g, hipStream_t s)
+{
+    const unsigned nb4 = (unsigned)((P.nw + 3) / 4);
+    hipLaunchKernelGGL(k_colnorms, dim3(nb4), dim3(256), 0, s, W.Fw, W.Gw, W.Zw, P.mfw, P.mgw,
+                       P.nzw, P.n, P.nw, W.sf, W.sg, W.sig, W.border, W.status);
+    hipLaunchKernelGGL(k_rank, dim3((unsigned)((P.nw + 255) / 256)), dim3(256), 0, s, W.sig,
+                       W.border, P.nw, W.rank);
+    hipLaunchKernelGGL(k_scatter, dim3(nb4), dim3(256), 0, s, W.Fw, W.Gw, W.Zw, P.mfw, P.mgw,
+                       P.nzw, P.mf, P.mg, P.n, P.nw, W.sf, W.sg, W.rank, F, ldf, G, ldg, Z, ldz,
+                       sigma, sigma_f, sigma_g);
+}
+
+void launch_n1_real(int64_t mf, int64_t mg, double *F, double *G, double *Z, double *sigma,
+                    double *sigma_f, double *sigma_g, int *status, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_n1, dim3(1), dim3(64), 0, s, mf, mg, F, G, Z, sigma, sigma_f, sigma_g,
+                       status);
+}
+
+}  // namespace hz

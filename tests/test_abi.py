@@ -1,0 +1,136 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function declared in include/hzgsvd.h, validates arguments before any
+device work, and builds orderings with the properties of Section 2.2."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hzgsvd.h")
+
+
+@pytest.fixture(scope="module")
+def hz():
+    import paper_1909_00101_amd as hz
+    if not os.path.exists(hz.LIB_PATH):
+        hz.build()
+    return hz
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b(hz_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for must in ("hz_dgsvd", "hz_dgsvd_work_size", "hz_default_params", "hz_strerror"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(hz):
+    L = ctypes.CDLL(hz.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_defaults(hz):
+    p = hz.params()
+    assert (p.variant, p.ordering, p.inner_ordering, p.w) == (0, hz.HZ_ORD_MM, hz.HZ_ORD_RR, 0)
+    assert (p.inner_max_sweeps, p.max_sweeps, p.sort) == (30, 30, 1)
+    assert p.tol == 0.0 and p.mixed_switch == 1e-5
+
+
+def test_strerror(hz):
+    L = hz.lib()
+    assert L.hz_strerror(0) == b"success"
+    assert b"positive definite" in L.hz_strerror(2)
+    assert L.hz_strerror(-3) == b"invalid argument"
+    assert L.hz_version().startswith(b"hzgsvd")
+
+
+def _call(hz, p, m_f, m_g, n, F=8, ldf=None, G=8, ldg=None, Z=8, ldz=None, s=8, sf=8, sg=8,
+          work=None, wb=0):
+    L = hz.lib()
+    v = ctypes.c_void_p
+    return L.hz_dgsvd(ctypes.byref(p) if p is not None else None, m_f, m_g, n,
+                      v(F), ldf if ldf is not None else m_f, v(G), ldg if ldg is not None else m_g,
+                      v(Z), ldz if ldz is not None else n, v(s), v(sf), v(sg), v(work), wb,
+                      None, None)
+
+
+@pytest.mark.parametrize("case,expect", [
+    (dict(m_f=0, m_g=5, n=1), -2), (dict(m_f=5, m_g=0, n=1), -3),
+    (dict(m_f=3, m_g=5, n=4), -4), (dict(m_f=5, m_g=3, n=4), -4), (dict(m_f=5, m_g=5, n=0), -4),
+    (dict(m_f=5, m_g=5, n=2, F=0), -5), (dict(m_f=5, m_g=5, n=2, F=12), -5),
+    (dict(m_f=5, m_g=5, n=2, ldf=4), -6), (dict(m_f=5, m_g=5, n=2, G=0), -7),
+    (dict(m_f=5, m_g=5, n=2, ldg=2), -8), (dict(m_f=5, m_g=5, n=2, Z=0), -9),
+    (dict(m_f=5, m_g=5, n=2, ldz=1), -10), (dict(m_f=5, m_g=5, n=2, s=0), -11),
+    (dict(m_f=5, m_g=5, n=2, sf=0), -12), (dict(m_f=5, m_g=5, n=2, sg=4), -13),
+    (dict(m_f=5, m_g=5, n=2, work=264), -14),
+    (dict(m_f=500, m_g=500, n=200, work=256, wb=100), -15),
+])
+def test_argument_validation_before_device_work(hz, case, expect):
+    # Every rejection happens on the host before any HIP call, so these run
+    # without a GPU.
+    assert _call(hz, hz.params(), **case) == expect
+
+
+def test_bad_params_rejected(hz):
+    for kw in (dict(variant=1), dict(w=12), dict(ordering=7), dict(inner_max_sweeps=0),
+               dict(max_sweeps=0), dict(inner_ordering=0)):
+        assert _call(hz, hz.params(**kw), 64, 64, 32) == -1
+
+
+def test_work_size(hz):
+    L = hz.lib()
+    p = hz.params(w=32)
+    a = L.hz_dgsvd_work_size(ctypes.byref(p), 4096, 4096, 1024)
+    # at least the working copies of F, G, Z
+    assert a >= 8 * (4096 * 1024 * 2 + 1024 * 1024)
+    assert a < 2 * 8 * (4096 * 1024 * 2 + 1024 * 1024)
+    assert L.hz_dgsvd_work_size(ctypes.byref(p), 10, 10, 11) == 0
+    assert L.hz_dgsvd_work_size(None, 10, 10, 1) > 0
+
+
+def _table(hz, kind, N):
+    L = hz.lib()
+    steps = L.hz_ordering(kind, N, None)
+    t = (ctypes.c_int * (steps * N))()
+    assert L.hz_ordering(kind, N, t) == steps
+    return np.array(t).reshape(steps, N // 2, 2)
+
+
+@pytest.mark.parametrize("N", [2, 4, 8, 16, 32, 64, 128])
+def test_library_orderings(hz, N):
+    mm = _table(hz, hz.HZ_ORD_MM, N)
+    rr = _table(hz, hz.HZ_ORD_RR, N)
+    assert mm.shape[0] == N and rr.shape[0] == N - 1
+    for t, cyclic in ((mm, False), (rr, True)):
+        seen = {}
+        for step in t:
+            assert sorted(step.reshape(-1).tolist()) == list(range(N))
+            for p, q in step:
+                assert p < q
+                seen[(p, q)] = seen.get((p, q), 0) + 1
+        assert len(seen) == N * (N - 1) // 2
+        if cyclic:
+            assert all(c == 1 for c in seen.values())
+    assert hz.lib().hz_ordering(hz.HZ_ORD_MM, 7, None) == -1
+    assert hz.lib().hz_ordering(5, 8, None) == -1
+
+
+def test_product_path_does_not_reach_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1909_00101_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "hz_oracle" not in src, f
+                assert "oracle/" not in src, f

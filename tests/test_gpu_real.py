@@ -1,0 +1,185 @@
+"""GPU parity of the real FP64 path (hz_dgsvd through the C ABI) against the
+CPU oracle, on seeded synthetic pairs.
+
+Bar: generalized singular values within 1e-10 relative of the oracle's for
+kappa(X) <= 1e2 (the benchmark spec's tolerance), and the GSVD contract of the GPU
+outputs (FZ = U Sigma_F, GZ = V Sigma_G, orthonormal U and V, Sigma_F^2 +
+Sigma_G^2 = I, descending sigma, the GEVD link) to blocked-algorithm rounding
+levels.  U, V, Z are unique only up to column signs, so they are compared
+through the contract rather than elementwise.
+"""
+
+import hashlib
+
+import numpy as np
+import pytest
+
+import gsvd_inputs as gi
+from contract import assert_contract, max_rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+SIG_TOL = 1e-10
+
+
+def _hz():
+    import paper_1909_00101_amd as hz
+    return hz
+
+
+def _oracle(F, G, **kw):
+    import oracle
+    return oracle.gsvd(F, G, **kw)
+
+
+def _run(F, G, **kw):
+    hz = _hz()
+    dF = torch.from_numpy(np.asfortranarray(F)).cuda()
+    dG = torch.from_numpy(np.asfortranarray(G)).cuda()
+    r = hz.gsvd(dF, dG, **kw)
+    torch.cuda.synchronize()
+    out = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in r.items()}
+    return out
+
+
+def _check(F, G, r, tol_res=1e-12):
+    return assert_contract(F, G, r["U"], r["V"], r["Z"], r["sigma_f"], r["sigma_g"],
+                           r["sigma"], tol_res=tol_res, tol_orth=1e-12)
+
+
+@pytest.mark.parametrize("w", [8, 16])
+def test_config1_parity(w):
+    F, G, s_true = gi.config_pair(1)
+    tol = 32 * EPS
+    o = _oracle(F, G, tol=tol)
+    r = _run(F, G, w=w, tol=tol)
+    print(f"config1 w={w}: sweeps={r['sweeps']} status={r['status']} "
+          f"err_vs_oracle={max_rel(r['sigma'], o['sigma']):.2e}")
+    assert r["status"] == 0 and r["converged"]
+    assert max_rel(r["sigma"], o["sigma"]) < SIG_TOL
+    assert max_rel(r["sigma"], s_true) < 1e-12
+    _check(F, G, r)
+
+
+SHAPES = [
+    # m_f, m_g, n, w, kappa
+    (100, 70, 48, 8, 10.0),
+    (130, 129, 37, 8, 30.0),      # ragged n: bordering to 48 columns
+    (256, 200, 96, 16, 1e2),
+    (300, 300, 160, 16, 1e2),     # 10 block columns, several row chunks
+    (700, 520, 256, 32, 1e2),     # 2w = 64 pivot blocks
+    (64, 64, 2, 8, 3.0),          # smallest blocked case (bordered to 16)
+    (333, 65, 65, 16, 50.0),      # square G, ragged everywhere
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[:4])))
+def test_shapes_parity(shape):
+    m_f, m_g, n, w, kappa = shape
+    F, G, s_true = gi.custom_pair(m_f, m_g, n, kappa=kappa, seed=n + w)
+    o = _oracle(F, G, ordering=1, threads=4)
+    r = _run(F, G, w=w)
+    err = max_rel(r["sigma"], o["sigma"])
+    print(f"{shape}: sweeps={r['sweeps']} status={r['status']} err={err:.2e}")
+    assert r["status"] == 0
+    assert err < SIG_TOL
+    assert max_rel(r["sigma"], s_true) < 1e-11
+    _check(F, G, r)
+
+
+def test_n1_closed_form():
+    rng = np.random.default_rng(3)
+    F = rng.standard_normal((9, 1))
+    G = rng.standard_normal((5, 1))
+    o = _oracle(F, G)
+    r = _run(F, G)
+    assert r["status"] == 0
+    assert max_rel(r["sigma"], o["sigma"]) < 4 * EPS
+    _check(F, G, r)
+
+
+@pytest.mark.parametrize("kw", [dict(ordering=2), dict(inner_ordering=1),
+                                dict(inner_max_sweeps=1), dict(sort=0)],
+                         ids=["outerRR", "innerMM", "BO", "nosort"])
+def test_variants_parity(kw):
+    F, G, _ = gi.custom_pair(200, 180, 64, kappa=1e2, seed=77)
+    o = _oracle(F, G)
+    r = _run(F, G, w=8, **kw)
+    assert r["status"] == 0
+    assert max_rel(r["sigma"], o["sigma"]) < SIG_TOL
+    _check(F, G, r)
+
+
+def _digest(r):
+    h = hashlib.sha256()
+    for k in ("U", "V", "Z", "sigma", "sigma_f", "sigma_g"):
+        h.update(np.ascontiguousarray(r[k]).tobytes())
+    return h.hexdigest()
+
+
+def test_bitwise_reruns():
+    F, G, _ = gi.custom_pair(512, 384, 128, kappa=1e2, seed=5)
+    digests = {_digest(_run(F, G, w=16)) for _ in range(3)}
+    assert len(digests) == 1
+
+
+def test_rank_deficient_reports_cholesky_failure():
+    hz = _hz()
+    F, G, _ = gi.custom_pair(80, 80, 32, seed=8)
+    G[:, 5] = G[:, 4]
+    with pytest.raises(hz.GsvdError) as e:
+        _run(F, G, w=8)
+    assert e.value.status == hz.HZ_ECHOL
+    assert e.value.info.failed_pair >= 0
+
+
+def test_nonfinite_input():
+    hz = _hz()
+    F, G, _ = gi.custom_pair(80, 80, 32, seed=9)
+    F[3, 7] = np.nan
+    with pytest.raises(hz.GsvdError) as e:
+        _run(F, G, w=8)
+    assert e.value.status == hz.HZ_ENONFINITE
+
+
+def test_sweep_cap():
+    F, G, _ = gi.custom_pair(80, 80, 32, seed=10)
+    r = _run(F, G, w=8, max_sweeps=1)
+    assert r["status"] == 1 and not r["converged"] and r["sweeps"] == 1
+
+
+def test_config2_full_size_vs_oracle_golden():
+    """The 4096x1024 workload in the benchmark's launch configuration
+    (w = 32, modified modulus, tol = 1024 eps) against the oracle's sigma for
+    the same seeded pair (tests/golden/oracle_config2.json, written by
+    tests/golden/make_golden.py from the oracle alone), plus the contract
+    residuals of the GPU outputs computed on the GPU."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "oracle_config2.json")))
+    F, G, s_true = gi.config_pair(2)
+    hz = _hz()
+    dF = torch.from_numpy(F).cuda()
+    dG = torch.from_numpy(G).cuda()
+    r = hz.gsvd(dF, dG, w=32, ordering=hz.HZ_ORD_MM, tol=1024 * EPS)
+    torch.cuda.synchronize()
+    s = r["sigma"].cpu().numpy()
+    err = max_rel(s, np.array(gold["sigma"]))
+    print(f"config2: sweeps={r['sweeps']} err_vs_oracle={err:.2e} "
+          f"err_vs_prescribed={max_rel(s, s_true):.2e}")
+    assert r["status"] == 0
+    assert err < SIG_TOL
+    U, V, Z = r["U"], r["V"], r["Z"]
+    sf, sg = r["sigma_f"], r["sigma_g"]
+    n = Z.shape[0]
+    fz = torch.linalg.norm(dF @ Z - U * sf) / (torch.linalg.norm(dF) * torch.linalg.norm(Z))
+    gz = torch.linalg.norm(dG @ Z - V * sg) / (torch.linalg.norm(dG) * torch.linalg.norm(Z))
+    eye = torch.eye(n, dtype=torch.float64, device=U.device)
+    uu = torch.linalg.norm(U.T @ U - eye) / n
+    vv = torch.linalg.norm(V.T @ V - eye) / n
+    assert float(fz) < 1e-12 and float(gz) < 1e-12, (float(fz), float(gz))
+    assert float(uu) < 1e-12 and float(vv) < 1e-12, (float(uu), float(vv))
+    assert float(torch.max(torch.abs(sf * sf + sg * sg - 1))) < 8 * EPS
