@@ -45,6 +45,19 @@ def algorithmic(m_f, m_g, n, w):
     return gram, upd
 
 
+def inner_flops(w, launches, inner_sweeps, rotations, npairs):
+    """Algorithmic FP64 work of the inner solver per launch (one step of
+    n/(2w) pivot pairs): two Cholesky factorizations of order 2w,
+    (2w)^3/3 multiply-adds each; per inner sweep (2w-1) steps of w column
+    pairs, each forming 4 dot products of length 2w (16w flops); per applied
+    transformation 6 columns of length 2w updated (36w flops)."""
+    W2 = 2 * w
+    chol = npairs * launches * 2.0 * (2.0 * W2 ** 3 / 3.0)
+    dots = inner_sweeps * (W2 - 1) * w * 16.0 * w
+    apply = rotations * 36.0 * w
+    return (chol + dots + apply) / max(1, launches)
+
+
 def cpu_baseline(F, G, tol, golden_sweeps):
     """Time one sweep of the CPU oracle (modified-modulus ordering, OpenMP over
     the disjoint pairs of each step, all host threads) on the same pair, and
@@ -67,7 +80,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--w", type=int, default=32)
-    ap.add_argument("--inner-max-sweeps", type=int, default=30)
+    ap.add_argument("--inner-max-sweeps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -106,10 +119,12 @@ def main():
     L.hz_profile_enable(1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sweeps = []
+    sweeps, isw, rots = [], 0, 0
     for _ in range(args.steps):
         r = solve()
         sweeps.append(r["sweeps"])
+        isw += r["inner_sweeps"]
+        rots += r["rot_total"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = (ctypes.c_double * 4)()
@@ -119,26 +134,45 @@ def main():
     err = float(np.max(np.abs(r["sigma"].cpu().numpy() - s_true) / s_true))
 
     gram, upd = algorithmic(spec.m_f, spec.m_g, spec.n, args.w)
-    kinds = {"gram": (ms[0], cnt[0], gram), "inner": (ms[1], cnt[1], None),
+    npairs = spec.n // (2 * args.w)
+    inner = dict(flops=inner_flops(args.w, cnt[1], isw, rots, npairs), bytes=None)
+    kinds = {"gram": (ms[0], cnt[0], gram), "inner": (ms[1], cnt[1], inner),
              "update": (ms[2], cnt[2], upd)}
     split = {k: round(v[0] / max(1e-9, sum(x[0] for x in kinds.values())), 4)
              for k, v in kinds.items()}
-    dom = max(("gram", "update"), key=lambda k: kinds[k][0])
+    dom = max(kinds, key=lambda k: kinds[k][0])
     t_launch = kinds[dom][0] / max(1, kinds[dom][1]) * 1e-3
     work_d = kinds[dom][2]
-    intensity = work_d["flops"] / work_d["bytes"]
     ridge = FP64_MFMA_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
-    if intensity < ridge:
-        achieved = work_d["bytes"] / t_launch / 1e9
-        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None)
-    else:
+    if dom == "inner":
+        # latency-bound FP64 VALU work on one workgroup per pivot pair
         achieved = work_d["flops"] / t_launch / 1e12
-        roof = dict(bound="mfma", achieved=round(achieved, 2), peak=FP64_MFMA_PEAK_TFS,
-                    unit="TFLOP/s", frac=round(achieved / FP64_MFMA_PEAK_TFS, 4), traffic=None)
+        roof = dict(bound="alu", achieved=round(achieved, 4), peak=FP64_MFMA_PEAK_TFS,
+                    unit="TFLOP/s", frac=round(achieved / FP64_MFMA_PEAK_TFS, 5), traffic=None,
+                    cus_used=npairs)
+        intensity = None
+    else:
+        intensity = work_d["flops"] / work_d["bytes"]
+        if intensity < ridge:
+            achieved = work_d["bytes"] / t_launch / 1e9
+            roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                        unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None)
+        else:
+            achieved = work_d["flops"] / t_launch / 1e12
+            roof = dict(bound="mfma", achieved=round(achieved, 2), peak=FP64_MFMA_PEAK_TFS,
+                        unit="TFLOP/s", frac=round(achieved / FP64_MFMA_PEAK_TFS, 4),
+                        traffic=None)
     roof["kernel"] = f"k_{dom}<W2={2 * args.w}>"
     roof["avg_launch_us"] = round(t_launch * 1e6, 2)
-    roof["intensity_flop_per_byte"] = round(intensity, 2)
+    if intensity is not None:
+        roof["intensity_flop_per_byte"] = round(intensity, 2)
+    per_kernel = {k: dict(avg_us=round(v[0] / max(1, v[1]) * 1e3, 2), launches=int(v[1]))
+                  for k, v in kinds.items()}
+    for k in ("gram", "update"):
+        wd = kinds[k][2]
+        t = kinds[k][0] / max(1, kinds[k][1]) * 1e-3
+        per_kernel[k]["GB_s"] = round(wd["bytes"] / t / 1e9, 1) if t > 0 else None
+        per_kernel[k]["TFLOP_s"] = round(wd["flops"] / t / 1e12, 2) if t > 0 else None
     # whole-solve FP64 MFMA utilisation from algorithmic flops of the executed steps
     steps_per_sweep = spec.n // args.w
     mean_sweeps = float(np.mean(sweeps))
@@ -157,7 +191,7 @@ def main():
                            parallelism="single GPU"),
                sweeps=sweeps, max_rel_sigma_err_vs_prescribed=err,
                fp64_mfma_util_solve=round(mfma_util, 4),
-               kernel_time_split=split, roofline=roof)
+               kernel_time_split=split, kernels=per_kernel, roofline=roof)
     if not args.no_cpu_baseline:
         golden = os.path.join(ROOT, "tests", "golden", "oracle_config2.json")
         gs = None

@@ -88,6 +88,11 @@ typedef struct hz_params {
                              off-diagonal Gram entry of an FP32 sweep falls below
                              this (default 1e-5) */
     int max_fp32_sweeps;  /* mixed form: cap on FP32 sweeps (default 20) */
+    /* kernel tunables (0 = built-in choice); they change rounding order, so a
+       fixed setting gives bitwise-reproducible results */
+    int inner_lanes;      /* lanes per column pair in the inner solver: 8 or 16 */
+    int gram_splits;      /* row splits of the Gram kernel (1..16) */
+    int update_rows;      /* rows per wave in the update kernel (multiple of 16) */
 } hz_params;
 
 typedef struct hz_info {
@@ -99,6 +104,7 @@ typedef struct hz_info {
     uint64_t rot_total;   /* transformations applied (inner level, all sweeps) */
     uint64_t rot_big;     /* big transformations among them */
     double last_offdiag;  /* mixed form: off-diagonal measure of the last FP32 sweep */
+    uint64_t inner_sweeps;/* inner sweeps run, summed over all block steps */
 } hz_info;
 
 /* Fill *p with the defaults listed above. */
@@ -128,12 +134,26 @@ int hz_dgsvd(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n,
  * NULL to query the step count. */
 int hz_ordering(int kind, int N, int *table);
 
+/* Diagnostic: evaluate the device's real 2x2 transformation (the one the
+ * inner solver uses, Section 2.1.2) on `count` pivot pairs.  in (device,
+ * 4*count doubles: a_ii, a_jj, a_ij, b_ij per pair, with |b_ij| < 1 and the
+ * 2x2 A positive semidefinite), out (device, 4*count doubles: Z11, Z21, Z12,
+ * Z22 of Z' per pair).  Returns 0 or HZ_EHIP. */
+int hz_eval_2x2(int64_t count, const double *in, double *out, void *stream);
+
 /* Per-kernel timing of later solves in this process, for measurement:
- * with enable != 0 every Gram, inner-solve and update launch is bracketed by
+ * with enable = 1 (or 2, see below) every Gram, inner-solve and update launch is bracketed by
  * HIP events on the solve's stream (resolved at the host syncs each sweep
  * already makes), and the sums are cleared; enable = 0 stops collecting.
  * Not for concurrent solves. */
 void hz_profile_enable(int enable);
+
+/* With hz_profile_enable(2), the inner solver also stamps the device wall
+ * clock at its phase boundaries; this returns the mean microseconds per
+ * inner launch and pivot pair of phases 0 = load Gram blocks, 1 =
+ * Cholesky, 2 = factor prescale, 3 = inner sweeps, 4 = Theta rescale and
+ * store, in a host array of nphases (<= 5) entries. */
+int hz_profile_read_phases(double *us, int nphases);
 
 /* Copy the accumulated per-kind kernel time (milliseconds) and launch
  * counts for kinds 0 = Gram, 1 = inner solve, 2 = update, 3 = other into

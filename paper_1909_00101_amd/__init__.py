@@ -60,14 +60,17 @@ class HzParams(ctypes.Structure):
                 ("inner_ordering", ctypes.c_int), ("w", ctypes.c_int),
                 ("inner_max_sweeps", ctypes.c_int), ("max_sweeps", ctypes.c_int),
                 ("tol", ctypes.c_double), ("sort", ctypes.c_int),
-                ("mixed_switch", ctypes.c_double), ("max_fp32_sweeps", ctypes.c_int)]
+                ("mixed_switch", ctypes.c_double), ("max_fp32_sweeps", ctypes.c_int),
+                ("inner_lanes", ctypes.c_int), ("gram_splits", ctypes.c_int),
+                ("update_rows", ctypes.c_int)]
 
 
 class HzInfo(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int), ("sweeps_fp32", ctypes.c_int),
                 ("converged", ctypes.c_int), ("w", ctypes.c_int),
                 ("failed_pair", ctypes.c_int64), ("rot_total", ctypes.c_uint64),
-                ("rot_big", ctypes.c_uint64), ("last_offdiag", ctypes.c_double)]
+                ("rot_big", ctypes.c_uint64), ("last_offdiag", ctypes.c_double),
+                ("inner_sweeps", ctypes.c_uint64)]
 
 
 _lib = None
@@ -90,6 +93,17 @@ def lib():
         L.hz_dgsvd.restype = ctypes.c_int
         L.hz_strerror.argtypes = [ctypes.c_int]
         L.hz_strerror.restype = ctypes.c_char_p
+        L.hz_eval_2x2.argtypes = [i64, vp, vp, vp]
+        L.hz_eval_2x2.restype = ctypes.c_int
+        L.hz_ordering.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.hz_ordering.restype = ctypes.c_int
+        L.hz_profile_enable.argtypes = [ctypes.c_int]
+        L.hz_profile_enable.restype = None
+        L.hz_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.c_int]
+        L.hz_profile_read.restype = ctypes.c_int
+        L.hz_profile_read_phases.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+        L.hz_profile_read_phases.restype = ctypes.c_int
         L.hz_version.argtypes = []
         L.hz_version.restype = ctypes.c_char_p
         _lib = L
@@ -104,6 +118,19 @@ def params(**kw) -> HzParams:
             raise TypeError(f"unknown parameter {k}")
         setattr(p, k, v)
     return p
+
+
+def eval_2x2(inp):
+    """Evaluate the device 2x2 transformation on a (k, 4) float64 CUDA tensor
+    of (a_ii, a_jj, a_ij, b_ij) rows; returns (k, 4) rows (Z11, Z21, Z12, Z22)."""
+    import torch
+    inp = inp.contiguous()
+    out = torch.empty_like(inp)
+    stream = torch.cuda.current_stream(inp.device).cuda_stream
+    st = lib().hz_eval_2x2(inp.shape[0], _ptr(inp), _ptr(out), ctypes.c_void_p(stream))
+    if st != 0:
+        raise RuntimeError(f"hz_eval_2x2 failed: {st}")
+    return out
 
 
 def _colmajor(t):
@@ -173,4 +200,5 @@ def gsvd(F, G, *, overwrite=False, raise_on_noconv=False, workspace=None, **kw):
         raise GsvdError(st, info)
     return dict(U=U, V=V, Z=Z, sigma=sig, sigma_f=sf, sigma_g=sg, status=st,
                 sweeps=info.sweeps, converged=bool(info.converged), w=info.w,
-                rot_total=info.rot_total, rot_big=info.rot_big)
+                rot_total=info.rot_total, rot_big=info.rot_big,
+                inner_sweeps=info.inner_sweeps)

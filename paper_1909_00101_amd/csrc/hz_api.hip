@@ -68,6 +68,8 @@ static int params_ok(const hz_params &p)
     if (p.inner_ordering != HZ_ORD_MM && p.inner_ordering != HZ_ORD_RR) return 0;
     if (p.w != 0 && p.w != 8 && p.w != 16 && p.w != 32) return 0;
     if (p.inner_max_sweeps < 1 || p.max_sweeps < 1) return 0;
+    if (p.inner_lanes != 0 && p.inner_lanes != 8 && p.inner_lanes != 16) return 0;
+    if (p.gram_splits < 0 || p.gram_splits > 16 || p.update_rows < 0 || (p.update_rows % 16) != 0) return 0;
     return 1;
 }
 
@@ -100,21 +102,26 @@ static bool make_plan(const hz_params &prm, int64_t mf, int64_t mg, int64_t n, i
     P.steps = (prm.ordering == HZ_ORD_MM) ? P.nblk : P.nblk - 1;
     P.isteps = (prm.inner_ordering == HZ_ORD_MM) ? P.W2 : P.W2 - 1;
     const int64_t maxch = (P.mfw > P.mgw ? P.mfw : P.mgw) / 64;
-    int64_t sp = (512 + 2 * P.npairs - 1) / (2 * P.npairs);
+    int64_t sp = prm.gram_splits ? prm.gram_splits : (512 + 2 * P.npairs - 1) / (2 * P.npairs);
+    if (sp > 16) sp = 16;
     if (sp > maxch) sp = maxch;
     if (sp < 1) sp = 1;
     P.splits = (int)sp;
-    P.upd_rows = 64;
+    P.upd_rows = prm.update_rows ? prm.update_rows : 128;
+    P.inner_lp = prm.inner_lanes ? prm.inner_lanes : ((P.W2 == 64) ? 16 : 8);
+    if (P.W2 == 16) P.inner_lp = 8;
     const size_t es = P.esz;
     size_t o = 0;
     P.o_fw = o; o = align256(o + es * (size_t)P.mfw * P.nw);
     P.o_gw = o; o = align256(o + es * (size_t)P.mgw * P.nw);
     P.o_zw = o; o = align256(o + es * (size_t)P.nzw * P.nw);
     P.o_part = o; o = align256(o + es * (size_t)P.npairs * 2 * P.splits * P.W2 * P.W2);
+    P.o_gram = o; o = align256(o + es * (size_t)P.npairs * 2 * P.W2 * P.W2);
+    P.o_arrive = o; o = align256(o + sizeof(unsigned) * (size_t)P.npairs * 2);
     P.o_zt = o; o = align256(o + es * (size_t)P.npairs * P.W2 * P.W2);
     P.o_otab = o; o = align256(o + sizeof(int) * (size_t)P.steps * P.npairs * 2);
     P.o_itab = o; o = align256(o + sizeof(int16_t) * (size_t)P.isteps * P.w * 2);
-    P.o_cnt = o; o = align256(o + sizeof(unsigned long long) * (size_t)P.steps * P.npairs * 2);
+    P.o_cnt = o; o = align256(o + sizeof(unsigned long long) * (size_t)P.steps * P.npairs * 4);
     P.o_status = o; o = align256(o + sizeof(int) * ST_NSLOTS);
     P.o_sf = o; o = align256(o + sizeof(double) * (size_t)P.nw);
     P.o_sg = o; o = align256(o + sizeof(double) * (size_t)P.nw);
@@ -134,6 +141,9 @@ static Ptrs make_ptrs(const Plan &P, void *work)
     W.Gw = (double *)(b + P.o_gw);
     W.Zw = (double *)(b + P.o_zw);
     W.part = (double *)(b + P.o_part);
+    W.gram = (double *)(b + P.o_gram);
+    W.arrive = (unsigned *)(b + P.o_arrive);
+    W.phase = nullptr;
     W.Zt = (double *)(b + P.o_zt);
     W.otab = (int *)(b + P.o_otab);
     W.itab = (int16_t *)(b + P.o_itab);
@@ -187,6 +197,9 @@ struct Prof {
     std::vector<int> kind;
     double ms[K_NKINDS] = {0, 0, 0, 0};
     int64_t launches[K_NKINDS] = {0, 0, 0, 0};
+    bool phases = false;           // also time the inner solver's phases
+    double phase_us[5] = {0, 0, 0, 0, 0};
+    int64_t phase_n = 0;
 };
 static Prof g_prof;
 
@@ -260,6 +273,16 @@ const char *hz_strerror(int status)
 
 const char *hz_version(void) { return "hzgsvd 0.1 (gfx950)"; }
 
+int hz_eval_2x2(int64_t count, const double *in, double *out, void *stream)
+{
+    if (count < 0 || (count > 0 && (!in || !out))) return -1;
+    if (count == 0) return 0;
+    launch_eval_2x2(count, in, out, (hipStream_t)stream);
+    if (hipGetLastError() != hipSuccess) return HZ_EHIP;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return HZ_EHIP;
+    return 0;
+}
+
 int hz_ordering(int kind, int N, int *table)
 {
     if ((kind != HZ_ORD_MM && kind != HZ_ORD_RR) || N < 2 || (N & 1) || N > (1 << 15)) return -1;
@@ -273,12 +296,24 @@ void hz_profile_enable(int enable)
 {
     std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.on = enable != 0;
+    g_prof.phases = enable == 2;
+    for (int k = 0; k < 5; ++k) g_prof.phase_us[k] = 0.0;
+    g_prof.phase_n = 0;
     g_prof.used = 0;
     g_prof.kind.clear();
     for (int k = 0; k < K_NKINDS; ++k) {
         g_prof.ms[k] = 0.0;
         g_prof.launches[k] = 0;
     }
+}
+
+int hz_profile_read_phases(double *us, int nphases)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    const int n = nphases < 5 ? nphases : 5;
+    for (int k = 0; k < n; ++k)
+        us[k] = g_prof.phase_n ? g_prof.phase_us[k] / (double)g_prof.phase_n : 0.0;
+    return n;
 }
 
 int hz_profile_read(double *ms, int64_t *launches, int nkinds)
@@ -357,15 +392,29 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
         own = true;
     }
     {
-        const Ptrs W = make_ptrs(P, work);
+        Ptrs W = make_ptrs(P, work);
+        unsigned long long *dphase = nullptr;
+        std::vector<unsigned long long> hph;
+        double clk_khz = 0.0;
+        if (g_prof.on && g_prof.phases) {
+            const size_t nph = (size_t)P.steps * P.npairs * 8;
+            if (hipMalloc(&dphase, nph * sizeof(unsigned long long)) == hipSuccess) {
+                W.phase = dphase;
+                hph.resize(nph);
+                int dev = 0, rate = 0;
+                (void)hipGetDevice(&dev);
+                (void)hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, dev);
+                clk_khz = rate;
+            }
+        }
         const double tol = (prm.tol > 0.0) ? prm.tol : sqrt((double)P.n) * DBL_EPSILON;
         std::vector<int> otab;
         std::vector<int16_t> itab;
         build_ordering<int>(prm.ordering, P.nblk, otab);
         build_ordering<int16_t>(prm.inner_ordering, P.W2, itab);
-        std::vector<unsigned long long> hc((size_t)P.steps * P.npairs * 2);
+        std::vector<unsigned long long> hc((size_t)P.steps * P.npairs * 4);
         int hs[ST_NSLOTS] = {0, INT_MAX, 0, 0};
-        uint64_t tot_all = 0, tot_big = 0;
+        uint64_t tot_all = 0, tot_big = 0, tot_isw = 0;
         int sweeps = 0, converged = 0;
         HZ_CHECK(hipMemcpyAsync(W.otab, otab.data(), otab.size() * sizeof(int),
                                 hipMemcpyHostToDevice, st));
@@ -381,13 +430,23 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
             HZ_CHECK(hipMemcpyAsync(hc.data(), W.cnt, hc.size() * sizeof(unsigned long long),
                                     hipMemcpyDeviceToHost, st));
             HZ_CHECK(hipMemcpyAsync(hs, W.status, sizeof(hs), hipMemcpyDeviceToHost, st));
+            if (dphase) HZ_CHECK(hipMemcpyAsync(hph.data(), dphase, hph.size() * 8,
+                                                hipMemcpyDeviceToHost, st));
             HZ_CHECK(hipStreamSynchronize(st));
             prof_flush();
+            if (dphase && clk_khz > 0) {
+                for (size_t i = 0; i < hph.size(); i += 8) {
+                    for (int k = 0; k < 5; ++k)
+                        g_prof.phase_us[k] += (double)(hph[i + k + 1] - hph[i + k]) / clk_khz * 1e3;
+                    g_prof.phase_n += 1;
+                }
+            }
             ++sweeps;
             uint64_t s_all = 0, s_big = 0;
-            for (size_t i = 0; i < hc.size(); i += 2) {
+            for (size_t i = 0; i < hc.size(); i += 4) {
                 s_all += hc[i];
                 s_big += hc[i + 1];
+                tot_isw += hc[i + 2];
             }
             tot_all += s_all;
             tot_big += s_big;
@@ -414,6 +473,11 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
             info->failed_pair = (hs[ST_FLAGS] & FLAG_CHOL) ? hs[ST_FAILPAIR] : -1;
             info->rot_total = tot_all;
             info->rot_big = tot_big;
+            info->inner_sweeps = tot_isw;
+        }
+        if (dphase) {
+            (void)hipStreamSynchronize(st);
+            (void)hipFree(dphase);
         }
     }
 done:

@@ -31,6 +31,58 @@ __device__ __forceinline__ double group_sum(double v)
 
 __device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
 
+// DPP lane exchange of a double within a row of 16 lanes (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over aligned groups of L = 2, 4, 8 or 16 lanes with DPP only (no LDS
+// traffic): quad xor-1 and xor-2 permutations, then the 8-lane half mirror
+// and the 16-lane mirror.  Each stage adds a lane's value to its partner's
+// (commutative), so all lanes of a group hold the bitwise same sum.
+template <int L>
+__device__ __forceinline__ double dpp_group_sum(double v)
+{
+    static_assert(L == 2 || L == 4 || L == 8 || L == 16, "group of 2..16 lanes");
+    v += dpp_d<0xB1>(v);                      // quad_perm [1,0,3,2]
+    if (L >= 4) v += dpp_d<0x4E>(v);          // quad_perm [2,3,0,1]
+    if (L >= 8) v += dpp_d<0x141>(v);         // row_half_mirror
+    if (L >= 16) v += dpp_d<0x140>(v);        // row_mirror
+    return v;
+}
+
+// Reciprocal square root from the hardware estimate y0 = v_rsq_f64(x)
+// (relative error e0 about 2^-22) refined by one third-order step
+// y = y0 (1 + e/2 + 3e^2/8), e = 1 - x y0^2, which leaves O(e0^3) -- below
+// double rounding -- with a dependency depth of four operations.  About one
+// ulp for positive normal finite x; exactly 1 for x = 1.  Deterministic.
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    const double p = fma(0.375, e, 0.5);
+    return fma(y * e, p, y);
+}
+
+__device__ __forceinline__ double sqrt_nr(double x) { return x * rsqrt_nr(x); }
+
+// a / b for finite b != 0: hardware reciprocal estimate r0 refined by one
+// third-order step r = r0 (1 + e + e^2), e = 1 - b r0, then a * r with one
+// residual correction.
+__device__ __forceinline__ double div_nr(double a, double b)
+{
+    const double r0 = __builtin_amdgcn_rcp(b);
+    const double e = fma(-b, r0, 1.0);
+    const double r = fma(r0, fma(e, e, e), r0);
+    const double q = a * r;
+    return fma(r, fma(-b, q, a), q);
+}
+
 // Scheduling fence between LDS traffic of lanes of one wave (LDS executes a
 // wave's operations in order; this only stops the compiler from moving
 // accesses across it).
@@ -93,6 +145,61 @@ __device__ __forceinline__ void hz_real_2x2(double aii, double ajj, double aij, 
     z21 = -spsi / t;
     z12 = sphi / t;
     z22 = cpsi / t;
+}
+
+// The real 2x2 transformation of Section 2.1.2 arranged for a short
+// dependency chain on gfx950 (used by the inner solver).  With
+// N = t (a_jj - a_ii) and D = 2 a_ij - (a_ii + a_jj) x, cot 2theta = N / D,
+// and the printed tan theta = sign(cot)/(|cot| + sqrt(1 + cot^2)) equals
+// sign(N) D / q with q = |N| + sqrt(N^2 + D^2) for every (N, D) != (0, 0),
+// including D = 0 (tan = 0) and N = 0 (tan = sign D), so no infinities
+// arise.  Then cos theta = q / sqrt(q^2 + D^2) and sin theta = sign(N) D /
+// sqrt(q^2 + D^2); when D^2 is below the rounding of q^2 the correctly
+// rounded cosine is exactly 1 and is set so (criterion C1 depends on exact
+// ones, as with the printed 1/sqrt(1 + tan^2)).  N^2 is formed as
+// t^2 h^2 so that sqrt(N^2 + D^2) does not wait for t.  The cosines and
+// sines of phi and psi follow as printed, scaled by 1/t.  The exception
+// (N = D = 0, A' proportional to B') returns the signed form of
+// hz_real_2x2.  Returns z11, z21, z12, z22 of Z' (column-major).
+__device__ __forceinline__ void hz_real_2x2_fast(double aii, double ajj, double aij, double x,
+                                                 double &z11, double &z21, double &z12,
+                                                 double &z22)
+{
+    const double t2 = fma(-x, x, 1.0);
+    const double h = ajj - aii;
+    const double D = fma(-(aii + ajj), x, 2.0 * aij);
+    if (h == 0.0 && D == 0.0) {
+        const double r2 = 0.70710678118654752440;
+        const double ax = fabs(x), s = (x < 0.0) ? -1.0 : 1.0;
+        const double p = r2 * rsqrt_nr(1.0 + ax), q = r2 * rsqrt_nr(1.0 - ax);
+        z11 = p;
+        z21 = s * p;
+        z12 = -s * q;
+        z22 = q;
+        return;
+    }
+    const double rt = rsqrt_nr(t2);                       // 1/t
+    const double D2 = D * D;
+    const double hyp = sqrt_nr(fma(t2 * h, h, D2));       // sqrt(N^2 + D^2)
+    const double q = fma(t2 * rt, fabs(h), hyp);          // |N| + hyp
+    const double q2 = q * q;
+    const double qd = q2 + D2;
+    const double r = rsqrt_nr(qd);
+    const double sD = (h < 0.0) ? -D : D;                 // sign(N) D
+    const bool tiny = (qd == q2);
+    const double c = tiny ? 1.0 : q * r;
+    const double s = sD * r;
+    const double sp = sqrt_nr(1.0 + x), sm = sqrt_nr(1.0 - x);
+    const double xi = div_nr(x, sp + sm);
+    const double eta = div_nr(x, (1.0 + sp) * (1.0 + sm));
+    const double cphi = fma(xi, fma(-eta, c, s), c);
+    const double cpsi = fma(-xi, fma(eta, c, s), c);
+    const double sphi = fma(-xi, fma(eta, s, c), s);
+    const double spsi = fma(xi, fma(-eta, s, c), s);
+    z11 = cphi * rt;
+    z21 = -spsi * rt;
+    z12 = sphi * rt;
+    z22 = cpsi * rt;
 }
 
 }  // namespace hz

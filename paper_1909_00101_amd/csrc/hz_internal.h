@@ -23,16 +23,19 @@ struct Plan {
     int isteps;               // inner steps per inner sweep
     int splits;               // row splits of the Gram kernel
     int upd_rows;             // rows per wave in the update kernel
+    int inner_lp;             // lanes per column pair in the inner solver (8 or 16)
     int is_complex;
     size_t esz;               // bytes per matrix element (8 or 16)
     // workspace offsets (bytes)
-    size_t o_fw, o_gw, o_zw, o_part, o_zt, o_otab, o_itab, o_cnt, o_status;
+    size_t o_fw, o_gw, o_zw, o_part, o_gram, o_arrive, o_zt, o_otab, o_itab, o_cnt, o_status;
     size_t o_sf, o_sg, o_sig, o_rank, o_border, total;
 };
 
 struct Ptrs {
     char *base;
-    double *Fw, *Gw, *Zw, *part, *Zt;
+    double *Fw, *Gw, *Zw, *part, *gram, *Zt;
+    unsigned *arrive;
+    unsigned long long *phase;   // optional per-(step, pair) phase clocks, or null
     int *otab;
     int16_t *itab;
     unsigned long long *cnt;
@@ -60,6 +63,7 @@ void launch_step_real(const Plan &P, const Ptrs &W, int step, const hz_params &p
 void launch_finish_real(const Plan &P, const Ptrs &W, double *F, int64_t ldf, double *G,
                         int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
                         double *sigma_g, hipStream_t s);
+void launch_eval_2x2(int64_t count, const double *in, double *out, hipStream_t s);
 void launch_n1_real(int64_t mf, int64_t mg, double *F, double *G, double *Z, double *sigma,
                     double *sigma_f, double *sigma_g, int *status, hipStream_t s);
 

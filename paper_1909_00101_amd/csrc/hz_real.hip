@@ -53,12 +53,13 @@ __global__ __launch_bounds__(256) void k_prescale_copy(
 
 // ------------------------------------------------------------------------
 // Pivot Gram blocks (paper: Section 2.3, A_hat = [F_p F_q]^T [F_p F_q] and
-// B_hat likewise; Section 3.5.1 computes both triangles).  FP64 MFMA
-// 16x16x4.  Grid (splits, pairs, 2): each workgroup sums the rows of its
-// split (64-row chunks staged in LDS, next chunk prefetched into registers)
-// into a full W2 x W2 partial Gram; the 4 waves take interleaved k-steps
-// and are summed in LDS in wave order.  Output part[pair][mat][split] is
-// column-major W2 x W2; the inner kernel adds the splits in split order.
+// B_hat likewise).  FP64 MFMA 16x16x4.  Grid (splits, pairs, 2): each
+// workgroup sums the rows of its split (64-row chunks staged in LDS, the
+// next chunk prefetched into registers) into the lower-triangle 16x16 tiles
+// of a W2 x W2 partial Gram (the inner solver reads only the lower
+// triangle); the four waves take interleaved k-steps and are summed in LDS
+// in wave order.  k_gram_sum then adds the split partials in split order:
+// no floating-point atomics, so the result is reproducible bit for bit.
 // ------------------------------------------------------------------------
 template <int W2>
 __global__ __launch_bounds__(256) void k_gram(const double *__restrict__ Fw,
@@ -67,7 +68,8 @@ __global__ __launch_bounds__(256) void k_gram(const double *__restrict__ Fw,
                                               int splits, double *__restrict__ part)
 {
     constexpr int W = W2 / 2, NB = W2 / 16, LDT = 66, NLD = W2 / 8;
-    __shared__ double tile[W2 * LDT];
+    constexpr int NT = NB * (NB + 1) / 2;    // lower-triangle tiles
+    __shared__ __attribute__((aligned(16))) double tile[W2 * LDT];
     const int split = blockIdx.x, pr = blockIdx.y, mat = blockIdx.z;
     const double *Y = mat ? Gw : Fw;
     const int64_t m = mat ? mgw : mfw;
@@ -77,11 +79,9 @@ __global__ __launch_bounds__(256) void k_gram(const double *__restrict__ Fw,
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lrow = 2 * (tid & 31), lcol = tid >> 5;
 
-    d4 acc[NB][NB];
+    d4 acc[NT];
 #pragma unroll
-    for (int a = 0; a < NB; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
     const double *colp[NLD];
 #pragma unroll
@@ -105,131 +105,189 @@ __global__ __launch_bounds__(256) void k_gram(const double *__restrict__ Fw,
             for (int t = 0; t < NLD; ++t) buf[t] = *(const d2 *)(colp[t] + (c + 1) * 64);
         }
 #pragma unroll
-        for (int s = wave; s < 16; s += 4) {
+        for (int s = 0; s < 4; ++s) {
+            const int ks = wave + 4 * s;
             double fr[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b)
-                fr[b] = tile[(16 * b + (lane & 15)) * LDT + 4 * s + (lane >> 4)];
+                fr[b] = tile[(16 * b + (lane & 15)) * LDT + 4 * ks + (lane >> 4)];
+            int t = 0;
 #pragma unroll
             for (int a = 0; a < NB; ++a)
 #pragma unroll
-                for (int b = 0; b < NB; ++b) acc[a][b] = mfma16(fr[a], fr[b], acc[a][b]);
+                for (int b = 0; b <= a; ++b, ++t) acc[t] = mfma16(fr[a], fr[b], acc[t]);
         }
     }
     // Sum the four waves' partial tiles in wave order (tile reused, ld W2).
     for (int wv = 0; wv < 4; ++wv) {
         __syncthreads();
         if (wave == wv) {
+            int t = 0;
 #pragma unroll
             for (int a = 0; a < NB; ++a)
 #pragma unroll
-                for (int b = 0; b < NB; ++b)
+                for (int b = 0; b <= a; ++b, ++t)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int gi = 16 * a + 4 * r + (lane >> 4), gj = 16 * b + (lane & 15);
                         double *dst = tile + gj * W2 + gi;
-                        *dst = (wv == 0) ? acc[a][b][r] : *dst + acc[a][b][r];
+                        *dst = (wv == 0) ? acc[t][r] : *dst + acc[t][r];
                     }
         }
     }
     __syncthreads();
+    // Only lower-triangle tiles are meaningful; upper ones are not written.
     double *out = part + ((size_t)(pr * 2 + mat) * splits + split) * (W2 * W2);
-    for (int e = tid; e < W2 * W2; e += 256) out[e] = tile[e];
+    for (int e = 2 * tid; e < W2 * W2; e += 512) *(d2 *)(out + e) = *(const d2 *)(tile + e);
+}
+
+// Sum of the Gram split partials in split order (fixed association, so the
+// result is reproducible bit for bit): grid (W2*W2/512, 2 * pairs), 256
+// threads, two consecutive elements per thread, every split's load issued
+// before the adds.
+template <int W2>
+__global__ __launch_bounds__(256) void k_gram_sum(const double *__restrict__ part, int splits,
+                                                  double *__restrict__ gram)
+{
+    constexpr int MAXS = 16;
+    const int pm = blockIdx.y;
+    const int e = 2 * (blockIdx.x * 256 + threadIdx.x);
+    if (e >= W2 * W2) return;
+    const double *src = part + (size_t)pm * splits * (W2 * W2) + e;
+    d2 v[MAXS];
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s)
+        if (s < splits) v[s] = *(const d2 *)(src + (size_t)s * (W2 * W2));
+    d2 acc = v[0];
+#pragma unroll
+    for (int s = 1; s < MAXS; ++s)
+        if (s < splits) acc += v[s];
+    *(d2 *)(gram + (size_t)pm * (W2 * W2) + e) = acc;
 }
 
 // ------------------------------------------------------------------------
 // Inner solve of one pivot block pair (paper: Section 2.3 factorization,
 // Section 2.1 pointwise method on the factors, Section 2.4 Theta rescale,
 // Section 2.5 counters; Sections 3.5.2-3.5.3 for the shared-memory flow).
-// One workgroup per block pair.  Steps:
-//  1. A_hat, B_hat = sum of the Gram partials (split order).
+// One workgroup per block pair, NT = (W2/2) * LP threads: LP lanes per
+// column pair of an inner step, RPL = W2/LP rows per lane.  Steps:
+//  1. A_hat, B_hat = sum of the Gram partials (split order) into LDS.
 //  2. Cholesky A_hat = F_hat^T F_hat, B_hat = G_hat^T G_hat (F_hat, G_hat
-//     upper triangular), one lane per row, the current column of L
-//     broadcast through LDS; a non-positive pivot flags HZ_ECHOL.
+//     upper triangular) inside one wave per matrix (both matrices in one
+//     wave when 2w <= 32): lane i keeps row i in registers, the pivot comes
+//     by readlane, the new column of L is broadcast through LDS; a
+//     non-positive pivot flags HZ_ECHOL.
 //  3. Z_hat = diag(1/||g_hat_j||), F_hat, G_hat scaled by it.
 //  4. Inner sweeps (<= inner_max, stop after a sweep without
-//     transformations): each step, LP lanes per column pair form a_ii,
-//     a_jj, a_ij, b_ij, apply the skip test, the 2x2 transformation, the
-//     C1 classification and the sorting swap to the columns of F_hat,
-//     G_hat, Z_hat in LDS.
+//     transformations): per step, the LP lanes of a column pair form a_ii,
+//     a_jj, a_ij, b_ij with DPP sums, then the skip test, the 2x2
+//     transformation, criterion C1, the sorting swap, applied in LDS.
 //  5. Z_tilde = Z_hat Theta, Theta_jj = (||f_hat_j||^2+||g_hat_j||^2)^-1/2.
+// Counters per (step, pair): transformations, big ones, inner sweeps run.
 // ------------------------------------------------------------------------
-template <int W2, int NT>
-__global__ __launch_bounds__(NT) void k_inner(
-    const double *__restrict__ part, int splits, int npairs, int step,
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int W2, int LP>
+__global__ __launch_bounds__((W2 / 2) * LP) void k_inner(
+    const double *__restrict__ gram, int npairs, int step,
     const int16_t *__restrict__ itab, int isteps, int inner_max, double tol, int sort,
-    double *__restrict__ Zt, unsigned long long *__restrict__ cnt, int *__restrict__ status)
+    double *__restrict__ Zt, unsigned long long *__restrict__ cnt, int *__restrict__ status,
+    unsigned long long *__restrict__ phase)
 {
     constexpr int W = W2 / 2;         // column pairs per inner step
-    constexpr int LP = NT / W;        // lanes per column pair
+    constexpr int NT = W * LP;
     constexpr int RPL = W2 / LP;      // rows per lane
     constexpr int LDI = W2 + 2;
-    static_assert(LP * W == NT && RPL * LP == W2 && LP <= 64, "bad inner geometry");
-    __shared__ double sF[W2 * LDI], sG[W2 * LDI], sZ[W2 * LDI];
+    static_assert(RPL >= 2 && RPL % 2 == 0 && NT >= 64, "bad inner geometry");
+    __shared__ __attribute__((aligned(16))) double sF[W2 * LDI];
+    __shared__ __attribute__((aligned(16))) double sG[W2 * LDI];
+    __shared__ __attribute__((aligned(16))) double sZ[W2 * LDI];
     __shared__ int16_t stab[W2 * W2];
-    __shared__ double lbuf[2][64];
+    __shared__ __attribute__((aligned(16))) double lbuf[2][64];
     __shared__ int s_fail;
+    __shared__ unsigned s_cnt[3 * W];
 
     const int pr = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // 1. sum the partial Grams
+    unsigned long long *myc = cnt + ((size_t)step * npairs + pr) * 4;
+    unsigned long long *ph = phase ? phase + ((size_t)step * npairs + pr) * 8 : nullptr;
+    if (ph && tid == 0) ph[0] = wall_clock64();
+    // 1. load the Gram blocks (lower triangles) into LDS
     {
-        const double *pa = part + (size_t)(pr * 2) * splits * (W2 * W2);
-        const double *pb = pa + (size_t)splits * (W2 * W2);
-        for (int e = tid; e < W2 * W2; e += NT) {
-            double a = 0.0, b = 0.0;
-            for (int s = 0; s < splits; ++s) {
-                a += pa[(size_t)s * (W2 * W2) + e];
-                b += pb[(size_t)s * (W2 * W2) + e];
-            }
+        const double *pa = gram + (size_t)(pr * 2) * (W2 * W2);
+        const double *pb = pa + (W2 * W2);
+        for (int e = 2 * tid; e < W2 * W2; e += 2 * NT) {
+            const d2 a = *(const d2 *)(pa + e), b = *(const d2 *)(pb + e);
             const int col = e / W2, row = e % W2;
-            sF[col * LDI + row] = a;
-            sG[col * LDI + row] = b;
+            *(d2 *)(sF + col * LDI + row) = a;
+            *(d2 *)(sG + col * LDI + row) = b;
         }
         for (int e = tid; e < isteps * W * 2; e += NT) stab[e] = itab[e];
         if (tid == 0) s_fail = 0;
     }
     __syncthreads();
+    if (ph && tid == 0) ph[1] = wall_clock64();
 
-    // 2. Cholesky factorizations, lane = row.
+    // 2. Cholesky factorizations, lane = row, one wave per matrix.
     {
-        const bool big = (W2 == 64);
-        const int mat = big ? wave : (lane >> 5);
-        const int i = big ? lane : (lane & 31);
-        const bool active = (big ? (wave < 2) : (wave == 0)) && i < W2;
-        if (active) {
+        constexpr bool two = (W2 == 64);
+        const int mat = two ? wave : (lane >> 5);
+        const int i = two ? lane : (lane & 31);
+        if ((two ? (wave < 2) : (wave == 0)) && i < W2) {
             double *M = mat ? sG : sF;
             double *lb = lbuf[mat];
-            const int base = big ? 0 : 32 * mat;
             double a[W2];
 #pragma unroll
             for (int k = 0; k < W2; ++k) a[k] = M[k * LDI + i];
             bool ok = true;
 #pragma unroll
             for (int j = 0; j < W2; ++j) {
-                const double djj = __shfl(a[j], base + j, 64);
-                ok = ok && (djj > 0.0) && isfinite(djj);
-                const double inv = 1.0 / sqrt(djj);
+                double piv;
+                if (two) {
+                    piv = readlane_d(a[j], j);
+                } else {
+                    const double p0 = readlane_d(a[j], j), p1 = readlane_d(a[j], 32 + j);
+                    piv = mat ? p1 : p0;
+                }
+                ok = ok && (piv > 0.0) && (piv < INFINITY);
+                const double inv = rsqrt_nr(piv);
                 const double l = (i >= j) ? a[j] * inv : 0.0;
                 a[j] = l;
                 lb[i] = l;
                 wave_fence();
 #pragma unroll
-                for (int k = j + 1; k < W2; ++k) a[k] = fma(-l, lb[k], a[k]);
+                for (int k = j + 1; k < W2; k += 2) {
+                    const d2 lk = *(const d2 *)(lb + k - (k & 1));
+                    if (k & 1) {
+                        a[k] = fma(-l, lk[1], a[k]);
+                        if (k + 1 < W2) a[k + 1] = fma(-l, (*(const d2 *)(lb + k + 1))[0], a[k + 1]);
+                    } else {
+                        a[k] = fma(-l, lk[0], a[k]);
+                        if (k + 1 < W2) a[k + 1] = fma(-l, lk[1], a[k + 1]);
+                    }
+                }
                 wave_fence();
             }
             // F_hat = L^T: column i of F_hat is row i of L.
 #pragma unroll
             for (int k = 0; k < W2; ++k) M[i * LDI + k] = (k <= i) ? a[k] : 0.0;
-            if (!ok) atomicOr(&s_fail, 1);
+            if (!ok) s_fail = 1;
         }
     }
     __syncthreads();
+    if (ph && tid == 0) ph[2] = wall_clock64();
     if (s_fail) {
         double *zt = Zt + (size_t)pr * (W2 * W2);
         for (int e = tid; e < W2 * W2; e += NT) zt[e] = (e % W2 == e / W2) ? 1.0 : 0.0;
         if (tid == 0) {
-            cnt[((size_t)step * npairs + pr) * 2 + 0] = 0;
-            cnt[((size_t)step * npairs + pr) * 2 + 1] = 0;
+            myc[0] = 0;
+            myc[1] = 0;
+            myc[2] = 0;
             atomicOr(status + ST_FLAGS, FLAG_CHOL);
             atomicMin(status + ST_FAILPAIR, step * 65536 + pr);
         }
@@ -247,8 +305,8 @@ __global__ __launch_bounds__(NT) void k_inner(
             const double g = sG[c * LDI + r0 + r];
             s = fma(g, g, s);
         }
-        s = group_sum<LP>(s);
-        const double d = 1.0 / sqrt(s);
+        s = dpp_group_sum<LP>(s);
+        const double d = rsqrt_nr(s);
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             sF[c * LDI + r0 + r] *= d;
@@ -257,65 +315,85 @@ __global__ __launch_bounds__(NT) void k_inner(
         }
     }
     __syncthreads();
+    if (ph && tid == 0) ph[3] = wall_clock64();
 
     // 4. inner sweeps
+    const double tol2 = tol * tol;
     unsigned my_all = 0, my_big = 0;
+    int nsw = 0;
     for (int sw = 0; sw < inner_max; ++sw) {
         unsigned sw_all = 0, sw_big = 0;
+        ++nsw;
         for (int st = 0; st < isteps; ++st) {
             const int ci = stab[(st * W + grp) * 2], cj = stab[(st * W + grp) * 2 + 1];
             double fi[RPL], fj[RPL], gi[RPL], gj[RPL], zi[RPL], zj[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; r += 2) {
+                const d2 a0 = *(const d2 *)(sF + ci * LDI + r0 + r);
+                const d2 a1 = *(const d2 *)(sF + cj * LDI + r0 + r);
+                const d2 b0 = *(const d2 *)(sG + ci * LDI + r0 + r);
+                const d2 b1 = *(const d2 *)(sG + cj * LDI + r0 + r);
+                const d2 c0 = *(const d2 *)(sZ + ci * LDI + r0 + r);
+                const d2 c1 = *(const d2 *)(sZ + cj * LDI + r0 + r);
+                fi[r] = a0[0]; fi[r + 1] = a0[1];
+                fj[r] = a1[0]; fj[r + 1] = a1[1];
+                gi[r] = b0[0]; gi[r + 1] = b0[1];
+                gj[r] = b1[0]; gj[r + 1] = b1[1];
+                zi[r] = c0[0]; zi[r + 1] = c0[1];
+                zj[r] = c1[0]; zj[r + 1] = c1[1];
+            }
             double aii = 0.0, ajj = 0.0, aij = 0.0, bij = 0.0;
 #pragma unroll
             for (int r = 0; r < RPL; ++r) {
-                fi[r] = sF[ci * LDI + r0 + r];
-                fj[r] = sF[cj * LDI + r0 + r];
-                gi[r] = sG[ci * LDI + r0 + r];
-                gj[r] = sG[cj * LDI + r0 + r];
-                zi[r] = sZ[ci * LDI + r0 + r];
-                zj[r] = sZ[cj * LDI + r0 + r];
                 aii = fma(fi[r], fi[r], aii);
                 ajj = fma(fj[r], fj[r], ajj);
                 aij = fma(fi[r], fj[r], aij);
                 bij = fma(gi[r], gj[r], bij);
             }
-            aii = group_sum<LP>(aii);
-            ajj = group_sum<LP>(ajj);
-            aij = group_sum<LP>(aij);
-            bij = group_sum<LP>(bij);
+            aii = dpp_group_sum<LP>(aii);
+            ajj = dpp_group_sum<LP>(ajj);
+            aij = dpp_group_sum<LP>(aij);
+            bij = dpp_group_sum<LP>(bij);
             double z11 = 1.0, z21 = 0.0, z12 = 0.0, z22 = 1.0;
-            bool swap = false;
-            const bool orth = fabs(aij) < sqrt(aii) * sqrt(ajj) * tol && fabs(bij) < tol;
+            bool swap;
+            const bool orth = (aij * aij < aii * ajj * tol2) && (fabs(bij) < tol);
             if (orth) {
                 swap = sort && (aii < ajj);
             } else {
-                hz_real_2x2(aii, ajj, aij, bij, z11, z21, z12, z22);
+                hz_real_2x2_fast(aii, ajj, aij, bij, z11, z21, z12, z22);
                 sw_all += 1;
                 if (!(z11 == 1.0 && z22 == 1.0)) sw_big += 1;
+                swap = false;
                 if (sort) {
-                    const double a11 = z11 * z11 * aii + 2.0 * z11 * z21 * aij + z21 * z21 * ajj;
-                    const double a22 = z12 * z12 * aii + 2.0 * z22 * z12 * aij + z22 * z22 * ajj;
+                    const double a11 = fma(z11 * z11, aii, fma(2.0 * z11 * z21, aij, z21 * z21 * ajj));
+                    const double a22 = fma(z12 * z12, aii, fma(2.0 * z22 * z12, aij, z22 * z22 * ajj));
                     swap = a11 < a22;
                 }
             }
+            if (swap) {
+                double t;
+                t = z11; z11 = z12; z12 = t;
+                t = z21; z21 = z22; z22 = t;
+            }
             if (!orth || swap) {
 #pragma unroll
-                for (int r = 0; r < RPL; ++r) {
-                    double nfi = fma(fj[r], z21, fi[r] * z11), nfj = fma(fi[r], z12, fj[r] * z22);
-                    double ngi = fma(gj[r], z21, gi[r] * z11), ngj = fma(gi[r], z12, gj[r] * z22);
-                    double nzi = fma(zj[r], z21, zi[r] * z11), nzj = fma(zi[r], z12, zj[r] * z22);
-                    if (swap) {
-                        double t;
-                        t = nfi; nfi = nfj; nfj = t;
-                        t = ngi; ngi = ngj; ngj = t;
-                        t = nzi; nzi = nzj; nzj = t;
+                for (int r = 0; r < RPL; r += 2) {
+                    d2 nfi, nfj, ngi, ngj, nzi, nzj;
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        nfi[u] = fma(fj[r + u], z21, fi[r + u] * z11);
+                        nfj[u] = fma(fi[r + u], z12, fj[r + u] * z22);
+                        ngi[u] = fma(gj[r + u], z21, gi[r + u] * z11);
+                        ngj[u] = fma(gi[r + u], z12, gj[r + u] * z22);
+                        nzi[u] = fma(zj[r + u], z21, zi[r + u] * z11);
+                        nzj[u] = fma(zi[r + u], z12, zj[r + u] * z22);
                     }
-                    sF[ci * LDI + r0 + r] = nfi;
-                    sF[cj * LDI + r0 + r] = nfj;
-                    sG[ci * LDI + r0 + r] = ngi;
-                    sG[cj * LDI + r0 + r] = ngj;
-                    sZ[ci * LDI + r0 + r] = nzi;
-                    sZ[cj * LDI + r0 + r] = nzj;
+                    *(d2 *)(sF + ci * LDI + r0 + r) = nfi;
+                    *(d2 *)(sF + cj * LDI + r0 + r) = nfj;
+                    *(d2 *)(sG + ci * LDI + r0 + r) = ngi;
+                    *(d2 *)(sG + cj * LDI + r0 + r) = ngj;
+                    *(d2 *)(sZ + ci * LDI + r0 + r) = nzi;
+                    *(d2 *)(sZ + cj * LDI + r0 + r) = nzj;
                 }
             }
             __syncthreads();
@@ -326,6 +404,7 @@ __global__ __launch_bounds__(NT) void k_inner(
         if (any == 0) break;
     }
 
+    if (ph && tid == 0) ph[4] = wall_clock64();
     // 5. Theta rescale and write Z_tilde (column-major W2 x W2).
     double *zt = Zt + (size_t)pr * (W2 * W2);
 #pragma unroll
@@ -338,39 +417,42 @@ __global__ __launch_bounds__(NT) void k_inner(
             s = fma(f, f, s);
             s = fma(g, g, s);
         }
-        s = group_sum<LP>(s);
-        const double th = 1.0 / sqrt(s);
+        s = dpp_group_sum<LP>(s);
+        const double th = rsqrt_nr(s);
 #pragma unroll
         for (int r = 0; r < RPL; ++r) zt[c * W2 + r0 + r] = sZ[c * LDI + r0 + r] * th;
     }
-    // counters: sum the groups' totals in group order through LDS
-    __syncthreads();
-    unsigned *cbuf = (unsigned *)lbuf;   // 2*W <= 128 slots
+    // counters: the groups' totals summed in group order
     if (gl == 0) {
-        cbuf[2 * grp] = my_all;
-        cbuf[2 * grp + 1] = my_big;
+        s_cnt[3 * grp] = my_all;
+        s_cnt[3 * grp + 1] = my_big;
     }
     __syncthreads();
     if (tid == 0) {
         unsigned long long ta = 0, tb = 0;
         for (int g = 0; g < W; ++g) {
-            ta += cbuf[2 * g];
-            tb += cbuf[2 * g + 1];
+            ta += s_cnt[3 * g];
+            tb += s_cnt[3 * g + 1];
         }
-        cnt[((size_t)step * npairs + pr) * 2 + 0] = ta;
-        cnt[((size_t)step * npairs + pr) * 2 + 1] = tb;
+        myc[0] = ta;
+        myc[1] = tb;
+        myc[2] = (unsigned long long)nsw;
+        if (ph) ph[5] = wall_clock64();
     }
 }
 
 // ------------------------------------------------------------------------
 // Block update (paper: Section 2.3, [F_p F_q] <- [F_p F_q] Z_tilde and the
 // same for G and Z; Section 3.5.4 does it in place with one read and one
-// write of the block columns).  FP64 MFMA: each wave holds Z_tilde^T as
-// MFMA A-fragments in registers and streams 16-row tiles X of the block
-// column pair: D' = Z_tilde^T X^T, so both the loads of X and the stores of
-// D' = (X Z_tilde)^T are 128-byte column segments.  A wave reads all W2
-// columns of its 16 rows before writing them: in place without races.
-// Grid (row tiles of Fw | Gw | Zw, pairs), 4 waves x rows_per_wave rows.
+// write of the block columns).  FP64 MFMA 16x16x4 computing
+// D' = Z_tilde^T X^T for 16-row tiles X of the block-column pair, so the
+// loads of X and the stores of D' = (X Z_tilde)^T are both 128-byte column
+// segments.  Z_tilde is staged once per workgroup in LDS (padded to avoid
+// bank conflicts) and read as MFMA A-fragments per k-step, which keeps the
+// register count low enough for several waves per SIMD.  A wave reads
+// all W2 columns of its 16 rows before writing them: in place, no races.
+// Grid (row blocks of Fw | Gw | Zw, pairs); each workgroup owns
+// 4 * rows_per_wave consecutive rows, its waves taking 16-row tiles in turn.
 // ------------------------------------------------------------------------
 template <int W2>
 __global__ __launch_bounds__(256) void k_update(double *__restrict__ Fw, double *__restrict__ Gw,
@@ -380,10 +462,13 @@ __global__ __launch_bounds__(256) void k_update(double *__restrict__ Fw, double 
                                                 const double *__restrict__ Zt, int tiles_f,
                                                 int tiles_g, int rows_per_wave)
 {
-    constexpr int W = W2 / 2, NB = W2 / 16, KS = W2 / 4;
+    constexpr int W = W2 / 2, NB = W2 / 16, KS = W2 / 4, LDZ = W2 + 1;
+    __shared__ double sz[W2 * LDZ];
     const int pr = blockIdx.y;
     const int p = pairs[2 * pr], q = pairs[2 * pr + 1];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double *zt = Zt + (size_t)pr * (W2 * W2);
+    for (int e = tid; e < W2 * W2; e += 256) sz[(e / W2) * LDZ + (e % W2)] = zt[e];
     int64_t t = blockIdx.x;
     double *Y;
     int64_t m;
@@ -399,41 +484,43 @@ __global__ __launch_bounds__(256) void k_update(double *__restrict__ Fw, double 
         m = nzw;
         t -= tiles_f + tiles_g;
     }
-    const int64_t rb = (t * 4 + wave) * rows_per_wave;
-    if (rb >= m) return;
-    const int64_t re = (rb + rows_per_wave < m) ? rb + rows_per_wave : m;
-    const double *zt = Zt + (size_t)pr * (W2 * W2);
-    double za[NB][KS];
-#pragma unroll
-    for (int jb = 0; jb < NB; ++jb)
-#pragma unroll
-        for (int s = 0; s < KS; ++s) za[jb][s] = zt[(16 * jb + (lane & 15)) * W2 + 4 * s + (lane >> 4)];
-    double *xcol[KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-        const int c = 4 * s + (lane >> 4);
-        const int gc = (c < W) ? p * W + c : q * W + (c - W);
-        xcol[s] = Y + (int64_t)gc * m + (lane & 15);
-    }
-    for (int64_t r0 = rb; r0 < re; r0 += 16) {
+    const int64_t rb = t * 4 * (int64_t)rows_per_wave;
+    const int64_t re = (rb + 4 * (int64_t)rows_per_wave < m) ? rb + 4 * (int64_t)rows_per_wave : m;
+    __syncthreads();
+    // Lane (i, k) = (lane % 16, lane / 16).  Columns 0..W-1 of the pair are
+    // block column p, W..2W-1 block column q; every k-step's column offset
+    // is a uniform multiple of m.
+    const int k4 = lane >> 4, i16 = lane & 15;
+    const double *bp = Y + ((int64_t)p * W + k4) * m + i16;
+    const double *bq = Y + ((int64_t)q * W + k4) * m + i16;
+    for (int64_t r0 = rb + 16 * wave; r0 < re; r0 += 64) {
+        // keep the Z_tilde fragment reads inside the loop (in LDS, not in
+        // 128 registers hoisted out of it)
+        __asm__ volatile("" ::: "memory");
         double xb[KS];
 #pragma unroll
-        for (int s = 0; s < KS; ++s) xb[s] = xcol[s][r0];
+        for (int s = 0; s < KS; ++s)
+            xb[s] = (4 * s < W) ? bp[(int64_t)(4 * s) * m + r0] : bq[(int64_t)(4 * s - W) * m + r0];
         d4 acc[NB];
 #pragma unroll
         for (int jb = 0; jb < NB; ++jb) acc[jb] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int s = 0; s < KS; ++s)
 #pragma unroll
-            for (int jb = 0; jb < NB; ++jb) acc[jb] = mfma16(za[jb][s], xb[s], acc[jb]);
+            for (int jb = 0; jb < NB; ++jb) {
+                // A'[j][k] = Z_tilde[4s+k][16jb+j], lane j + 16k
+                const double za = sz[(16 * jb + i16) * LDZ + 4 * s + k4];
+                acc[jb] = mfma16(za, xb[s], acc[jb]);
+            }
         // element r of acc[jb] in lane l is output column 16jb + 4r + l/16, row l%16
 #pragma unroll
         for (int jb = 0; jb < NB; ++jb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int c = 16 * jb + 4 * r + (lane >> 4);
-                const int gc = (c < W) ? p * W + c : q * W + (c - W);
-                Y[(int64_t)gc * m + r0 + (lane & 15)] = acc[jb][r];
+                const int c0 = 16 * jb + 4 * r;
+                double *dst = (c0 < W) ? (double *)bp + (int64_t)c0 * m + r0
+                                       : (double *)bq + (int64_t)(c0 - W) * m + r0;
+                *dst = acc[jb][r];
             }
     }
 }
@@ -554,6 +641,26 @@ __global__ __launch_bounds__(64) void k_n1(int64_t mf, int64_t mg, double *__res
     }
 }
 
+// Diagnostic evaluation of hz_real_2x2_fast, one thread per pivot pair.
+__global__ __launch_bounds__(256) void k_eval_2x2(int64_t count, const double *__restrict__ in,
+                                                  double *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    double z11, z21, z12, z22;
+    hz_real_2x2_fast(in[4 * i], in[4 * i + 1], in[4 * i + 2], in[4 * i + 3], z11, z21, z12, z22);
+    out[4 * i] = z11;
+    out[4 * i + 1] = z21;
+    out[4 * i + 2] = z12;
+    out[4 * i + 3] = z22;
+}
+
+void launch_eval_2x2(int64_t count, const double *in, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_eval_2x2, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count,
+                       in, out);
+}
+
 // ------------------------------------------------------------------ launchers
 
 void launch_prescale_real(const Plan &P, const Ptrs &W, const double *F, int64_t ldf,
@@ -572,12 +679,26 @@ static void step_impl(const Plan &P, const Ptrs &W, int step, const hz_params &p
     prof_mark(K_GRAM, true, s);
     hipLaunchKernelGGL(k_gram<W2>, dim3(P.splits, P.npairs, 2), dim3(256), 0, s, W.Fw, W.Gw,
                        P.mfw, P.mgw, pairs, P.splits, W.part);
+    hipLaunchKernelGGL(k_gram_sum<W2>, dim3((W2 * W2 + 511) / 512, 2 * P.npairs), dim3(256), 0,
+                       s, W.part, P.splits, W.gram);
     prof_mark(K_GRAM, false, s);
-    constexpr int NT = (W2 == 64) ? 512 : (W2 == 32 ? 128 : 64);
     prof_mark(K_INNER, true, s);
-    hipLaunchKernelGGL((k_inner<W2, NT>), dim3(P.npairs), dim3(NT), 0, s, W.part, P.splits,
-                       P.npairs, step, W.itab, P.isteps, prm.inner_max_sweeps, tol, prm.sort,
-                       W.Zt, W.cnt, W.status);
+    if constexpr (W2 == 16) {
+        hipLaunchKernelGGL((k_inner<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s, W.gram,
+                           P.npairs, step, W.itab, P.isteps, prm.inner_max_sweeps, tol,
+                           prm.sort, W.Zt, W.cnt, W.status, W.phase);
+    } else {
+        if (P.inner_lp == 8)
+            hipLaunchKernelGGL((k_inner<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s,
+                               W.gram, P.npairs, step, W.itab, P.isteps,
+                               prm.inner_max_sweeps, tol, prm.sort, W.Zt, W.cnt, W.status,
+                               W.phase);
+        else
+            hipLaunchKernelGGL((k_inner<W2, 16>), dim3(P.npairs), dim3((W2 / 2) * 16), 0, s,
+                               W.gram, P.npairs, step, W.itab, P.isteps,
+                               prm.inner_max_sweeps, tol, prm.sort, W.Zt, W.cnt, W.status,
+                               W.phase);
+    }
     prof_mark(K_INNER, false, s);
     const int64_t rpt = 4 * (int64_t)P.upd_rows;
     const int tf = (int)((P.mfw + rpt - 1) / rpt), tg = (int)((P.mgw + rpt - 1) / rpt),

@@ -183,3 +183,37 @@ def test_config2_full_size_vs_oracle_golden():
     assert float(fz) < 1e-12 and float(gz) < 1e-12, (float(fz), float(gz))
     assert float(uu) < 1e-12 and float(vv) < 1e-12, (float(uu), float(vv))
     assert float(torch.max(torch.abs(sf * sf + sg * sg - 1))) < 8 * EPS
+
+
+def test_device_2x2_invariants():
+    """The device 2x2 transformation (Section 2.1.2) on random pivot pairs and
+    on the special cases: Z^T B Z = I, Z^T A Z diagonal, positive scaled
+    cosines, exact identity for an already diagonal pair (criterion C1)."""
+    hz = _hz()
+    rng = np.random.default_rng(31)
+    rows = []
+    for _ in range(4000):
+        a = rng.standard_normal((2, 2))
+        A = a @ a.T
+        rows.append((A[0, 0], A[1, 1], A[0, 1], rng.uniform(-0.99, 0.99)))
+    special = [(2.5, 2.5, 2.5 * 0.6, 0.6), (2.5, 2.5, -2.5 * 0.6, -0.6), (2.5, 2.5, 0.0, 0.0),
+               (2.0, 2.0, 0.7, 0.3), (3.0, 1.0, 0.5, 0.0), (3.0, 1.0, 0.0, 0.3),
+               (1.0, 2.0, 0.27, 0.3), (1.0, 1e-6, 1e-9, 1e-7)]
+    rows += special
+    inp = torch.tensor(rows, dtype=torch.float64, device="cuda")
+    out = hz.eval_2x2(inp).cpu().numpy()
+    for (aii, ajj, aij, x), z in zip(rows, out):
+        A = np.array([[aii, aij], [aij, ajj]])
+        B = np.array([[1.0, x], [x, 1.0]])
+        Z = np.array([[z[0], z[2]], [z[1], z[3]]])
+        N = Z.T @ B @ Z
+        M = Z.T @ A @ Z
+        kB = np.linalg.cond(B)
+        zn = np.linalg.norm(Z) ** 2
+        assert np.max(np.abs(N - np.eye(2))) < 64 * EPS * kB, (aii, ajj, aij, x, N)
+        assert abs(M[0, 1]) < 64 * EPS * np.linalg.norm(A) * zn, (aii, ajj, aij, x, M)
+        assert Z[0, 0] > 0 and Z[1, 1] > 0
+    # a diagonal pair with B = I: the transformation is exactly the identity
+    one = hz.eval_2x2(torch.tensor([[3.0, 1.0, 0.0, 0.0]], dtype=torch.float64,
+                                   device="cuda")).cpu().numpy()[0]
+    assert one[0] == 1.0 and one[3] == 1.0 and one[1] == 0.0 and one[2] == 0.0
