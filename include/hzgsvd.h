@@ -110,9 +110,10 @@ typedef struct hz_info {
 /* Fill *p with the defaults listed above. */
 void hz_default_params(hz_params *p);
 
-/* Workspace bytes needed by hz_dgsvd for the given shape (0 if the shape is
- * invalid). */
+/* Workspace bytes needed by hz_dgsvd / hz_zgsvd for the given shape (0 if
+ * the shape or the parameters are invalid). */
 size_t hz_dgsvd_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n);
+size_t hz_zgsvd_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n);
 
 /* Real FP64 GSVD (variant 0, Sections 2-3).  Arguments in order:
  *  1 p (host, may be NULL = defaults), 2 m_f, 3 m_g, 4 n,
@@ -141,6 +142,13 @@ int hz_ordering(int kind, int N, int *table);
  * Z22 of Z' per pair).  Returns 0 or HZ_EHIP. */
 int hz_eval_2x2(int64_t count, const double *in, double *out, void *stream);
 
+/* Diagnostic: the device's complex 2x2 transformation (Section 2.1.1) on
+ * `count` pivot pairs.  in (device, 6*count doubles per pair: a_ii, a_jj,
+ * Re a_ij, Im a_ij, Re b_ij, Im b_ij, with |b_ij| < 1), out (device,
+ * 6*count doubles: Z11, Re Z21, Im Z21, Re Z12, Im Z12, Z22 of Z').
+ * Returns 0 or HZ_EHIP. */
+int hz_eval_2x2_z(int64_t count, const double *in, double *out, void *stream);
+
 /* Per-kernel timing of later solves in this process, for measurement:
  * with enable = 1 (or 2, see below) every Gram, inner-solve and update launch is bracketed by
  * HIP events on the solve's stream (resolved at the host syncs each sweep
@@ -160,6 +168,16 @@ int hz_profile_read_phases(double *us, int nphases);
  * host arrays of nkinds entries (either may be NULL); returns the number of
  * kinds written. */
 int hz_profile_read(double *ms, int64_t *launches, int nkinds);
+
+/* Complex128 GSVD (transformations of Section 2.1.1, Hermitian Gram blocks
+ * and Cholesky).  F, G, Z are interleaved complex (re, im) device buffers,
+ * 16-byte aligned; sigma, sigma_f, sigma_g stay real (Section 3.1.1).
+ * Arguments and status codes as hz_dgsvd; w must be 0, 8 or 16 (pivot blocks
+ * of order <= 32). */
+int hz_zgsvd(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n,
+             double *F, int64_t ldf, double *G, int64_t ldg, double *Z, int64_t ldz,
+             double *sigma, double *sigma_f, double *sigma_g,
+             void *work, size_t work_bytes, hz_info *info, void *stream);
 
 /* Short English description of a status code. */
 const char *hz_strerror(int status);

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libhzgsvd.so")
 CSRC = os.path.join(_HERE, "csrc")
-SOURCES = ["hz_api.hip", "hz_real.hip"]
+SOURCES = ["hz_api.hip", "hz_real.hip", "hz_cplx.hip"]
 
 HZ_OK, HZ_ENOCONV, HZ_ECHOL, HZ_ENONFINITE, HZ_EHIP = 0, 1, 2, 3, 4
 HZ_ORD_MM, HZ_ORD_RR = 1, 2
@@ -91,6 +91,12 @@ def lib():
         L.hz_dgsvd.argtypes = [ctypes.POINTER(HzParams), i64, i64, i64, dp, i64, dp, i64, dp,
                                i64, dp, dp, dp, vp, ctypes.c_size_t, ctypes.POINTER(HzInfo), vp]
         L.hz_dgsvd.restype = ctypes.c_int
+        L.hz_zgsvd.argtypes = L.hz_dgsvd.argtypes
+        L.hz_zgsvd.restype = ctypes.c_int
+        L.hz_zgsvd_work_size.argtypes = L.hz_dgsvd_work_size.argtypes
+        L.hz_zgsvd_work_size.restype = ctypes.c_size_t
+        L.hz_eval_2x2_z.argtypes = [i64, vp, vp, vp]
+        L.hz_eval_2x2_z.restype = ctypes.c_int
         L.hz_strerror.argtypes = [ctypes.c_int]
         L.hz_strerror.restype = ctypes.c_char_p
         L.hz_eval_2x2.argtypes = [i64, vp, vp, vp]
@@ -121,13 +127,16 @@ def params(**kw) -> HzParams:
 
 
 def eval_2x2(inp):
-    """Evaluate the device 2x2 transformation on a (k, 4) float64 CUDA tensor
-    of (a_ii, a_jj, a_ij, b_ij) rows; returns (k, 4) rows (Z11, Z21, Z12, Z22)."""
+    """Evaluate the device 2x2 transformation on a CUDA float64 tensor of rows
+    (a_ii, a_jj, a_ij, b_ij) -> (Z11, Z21, Z12, Z22) (real, shape (k, 4)) or
+    (a_ii, a_jj, Re a_ij, Im a_ij, Re b_ij, Im b_ij) -> (Z11, Re Z21, Im Z21,
+    Re Z12, Im Z12, Z22) (complex, shape (k, 6))."""
     import torch
     inp = inp.contiguous()
     out = torch.empty_like(inp)
     stream = torch.cuda.current_stream(inp.device).cuda_stream
-    st = lib().hz_eval_2x2(inp.shape[0], _ptr(inp), _ptr(out), ctypes.c_void_p(stream))
+    fn = lib().hz_eval_2x2 if inp.shape[1] == 4 else lib().hz_eval_2x2_z
+    st = fn(inp.shape[0], _ptr(inp), _ptr(out), ctypes.c_void_p(stream))
     if st != 0:
         raise RuntimeError(f"hz_eval_2x2 failed: {st}")
     return out
@@ -158,7 +167,8 @@ class GsvdError(RuntimeError):
 def gsvd(F, G, *, overwrite=False, raise_on_noconv=False, workspace=None, **kw):
     """GSVD of (F, G) on the GPU.
 
-    F (m_F x n) and G (m_G x n) are float64 CUDA tensors.  Returns a dict
+    F (m_F x n) and G (m_G x n) are float64 or complex128 CUDA tensors
+    (hz_dgsvd or hz_zgsvd).  Returns a dict
     with U, V (overwriting column-major copies of F, G unless ``overwrite``
     and the inputs are already column-major), Z, sigma, sigma_f, sigma_g
     (descending in sigma), the hz_info fields and the status code.
@@ -167,8 +177,9 @@ def gsvd(F, G, *, overwrite=False, raise_on_noconv=False, workspace=None, **kw):
     """
     import torch
     L = lib()
-    if F.dtype != torch.float64 or G.dtype != torch.float64:
-        raise TypeError("hz_dgsvd takes float64 tensors")
+    cplx = F.dtype == torch.complex128
+    if F.dtype not in (torch.float64, torch.complex128) or G.dtype != F.dtype:
+        raise TypeError("F and G must both be float64 or both complex128")
     if not (F.is_cuda and G.is_cuda):
         raise ValueError("F and G must be CUDA (HIP) tensors")
     U = _colmajor(F) if overwrite else F.t().contiguous().t().clone() if F.t().is_contiguous() \
@@ -178,12 +189,12 @@ def gsvd(F, G, *, overwrite=False, raise_on_noconv=False, workspace=None, **kw):
     m_f, n = U.shape
     m_g = V.shape[0]
     dev = U.device
-    Z = torch.empty((n, n), dtype=torch.float64, device=dev).t()
+    Z = torch.empty((n, n), dtype=F.dtype, device=dev).t()
     sig = torch.empty(n, dtype=torch.float64, device=dev)
     sf = torch.empty_like(sig)
     sg = torch.empty_like(sig)
     p = params(**kw)
-    nbytes = L.hz_dgsvd_work_size(ctypes.byref(p), m_f, m_g, n)
+    nbytes = (L.hz_zgsvd_work_size if cplx else L.hz_dgsvd_work_size)(ctypes.byref(p), m_f, m_g, n)
     if nbytes == 0:
         raise ValueError("invalid shape or parameters")
     if workspace is None or workspace.numel() < nbytes:
@@ -191,11 +202,12 @@ def gsvd(F, G, *, overwrite=False, raise_on_noconv=False, workspace=None, **kw):
     wptr = (workspace.data_ptr() + 255) & ~255
     info = HzInfo()
     stream = torch.cuda.current_stream(dev).cuda_stream
-    st = L.hz_dgsvd(ctypes.byref(p), m_f, m_g, n, _ptr(U), _ld(U), _ptr(V), _ld(V),
+    fn = L.hz_zgsvd if cplx else L.hz_dgsvd
+    st = fn(ctypes.byref(p), m_f, m_g, n, _ptr(U), _ld(U), _ptr(V), _ld(V),
                     _ptr(Z), _ld(Z), _ptr(sig), _ptr(sf), _ptr(sg), ctypes.c_void_p(wptr),
                     nbytes, ctypes.byref(info), ctypes.c_void_p(stream))
     if st < 0:
-        raise ValueError(f"hz_dgsvd rejected argument {-st}")
+        raise ValueError(f"{'hz_zgsvd' if cplx else 'hz_dgsvd'} rejected argument {-st}")
     if st in (HZ_ECHOL, HZ_ENONFINITE, HZ_EHIP) or (raise_on_noconv and st == HZ_ENOCONV):
         raise GsvdError(st, info)
     return dict(U=U, V=V, Z=Z, sigma=sig, sigma_f=sf, sigma_g=sg, status=st,

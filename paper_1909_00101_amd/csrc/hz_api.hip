@@ -80,6 +80,13 @@ static int default_w(int64_t n, int is_complex)
     return 16;
 }
 
+// Complex pivot blocks are kept at order 2w <= 32 (three interleaved
+// complex 32x32 tiles in LDS).
+static int w_ok_for(const hz_params &p, int is_complex)
+{
+    return !is_complex || p.w == 0 || p.w == 8 || p.w == 16;
+}
+
 static bool make_plan(const hz_params &prm, int64_t mf, int64_t mg, int64_t n, int is_complex,
                       Plan &P)
 {
@@ -327,26 +334,21 @@ int hz_profile_read(double *ms, int64_t *launches, int nkinds)
     return n;
 }
 
-size_t hz_dgsvd_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n)
-{
-    hz_params prm;
-    if (p) prm = *p; else hz_default_params(&prm);
-    if (!params_ok(prm) || m_f < n || m_g < n || n < 1) return 0;
-    if (n == 1) return 256;
-    Plan P;
-    if (!make_plan(prm, m_f, m_g, n, 0, P)) return 0;
-    return P.total;
-}
+size_t hz_dgsvd_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n);
 
-int hz_dgsvd(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, double *F, int64_t ldf,
-             double *G, int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
-             double *sigma_g, void *work, size_t work_bytes, hz_info *info, void *stream)
+
+static int solve_entry(int is_complex, const hz_params *p, int64_t m_f, int64_t m_g, int64_t n,
+                       double *F, int64_t ldf, double *G, int64_t ldg, double *Z, int64_t ldz,
+                       double *sigma, double *sigma_f, double *sigma_g, void *work,
+                       size_t work_bytes, hz_info *info, void *stream)
 {
     hz_params prm;
     if (p) prm = *p; else hz_default_params(&prm);
-    if (!params_ok(prm)) return -1;
+    if (!params_ok(prm) || !w_ok_for(prm, is_complex)) return -1;
     const int a = check_args(m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g);
     if (a) return a;
+    if (is_complex && (((uintptr_t)F | (uintptr_t)G | (uintptr_t)Z) & 15))
+        return ((uintptr_t)F & 15) ? -5 : (((uintptr_t)G & 15) ? -7 : -9);
     if (work && ((uintptr_t)work & 255)) return -14;
     hipStream_t st = (hipStream_t)stream;
     if (info) memset(info, 0, sizeof(*info));
@@ -358,7 +360,8 @@ int hz_dgsvd(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, double *F,
         if (work && work_bytes >= 256) status = (int *)work;
         else { if (hipMalloc(&status, 256) != hipSuccess) return HZ_EHIP; own = true; }
         HZ_CHECK(hipMemsetAsync(status, 0, sizeof(int) * ST_NSLOTS, st));
-        launch_n1_real(m_f, m_g, F, G, Z, sigma, sigma_f, sigma_g, status, st);
+        if (is_complex) launch_n1_cplx(m_f, m_g, F, G, Z, sigma, sigma_f, sigma_g, status, st);
+        else launch_n1_real(m_f, m_g, F, G, Z, sigma, sigma_f, sigma_g, status, st);
         HZ_CHECK(hipGetLastError());
         HZ_CHECK(hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, st));
         HZ_CHECK(hipStreamSynchronize(st));
@@ -369,10 +372,58 @@ int hz_dgsvd(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, double *F,
         return rc;
     }
     Plan P;
-    if (!make_plan(prm, m_f, m_g, n, 0, P)) return -4;
+    if (!make_plan(prm, m_f, m_g, n, is_complex, P)) return -4;
     if (work && work_bytes < P.total) return -15;
-    return run_solve(prm, P, work, work_bytes, info, st, false, F, ldf, G, ldg, F, G, Z, ldz,
-                     sigma, sigma_f, sigma_g);
+    return run_solve(prm, P, work, work_bytes, info, st, is_complex != 0, F, ldf, G, ldg, F, G, Z,
+                     ldz, sigma, sigma_f, sigma_g);
+}
+
+static size_t work_size_entry(int is_complex, const hz_params *p, int64_t m_f, int64_t m_g,
+                              int64_t n)
+{
+    hz_params prm;
+    if (p) prm = *p; else hz_default_params(&prm);
+    if (!params_ok(prm) || !w_ok_for(prm, is_complex) || m_f < n || m_g < n || n < 1) return 0;
+    if (n == 1) return 256;
+    Plan P;
+    if (!make_plan(prm, m_f, m_g, n, is_complex, P)) return 0;
+    return P.total;
+}
+
+int hz_dgsvd(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, double *F, int64_t ldf,
+             double *G, int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
+             double *sigma_g, void *work, size_t work_bytes, hz_info *info, void *stream)
+{
+    return solve_entry(0, p, m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g, work,
+                       work_bytes, info, stream);
+}
+
+int hz_zgsvd(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, double *F, int64_t ldf,
+             double *G, int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
+             double *sigma_g, void *work, size_t work_bytes, hz_info *info, void *stream)
+{
+    return solve_entry(1, p, m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g, work,
+                       work_bytes, info, stream);
+}
+
+size_t hz_zgsvd_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n)
+{
+    return work_size_entry(1, p, m_f, m_g, n);
+}
+
+size_t hz_dgsvd_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n)
+{
+    return work_size_entry(0, p, m_f, m_g, n);
+}
+
+int hz_eval_2x2_z(int64_t count, const double *in, double *out, void *stream)
+{
+    if (count < 0 || (count > 0 && (!in || !out))) return -1;
+    if (count == 0) return 0;
+    launch_eval_2x2_cplx(count, in, out, (hipStream_t)stream);
+    if (hipGetLastError() != hipSuccess) return HZ_EHIP;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return HZ_EHIP;
+    return 0;
 }
 
 }  // extern "C"
@@ -421,11 +472,16 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
         HZ_CHECK(hipMemcpyAsync(W.itab, itab.data(), itab.size() * sizeof(int16_t),
                                 hipMemcpyHostToDevice, st));
         HZ_CHECK(hipMemcpyAsync(W.status, hs, sizeof(hs), hipMemcpyHostToDevice, st));
-        if (complex_path) { rc = HZ_EHIP; goto done; }
-        launch_prescale_real(P, W, (const double *)F, ldf, (const double *)G, ldg, st);
+        if (complex_path)
+            launch_prescale_cplx(P, W, (const double *)F, ldf, (const double *)G, ldg, st);
+        else
+            launch_prescale_real(P, W, (const double *)F, ldf, (const double *)G, ldg, st);
         HZ_CHECK(hipGetLastError());
         for (int sw = 0; sw < prm.max_sweeps; ++sw) {
-            for (int k = 0; k < P.steps; ++k) launch_step_real(P, W, k, prm, tol, st);
+            for (int k = 0; k < P.steps; ++k) {
+                if (complex_path) launch_step_cplx(P, W, k, prm, tol, st);
+                else launch_step_real(P, W, k, prm, tol, st);
+            }
             HZ_CHECK(hipGetLastError());
             HZ_CHECK(hipMemcpyAsync(hc.data(), W.cnt, hc.size() * sizeof(unsigned long long),
                                     hipMemcpyDeviceToHost, st));
@@ -457,8 +513,12 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
             }
         }
         if (!(hs[ST_FLAGS] & FLAG_CHOL)) {
-            launch_finish_real(P, W, (double *)U, ldf, (double *)V, ldg, (double *)Z, ldz, sigma,
-                               sigma_f, sigma_g, st);
+            if (complex_path)
+                launch_finish_cplx(P, W, (double *)U, ldf, (double *)V, ldg, (double *)Z, ldz,
+                                   sigma, sigma_f, sigma_g, st);
+            else
+                launch_finish_real(P, W, (double *)U, ldf, (double *)V, ldg, (double *)Z, ldz,
+                                   sigma, sigma_f, sigma_g, st);
             HZ_CHECK(hipGetLastError());
             HZ_CHECK(hipMemcpyAsync(hs, W.status, sizeof(hs), hipMemcpyDeviceToHost, st));
         }

@@ -1,0 +1,657 @@
+// hz_cplx.hip -- complex128 kernels of the blocked one-sided implicit
+// Hari-Zimmermann GSVD on gfx950 (paper: the complex case of Sections 2.1.1
+// and 3; matrices kept interleaved (re, im) in HBM and LDS).
+//
+// The structure mirrors the real path (hz_real.hip): prescale/copy-in,
+// block steps of Gram -> inner solve -> update, then extraction and sort.
+// Complex products on FP64 MFMA use four real products per complex
+// multiply-accumulate.  No floating-point atomics; fixed reduction orders.
+#include "hz_device.h"
+#include "hz_internal.h"
+
+namespace hz {
+
+// Prescale and copy-in with bordering (Section 2, Section 3.1, Section 3.3).
+__global__ __launch_bounds__(256) void k_prescale_copy_z(
+    int64_t mf, int64_t mg, int64_t n, const d2 *__restrict__ F, int64_t ldf,
+    const d2 *__restrict__ G, int64_t ldg, int64_t nw, int64_t mfw, int64_t mgw, int64_t nzw,
+    d2 *__restrict__ Fw, d2 *__restrict__ Gw, d2 *__restrict__ Zw, int *__restrict__ status)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= nw) return;
+    d2 *fw = Fw + j * mfw, *gw = Gw + j * mgw, *zw = Zw + j * nzw;
+    const d2 zero = {0.0, 0.0};
+    if (j < n) {
+        const d2 *f = F + j * ldf, *g = G + j * ldg;
+        double s = 0.0;
+        for (int64_t r = lane; r < mg; r += 64) {
+            const d2 v = g[r];
+            s = fma(v[0], v[0], s);
+            s = fma(v[1], v[1], s);
+        }
+        s = wave_sum(s);
+        const double d = 1.0 / sqrt(s);
+        bool bad = !(s > 0.0) || !isfinite(s);
+        for (int64_t r = lane; r < mfw; r += 64) {
+            const d2 v = (r < mf) ? f[r] * d : zero;
+            bad |= !isfinite(v[0]) || !isfinite(v[1]);
+            fw[r] = v;
+        }
+        for (int64_t r = lane; r < mgw; r += 64) gw[r] = (r < mg) ? g[r] * d : zero;
+        for (int64_t r = lane; r < nzw; r += 64) zw[r] = (r == j) ? d2{d, 0.0} : zero;
+        if (bad) atomicOr(status + ST_FLAGS, FLAG_NONFINITE);
+    } else {
+        const int64_t k = j - n;
+        const d2 one = {1.0, 0.0};
+        for (int64_t r = lane; r < mfw; r += 64) fw[r] = (r == mf + k) ? one : zero;
+        for (int64_t r = lane; r < mgw; r += 64) gw[r] = (r == mg + k) ? one : zero;
+        for (int64_t r = lane; r < nzw; r += 64) zw[r] = (r == j) ? one : zero;
+    }
+}
+
+// Hermitian pivot Gram blocks A_hat = X^H X (Section 2.3, ZHERK-like),
+// lower-triangle 16x16 tiles, split-K partials (interleaved complex,
+// column-major W2 x W2).  Re = Xr^T Xr + Xi^T Xi, Im = Xr^T Xi - Xi^T Xr.
+template <int W2>
+__global__ __launch_bounds__(256) void k_gram_z(const d2 *__restrict__ Fw,
+                                                const d2 *__restrict__ Gw, int64_t mfw,
+                                                int64_t mgw, const int *__restrict__ pairs,
+                                                int splits, d2 *__restrict__ part)
+{
+    constexpr int W = W2 / 2, NB = W2 / 16, LDT = 66, NLD = W2 / 4;
+    constexpr int NT = NB * (NB + 1) / 2;
+    __shared__ __attribute__((aligned(16))) double tre[W2 * LDT];
+    __shared__ __attribute__((aligned(16))) double tim[W2 * LDT];
+    const int split = blockIdx.x, pr = blockIdx.y, mat = blockIdx.z;
+    const d2 *Y = mat ? Gw : Fw;
+    const int64_t m = mat ? mgw : mfw;
+    const int p = pairs[2 * pr], q = pairs[2 * pr + 1];
+    const int64_t nch = m / 64;
+    const int64_t c0 = nch * split / splits, c1 = nch * (split + 1) / splits;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lrow = tid & 63, lcol = tid >> 6;
+
+    d4 accr[NT], acci[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        accr[t] = d4{0.0, 0.0, 0.0, 0.0};
+        acci[t] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+    const d2 *colp[NLD];
+#pragma unroll
+    for (int t = 0; t < NLD; ++t) {
+        const int cc = lcol + 4 * t;
+        const int gc = (cc < W) ? p * W + cc : q * W + (cc - W);
+        colp[t] = Y + (int64_t)gc * m + lrow;
+    }
+    d2 buf[NLD];
+    if (c0 < c1) {
+#pragma unroll
+        for (int t = 0; t < NLD; ++t) buf[t] = colp[t][c0 * 64];
+    }
+    for (int64_t c = c0; c < c1; ++c) {
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < NLD; ++t) {
+            tre[(lcol + 4 * t) * LDT + lrow] = buf[t][0];
+            tim[(lcol + 4 * t) * LDT + lrow] = buf[t][1];
+        }
+        __syncthreads();
+        if (c + 1 < c1) {
+#pragma unroll
+            for (int t = 0; t < NLD; ++t) buf[t] = colp[t][(c + 1) * 64];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int ks = wave + 4 * s;
+            double fr[NB], fi[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int o = (16 * b + (lane & 15)) * LDT + 4 * ks + (lane >> 4);
+                fr[b] = tre[o];
+                fi[b] = tim[o];
+            }
+            int t = 0;
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+                for (int b = 0; b <= a; ++b, ++t) {
+                    accr[t] = mfma16(fr[a], fr[b], accr[t]);
+                    accr[t] = mfma16(fi[a], fi[b], accr[t]);
+                    acci[t] = mfma16(fr[a], fi[b], acci[t]);
+                    acci[t] = mfma16(-fi[a], fr[b], acci[t]);
+                }
+        }
+    }
+    for (int wv = 0; wv < 4; ++wv) {
+        __syncthreads();
+        if (wave == wv) {
+            int t = 0;
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+                for (int b = 0; b <= a; ++b, ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int gi = 16 * a + 4 * r + (lane >> 4), gj = 16 * b + (lane & 15);
+                        double *dr = tre + gj * W2 + gi, *di = tim + gj * W2 + gi;
+                        *dr = (wv == 0) ? accr[t][r] : *dr + accr[t][r];
+                        *di = (wv == 0) ? acci[t][r] : *di + acci[t][r];
+                    }
+        }
+    }
+    __syncthreads();
+    d2 *out = part + ((size_t)(pr * 2 + mat) * splits + split) * (W2 * W2);
+    for (int e = tid; e < W2 * W2; e += 256) out[e] = d2{tre[e], tim[e]};
+}
+
+template <int W2>
+__global__ __launch_bounds__(256) void k_gram_sum_z(const d2 *__restrict__ part, int splits,
+                                                    d2 *__restrict__ gram)
+{
+    constexpr int MAXS = 16;
+    const int pm = blockIdx.y;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= W2 * W2) return;
+    const d2 *src = part + (size_t)pm * splits * (W2 * W2) + e;
+    d2 v[MAXS];
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s)
+        if (s < splits) v[s] = src[(size_t)s * (W2 * W2)];
+    d2 acc = v[0];
+#pragma unroll
+    for (int s = 1; s < MAXS; ++s)
+        if (s < splits) acc += v[s];
+    gram[(size_t)pm * (W2 * W2) + e] = acc;
+}
+
+// Inner solve of one complex pivot block pair: Hermitian Cholesky
+// (A_hat = F_hat^H F_hat), factor prescale, inner sweeps of the complex
+// pointwise method (Section 2.1.1), Theta rescale (Section 2.4).  Layout and
+// phases as the real k_inner; columns of F_hat, G_hat, Z_hat are
+// interleaved complex in LDS.
+template <int W2, int LP>
+__global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
+    const d2 *__restrict__ gram, int npairs, int step, const int16_t *__restrict__ itab,
+    int isteps, int inner_max, double tol, int sort, d2 *__restrict__ Zt,
+    unsigned long long *__restrict__ cnt, int *__restrict__ status)
+{
+    constexpr int W = W2 / 2;
+    constexpr int NT = W * LP;
+    constexpr int RPL = W2 / LP;
+    constexpr int LDI = W2 + 1;
+    static_assert(RPL >= 1 && NT >= 64 && W2 <= 32, "bad complex inner geometry");
+    __shared__ d2 sF[W2 * LDI];
+    __shared__ d2 sG[W2 * LDI];
+    __shared__ d2 sZ[W2 * LDI];
+    __shared__ int16_t stab[W2 * W2];
+    __shared__ d2 lbuf[2][32];
+    __shared__ int s_fail;
+    __shared__ unsigned s_cnt[2 * W];
+
+    const int pr = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    unsigned long long *myc = cnt + ((size_t)step * npairs + pr) * 4;
+    {
+        const d2 *pa = gram + (size_t)(pr * 2) * (W2 * W2);
+        const d2 *pb = pa + (W2 * W2);
+        for (int e = tid; e < W2 * W2; e += NT) {
+            const int col = e / W2, row = e % W2;
+            sF[col * LDI + row] = pa[e];
+            sG[col * LDI + row] = pb[e];
+        }
+        for (int e = tid; e < isteps * W * 2; e += NT) stab[e] = itab[e];
+        if (tid == 0) s_fail = 0;
+    }
+    __syncthreads();
+
+    // Hermitian Cholesky, lane = row, A in lanes 0..31 and B in 32..63 of wave 0.
+    {
+        const int mat = lane >> 5, i = lane & 31;
+        if (wave == 0 && i < W2) {
+            d2 *M = mat ? sG : sF;
+            d2 *lb = lbuf[mat];
+            d2 a[W2];
+#pragma unroll
+            for (int k = 0; k < W2; ++k) a[k] = M[k * LDI + i];
+            bool ok = true;
+#pragma unroll
+            for (int j = 0; j < W2; ++j) {
+                const double p0 = readlane_d(a[j][0], j), p1 = readlane_d(a[j][0], 32 + j);
+                const double piv = mat ? p1 : p0;
+                ok = ok && (piv > 0.0) && (piv < INFINITY);
+                const double inv = rsqrt_nr(piv);
+                d2 l = (i > j) ? a[j] * inv : d2{0.0, 0.0};
+                if (i == j) l = d2{piv * inv, 0.0};
+                a[j] = l;
+                lb[i] = l;
+                wave_fence();
+#pragma unroll
+                for (int k = j + 1; k < W2; ++k) {
+                    const d2 lk = lb[k];
+                    // a[k] -= l * conj(lk)
+                    a[k][0] = fma(-l[0], lk[0], fma(-l[1], lk[1], a[k][0]));
+                    a[k][1] = fma(-l[1], lk[0], fma(l[0], lk[1], a[k][1]));
+                }
+                wave_fence();
+            }
+            // F_hat = L^H: column i of F_hat is the conjugate of row i of L.
+#pragma unroll
+            for (int k = 0; k < W2; ++k)
+                M[i * LDI + k] = (k <= i) ? d2{a[k][0], -a[k][1]} : d2{0.0, 0.0};
+            if (!ok) s_fail = 1;
+        }
+    }
+    __syncthreads();
+    if (s_fail) {
+        d2 *zt = Zt + (size_t)pr * (W2 * W2);
+        for (int e = tid; e < W2 * W2; e += NT)
+            zt[e] = (e % W2 == e / W2) ? d2{1.0, 0.0} : d2{0.0, 0.0};
+        if (tid == 0) {
+            myc[0] = 0;
+            myc[1] = 0;
+            myc[2] = 0;
+            atomicOr(status + ST_FLAGS, FLAG_CHOL);
+            atomicMin(status + ST_FAILPAIR, step * 65536 + pr);
+        }
+        return;
+    }
+
+    const int grp = tid / LP, gl = tid % LP, r0 = gl * RPL;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = 2 * grp + h;
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const d2 g = sG[c * LDI + r0 + r];
+            s = fma(g[0], g[0], fma(g[1], g[1], s));
+        }
+        s = dpp_group_sum<LP>(s);
+        const double d = rsqrt_nr(s);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            sF[c * LDI + r0 + r] *= d;
+            sG[c * LDI + r0 + r] *= d;
+            sZ[c * LDI + r0 + r] = (r0 + r == c) ? d2{d, 0.0} : d2{0.0, 0.0};
+        }
+    }
+    __syncthreads();
+
+    const double tol2 = tol * tol;
+    unsigned my_all = 0, my_big = 0;
+    int nsw = 0;
+    for (int sw = 0; sw < inner_max; ++sw) {
+        unsigned sw_all = 0, sw_big = 0;
+        ++nsw;
+        for (int st = 0; st < isteps; ++st) {
+            const int ci = stab[(st * W + grp) * 2], cj = stab[(st * W + grp) * 2 + 1];
+            d2 fi[RPL], fj[RPL], gi[RPL], gj[RPL], zi[RPL], zj[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                fi[r] = sF[ci * LDI + r0 + r];
+                fj[r] = sF[cj * LDI + r0 + r];
+                gi[r] = sG[ci * LDI + r0 + r];
+                gj[r] = sG[cj * LDI + r0 + r];
+                zi[r] = sZ[ci * LDI + r0 + r];
+                zj[r] = sZ[cj * LDI + r0 + r];
+            }
+            double aii = 0.0, ajj = 0.0, ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                aii = fma(fi[r][0], fi[r][0], fma(fi[r][1], fi[r][1], aii));
+                ajj = fma(fj[r][0], fj[r][0], fma(fj[r][1], fj[r][1], ajj));
+                ar = fma(fi[r][0], fj[r][0], fma(fi[r][1], fj[r][1], ar));
+                ai = fma(fi[r][0], fj[r][1], fma(-fi[r][1], fj[r][0], ai));
+                br = fma(gi[r][0], gj[r][0], fma(gi[r][1], gj[r][1], br));
+                bi = fma(gi[r][0], gj[r][1], fma(-gi[r][1], gj[r][0], bi));
+            }
+            aii = dpp_group_sum<LP>(aii);
+            ajj = dpp_group_sum<LP>(ajj);
+            ar = dpp_group_sum<LP>(ar);
+            ai = dpp_group_sum<LP>(ai);
+            br = dpp_group_sum<LP>(br);
+            bi = dpp_group_sum<LP>(bi);
+            double z11 = 1.0, z22 = 1.0, z21r = 0.0, z21i = 0.0, z12r = 0.0, z12i = 0.0;
+            bool swap;
+            const bool orth = (fma(ar, ar, ai * ai) < aii * ajj * tol2) &&
+                              (fma(br, br, bi * bi) < tol2);
+            if (orth) {
+                swap = sort && (aii < ajj);
+            } else {
+                hz_cplx_2x2_fast(aii, ajj, ar, ai, br, bi, z11, z21r, z21i, z12r, z12i, z22);
+                sw_all += 1;
+                if (!(z11 == 1.0 && z22 == 1.0)) sw_big += 1;
+                swap = false;
+                if (sort) {
+                    // diagonal of Z^H A Z
+                    const double a11 = fma(z11 * z11, aii,
+                                           fma(2.0 * z11, fma(ar, z21r, -ai * z21i),
+                                               fma(z21r, z21r, z21i * z21i) * ajj));
+                    const double a22 = fma(fma(z12r, z12r, z12i * z12i), aii,
+                                           fma(2.0 * z22, fma(z12r, ar, z12i * ai),
+                                               z22 * z22 * ajj));
+                    swap = a11 < a22;
+                }
+            }
+            if (!orth || swap) {
+                // [y_i y_j] <- [y_i y_j] Z (z11, z22 real), then the sorting swap
+                auto rot = [&](const d2 yi, const d2 yj, d2 &oi, d2 &oj) {
+                    d2 a, b;
+                    a[0] = fma(yi[0], z11, fma(yj[0], z21r, -yj[1] * z21i));
+                    a[1] = fma(yi[1], z11, fma(yj[0], z21i, yj[1] * z21r));
+                    b[0] = fma(yj[0], z22, fma(yi[0], z12r, -yi[1] * z12i));
+                    b[1] = fma(yj[1], z22, fma(yi[0], z12i, yi[1] * z12r));
+                    oi = swap ? b : a;
+                    oj = swap ? a : b;
+                };
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) {
+                    d2 oi, oj;
+                    rot(fi[r], fj[r], oi, oj);
+                    sF[ci * LDI + r0 + r] = oi;
+                    sF[cj * LDI + r0 + r] = oj;
+                    rot(gi[r], gj[r], oi, oj);
+                    sG[ci * LDI + r0 + r] = oi;
+                    sG[cj * LDI + r0 + r] = oj;
+                    rot(zi[r], zj[r], oi, oj);
+                    sZ[ci * LDI + r0 + r] = oi;
+                    sZ[cj * LDI + r0 + r] = oj;
+                }
+            }
+            __syncthreads();
+        }
+        my_all += sw_all;
+        my_big += sw_big;
+        const int any = __syncthreads_count(gl == 0 && sw_all > 0);
+        if (any == 0) break;
+    }
+
+    d2 *zt = Zt + (size_t)pr * (W2 * W2);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = 2 * grp + h;
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const d2 f = sF[c * LDI + r0 + r], g = sG[c * LDI + r0 + r];
+            s = fma(f[0], f[0], fma(f[1], f[1], s));
+            s = fma(g[0], g[0], fma(g[1], g[1], s));
+        }
+        s = dpp_group_sum<LP>(s);
+        const double th = rsqrt_nr(s);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) zt[c * W2 + r0 + r] = sZ[c * LDI + r0 + r] * th;
+    }
+    if (gl == 0) {
+        s_cnt[2 * grp] = my_all;
+        s_cnt[2 * grp + 1] = my_big;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long ta = 0, tb = 0;
+        for (int g = 0; g < W; ++g) {
+            ta += s_cnt[2 * g];
+            tb += s_cnt[2 * g + 1];
+        }
+        myc[0] = ta;
+        myc[1] = tb;
+        myc[2] = (unsigned long long)nsw;
+    }
+}
+
+// Complex block update [Y_p Y_q] <- [Y_p Y_q] Z_tilde in place
+// (Section 2.3, Section 3.5.4): D' = Z_tilde^T X^T with
+// Re = Zr^T Xr^T - Zi^T Xi^T, Im = Zi^T Xr^T + Zr^T Xi^T on FP64 MFMA.
+template <int W2>
+__global__ __launch_bounds__(256) void k_update_z(d2 *__restrict__ Fw, d2 *__restrict__ Gw,
+                                                  d2 *__restrict__ Zw, int64_t mfw, int64_t mgw,
+                                                  int64_t nzw, const int *__restrict__ pairs,
+                                                  const d2 *__restrict__ Zt, int tiles_f,
+                                                  int tiles_g, int rows_per_wave)
+{
+    constexpr int W = W2 / 2, NB = W2 / 16, KS = W2 / 4, LDZ = W2 + 1;
+    __shared__ d2 sz[W2 * LDZ];
+    const int pr = blockIdx.y;
+    const int p = pairs[2 * pr], q = pairs[2 * pr + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const d2 *zt = Zt + (size_t)pr * (W2 * W2);
+    for (int e = tid; e < W2 * W2; e += 256) sz[(e / W2) * LDZ + (e % W2)] = zt[e];
+    int64_t t = blockIdx.x;
+    d2 *Y;
+    int64_t m;
+    if (t < tiles_f) {
+        Y = Fw;
+        m = mfw;
+    } else if (t < tiles_f + tiles_g) {
+        Y = Gw;
+        m = mgw;
+        t -= tiles_f;
+    } else {
+        Y = Zw;
+        m = nzw;
+        t -= tiles_f + tiles_g;
+    }
+    const int64_t rb = t * 4 * (int64_t)rows_per_wave;
+    const int64_t re = (rb + 4 * (int64_t)rows_per_wave < m) ? rb + 4 * (int64_t)rows_per_wave : m;
+    __syncthreads();
+    const int k4 = lane >> 4, i16 = lane & 15;
+    d2 *bp = Y + ((int64_t)p * W + k4) * m + i16;
+    d2 *bq = Y + ((int64_t)q * W + k4) * m + i16;
+    for (int64_t r0 = rb + 16 * wave; r0 < re; r0 += 64) {
+        __asm__ volatile("" ::: "memory");
+        d2 xb[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            xb[s] = (4 * s < W) ? bp[(int64_t)(4 * s) * m + r0] : bq[(int64_t)(4 * s - W) * m + r0];
+        d4 accr[NB], acci[NB];
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+            accr[jb] = d4{0.0, 0.0, 0.0, 0.0};
+            acci[jb] = d4{0.0, 0.0, 0.0, 0.0};
+        }
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+                const d2 za = sz[(16 * jb + i16) * LDZ + 4 * s + k4];
+                accr[jb] = mfma16(za[0], xb[s][0], accr[jb]);
+                accr[jb] = mfma16(-za[1], xb[s][1], accr[jb]);
+                acci[jb] = mfma16(za[1], xb[s][0], acci[jb]);
+                acci[jb] = mfma16(za[0], xb[s][1], acci[jb]);
+            }
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c0 = 16 * jb + 4 * r;
+                d2 *dst = (c0 < W) ? bp + (int64_t)c0 * m + r0 : bq + (int64_t)(c0 - W) * m + r0;
+                *dst = d2{accr[jb][r], acci[jb][r]};
+            }
+    }
+}
+
+// Extraction (Section 2.4, Section 3.4): norms and bordering flags.
+__global__ __launch_bounds__(256) void k_colnorms_z(const d2 *__restrict__ Fw,
+                                                    const d2 *__restrict__ Gw,
+                                                    const d2 *__restrict__ Zw, int64_t mfw,
+                                                    int64_t mgw, int64_t nzw, int64_t n,
+                                                    int64_t nw, double *__restrict__ sf,
+                                                    double *__restrict__ sg,
+                                                    double *__restrict__ sig,
+                                                    int *__restrict__ border,
+                                                    int *__restrict__ status)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= nw) return;
+    const d2 *f = Fw + j * mfw, *g = Gw + j * mgw, *z = Zw + j * nzw;
+    double a = 0.0, b = 0.0;
+    for (int64_t r = lane; r < mfw; r += 64) a = fma(f[r][0], f[r][0], fma(f[r][1], f[r][1], a));
+    for (int64_t r = lane; r < mgw; r += 64) b = fma(g[r][0], g[r][0], fma(g[r][1], g[r][1], b));
+    int bz = 0;
+    for (int64_t r = n + lane; r < nw; r += 64) bz |= (z[r][0] != 0.0 || z[r][1] != 0.0);
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int isb = __any(bz) ? 1 : 0;
+    if (lane == 0) {
+        const double x = sqrt(a), y = sqrt(b);
+        sf[j] = x;
+        sg[j] = y;
+        sig[j] = x / y;
+        border[j] = isb;
+        if (!isb && !(isfinite(x / y) && x > 0.0 && y > 0.0)) atomicOr(status + ST_FLAGS, FLAG_NONFINITE);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scatter_z(
+    const d2 *__restrict__ Fw, const d2 *__restrict__ Gw, const d2 *__restrict__ Zw, int64_t mfw,
+    int64_t mgw, int64_t nzw, int64_t mf, int64_t mg, int64_t n, int64_t nw,
+    const double *__restrict__ sf, const double *__restrict__ sg, const int *__restrict__ rank,
+    d2 *__restrict__ U, int64_t ldu, d2 *__restrict__ V, int64_t ldv, d2 *__restrict__ Z,
+    int64_t ldz, double *__restrict__ sigma, double *__restrict__ sigma_f,
+    double *__restrict__ sigma_g)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= nw) return;
+    const int rk = rank[j];
+    if (rk < 0 || rk >= n) return;
+    const double x = sf[j], y = sg[j];
+    const double th = 1.0 / sqrt(x * x + y * y);
+    const double ix = 1.0 / x, iy = 1.0 / y;
+    const d2 *f = Fw + j * mfw, *g = Gw + j * mgw, *z = Zw + j * nzw;
+    d2 *u = U + (int64_t)rk * ldu, *v = V + (int64_t)rk * ldv, *zo = Z + (int64_t)rk * ldz;
+    for (int64_t r = lane; r < mf; r += 64) u[r] = f[r] * ix;
+    for (int64_t r = lane; r < mg; r += 64) v[r] = g[r] * iy;
+    for (int64_t r = lane; r < n; r += 64) zo[r] = z[r] * th;
+    if (lane == 0) {
+        sigma[rk] = x / y;
+        sigma_f[rk] = x * th;
+        sigma_g[rk] = y * th;
+    }
+}
+
+// n = 1 closed form (Section 2), complex.
+__global__ __launch_bounds__(64) void k_n1_z(int64_t mf, int64_t mg, d2 *__restrict__ F,
+                                             d2 *__restrict__ G, d2 *__restrict__ Z,
+                                             double *__restrict__ sigma,
+                                             double *__restrict__ sigma_f,
+                                             double *__restrict__ sigma_g,
+                                             int *__restrict__ status)
+{
+    const int lane = threadIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int64_t r = lane; r < mf; r += 64) a = fma(F[r][0], F[r][0], fma(F[r][1], F[r][1], a));
+    for (int64_t r = lane; r < mg; r += 64) b = fma(G[r][0], G[r][0], fma(G[r][1], G[r][1], b));
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const double nf = sqrt(a), ng = sqrt(b), rr = sqrt(a + b);
+    for (int64_t r = lane; r < mf; r += 64) F[r] = F[r] / nf;
+    for (int64_t r = lane; r < mg; r += 64) G[r] = G[r] / ng;
+    if (lane == 0) {
+        Z[0] = d2{1.0 / rr, 0.0};
+        sigma[0] = nf / ng;
+        sigma_f[0] = nf / rr;
+        sigma_g[0] = ng / rr;
+        if (!(isfinite(nf / ng) && nf > 0.0 && ng > 0.0)) atomicOr(status + ST_FLAGS, FLAG_NONFINITE);
+    }
+}
+
+// Diagnostic evaluation of hz_cplx_2x2_fast: in rows (aii, ajj, ar, ai, br,
+// bi), out rows (z11, z21r, z21i, z12r, z12i, z22).
+__global__ __launch_bounds__(256) void k_eval_2x2_z(int64_t count, const double *__restrict__ in,
+                                                    double *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    const double *a = in + 6 * i;
+    double *o = out + 6 * i;
+    hz_cplx_2x2_fast(a[0], a[1], a[2], a[3], a[4], a[5], o[0], o[1], o[2], o[3], o[4], o[5]);
+}
+
+// ------------------------------------------------------------------ launchers
+
+void launch_prescale_cplx(const Plan &P, const Ptrs &W, const double *F, int64_t ldf,
+                          const double *G, int64_t ldg, hipStream_t s)
+{
+    const unsigned nb = (unsigned)((P.nw + 3) / 4);
+    hipLaunchKernelGGL(k_prescale_copy_z, dim3(nb), dim3(256), 0, s, P.mf, P.mg, P.n,
+                       (const d2 *)F, ldf, (const d2 *)G, ldg, P.nw, P.mfw, P.mgw, P.nzw,
+                       (d2 *)W.Fw, (d2 *)W.Gw, (d2 *)W.Zw, W.status);
+}
+
+template <int W2>
+static void step_impl_z(const Plan &P, const Ptrs &W, int step, const hz_params &prm,
+                        double tol, hipStream_t s)
+{
+    const int *pairs = W.otab + (size_t)step * P.npairs * 2;
+    prof_mark(K_GRAM, true, s);
+    hipLaunchKernelGGL(k_gram_z<W2>, dim3(P.splits, P.npairs, 2), dim3(256), 0, s,
+                       (const d2 *)W.Fw, (const d2 *)W.Gw, P.mfw, P.mgw, pairs, P.splits,
+                       (d2 *)W.part);
+    hipLaunchKernelGGL(k_gram_sum_z<W2>, dim3((W2 * W2 + 255) / 256, 2 * P.npairs), dim3(256), 0,
+                       s, (const d2 *)W.part, P.splits, (d2 *)W.gram);
+    prof_mark(K_GRAM, false, s);
+    prof_mark(K_INNER, true, s);
+    if constexpr (W2 == 32) {
+        if (P.inner_lp == 16)
+            hipLaunchKernelGGL((k_inner_z<W2, 16>), dim3(P.npairs), dim3((W2 / 2) * 16), 0, s,
+                               (const d2 *)W.gram, P.npairs, step, W.itab, P.isteps,
+                               prm.inner_max_sweeps, tol, prm.sort, (d2 *)W.Zt, W.cnt, W.status);
+        else
+            hipLaunchKernelGGL((k_inner_z<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s,
+                               (const d2 *)W.gram, P.npairs, step, W.itab, P.isteps,
+                               prm.inner_max_sweeps, tol, prm.sort, (d2 *)W.Zt, W.cnt, W.status);
+    } else {
+        hipLaunchKernelGGL((k_inner_z<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s,
+                           (const d2 *)W.gram, P.npairs, step, W.itab, P.isteps,
+                           prm.inner_max_sweeps, tol, prm.sort, (d2 *)W.Zt, W.cnt, W.status);
+    }
+    prof_mark(K_INNER, false, s);
+    const int64_t rpt = 4 * (int64_t)P.upd_rows;
+    const int tf = (int)((P.mfw + rpt - 1) / rpt), tg = (int)((P.mgw + rpt - 1) / rpt),
+              tz = (int)((P.nzw + rpt - 1) / rpt);
+    prof_mark(K_UPDATE, true, s);
+    hipLaunchKernelGGL(k_update_z<W2>, dim3(tf + tg + tz, P.npairs), dim3(256), 0, s,
+                       (d2 *)W.Fw, (d2 *)W.Gw, (d2 *)W.Zw, P.mfw, P.mgw, P.nzw, pairs,
+                       (const d2 *)W.Zt, tf, tg, P.upd_rows);
+    prof_mark(K_UPDATE, false, s);
+}
+
+void launch_step_cplx(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
+                      hipStream_t s)
+{
+    if (P.W2 == 16) step_impl_z<16>(P, W, step, prm, tol, s);
+    else step_impl_z<32>(P, W, step, prm, tol, s);
+}
+
+void launch_finish_cplx(const Plan &P, const Ptrs &W, double *F, int64_t ldf, double *G,
+                        int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
+                        double *sigma_g, hipStream_t s)
+{
+    const unsigned nb4 = (unsigned)((P.nw + 3) / 4);
+    hipLaunchKernelGGL(k_colnorms_z, dim3(nb4), dim3(256), 0, s, (const d2 *)W.Fw,
+                       (const d2 *)W.Gw, (const d2 *)W.Zw, P.mfw, P.mgw, P.nzw, P.n, P.nw, W.sf,
+                       W.sg, W.sig, W.border, W.status);
+    launch_rank(P, W, s);
+    hipLaunchKernelGGL(k_scatter_z, dim3(nb4), dim3(256), 0, s, (const d2 *)W.Fw,
+                       (const d2 *)W.Gw, (const d2 *)W.Zw, P.mfw, P.mgw, P.nzw, P.mf, P.mg, P.n,
+                       P.nw, W.sf, W.sg, W.rank, (d2 *)F, ldf, (d2 *)G, ldg, (d2 *)Z, ldz, sigma,
+                       sigma_f, sigma_g);
+}
+
+void launch_n1_cplx(int64_t mf, int64_t mg, double *F, double *G, double *Z, double *sigma,
+                    double *sigma_f, double *sigma_g, int *status, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_n1_z, dim3(1), dim3(64), 0, s, mf, mg, (d2 *)F, (d2 *)G, (d2 *)Z, sigma,
+                       sigma_f, sigma_g, status);
+}
+
+void launch_eval_2x2_cplx(int64_t count, const double *in, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_eval_2x2_z, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                       count, in, out);
+}
+
+}  // namespace hz

@@ -56,6 +56,15 @@ __device__ __forceinline__ double dpp_group_sum(double v)
     return v;
 }
 
+// Broadcast lane l's double to the wave (two v_readlane_b32; l uniform).
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
 // Reciprocal square root from the hardware estimate y0 = v_rsq_f64(x)
 // (relative error e0 about 2^-22) refined by one third-order step
 // y = y0 (1 + e/2 + 3e^2/8), e = 1 - x y0^2, which leaves O(e0^3) -- below
@@ -199,6 +208,76 @@ __device__ __forceinline__ void hz_real_2x2_fast(double aii, double ajj, double 
     z11 = cphi * rt;
     z21 = -spsi * rt;
     z12 = sphi * rt;
+    z22 = cpsi * rt;
+}
+
+// The complex 2x2 transformation of Section 2.1.1 without infinities, for
+// A' = [[aii, a], [conj(a), ajj]], B' = [[1, b], [conj(b), 1]], |b| < 1.
+// x = |b|, e^{i zeta} = b/|b| (1 for b = 0), z = e^{-i zeta} a = u + i v,
+// h = ajj - aii, tau = sign(1, h), s = aii + ajj, t = sqrt(1 - x^2).
+// With P = tau (2u - s x), R = sqrt(h^2 + 4 v^2) and Q = t R,
+// tan 2theta = P / Q gives cos 2theta = Q / sqrt(P^2 + Q^2) and
+// sin 2theta = P / sqrt(P^2 + Q^2); tan gamma = 2v / h gives cos gamma =
+// |h| / R and sin gamma = tau 2v / R (so h = 0, v != 0 yields cos 0 and
+// sin = sign(v)).  Then, as printed,
+//   cos phi = sqrt((1 + x s2 + t cg c2) / 2), cos psi = sqrt((1 - x s2 + t cg c2) / 2),
+//   e^{i alpha} sin phi = e^{i zeta} ((s2 - x) + i t sg c2) / (2 cos psi),
+//   e^{-i beta} sin psi = e^{-i zeta} ((s2 + x) - i t sg c2) / (2 cos phi),
+// and Z' = (1/t)[[cos phi, e^{ia} sin phi], [-e^{-ib} sin psi, cos psi]].
+// The exception v = h = 0 returns the printed congruence.  Cosines that
+// round to 1 are exactly 1 (criterion C1).  Output: z11, z22 real; z21 =
+// (z21r, z21i), z12 = (z12r, z12i) (column-major Z).
+__device__ __forceinline__ void hz_cplx_2x2_fast(double aii, double ajj, double ar, double ai,
+                                                 double br, double bi, double &z11,
+                                                 double &z21r, double &z21i, double &z12r,
+                                                 double &z12i, double &z22)
+{
+    const double x2 = fma(br, br, bi * bi);
+    const bool bz = (x2 == 0.0);
+    const double rx = bz ? 0.0 : rsqrt_nr(x2);
+    const double x = x2 * rx;
+    const double er = bz ? 1.0 : br * rx, ei = bz ? 0.0 : bi * rx;   // e^{i zeta}
+    const double u = fma(er, ar, ei * ai), v = fma(er, ai, -ei * ar);  // e^{-i zeta} a
+    const double h = ajj - aii;
+    const double t2 = fma(-x, x, 1.0);
+    const double rt = rsqrt_nr(t2);
+    const double t = t2 * rt;
+    if (v == 0.0 && h == 0.0) {
+        const double r2 = 0.70710678118654752440;
+        const double p = r2 * rsqrt_nr(1.0 + x), q = r2 * rsqrt_nr(1.0 - x);
+        z11 = p;
+        z21r = er * p;
+        z21i = -ei * p;
+        z12r = -er * q;
+        z12i = -ei * q;
+        z22 = q;
+        return;
+    }
+    const double tau = (h < 0.0) ? -1.0 : 1.0;
+    const double h2 = h * h, v4 = 4.0 * v * v;
+    const double R2 = h2 + v4;
+    const double rR = rsqrt_nr(R2);
+    const double cg = (R2 == h2) ? 1.0 : fabs(h) * rR;
+    const double sg = tau * 2.0 * v * rR;
+    const double P = tau * fma(-(aii + ajj), x, 2.0 * u);
+    const double Q2 = t2 * R2;
+    const double PQ = fma(P, P, Q2);
+    const double rPQ = rsqrt_nr(PQ);
+    const double c2 = (PQ == Q2) ? 1.0 : sqrt_nr(Q2) * rPQ;
+    const double s2 = P * rPQ;
+    const double tcc = t * cg * c2;
+    const double cphi = sqrt_nr(0.5 * (fma(x, s2, 1.0) + tcc));
+    const double cpsi = sqrt_nr(0.5 * (fma(-x, s2, 1.0) + tcc));
+    const double im = t * sg * c2;
+    const double dpsi = div_nr(rt, 2.0 * cpsi), dphi = div_nr(rt, 2.0 * cphi);
+    // e^{i zeta} ((s2 - x) + i im) / (2 cos psi) / t
+    const double ar_ = s2 - x, br_ = s2 + x;
+    z12r = (er * ar_ - ei * im) * dpsi;
+    z12i = (er * im + ei * ar_) * dpsi;
+    // -e^{-i zeta} ((s2 + x) - i im) / (2 cos phi) / t
+    z21r = -(er * br_ - ei * im) * dphi;
+    z21i = -(-er * im - ei * br_) * dphi;
+    z11 = cphi * rt;
     z22 = cpsi * rt;
 }
 

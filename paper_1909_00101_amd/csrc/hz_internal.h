@@ -64,6 +64,19 @@ void launch_finish_real(const Plan &P, const Ptrs &W, double *F, int64_t ldf, do
                         int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
                         double *sigma_g, hipStream_t s);
 void launch_eval_2x2(int64_t count, const double *in, double *out, hipStream_t s);
+void launch_rank(const Plan &P, const Ptrs &W, hipStream_t s);
+
+// launchers (complex128), hz_cplx.hip; matrices are interleaved complex
+void launch_prescale_cplx(const Plan &P, const Ptrs &W, const double *F, int64_t ldf,
+                          const double *G, int64_t ldg, hipStream_t s);
+void launch_step_cplx(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
+                      hipStream_t s);
+void launch_finish_cplx(const Plan &P, const Ptrs &W, double *F, int64_t ldf, double *G,
+                        int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
+                        double *sigma_g, hipStream_t s);
+void launch_n1_cplx(int64_t mf, int64_t mg, double *F, double *G, double *Z, double *sigma,
+                    double *sigma_f, double *sigma_g, int *status, hipStream_t s);
+void launch_eval_2x2_cplx(int64_t count, const double *in, double *out, hipStream_t s);
 void launch_n1_real(int64_t mf, int64_t mg, double *F, double *G, double *Z, double *sigma,
                     double *sigma_f, double *sigma_g, int *status, hipStream_t s);
 

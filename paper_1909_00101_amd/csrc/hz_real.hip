@@ -185,14 +185,6 @@ __global__ __launch_bounds__(256) void k_gram_sum(const double *__restrict__ par
 //  5. Z_tilde = Z_hat Theta, Theta_jj = (||f_hat_j||^2+||g_hat_j||^2)^-1/2.
 // Counters per (step, pair): transformations, big ones, inner sweeps run.
 // ------------------------------------------------------------------------
-__device__ __forceinline__ double readlane_d(double v, int l)
-{
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_readlane((int)b, l);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-
 template <int W2, int LP>
 __global__ __launch_bounds__((W2 / 2) * LP) void k_inner(
     const double *__restrict__ gram, int npairs, int step,
@@ -719,6 +711,12 @@ void launch_step_real(const Plan &P, const Ptrs &W, int step, const hz_params &p
     }
 }
 
+void launch_rank(const Plan &P, const Ptrs &W, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rank, dim3((unsigned)((P.nw + 255) / 256)), dim3(256), 0, s, W.sig,
+                       W.border, P.nw, W.rank);
+}
+
 void launch_finish_real(const Plan &P, const Ptrs &W, double *F, int64_t ldf, double *G,
                         int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
                         double *sigma_g, hipStream_t s)
@@ -726,8 +724,7 @@ void launch_finish_real(const Plan &P, const Ptrs &W, double *F, int64_t ldf, do
     const unsigned nb4 = (unsigned)((P.nw + 3) / 4);
     hipLaunchKernelGGL(k_colnorms, dim3(nb4), dim3(256), 0, s, W.Fw, W.Gw, W.Zw, P.mfw, P.mgw,
                        P.nzw, P.n, P.nw, W.sf, W.sg, W.sig, W.border, W.status);
-    hipLaunchKernelGGL(k_rank, dim3((unsigned)((P.nw + 255) / 256)), dim3(256), 0, s, W.sig,
-                       W.border, P.nw, W.rank);
+    launch_rank(P, W, s);
     hipLaunchKernelGGL(k_scatter, dim3(nb4), dim3(256), 0, s, W.Fw, W.Gw, W.Zw, P.mfw, P.mgw,
                        P.nzw, P.mf, P.mg, P.n, P.nw, W.sf, W.sg, W.rank, F, ldf, G, ldg, Z, ldz,
                        sigma, sigma_f, sigma_g);
