@@ -114,6 +114,7 @@ void hz_default_params(hz_params *p);
  * the shape or the parameters are invalid). */
 size_t hz_dgsvd_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n);
 size_t hz_zgsvd_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n);
+size_t hz_dgsvd_mixed_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n);
 
 /* Real FP64 GSVD (variant 0, Sections 2-3).  Arguments in order:
  *  1 p (host, may be NULL = defaults), 2 m_f, 3 m_g, 4 n,
@@ -178,6 +179,24 @@ int hz_zgsvd(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n,
              double *F, int64_t ldf, double *G, int64_t ldg, double *Z, int64_t ldz,
              double *sigma, double *sigma_f, double *sigma_g,
              void *work, size_t work_bytes, hz_info *info, void *stream);
+
+/* Mixed-precision real GSVD.  Early sweeps run on FP32 copies of the
+ * prescaled pair (FP32 MFMA Gram blocks with FP32 accumulation, widened to
+ * FP64; FP32 MFMA block updates with Z_tilde rounded to FP32); Cholesky, the
+ * inner Hari-Zimmermann solve, the convergence counters and Theta stay in
+ * FP64.  After the FP32 sweep whose largest scaled off-diagonal Gram entry
+ * |a_pq|/sqrt(a_pp a_qq) (over A_hat and B_hat) is below p->mixed_switch,
+ * or one without big transformations, or after p->max_fp32_sweeps, the
+ * iteration restarts in FP64 from F Z32, G Z32 (FP64 MFMA GEMMs with the
+ * original F, G; every iterate satisfies F_k = F Z_k, Section 2.1) and
+ * FP64 sweeps run to the FP64 stopping rule.  Arguments and status codes
+ * as hz_dgsvd; F and G are read again for the restart and only overwritten
+ * by U and V at the end; info->sweeps_fp32 and info->last_offdiag report
+ * the FP32 phase. */
+int hz_dgsvd_mixed(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n,
+                   double *F, int64_t ldf, double *G, int64_t ldg, double *Z, int64_t ldz,
+                   double *sigma, double *sigma_f, double *sigma_g,
+                   void *work, size_t work_bytes, hz_info *info, void *stream);
 
 /* Short English description of a status code. */
 const char *hz_strerror(int status);

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libhzgsvd.so")
 CSRC = os.path.join(_HERE, "csrc")
-SOURCES = ["hz_api.hip", "hz_real.hip", "hz_cplx.hip"]
+SOURCES = ["hz_api.hip", "hz_real.hip", "hz_cplx.hip", "hz_mixed.hip"]
 
 HZ_OK, HZ_ENOCONV, HZ_ECHOL, HZ_ENONFINITE, HZ_EHIP = 0, 1, 2, 3, 4
 HZ_ORD_MM, HZ_ORD_RR = 1, 2
@@ -95,6 +95,10 @@ def lib():
         L.hz_zgsvd.restype = ctypes.c_int
         L.hz_zgsvd_work_size.argtypes = L.hz_dgsvd_work_size.argtypes
         L.hz_zgsvd_work_size.restype = ctypes.c_size_t
+        L.hz_dgsvd_mixed.argtypes = L.hz_dgsvd.argtypes
+        L.hz_dgsvd_mixed.restype = ctypes.c_int
+        L.hz_dgsvd_mixed_work_size.argtypes = L.hz_dgsvd_work_size.argtypes
+        L.hz_dgsvd_mixed_work_size.restype = ctypes.c_size_t
         L.hz_eval_2x2_z.argtypes = [i64, vp, vp, vp]
         L.hz_eval_2x2_z.restype = ctypes.c_int
         L.hz_strerror.argtypes = [ctypes.c_int]
@@ -164,7 +168,7 @@ class GsvdError(RuntimeError):
         self.info = info
 
 
-def gsvd(F, G, *, overwrite=False, raise_on_noconv=False, workspace=None, **kw):
+def gsvd(F, G, *, overwrite=False, raise_on_noconv=False, workspace=None, mixed=False, **kw):
     """GSVD of (F, G) on the GPU.
 
     F (m_F x n) and G (m_G x n) are float64 or complex128 CUDA tensors
@@ -173,7 +177,8 @@ def gsvd(F, G, *, overwrite=False, raise_on_noconv=False, workspace=None, **kw):
     and the inputs are already column-major), Z, sigma, sigma_f, sigma_g
     (descending in sigma), the hz_info fields and the status code.
     Keyword arguments set hz_params fields (w, ordering, inner_max_sweeps,
-    max_sweeps, tol, sort, ...).
+    max_sweeps, tol, sort, ...).  ``mixed=True`` selects the mixed-precision
+    real solver (hz_dgsvd_mixed).
     """
     import torch
     L = lib()
@@ -194,7 +199,11 @@ def gsvd(F, G, *, overwrite=False, raise_on_noconv=False, workspace=None, **kw):
     sf = torch.empty_like(sig)
     sg = torch.empty_like(sig)
     p = params(**kw)
-    nbytes = (L.hz_zgsvd_work_size if cplx else L.hz_dgsvd_work_size)(ctypes.byref(p), m_f, m_g, n)
+    if mixed and cplx:
+        raise TypeError("the mixed-precision solver is real only")
+    wsz = L.hz_zgsvd_work_size if cplx else (L.hz_dgsvd_mixed_work_size if mixed
+                                             else L.hz_dgsvd_work_size)
+    nbytes = wsz(ctypes.byref(p), m_f, m_g, n)
     if nbytes == 0:
         raise ValueError("invalid shape or parameters")
     if workspace is None or workspace.numel() < nbytes:
@@ -202,7 +211,7 @@ def gsvd(F, G, *, overwrite=False, raise_on_noconv=False, workspace=None, **kw):
     wptr = (workspace.data_ptr() + 255) & ~255
     info = HzInfo()
     stream = torch.cuda.current_stream(dev).cuda_stream
-    fn = L.hz_zgsvd if cplx else L.hz_dgsvd
+    fn = L.hz_zgsvd if cplx else (L.hz_dgsvd_mixed if mixed else L.hz_dgsvd)
     st = fn(ctypes.byref(p), m_f, m_g, n, _ptr(U), _ld(U), _ptr(V), _ld(V),
                     _ptr(Z), _ld(Z), _ptr(sig), _ptr(sf), _ptr(sg), ctypes.c_void_p(wptr),
                     nbytes, ctypes.byref(info), ctypes.c_void_p(stream))
@@ -213,4 +222,5 @@ def gsvd(F, G, *, overwrite=False, raise_on_noconv=False, workspace=None, **kw):
     return dict(U=U, V=V, Z=Z, sigma=sig, sigma_f=sf, sigma_g=sg, status=st,
                 sweeps=info.sweeps, converged=bool(info.converged), w=info.w,
                 rot_total=info.rot_total, rot_big=info.rot_big,
-                inner_sweeps=info.inner_sweeps)
+                inner_sweeps=info.inner_sweeps, sweeps_fp32=info.sweeps_fp32,
+                last_offdiag=info.last_offdiag)

@@ -88,7 +88,7 @@ static int w_ok_for(const hz_params &p, int is_complex)
 }
 
 static bool make_plan(const hz_params &prm, int64_t mf, int64_t mg, int64_t n, int is_complex,
-                      Plan &P)
+                      Plan &P, int mixed = 0)
 {
     if (n < 2) return false;
     memset(&P, 0, sizeof(P));
@@ -135,6 +135,13 @@ static bool make_plan(const hz_params &prm, int64_t mf, int64_t mg, int64_t n, i
     P.o_sig = o; o = align256(o + sizeof(double) * (size_t)P.nw);
     P.o_rank = o; o = align256(o + sizeof(int) * (size_t)P.nw);
     P.o_border = o; o = align256(o + sizeof(int) * (size_t)P.nw);
+    P.mixed = mixed;
+    if (mixed) {
+        P.o_fs = o; o = align256(o + sizeof(float) * (size_t)P.mfw * P.nw);
+        P.o_gs = o; o = align256(o + sizeof(float) * (size_t)P.mgw * P.nw);
+        P.o_zs = o; o = align256(o + sizeof(float) * (size_t)P.nzw * P.nw);
+        P.o_offd = o; o = align256(o + sizeof(double) * (size_t)P.steps * P.npairs * 2);
+    }
     P.total = o;
     return true;
 }
@@ -161,6 +168,10 @@ static Ptrs make_ptrs(const Plan &P, void *work)
     W.sig = (double *)(b + P.o_sig);
     W.rank = (int *)(b + P.o_rank);
     W.border = (int *)(b + P.o_border);
+    W.Fs = P.mixed ? (float *)(b + P.o_fs) : nullptr;
+    W.Gs = P.mixed ? (float *)(b + P.o_gs) : nullptr;
+    W.Zs = P.mixed ? (float *)(b + P.o_zs) : nullptr;
+    W.offd = P.mixed ? (double *)(b + P.o_offd) : nullptr;
     return W;
 }
 
@@ -238,9 +249,11 @@ static void prof_flush()
     g_prof.kind.clear();
 }
 
-// The host sweep loop shared by the real and complex solvers.
+enum { KIND_REAL = 0, KIND_COMPLEX = 1, KIND_MIXED = 2 };
+
+// The host sweep loop shared by the real, complex and mixed solvers.
 static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t work_bytes,
-                     hz_info *info, hipStream_t st, bool complex_path, const void *F, int64_t ldf,
+                     hz_info *info, hipStream_t st, int kind, const void *F, int64_t ldf,
                      const void *G, int64_t ldg, void *U, void *V, void *Z, int64_t ldz,
                      double *sigma, double *sigma_f, double *sigma_g);
 
@@ -337,14 +350,16 @@ int hz_profile_read(double *ms, int64_t *launches, int nkinds)
 size_t hz_dgsvd_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n);
 
 
-static int solve_entry(int is_complex, const hz_params *p, int64_t m_f, int64_t m_g, int64_t n,
+static int solve_entry(int kind, const hz_params *p, int64_t m_f, int64_t m_g, int64_t n,
                        double *F, int64_t ldf, double *G, int64_t ldg, double *Z, int64_t ldz,
                        double *sigma, double *sigma_f, double *sigma_g, void *work,
                        size_t work_bytes, hz_info *info, void *stream)
 {
+    const int is_complex = (kind == KIND_COMPLEX);
     hz_params prm;
     if (p) prm = *p; else hz_default_params(&prm);
     if (!params_ok(prm) || !w_ok_for(prm, is_complex)) return -1;
+    if (kind == KIND_MIXED && (prm.max_fp32_sweeps < 0 || !(prm.mixed_switch >= 0.0))) return -1;
     const int a = check_args(m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g);
     if (a) return a;
     if (is_complex && (((uintptr_t)F | (uintptr_t)G | (uintptr_t)Z) & 15))
@@ -372,21 +387,22 @@ static int solve_entry(int is_complex, const hz_params *p, int64_t m_f, int64_t 
         return rc;
     }
     Plan P;
-    if (!make_plan(prm, m_f, m_g, n, is_complex, P)) return -4;
+    if (!make_plan(prm, m_f, m_g, n, is_complex, P, kind == KIND_MIXED)) return -4;
     if (work && work_bytes < P.total) return -15;
-    return run_solve(prm, P, work, work_bytes, info, st, is_complex != 0, F, ldf, G, ldg, F, G, Z,
-                     ldz, sigma, sigma_f, sigma_g);
+    return run_solve(prm, P, work, work_bytes, info, st, kind, F, ldf, G, ldg, F, G, Z, ldz,
+                     sigma, sigma_f, sigma_g);
 }
 
-static size_t work_size_entry(int is_complex, const hz_params *p, int64_t m_f, int64_t m_g,
+static size_t work_size_entry(int kind, const hz_params *p, int64_t m_f, int64_t m_g,
                               int64_t n)
 {
+    const int is_complex = (kind == KIND_COMPLEX);
     hz_params prm;
     if (p) prm = *p; else hz_default_params(&prm);
     if (!params_ok(prm) || !w_ok_for(prm, is_complex) || m_f < n || m_g < n || n < 1) return 0;
     if (n == 1) return 256;
     Plan P;
-    if (!make_plan(prm, m_f, m_g, n, is_complex, P)) return 0;
+    if (!make_plan(prm, m_f, m_g, n, is_complex, P, kind == KIND_MIXED)) return 0;
     return P.total;
 }
 
@@ -394,26 +410,40 @@ int hz_dgsvd(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, double *F,
              double *G, int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
              double *sigma_g, void *work, size_t work_bytes, hz_info *info, void *stream)
 {
-    return solve_entry(0, p, m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g, work,
-                       work_bytes, info, stream);
+    return solve_entry(KIND_REAL, p, m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f,
+                       sigma_g, work, work_bytes, info, stream);
+}
+
+int hz_dgsvd_mixed(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, double *F,
+                   int64_t ldf, double *G, int64_t ldg, double *Z, int64_t ldz, double *sigma,
+                   double *sigma_f, double *sigma_g, void *work, size_t work_bytes, hz_info *info,
+                   void *stream)
+{
+    return solve_entry(KIND_MIXED, p, m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f,
+                       sigma_g, work, work_bytes, info, stream);
 }
 
 int hz_zgsvd(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, double *F, int64_t ldf,
              double *G, int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
              double *sigma_g, void *work, size_t work_bytes, hz_info *info, void *stream)
 {
-    return solve_entry(1, p, m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g, work,
-                       work_bytes, info, stream);
+    return solve_entry(KIND_COMPLEX, p, m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f,
+                       sigma_g, work, work_bytes, info, stream);
 }
 
 size_t hz_zgsvd_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n)
 {
-    return work_size_entry(1, p, m_f, m_g, n);
+    return work_size_entry(KIND_COMPLEX, p, m_f, m_g, n);
+}
+
+size_t hz_dgsvd_mixed_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n)
+{
+    return work_size_entry(KIND_MIXED, p, m_f, m_g, n);
 }
 
 size_t hz_dgsvd_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n)
 {
-    return work_size_entry(0, p, m_f, m_g, n);
+    return work_size_entry(KIND_REAL, p, m_f, m_g, n);
 }
 
 int hz_eval_2x2_z(int64_t count, const double *in, double *out, void *stream)
@@ -431,7 +461,7 @@ int hz_eval_2x2_z(int64_t count, const double *in, double *out, void *stream)
 namespace hz {
 
 static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t work_bytes,
-                     hz_info *info, hipStream_t st, bool complex_path, const void *F, int64_t ldf,
+                     hz_info *info, hipStream_t st, int kind, const void *F, int64_t ldf,
                      const void *G, int64_t ldg, void *U, void *V, void *Z, int64_t ldz,
                      double *sigma, double *sigma_f, double *sigma_g)
 {
@@ -447,7 +477,7 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
         unsigned long long *dphase = nullptr;
         std::vector<unsigned long long> hph;
         double clk_khz = 0.0;
-        if (g_prof.on && g_prof.phases) {
+        if (g_prof.on && g_prof.phases && kind != KIND_COMPLEX) {
             const size_t nph = (size_t)P.steps * P.npairs * 8;
             if (hipMalloc(&dphase, nph * sizeof(unsigned long long)) == hipSuccess) {
                 W.phase = dphase;
@@ -464,41 +494,60 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
         build_ordering<int>(prm.ordering, P.nblk, otab);
         build_ordering<int16_t>(prm.inner_ordering, P.W2, itab);
         std::vector<unsigned long long> hc((size_t)P.steps * P.npairs * 4);
+        std::vector<double> hoff;
         int hs[ST_NSLOTS] = {0, INT_MAX, 0, 0};
         uint64_t tot_all = 0, tot_big = 0, tot_isw = 0;
-        int sweeps = 0, converged = 0;
+        int sweeps = 0, sweeps32 = 0, converged = 0;
+        double last_off = 0.0;
         HZ_CHECK(hipMemcpyAsync(W.otab, otab.data(), otab.size() * sizeof(int),
                                 hipMemcpyHostToDevice, st));
         HZ_CHECK(hipMemcpyAsync(W.itab, itab.data(), itab.size() * sizeof(int16_t),
                                 hipMemcpyHostToDevice, st));
         HZ_CHECK(hipMemcpyAsync(W.status, hs, sizeof(hs), hipMemcpyHostToDevice, st));
-        if (complex_path)
+        if (kind == KIND_COMPLEX)
             launch_prescale_cplx(P, W, (const double *)F, ldf, (const double *)G, ldg, st);
+        else if (kind == KIND_MIXED)
+            launch_prescale_mixed(P, W, (const double *)F, ldf, (const double *)G, ldg, st);
         else
             launch_prescale_real(P, W, (const double *)F, ldf, (const double *)G, ldg, st);
         HZ_CHECK(hipGetLastError());
-        for (int sw = 0; sw < prm.max_sweeps; ++sw) {
+
+        // One outer sweep: all block steps, then the counters (and the
+        // off-diagonal measure of an FP32 sweep) read back once (Algorithm 1).
+        auto sweep = [&](bool fp32, uint64_t &s_all, uint64_t &s_big) -> hipError_t {
             for (int k = 0; k < P.steps; ++k) {
-                if (complex_path) launch_step_cplx(P, W, k, prm, tol, st);
+                if (fp32) launch_step_mixed32(P, W, k, prm, tol, st);
+                else if (kind == KIND_COMPLEX) launch_step_cplx(P, W, k, prm, tol, st);
                 else launch_step_real(P, W, k, prm, tol, st);
             }
-            HZ_CHECK(hipGetLastError());
-            HZ_CHECK(hipMemcpyAsync(hc.data(), W.cnt, hc.size() * sizeof(unsigned long long),
-                                    hipMemcpyDeviceToHost, st));
-            HZ_CHECK(hipMemcpyAsync(hs, W.status, sizeof(hs), hipMemcpyDeviceToHost, st));
-            if (dphase) HZ_CHECK(hipMemcpyAsync(hph.data(), dphase, hph.size() * 8,
-                                                hipMemcpyDeviceToHost, st));
-            HZ_CHECK(hipStreamSynchronize(st));
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            e = hipMemcpyAsync(hc.data(), W.cnt, hc.size() * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, st);
+            if (e != hipSuccess) return e;
+            e = hipMemcpyAsync(hs, W.status, sizeof(hs), hipMemcpyDeviceToHost, st);
+            if (e != hipSuccess) return e;
+            if (fp32) {
+                hoff.resize((size_t)P.steps * P.npairs * 2);
+                e = hipMemcpyAsync(hoff.data(), W.offd, hoff.size() * sizeof(double),
+                                   hipMemcpyDeviceToHost, st);
+                if (e != hipSuccess) return e;
+            }
+            if (dphase) {
+                e = hipMemcpyAsync(hph.data(), dphase, hph.size() * 8, hipMemcpyDeviceToHost, st);
+                if (e != hipSuccess) return e;
+            }
+            e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return e;
             prof_flush();
             if (dphase && clk_khz > 0) {
                 for (size_t i = 0; i < hph.size(); i += 8) {
-                    for (int k = 0; k < 5; ++k)
-                        g_prof.phase_us[k] += (double)(hph[i + k + 1] - hph[i + k]) / clk_khz * 1e3;
+                    for (int q = 0; q < 5; ++q)
+                        g_prof.phase_us[q] += (double)(hph[i + q + 1] - hph[i + q]) / clk_khz * 1e3;
                     g_prof.phase_n += 1;
                 }
             }
-            ++sweeps;
-            uint64_t s_all = 0, s_big = 0;
+            s_all = s_big = 0;
             for (size_t i = 0; i < hc.size(); i += 4) {
                 s_all += hc[i];
                 s_big += hc[i + 1];
@@ -506,14 +555,41 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
             }
             tot_all += s_all;
             tot_big += s_big;
-            if (hs[ST_FLAGS]) break;
-            if (s_big == 0) {
-                converged = 1;
-                break;
+            return hipSuccess;
+        };
+
+        if (kind == KIND_MIXED) {
+            // FP32 sweeps until the largest scaled off-diagonal Gram entry of a
+            // sweep is below mixed_switch, a sweep has no big transformation, or
+            // max_fp32_sweeps have run; then restart in FP64 from F Z32, G Z32.
+            for (int sw = 0; sw < prm.max_fp32_sweeps; ++sw) {
+                uint64_t s_all, s_big;
+                HZ_CHECK(sweep(true, s_all, s_big));
+                ++sweeps32;
+                last_off = 0.0;
+                for (double v : hoff) last_off = (v > last_off) ? v : last_off;
+                if (hs[ST_FLAGS]) break;
+                if (s_big == 0 || last_off < prm.mixed_switch) break;
+            }
+            if (!hs[ST_FLAGS]) {
+                launch_restart_mixed(P, W, (const double *)F, ldf, (const double *)G, ldg, st);
+                HZ_CHECK(hipGetLastError());
+            }
+        }
+        if (!hs[ST_FLAGS]) {
+            for (int sw = 0; sw < prm.max_sweeps; ++sw) {
+                uint64_t s_all, s_big;
+                HZ_CHECK(sweep(false, s_all, s_big));
+                ++sweeps;
+                if (hs[ST_FLAGS]) break;
+                if (s_big == 0) {
+                    converged = 1;
+                    break;
+                }
             }
         }
         if (!(hs[ST_FLAGS] & FLAG_CHOL)) {
-            if (complex_path)
+            if (kind == KIND_COMPLEX)
                 launch_finish_cplx(P, W, (double *)U, ldf, (double *)V, ldg, (double *)Z, ldz,
                                    sigma, sigma_f, sigma_g, st);
             else
@@ -528,12 +604,14 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
         else if (!converged) rc = HZ_ENOCONV;
         if (info) {
             info->sweeps = sweeps;
+            info->sweeps_fp32 = sweeps32;
             info->converged = converged;
             info->w = P.w;
             info->failed_pair = (hs[ST_FLAGS] & FLAG_CHOL) ? hs[ST_FAILPAIR] : -1;
             info->rot_total = tot_all;
             info->rot_big = tot_big;
             info->inner_sweeps = tot_isw;
+            info->last_offdiag = last_off;
         }
         if (dphase) {
             (void)hipStreamSynchronize(st);

@@ -28,7 +28,10 @@ struct Plan {
     size_t esz;               // bytes per matrix element (8 or 16)
     // workspace offsets (bytes)
     size_t o_fw, o_gw, o_zw, o_part, o_gram, o_arrive, o_zt, o_otab, o_itab, o_cnt, o_status;
-    size_t o_sf, o_sg, o_sig, o_rank, o_border, total;
+    size_t o_sf, o_sg, o_sig, o_rank, o_border;
+    size_t o_fs, o_gs, o_zs, o_offd;   // mixed form only (FP32 copies, off-diagonal measure)
+    int mixed;
+    size_t total;
 };
 
 struct Ptrs {
@@ -42,6 +45,8 @@ struct Ptrs {
     int *status;
     double *sf, *sg, *sig;
     int *rank, *border;
+    float *Fs, *Gs, *Zs;         // mixed form: FP32 working copies
+    double *offd;                // mixed form: per (step, pair, matrix) off-diagonal measure
 };
 
 // status[] slots written by kernels (integer atomics only)
@@ -65,6 +70,17 @@ void launch_finish_real(const Plan &P, const Ptrs &W, double *F, int64_t ldf, do
                         double *sigma_g, hipStream_t s);
 void launch_eval_2x2(int64_t count, const double *in, double *out, hipStream_t s);
 void launch_rank(const Plan &P, const Ptrs &W, hipStream_t s);
+void launch_gram_sum(const Plan &P, const Ptrs &W, hipStream_t s);
+void launch_inner_real(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
+                       hipStream_t s);
+
+// launchers (mixed precision), hz_mixed.hip
+void launch_prescale_mixed(const Plan &P, const Ptrs &W, const double *F, int64_t ldf,
+                           const double *G, int64_t ldg, hipStream_t s);
+void launch_step_mixed32(const Plan &P, const Ptrs &W, int step, const hz_params &prm,
+                         double tol, hipStream_t s);
+void launch_restart_mixed(const Plan &P, const Ptrs &W, const double *F, int64_t ldf,
+                          const double *G, int64_t ldg, hipStream_t s);
 
 // launchers (complex128), hz_cplx.hip; matrices are interleaved complex
 void launch_prescale_cplx(const Plan &P, const Ptrs &W, const double *F, int64_t ldf,

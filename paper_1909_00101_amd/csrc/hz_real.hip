@@ -664,21 +664,13 @@ void launch_prescale_real(const Plan &P, const Ptrs &W, const double *F, int64_t
 }
 
 template <int W2>
-static void step_impl(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
-                      hipStream_t s)
+static void inner_impl(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
+                       hipStream_t s)
 {
-    const int *pairs = W.otab + (size_t)step * P.npairs * 2;
-    prof_mark(K_GRAM, true, s);
-    hipLaunchKernelGGL(k_gram<W2>, dim3(P.splits, P.npairs, 2), dim3(256), 0, s, W.Fw, W.Gw,
-                       P.mfw, P.mgw, pairs, P.splits, W.part);
-    hipLaunchKernelGGL(k_gram_sum<W2>, dim3((W2 * W2 + 511) / 512, 2 * P.npairs), dim3(256), 0,
-                       s, W.part, P.splits, W.gram);
-    prof_mark(K_GRAM, false, s);
-    prof_mark(K_INNER, true, s);
     if constexpr (W2 == 16) {
         hipLaunchKernelGGL((k_inner<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s, W.gram,
-                           P.npairs, step, W.itab, P.isteps, prm.inner_max_sweeps, tol,
-                           prm.sort, W.Zt, W.cnt, W.status, W.phase);
+                           P.npairs, step, W.itab, P.isteps, prm.inner_max_sweeps, tol, prm.sort,
+                           W.Zt, W.cnt, W.status, W.phase);
     } else {
         if (P.inner_lp == 8)
             hipLaunchKernelGGL((k_inner<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s,
@@ -691,6 +683,49 @@ static void step_impl(const Plan &P, const Ptrs &W, int step, const hz_params &p
                                prm.inner_max_sweeps, tol, prm.sort, W.Zt, W.cnt, W.status,
                                W.phase);
     }
+}
+
+void launch_inner_real(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
+                       hipStream_t s)
+{
+    switch (P.W2) {
+    case 16: inner_impl<16>(P, W, step, prm, tol, s); break;
+    case 32: inner_impl<32>(P, W, step, prm, tol, s); break;
+    default: inner_impl<64>(P, W, step, prm, tol, s); break;
+    }
+}
+
+void launch_gram_sum(const Plan &P, const Ptrs &W, hipStream_t s)
+{
+    const int W2 = P.W2;
+    switch (W2) {
+    case 16:
+        hipLaunchKernelGGL(k_gram_sum<16>, dim3(1, 2 * P.npairs), dim3(256), 0, s, W.part,
+                           P.splits, W.gram);
+        break;
+    case 32:
+        hipLaunchKernelGGL(k_gram_sum<32>, dim3(2, 2 * P.npairs), dim3(256), 0, s, W.part,
+                           P.splits, W.gram);
+        break;
+    default:
+        hipLaunchKernelGGL(k_gram_sum<64>, dim3(8, 2 * P.npairs), dim3(256), 0, s, W.part,
+                           P.splits, W.gram);
+        break;
+    }
+}
+
+template <int W2>
+static void step_impl(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
+                      hipStream_t s)
+{
+    const int *pairs = W.otab + (size_t)step * P.npairs * 2;
+    prof_mark(K_GRAM, true, s);
+    hipLaunchKernelGGL(k_gram<W2>, dim3(P.splits, P.npairs, 2), dim3(256), 0, s, W.Fw, W.Gw,
+                       P.mfw, P.mgw, pairs, P.splits, W.part);
+    launch_gram_sum(P, W, s);
+    prof_mark(K_GRAM, false, s);
+    prof_mark(K_INNER, true, s);
+    inner_impl<W2>(P, W, step, prm, tol, s);
     prof_mark(K_INNER, false, s);
     const int64_t rpt = 4 * (int64_t)P.upd_rows;
     const int tf = (int)((P.mfw + rpt - 1) / rpt), tg = (int)((P.mgw + rpt - 1) / rpt),

@@ -1,0 +1,81 @@
+"""GPU parity of the mixed-precision real form (hz_dgsvd_mixed): FP32 sweeps
+then an FP64 restart from F Z32, G Z32 and FP64 sweeps.  Bar: the same as the
+FP64 solver -- sigma within 1e-10 relative of the oracle's and the output
+contract -- i.e. equal final accuracy."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import gsvd_inputs as gi
+from contract import assert_contract, max_rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+SIG_TOL = 1e-10
+
+
+def _run(F, G, **kw):
+    import paper_1909_00101_amd as hz
+    dF = torch.from_numpy(np.asfortranarray(F)).cuda()
+    dG = torch.from_numpy(np.asfortranarray(G)).cuda()
+    r = hz.gsvd(dF, dG, **kw)
+    torch.cuda.synchronize()
+    return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in r.items()}
+
+
+@pytest.mark.parametrize("shape", [(100, 90, 48, 8), (130, 129, 37, 8), (400, 300, 160, 16),
+                                   (700, 600, 256, 32)], ids=lambda s: "x".join(map(str, s)))
+def test_mixed_parity(shape):
+    import oracle
+    m_f, m_g, n, w = shape
+    F, G, s_true = gi.custom_pair(m_f, m_g, n, kappa=1e2, seed=n + 11)
+    o = oracle.gsvd(F, G, ordering=1, threads=4)
+    r = _run(F, G, w=w, mixed=True, tol=n * EPS)
+    err = max_rel(r["sigma"], o["sigma"])
+    print(f"{shape}: fp32 sweeps={r['sweeps_fp32']} off={r['last_offdiag']:.1e} "
+          f"fp64 sweeps={r['sweeps']} err={err:.2e}")
+    assert r["status"] == 0 and r["sweeps_fp32"] >= 1
+    assert err < SIG_TOL
+    assert max_rel(r["sigma"], s_true) < 1e-11
+    assert_contract(F, G, r["U"], r["V"], r["Z"], r["sigma_f"], r["sigma_g"], r["sigma"],
+                    tol_res=1e-12, tol_orth=1e-12)
+
+
+def test_mixed_matches_plain():
+    F, G, _ = gi.custom_pair(1024, 768, 256, kappa=1e2, seed=31)
+    a = _run(F, G, w=16, tol=256 * EPS)
+    b = _run(F, G, w=16, tol=256 * EPS, mixed=True)
+    assert a["status"] == 0 and b["status"] == 0
+    assert max_rel(b["sigma"], a["sigma"]) < SIG_TOL
+
+
+def test_mixed_zero_fp32_sweeps_is_plain_fp64():
+    # With no FP32 sweep the restart uses Z32 = fl32(prescale), still exact
+    # FP64 data F Z32, G Z32; the FP64 sweeps must reach the same sigma.
+    import oracle
+    F, G, _ = gi.custom_pair(200, 150, 64, seed=33)
+    o = oracle.gsvd(F, G)
+    r = _run(F, G, w=8, mixed=True, max_fp32_sweeps=0)
+    assert r["status"] == 0 and r["sweeps_fp32"] == 0
+    assert max_rel(r["sigma"], o["sigma"]) < SIG_TOL
+
+
+def test_config4_mixed_vs_oracle_golden():
+    """The 8192x2048 mixed-precision workload against the oracle's sigma for
+    the same seeded pair (tests/golden/oracle_config4.json), and the plain
+    FP64 solver on the same pair reaching the same accuracy."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_config4.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle golden for the 8192x2048 pair not generated")
+    gold = np.array(json.load(open(path))["sigma"])
+    F, G, s_true = gi.config_pair(4)
+    tol = 2048 * EPS
+    rm = _run(F, G, w=32, mixed=True, tol=tol, inner_max_sweeps=1)
+    em = max_rel(rm["sigma"], gold)
+    print(f"config4 mixed: fp32 sweeps={rm['sweeps_fp32']} fp64 sweeps={rm['sweeps']} err={em:.2e}")
+    assert rm["status"] == 0 and em < SIG_TOL
