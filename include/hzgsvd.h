@@ -105,6 +105,7 @@ typedef struct hz_info {
     uint64_t rot_big;     /* big transformations among them */
     double last_offdiag;  /* mixed form: off-diagonal measure of the last FP32 sweep */
     uint64_t inner_sweeps;/* inner sweeps run, summed over all block steps */
+    int status;           /* this solve's status code (per pair in the batched form) */
 } hz_info;
 
 /* Fill *p with the defaults listed above. */
@@ -197,6 +198,37 @@ int hz_dgsvd_mixed(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n,
                    double *F, int64_t ldf, double *G, int64_t ldg, double *Z, int64_t ldz,
                    double *sigma, double *sigma_f, double *sigma_g,
                    void *work, size_t work_bytes, hz_info *info, void *stream);
+
+/* Batched real FP64 GSVD of `batch` independent pairs of uneven sizes
+ * (pair i: F_i m_f[i] x n[i], G_i m_g[i] x n[i]).  Every block step of the
+ * sweep is one launch over the pivot block pairs of all pairs still
+ * iterating, largest pairs first; each pair stops after its own sweep
+ * without big transformations (Section 2.5 stopping rule, per pair),
+ * decided on the device, so the host reads back one count per sweep.
+ * One sweep is captured once as a hipGraph and replayed (direct launches
+ * when the profiler is on).  All pairs share the block width w (0 = 8 if
+ * every n <= 32, else 16).  Arguments in order:
+ *  1 p (host, may be NULL),  2 batch (0..65535),
+ *  3 m_f, 4 m_g, 5 n (host arrays of batch sizes, same rules as hz_dgsvd),
+ *  6 F (host array of batch device pointers, overwritten by U_i), 7 ldf,
+ *  8 G (likewise, overwritten by V_i), 9 ldg, 10 Z (device outputs), 11 ldz,
+ * 12 sigma, 13 sigma_f, 14 sigma_g (host arrays of device outputs),
+ * 15 work (device or NULL, 256-byte aligned), 16 work_bytes,
+ * 17 infos (host array of batch hz_info or NULL; infos[i].status is pair
+ *    i's own status), 18 stream.
+ * Returns the most severe per-pair status (HZ_ENONFINITE, then HZ_ECHOL,
+ * then HZ_ENOCONV), HZ_OK when every pair converged, or -(argument index)
+ * for a bad argument (the first offending pair's). */
+int hz_dgsvd_batched(const hz_params *p, int batch, const int64_t *m_f, const int64_t *m_g,
+                     const int64_t *n, double *const *F, const int64_t *ldf,
+                     double *const *G, const int64_t *ldg, double *const *Z,
+                     const int64_t *ldz, double *const *sigma, double *const *sigma_f,
+                     double *const *sigma_g, void *work, size_t work_bytes, hz_info *infos,
+                     void *stream);
+
+/* Workspace bytes hz_dgsvd_batched needs for these sizes (0 if invalid). */
+size_t hz_dgsvd_batched_work_size(const hz_params *p, int batch, const int64_t *m_f,
+                                  const int64_t *m_g, const int64_t *n);
 
 /* Short English description of a status code. */
 const char *hz_strerror(int status);

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libhzgsvd.so")
 CSRC = os.path.join(_HERE, "csrc")
-SOURCES = ["hz_api.hip", "hz_real.hip", "hz_cplx.hip", "hz_mixed.hip"]
+SOURCES = ["hz_api.hip", "hz_real.hip", "hz_cplx.hip", "hz_mixed.hip", "hz_batched.hip"]
 
 HZ_OK, HZ_ENOCONV, HZ_ECHOL, HZ_ENONFINITE, HZ_EHIP = 0, 1, 2, 3, 4
 HZ_ORD_MM, HZ_ORD_RR = 1, 2
@@ -70,7 +70,7 @@ class HzInfo(ctypes.Structure):
                 ("converged", ctypes.c_int), ("w", ctypes.c_int),
                 ("failed_pair", ctypes.c_int64), ("rot_total", ctypes.c_uint64),
                 ("rot_big", ctypes.c_uint64), ("last_offdiag", ctypes.c_double),
-                ("inner_sweeps", ctypes.c_uint64)]
+                ("inner_sweeps", ctypes.c_uint64), ("status", ctypes.c_int)]
 
 
 _lib = None
@@ -114,6 +114,14 @@ def lib():
         L.hz_profile_read.restype = ctypes.c_int
         L.hz_profile_read_phases.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int]
         L.hz_profile_read_phases.restype = ctypes.c_int
+        pa = ctypes.POINTER(ctypes.c_int64)
+        L.hz_dgsvd_batched_work_size.argtypes = [ctypes.POINTER(HzParams), ctypes.c_int, pa, pa, pa]
+        L.hz_dgsvd_batched_work_size.restype = ctypes.c_size_t
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        L.hz_dgsvd_batched.argtypes = [ctypes.POINTER(HzParams), ctypes.c_int, pa, pa, pa,
+                                       pp, pa, pp, pa, pp, pa, pp, pp, pp, vp, ctypes.c_size_t,
+                                       ctypes.POINTER(HzInfo), vp]
+        L.hz_dgsvd_batched.restype = ctypes.c_int
         L.hz_version.argtypes = []
         L.hz_version.restype = ctypes.c_char_p
         _lib = L
@@ -224,3 +232,72 @@ def gsvd(F, G, *, overwrite=False, raise_on_noconv=False, workspace=None, mixed=
                 rot_total=info.rot_total, rot_big=info.rot_big,
                 inner_sweeps=info.inner_sweeps, sweeps_fp32=info.sweeps_fp32,
                 last_offdiag=info.last_offdiag)
+
+
+def _i64s(vals):
+    return (ctypes.c_int64 * len(vals))(*vals)
+
+
+def _ptrs(ts):
+    return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+
+def gsvd_batched(pairs, *, overwrite=False, workspace=None, **kw):
+    """Batched GSVD of independent real pairs [(F_i, G_i), ...] of any sizes
+    (float64 CUDA tensors on one device) with one call of hz_dgsvd_batched.
+    Returns (status, [dict per pair]) where each dict holds U, V, Z, sigma,
+    sigma_f, sigma_g and the pair's hz_info fields, including its own
+    status.  Keyword arguments set hz_params fields."""
+    import torch
+    L = lib()
+    batch = len(pairs)
+    if batch == 0:
+        return HZ_OK, []
+    Us, Vs, Zs, sg_, sfs, sgs = [], [], [], [], [], []
+    dev = pairs[0][0].device
+    for F, G in pairs:
+        if F.dtype != torch.float64 or G.dtype != torch.float64:
+            raise TypeError("the batched solver takes float64 pairs")
+        if not (F.is_cuda and G.is_cuda) or F.device != dev or G.device != dev:
+            raise ValueError("all pairs must be CUDA (HIP) tensors on one device")
+        U = _colmajor(F) if overwrite else F.t().contiguous().t().clone() \
+            if F.t().is_contiguous() else _colmajor(F)
+        V = _colmajor(G) if overwrite else G.t().contiguous().t().clone() \
+            if G.t().is_contiguous() else _colmajor(G)
+        n = U.shape[1]
+        Us.append(U)
+        Vs.append(V)
+        Zs.append(torch.empty((n, n), dtype=torch.float64, device=dev).t())
+        sg_.append(torch.empty(n, dtype=torch.float64, device=dev))
+        sfs.append(torch.empty(n, dtype=torch.float64, device=dev))
+        sgs.append(torch.empty(n, dtype=torch.float64, device=dev))
+    mf = _i64s([u.shape[0] for u in Us])
+    mg = _i64s([v.shape[0] for v in Vs])
+    nn = _i64s([u.shape[1] for u in Us])
+    p = params(**kw)
+    nbytes = L.hz_dgsvd_batched_work_size(ctypes.byref(p), batch, mf, mg, nn)
+    if nbytes == 0:
+        raise ValueError("invalid shapes or parameters")
+    if workspace is None or workspace.numel() < nbytes + 256:
+        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    wptr = (workspace.data_ptr() + 255) & ~255
+    infos = (HzInfo * batch)()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    st = L.hz_dgsvd_batched(ctypes.byref(p), batch, mf, mg, nn,
+                            _ptrs(Us), _i64s([_ld(u) for u in Us]),
+                            _ptrs(Vs), _i64s([_ld(v) for v in Vs]),
+                            _ptrs(Zs), _i64s([_ld(z) for z in Zs]),
+                            _ptrs(sg_), _ptrs(sfs), _ptrs(sgs), ctypes.c_void_p(wptr), nbytes,
+                            infos, ctypes.c_void_p(stream))
+    if st < 0:
+        raise ValueError(f"hz_dgsvd_batched rejected argument {-st}")
+    if st == HZ_EHIP:
+        raise GsvdError(st, None)
+    out = []
+    for i in range(batch):
+        f = infos[i]
+        out.append(dict(U=Us[i], V=Vs[i], Z=Zs[i], sigma=sg_[i], sigma_f=sfs[i],
+                        sigma_g=sgs[i], status=f.status, sweeps=f.sweeps,
+                        converged=bool(f.converged), w=f.w, rot_total=f.rot_total,
+                        rot_big=f.rot_big, inner_sweeps=f.inner_sweeps))
+    return st, out

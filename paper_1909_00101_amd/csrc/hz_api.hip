@@ -8,6 +8,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <vector>
 
@@ -381,7 +382,7 @@ static int solve_entry(int kind, const hz_params *p, int64_t m_f, int64_t m_g, i
         HZ_CHECK(hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, st));
         HZ_CHECK(hipStreamSynchronize(st));
         if (hs[ST_FLAGS] & FLAG_NONFINITE) rc = HZ_ENONFINITE;
-        if (info) { info->converged = 1; info->w = 1; }
+        if (info) { info->converged = 1; info->w = 1; info->status = rc; }
     done:
         if (own) (void)hipFree(status);
         return rc;
@@ -612,6 +613,7 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
             info->rot_big = tot_big;
             info->inner_sweeps = tot_isw;
             info->last_offdiag = last_off;
+            info->status = rc;
         }
         if (dphase) {
             (void)hipStreamSynchronize(st);
@@ -627,3 +629,368 @@ done:
 }
 
 }  // namespace hz
+
+// ------------------------------------------------------------ batched form
+namespace hz {
+
+// Workspace layout of a batched solve.  The metadata region at the front
+// (pair descriptors, per-step task lists, ordering tables, flags and
+// counters) is staged on the host and copied in once; the per-pair working
+// arrays follow, each 256-byte aligned.
+struct BLayout {
+    int w = 0, W2 = 0, isteps = 0, inner_lp = 0, kmax = 0;
+    int64_t max_nw = 0;
+    size_t o_probs = 0, o_tasks = 0, o_itab = 0, o_active = 0, o_pinfo = 0, o_pstatus = 0,
+           o_nactive = 0, o_pcnt = 0, o_ptot = 0, meta = 0, total = 0;
+    std::vector<Plan> plan;              // per pair (n >= 2)
+    std::vector<size_t> pair_off;        // per pair: start of its arrays
+    std::vector<int> order;              // pairs by decreasing work
+    std::vector<int> ntasks, task_off;   // per step
+    std::vector<int> otab_nblk;          // distinct block counts
+    std::vector<size_t> otab_off;
+};
+
+static size_t pair_bytes(const Plan &P)
+{
+    size_t o = 0;
+    o = align256(o + 8 * (size_t)P.mfw * P.nw);
+    o = align256(o + 8 * (size_t)P.mgw * P.nw);
+    o = align256(o + 8 * (size_t)P.nzw * P.nw);
+    o = align256(o + 8 * (size_t)P.npairs * 2 * P.W2 * P.W2);
+    o = align256(o + 8 * (size_t)P.npairs * P.W2 * P.W2);
+    o = align256(o + 3 * 8 * (size_t)P.nw);
+    o = align256(o + 2 * 4 * (size_t)P.nw);
+    return o;
+}
+
+static bool plan_batched(const hz_params &prm, int batch, const int64_t *mf, const int64_t *mg,
+                         const int64_t *n, BLayout &L)
+{
+    int64_t nmax = 1;
+    for (int i = 0; i < batch; ++i) nmax = n[i] > nmax ? n[i] : nmax;
+    hz_params q = prm;
+    L.w = prm.w ? prm.w : (nmax <= 32 ? 8 : 16);
+    q.w = L.w;
+    L.W2 = 2 * L.w;
+    L.isteps = (prm.inner_ordering == HZ_ORD_MM) ? L.W2 : L.W2 - 1;
+    L.inner_lp = prm.inner_lanes ? prm.inner_lanes : (L.W2 == 64 ? 16 : 8);
+    if (L.W2 == 16) L.inner_lp = 8;
+    L.plan.assign(batch, Plan{});
+    std::vector<int64_t> work(batch, 0);
+    for (int i = 0; i < batch; ++i) {
+        if (n[i] < 2) continue;
+        if (!make_plan(q, mf[i], mg[i], n[i], 0, L.plan[i])) return false;
+        const Plan &P = L.plan[i];
+        L.kmax = P.steps > L.kmax ? P.steps : L.kmax;
+        L.max_nw = P.nw > L.max_nw ? P.nw : L.max_nw;
+        work[i] = (P.mfw + P.mgw + P.nzw) * P.nw * P.nw;
+        bool seen = false;
+        for (int b : L.otab_nblk) seen |= (b == P.nblk);
+        if (!seen) L.otab_nblk.push_back(P.nblk);
+    }
+    if (L.max_nw == 0) L.max_nw = 1;
+    L.order.resize(batch);
+    for (int i = 0; i < batch; ++i) L.order[i] = i;
+    std::stable_sort(L.order.begin(), L.order.end(),
+                     [&](int a, int b) { return work[a] > work[b]; });
+    L.ntasks.assign(L.kmax, 0);
+    L.task_off.assign(L.kmax, 0);
+    int tot = 0;
+    for (int k = 0; k < L.kmax; ++k) {
+        L.task_off[k] = tot;
+        for (int i : L.order)
+            if (n[i] >= 2 && k < L.plan[i].steps) L.ntasks[k] += L.plan[i].npairs;
+        tot += L.ntasks[k];
+    }
+    size_t o = 0;
+    L.o_probs = o; o = align256(o + sizeof(BProb) * (size_t)batch);
+    L.o_tasks = o; o = align256(o + sizeof(int2) * (size_t)(tot > 0 ? tot : 1));
+    L.o_itab = o; o = align256(o + sizeof(int16_t) * (size_t)L.isteps * L.w * 2);
+    L.otab_off.clear();
+    for (int b : L.otab_nblk) {
+        L.otab_off.push_back(o);
+        const int steps = (prm.ordering == HZ_ORD_MM) ? b : b - 1;
+        o = align256(o + sizeof(int) * (size_t)steps * (b / 2) * 2);
+    }
+    L.o_active = o; o = align256(o + sizeof(int) * (size_t)batch);
+    L.o_pinfo = o; o = align256(o + sizeof(int) * 4 * (size_t)batch);
+    L.o_pstatus = o; o = align256(o + sizeof(int) * ST_NSLOTS * (size_t)batch);
+    L.o_nactive = o; o = align256(o + sizeof(int) * 4);
+    L.o_pcnt = o; o = align256(o + sizeof(unsigned long long) * 4 * (size_t)batch);
+    L.o_ptot = o; o = align256(o + sizeof(unsigned long long) * 4 * (size_t)batch);
+    L.meta = o;
+    L.pair_off.assign(batch, 0);
+    for (int i = 0; i < batch; ++i) {
+        if (n[i] < 2) continue;
+        L.pair_off[i] = o;
+        o += pair_bytes(L.plan[i]);
+    }
+    L.total = o;
+    return true;
+}
+
+// Validation of the batched arguments: 0 or -(argument index).
+static int check_batched(int batch, const int64_t *mf, const int64_t *mg, const int64_t *n,
+                         double *const *F, const int64_t *ldf, double *const *G,
+                         const int64_t *ldg, double *const *Z, const int64_t *ldz,
+                         double *const *s, double *const *sf, double *const *sg)
+{
+    if (batch < 0 || batch > 65535) return -2;
+    if (batch == 0) return 0;
+    if (!mf) return -3;
+    if (!mg) return -4;
+    if (!n) return -5;
+    if (!F) return -6;
+    if (!ldf) return -7;
+    if (!G) return -8;
+    if (!ldg) return -9;
+    if (!Z) return -10;
+    if (!ldz) return -11;
+    if (!s) return -12;
+    if (!sf) return -13;
+    if (!sg) return -14;
+    for (int i = 0; i < batch; ++i) {
+        const int a = check_args(mf[i], mg[i], n[i], F[i], ldf[i], G[i], ldg[i], Z[i], ldz[i],
+                                 s[i], sf[i], sg[i]);
+        if (a) return a - 1;
+    }
+    return 0;
+}
+
+// One private non-blocking stream per device to capture the sweep graph on
+// (the caller's stream may be the null stream, which cannot be captured).
+static hipStream_t capture_stream()
+{
+    static std::mutex mu;
+    static std::vector<hipStream_t> streams;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+        streams[dev] = nullptr;
+    return streams[dev];
+}
+
+static int run_batched(const hz_params &prm, int batch, const int64_t *mf, const int64_t *mg,
+                       const int64_t *n, double *const *F, const int64_t *ldf, double *const *G,
+                       const int64_t *ldg, double *const *Z, const int64_t *ldz,
+                       double *const *sigma, double *const *sigma_f, double *const *sigma_g,
+                       const BLayout &L, void *work, hz_info *infos, hipStream_t st)
+{
+    int rc = HZ_OK;
+    bool own = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<char> meta(L.meta, 0);
+    std::vector<int> hinfo((size_t)batch * 4), hstat((size_t)batch * ST_NSLOTS);
+    std::vector<unsigned long long> htot((size_t)batch * 4);
+    int nact = 0, sweeps = 0;
+    if (!work) {
+        if (hipMalloc(&work, L.total) != hipSuccess) return HZ_EHIP;
+        own = true;
+    }
+    {
+        char *base = (char *)work;
+        BPlan B;
+        B.batch = batch;
+        B.w = L.w;
+        B.W2 = L.W2;
+        B.inner_lp = L.inner_lp;
+        B.isteps = L.isteps;
+        B.kmax = L.kmax;
+        B.max_nw = L.max_nw;
+        B.probs = (BProb *)(base + L.o_probs);
+        B.tasks = (int2 *)(base + L.o_tasks);
+        B.ntasks = L.ntasks;
+        B.task_off = L.task_off;
+        B.itab = (int16_t *)(base + L.o_itab);
+        B.active = (int *)(base + L.o_active);
+        B.pinfo = (int *)(base + L.o_pinfo);
+        B.pstatus = (int *)(base + L.o_pstatus);
+        B.nactive = (int *)(base + L.o_nactive);
+        B.pcnt = (unsigned long long *)(base + L.o_pcnt);
+        B.ptot = (unsigned long long *)(base + L.o_ptot);
+        B.total = L.total;
+
+        // host staging of the metadata region
+        char *hm = meta.data();
+        BProb *hp = (BProb *)(hm + L.o_probs);
+        int2 *ht = (int2 *)(hm + L.o_tasks);
+        int *hact = (int *)(hm + L.o_active);
+        int *hst = (int *)(hm + L.o_pstatus);
+        {
+            std::vector<int16_t> it;
+            build_ordering<int16_t>(prm.inner_ordering, L.W2, it);
+            memcpy(hm + L.o_itab, it.data(), it.size() * sizeof(int16_t));
+            for (size_t t = 0; t < L.otab_nblk.size(); ++t) {
+                std::vector<int> ot;
+                build_ordering<int>(prm.ordering, L.otab_nblk[t], ot);
+                memcpy(hm + L.otab_off[t], ot.data(), ot.size() * sizeof(int));
+            }
+        }
+        for (int i = 0; i < batch; ++i) {
+            hst[(size_t)i * ST_NSLOTS + ST_FAILPAIR] = INT_MAX;
+            BProb &q = hp[i];
+            memset(&q, 0, sizeof(q));
+            q.F = F[i];
+            q.G = G[i];
+            q.U = F[i];
+            q.V = G[i];
+            q.Zo = Z[i];
+            q.sigma = sigma[i];
+            q.sigma_f = sigma_f[i];
+            q.sigma_g = sigma_g[i];
+            q.mf = mf[i];
+            q.mg = mg[i];
+            q.n = n[i];
+            q.ldf = ldf[i];
+            q.ldg = ldg[i];
+            q.ldz = ldz[i];
+            if (n[i] < 2) continue;
+            const Plan &P = L.plan[i];
+            hact[i] = 1;
+            q.mfw = P.mfw;
+            q.mgw = P.mgw;
+            q.nzw = P.nzw;
+            q.nw = P.nw;
+            q.nblk = P.nblk;
+            q.npairs = P.npairs;
+            q.steps = P.steps;
+            q.tol = (prm.tol > 0.0) ? prm.tol : sqrt((double)n[i]) * DBL_EPSILON;
+            for (size_t t = 0; t < L.otab_nblk.size(); ++t)
+                if (L.otab_nblk[t] == P.nblk) q.otab = (const int *)(base + L.otab_off[t]);
+            size_t o = L.pair_off[i];
+            q.Fw = (double *)(base + o); o = align256(o + 8 * (size_t)P.mfw * P.nw);
+            q.Gw = (double *)(base + o); o = align256(o + 8 * (size_t)P.mgw * P.nw);
+            q.Zw = (double *)(base + o); o = align256(o + 8 * (size_t)P.nzw * P.nw);
+            q.gram = (double *)(base + o); o = align256(o + 8 * (size_t)P.npairs * 2 * P.W2 * P.W2);
+            q.Zt = (double *)(base + o); o = align256(o + 8 * (size_t)P.npairs * P.W2 * P.W2);
+            q.sf = (double *)(base + o);
+            q.sg = q.sf + P.nw;
+            q.sig = q.sg + P.nw;
+            o = align256(o + 3 * 8 * (size_t)P.nw);
+            q.rank = (int *)(base + o);
+            q.border = q.rank + P.nw;
+        }
+        for (int k = 0; k < L.kmax; ++k) {
+            int c = L.task_off[k];
+            for (int i : L.order) {
+                if (n[i] < 2 || k >= L.plan[i].steps) continue;
+                for (int l = 0; l < L.plan[i].npairs; ++l) ht[c++] = make_int2(i, l);
+            }
+        }
+        HZ_CHECK(hipMemcpyAsync(base, hm, L.meta, hipMemcpyHostToDevice, st));
+        for (int i = 0; i < batch; ++i) {
+            if (n[i] != 1) continue;
+            launch_n1_real(mf[i], mg[i], F[i], G[i], Z[i], sigma[i], sigma_f[i], sigma_g[i],
+                           B.pstatus + (size_t)i * ST_NSLOTS, st);
+        }
+        launchb_prescale(B, st);
+        HZ_CHECK(hipGetLastError());
+
+        const bool use_graph = !g_prof.on;
+        if (use_graph && L.kmax > 0) {
+            hipStream_t cs = capture_stream();
+            if (!cs) { rc = HZ_EHIP; goto done; }
+            HZ_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            launchb_sweep(B, prm, cs);
+            HZ_CHECK(hipStreamEndCapture(cs, &graph));
+            HZ_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        }
+        for (int sw = 0; sw < prm.max_sweeps && L.kmax > 0; ++sw) {
+            if (use_graph) HZ_CHECK(hipGraphLaunch(exec, st));
+            else launchb_sweep(B, prm, st);
+            HZ_CHECK(hipGetLastError());
+            HZ_CHECK(hipMemcpyAsync(&nact, B.nactive, sizeof(int), hipMemcpyDeviceToHost, st));
+            HZ_CHECK(hipStreamSynchronize(st));
+            prof_flush();
+            ++sweeps;
+            if (nact == 0) break;
+        }
+        launchb_finish(B, st);
+        HZ_CHECK(hipGetLastError());
+        HZ_CHECK(hipMemcpyAsync(hinfo.data(), B.pinfo, hinfo.size() * sizeof(int),
+                                hipMemcpyDeviceToHost, st));
+        HZ_CHECK(hipMemcpyAsync(hstat.data(), B.pstatus, hstat.size() * sizeof(int),
+                                hipMemcpyDeviceToHost, st));
+        HZ_CHECK(hipMemcpyAsync(htot.data(), B.ptot, htot.size() * sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, st));
+        HZ_CHECK(hipStreamSynchronize(st));
+        int worst = 0;   // 3 nonfinite, 2 chol, 1 noconv
+        for (int i = 0; i < batch; ++i) {
+            const int fl = hstat[(size_t)i * ST_NSLOTS + ST_FLAGS];
+            const bool conv = (n[i] == 1) || hinfo[(size_t)i * 4 + 1];
+            int prc = HZ_OK, sev = 0;
+            if (fl & FLAG_NONFINITE) { prc = HZ_ENONFINITE; sev = 3; }
+            else if (fl & FLAG_CHOL) { prc = HZ_ECHOL; sev = 2; }
+            else if (!conv) { prc = HZ_ENOCONV; sev = 1; }
+            worst = sev > worst ? sev : worst;
+            if (infos) {
+                hz_info &f = infos[i];
+                memset(&f, 0, sizeof(f));
+                f.sweeps = hinfo[(size_t)i * 4];
+                f.converged = conv ? 1 : 0;
+                f.w = (n[i] == 1) ? 1 : L.w;
+                f.failed_pair = (fl & FLAG_CHOL) ? hstat[(size_t)i * ST_NSLOTS + ST_FAILPAIR] : -1;
+                f.rot_total = htot[(size_t)i * 4];
+                f.rot_big = htot[(size_t)i * 4 + 1];
+                f.inner_sweeps = htot[(size_t)i * 4 + 2];
+                f.status = prc;
+            }
+        }
+        rc = worst == 3 ? HZ_ENONFINITE : worst == 2 ? HZ_ECHOL : worst == 1 ? HZ_ENOCONV : HZ_OK;
+    }
+done:
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (own) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(work);
+    }
+    (void)sweeps;
+    return rc;
+}
+
+}  // namespace hz
+
+extern "C" {
+
+size_t hz_dgsvd_batched_work_size(const hz_params *p, int batch, const int64_t *m_f,
+                                  const int64_t *m_g, const int64_t *n)
+{
+    hz_params prm;
+    if (p) prm = *p; else hz_default_params(&prm);
+    if (!params_ok(prm) || batch < 0 || batch > 65535) return 0;
+    if (batch == 0) return 256;
+    if (!m_f || !m_g || !n) return 0;
+    for (int i = 0; i < batch; ++i)
+        if (n[i] < 1 || m_f[i] < n[i] || m_g[i] < n[i] || n[i] > (int64_t)INT_MAX / 2) return 0;
+    BLayout L;
+    if (!plan_batched(prm, batch, m_f, m_g, n, L)) return 0;
+    return L.total;
+}
+
+int hz_dgsvd_batched(const hz_params *p, int batch, const int64_t *m_f, const int64_t *m_g,
+                     const int64_t *n, double *const *F, const int64_t *ldf,
+                     double *const *G, const int64_t *ldg, double *const *Z,
+                     const int64_t *ldz, double *const *sigma, double *const *sigma_f,
+                     double *const *sigma_g, void *work, size_t work_bytes, hz_info *infos,
+                     void *stream)
+{
+    hz_params prm;
+    if (p) prm = *p; else hz_default_params(&prm);
+    if (!params_ok(prm)) return -1;
+    const int a = check_batched(batch, m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f,
+                                sigma_g);
+    if (a) return a;
+    if (batch == 0) return HZ_OK;
+    if (work && ((uintptr_t)work & 255)) return -15;
+    BLayout L;
+    if (!plan_batched(prm, batch, m_f, m_g, n, L)) return -5;
+    if (work && work_bytes < L.total) return -16;
+    return run_batched(prm, batch, m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g,
+                       L, work, infos, (hipStream_t)stream);
+}
+
+}  // extern "C"

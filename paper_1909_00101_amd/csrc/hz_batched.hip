@@ -1,0 +1,273 @@
+// hz_batched.hip -- batched real GSVD of many independent pairs of uneven
+// sizes.  Every block step is one launch of each phase over the tasks of
+// all pairs that still iterate (a pair with fewer steps per sweep, or one
+// that has converged, simply has no tasks or exits at once), so hundreds
+// of small problems fill the GPU together.  Per-pair convergence is
+// decided on the device after every sweep (paper, Section 2.5 stopping
+// rule per pair); the host replays one captured hipGraph per sweep and
+// reads back a single count of still-active pairs.
+#include "hz_device.h"
+#include "hz_internal.h"
+#include "hz_kernels_real.h"
+
+namespace hz {
+
+// Prescale and copy-in of every pair (grid (column blocks, pairs)).
+__global__ __launch_bounds__(256) void kb_prescale(const BProb *__restrict__ probs,
+                                                   int *__restrict__ pstatus)
+{
+    const BProb &P = probs[blockIdx.y];
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= P.nw) return;
+    double *fw = P.Fw + j * P.mfw, *gw = P.Gw + j * P.mgw, *zw = P.Zw + j * P.nzw;
+    if (j < P.n) {
+        const double *f = P.F + j * P.ldf, *g = P.G + j * P.ldg;
+        double s = 0.0;
+        for (int64_t r = lane; r < P.mg; r += 64) s = fma(g[r], g[r], s);
+        s = wave_sum(s);
+        const double d = 1.0 / sqrt(s);
+        bool bad = !(s > 0.0) || !isfinite(s);
+        for (int64_t r = lane; r < P.mfw; r += 64) {
+            const double v = (r < P.mf) ? f[r] * d : 0.0;
+            bad |= !isfinite(v);
+            fw[r] = v;
+        }
+        for (int64_t r = lane; r < P.mgw; r += 64) gw[r] = (r < P.mg) ? g[r] * d : 0.0;
+        for (int64_t r = lane; r < P.nzw; r += 64) zw[r] = (r == j) ? d : 0.0;
+        if (bad) atomicOr(pstatus + (size_t)blockIdx.y * ST_NSLOTS + ST_FLAGS, FLAG_NONFINITE);
+    } else {
+        const int64_t k = j - P.n;
+        for (int64_t r = lane; r < P.mfw; r += 64) fw[r] = (r == P.mf + k) ? 1.0 : 0.0;
+        for (int64_t r = lane; r < P.mgw; r += 64) gw[r] = (r == P.mg + k) ? 1.0 : 0.0;
+        for (int64_t r = lane; r < P.nzw; r += 64) zw[r] = (r == j) ? 1.0 : 0.0;
+    }
+}
+
+// Gram blocks of step k: task t = (pair i, block pair l), blockIdx.y = matrix.
+template <int W2>
+__global__ __launch_bounds__(256) void kb_gram(const BProb *__restrict__ probs,
+                                               const int2 *__restrict__ tasks,
+                                               const int *__restrict__ active, int step)
+{
+    const int2 tk = tasks[blockIdx.x];
+    if (!active[tk.x]) return;
+    const BProb &P = probs[tk.x];
+    const int mat = blockIdx.y;
+    const int *pr = P.otab + ((size_t)step * P.npairs + tk.y) * 2;
+    const int64_t m = mat ? P.mgw : P.mfw;
+    gram_block<W2>(mat ? P.Gw : P.Fw, m, pr[0], pr[1], 0, m / 64,
+                   P.gram + ((size_t)tk.y * 2 + mat) * (W2 * W2));
+}
+
+template <int W2, int LP>
+__global__ __launch_bounds__((W2 / 2) * LP) void kb_inner(
+    const BProb *__restrict__ probs, const int2 *__restrict__ tasks, const int *__restrict__ active,
+    int step, const int16_t *__restrict__ itab, int isteps, int inner_max, int sort,
+    unsigned long long *__restrict__ pcnt, int *__restrict__ pstatus)
+{
+    __shared__ unsigned long long c[4];
+    const int2 tk = tasks[blockIdx.x];
+    if (!active[tk.x]) return;
+    const BProb &P = probs[tk.x];
+    const double *pa = P.gram + (size_t)tk.y * 2 * (W2 * W2);
+    inner_solve<W2, LP>(pa, pa + W2 * W2, itab, isteps, inner_max, P.tol, sort,
+                        P.Zt + (size_t)tk.y * (W2 * W2), c,
+                        pstatus + (size_t)tk.x * ST_NSLOTS, step * 65536 + tk.y, nullptr);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // integer sums: the result does not depend on the order of arrival
+        atomicAdd(pcnt + (size_t)tk.x * 4 + 0, c[0]);
+        atomicAdd(pcnt + (size_t)tk.x * 4 + 1, c[1]);
+        atomicAdd(pcnt + (size_t)tk.x * 4 + 2, c[2]);
+    }
+}
+
+template <int W2>
+__global__ __launch_bounds__(256) void kb_update(const BProb *__restrict__ probs,
+                                                 const int2 *__restrict__ tasks,
+                                                 const int *__restrict__ active, int step)
+{
+    const int2 tk = tasks[blockIdx.x];
+    if (!active[tk.x]) return;
+    const BProb &P = probs[tk.x];
+    const int *pr = P.otab + ((size_t)step * P.npairs + tk.y) * 2;
+    const int part = blockIdx.y;
+    double *Y = part == 0 ? P.Fw : (part == 1 ? P.Gw : P.Zw);
+    const int64_t m = part == 0 ? P.mfw : (part == 1 ? P.mgw : P.nzw);
+    update_rows<W2>(Y, m, pr[0], pr[1], 0, m, P.Zt + (size_t)tk.y * (W2 * W2));
+}
+
+// End of a sweep, one workgroup: per pair, add the sweep's counters to the
+// totals, stop the pair after a sweep with no big transformation (converged),
+// at the sweep cap, or on a failure flag; count the pairs still active.
+__global__ __launch_bounds__(256) void kb_converge(int batch, int max_sweeps,
+                                                   int *__restrict__ active,
+                                                   unsigned long long *__restrict__ pcnt,
+                                                   unsigned long long *__restrict__ ptot,
+                                                   int *__restrict__ pinfo,
+                                                   const int *__restrict__ pstatus,
+                                                   int *__restrict__ nactive)
+{
+    __shared__ int red[256];
+    int cntv = 0;
+    for (int i = threadIdx.x; i < batch; i += 256) {
+        if (active[i]) {
+            unsigned long long *c = pcnt + (size_t)i * 4;
+            ptot[(size_t)i * 4 + 0] += c[0];
+            ptot[(size_t)i * 4 + 1] += c[1];
+            ptot[(size_t)i * 4 + 2] += c[2];
+            const int sw = ++pinfo[(size_t)i * 4 + 0];
+            if (pstatus[(size_t)i * ST_NSLOTS + ST_FLAGS]) {
+                active[i] = 0;
+            } else if (c[1] == 0) {
+                active[i] = 0;
+                pinfo[(size_t)i * 4 + 1] = 1;   // converged
+            } else if (sw >= max_sweeps) {
+                active[i] = 0;
+            }
+            c[0] = c[1] = c[2] = 0;
+        }
+        cntv += active[i];
+    }
+    red[threadIdx.x] = cntv;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) nactive[0] = red[0];
+}
+
+// Extraction and sort per pair (grid (column blocks, pairs)).
+__global__ __launch_bounds__(256) void kb_colnorms(const BProb *__restrict__ probs,
+                                                   int *__restrict__ pstatus)
+{
+    const BProb &P = probs[blockIdx.y];
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= P.nw) return;
+    const double *f = P.Fw + j * P.mfw, *g = P.Gw + j * P.mgw, *z = P.Zw + j * P.nzw;
+    double a = 0.0, b = 0.0;
+    for (int64_t r = lane; r < P.mfw; r += 64) a = fma(f[r], f[r], a);
+    for (int64_t r = lane; r < P.mgw; r += 64) b = fma(g[r], g[r], b);
+    int bz = 0;
+    for (int64_t r = P.n + lane; r < P.nw; r += 64) bz |= (z[r] != 0.0);
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int isb = __any(bz) ? 1 : 0;
+    if (lane == 0) {
+        const double x = sqrt(a), y = sqrt(b);
+        P.sf[j] = x;
+        P.sg[j] = y;
+        P.sig[j] = x / y;
+        P.border[j] = isb;
+        if (!isb && !(isfinite(x / y) && x > 0.0 && y > 0.0))
+            atomicOr(pstatus + (size_t)blockIdx.y * ST_NSLOTS + ST_FLAGS, FLAG_NONFINITE);
+    }
+}
+
+__global__ __launch_bounds__(256) void kb_rank(const BProb *__restrict__ probs)
+{
+    const BProb &P = probs[blockIdx.y];
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= P.nw) return;
+    if (P.border[j]) {
+        P.rank[j] = -1;
+        return;
+    }
+    const double s = P.sig[j];
+    int64_t r = 0;
+    for (int64_t k = 0; k < P.nw; ++k) {
+        if (P.border[k]) continue;
+        const double t = P.sig[k];
+        r += (t > s) || (t == s && k < j);
+    }
+    P.rank[j] = (int)r;
+}
+
+__global__ __launch_bounds__(256) void kb_scatter(const BProb *__restrict__ probs)
+{
+    const BProb &P = probs[blockIdx.y];
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= P.nw) return;
+    const int rk = P.rank[j];
+    if (rk < 0 || rk >= P.n) return;
+    const double x = P.sf[j], y = P.sg[j];
+    const double th = 1.0 / sqrt(x * x + y * y);
+    const double ix = 1.0 / x, iy = 1.0 / y;
+    const double *f = P.Fw + j * P.mfw, *g = P.Gw + j * P.mgw, *z = P.Zw + j * P.nzw;
+    double *u = P.U + (int64_t)rk * P.ldf, *v = P.V + (int64_t)rk * P.ldg;
+    double *zo = P.Zo + (int64_t)rk * P.ldz;
+    for (int64_t r = lane; r < P.mf; r += 64) u[r] = f[r] * ix;
+    for (int64_t r = lane; r < P.mg; r += 64) v[r] = g[r] * iy;
+    for (int64_t r = lane; r < P.n; r += 64) zo[r] = z[r] * th;
+    if (lane == 0) {
+        P.sigma[rk] = x / y;
+        P.sigma_f[rk] = x * th;
+        P.sigma_g[rk] = y * th;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+void launchb_prescale(const BPlan &B, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_prescale, dim3((unsigned)((B.max_nw + 3) / 4), B.batch), dim3(256), 0,
+                       s, B.probs, B.pstatus);
+}
+
+template <int W2>
+static void stepb_impl(const BPlan &B, int k, const hz_params &prm, hipStream_t s)
+{
+    const int nt = B.ntasks[k];
+    if (nt == 0) return;
+    const int2 *tasks = B.tasks + B.task_off[k];
+    prof_mark(K_GRAM, true, s);
+    hipLaunchKernelGGL(kb_gram<W2>, dim3(nt, 2), dim3(256), 0, s, B.probs, tasks, B.active, k);
+    prof_mark(K_GRAM, false, s);
+    prof_mark(K_INNER, true, s);
+    if constexpr (W2 == 16) {
+        hipLaunchKernelGGL((kb_inner<W2, 8>), dim3(nt), dim3((W2 / 2) * 8), 0, s, B.probs, tasks,
+                           B.active, k, B.itab, B.isteps, prm.inner_max_sweeps, prm.sort, B.pcnt,
+                           B.pstatus);
+    } else {
+        if (B.inner_lp == 16)
+            hipLaunchKernelGGL((kb_inner<W2, 16>), dim3(nt), dim3((W2 / 2) * 16), 0, s, B.probs,
+                               tasks, B.active, k, B.itab, B.isteps, prm.inner_max_sweeps,
+                               prm.sort, B.pcnt, B.pstatus);
+        else
+            hipLaunchKernelGGL((kb_inner<W2, 8>), dim3(nt), dim3((W2 / 2) * 8), 0, s, B.probs,
+                               tasks, B.active, k, B.itab, B.isteps, prm.inner_max_sweeps,
+                               prm.sort, B.pcnt, B.pstatus);
+    }
+    prof_mark(K_INNER, false, s);
+    prof_mark(K_UPDATE, true, s);
+    hipLaunchKernelGGL(kb_update<W2>, dim3(nt, 3), dim3(256), 0, s, B.probs, tasks, B.active, k);
+    prof_mark(K_UPDATE, false, s);
+}
+
+void launchb_sweep(const BPlan &B, const hz_params &prm, hipStream_t s)
+{
+    for (int k = 0; k < B.kmax; ++k) {
+        switch (B.W2) {
+        case 16: stepb_impl<16>(B, k, prm, s); break;
+        case 32: stepb_impl<32>(B, k, prm, s); break;
+        default: stepb_impl<64>(B, k, prm, s); break;
+        }
+    }
+    hipLaunchKernelGGL(kb_converge, dim3(1), dim3(256), 0, s, B.batch, prm.max_sweeps, B.active,
+                       B.pcnt, B.ptot, B.pinfo, B.pstatus, B.nactive);
+}
+
+void launchb_finish(const BPlan &B, hipStream_t s)
+{
+    const dim3 g4((unsigned)((B.max_nw + 3) / 4), B.batch);
+    hipLaunchKernelGGL(kb_colnorms, g4, dim3(256), 0, s, B.probs, B.pstatus);
+    hipLaunchKernelGGL(kb_rank, dim3((unsigned)((B.max_nw + 255) / 256), B.batch), dim3(256), 0,
+                       s, B.probs);
+    hipLaunchKernelGGL(kb_scatter, g4, dim3(256), 0, s, B.probs);
+}
+
+}  // namespace hz

@@ -4,6 +4,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/hzgsvd.h"
 
 namespace hz {
@@ -49,6 +51,35 @@ struct Ptrs {
     double *offd;                // mixed form: per (step, pair, matrix) off-diagonal measure
 };
 
+// One pair of a batched solve, as the batched kernels see it.
+struct BProb {
+    const double *F, *G;        // caller input (device)
+    double *U, *V, *Zo;         // caller outputs (U aliases F, V aliases G)
+    double *sigma, *sigma_f, *sigma_g;
+    int64_t mf, mg, n, ldf, ldg, ldz;
+    double *Fw, *Gw, *Zw;       // working copies (bordered, 64-row padded)
+    int64_t mfw, mgw, nzw, nw;
+    double *gram, *Zt;          // per block pair: Gram blocks, Z_tilde
+    double *sf, *sg, *sig;
+    int *rank, *border;
+    const int *otab;            // this pair's block ordering (steps x npairs x 2)
+    int nblk, npairs, steps, pad;
+    double tol;
+};
+
+// Host-side plan of a batched solve (device pointers into one workspace).
+struct BPlan {
+    int batch, w, W2, inner_lp, isteps, kmax;
+    int64_t max_nw;
+    BProb *probs;
+    int2 *tasks;                        // per step: (pair, block pair), largest pairs first
+    std::vector<int> ntasks, task_off;  // per step
+    int16_t *itab;
+    int *active, *pinfo, *pstatus, *nactive;
+    unsigned long long *pcnt, *ptot;
+    size_t total;
+};
+
 // status[] slots written by kernels (integer atomics only)
 enum { ST_FLAGS = 0, ST_FAILPAIR = 1, ST_NSLOTS = 4 };
 enum { FLAG_NONFINITE = 1, FLAG_CHOL = 2 };
@@ -73,6 +104,11 @@ void launch_rank(const Plan &P, const Ptrs &W, hipStream_t s);
 void launch_gram_sum(const Plan &P, const Ptrs &W, hipStream_t s);
 void launch_inner_real(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
                        hipStream_t s);
+
+// launchers (batched), hz_batched.hip
+void launchb_prescale(const BPlan &B, hipStream_t s);
+void launchb_sweep(const BPlan &B, const hz_params &prm, hipStream_t s);
+void launchb_finish(const BPlan &B, hipStream_t s);
 
 // launchers (mixed precision), hz_mixed.hip
 void launch_prescale_mixed(const Plan &P, const Ptrs &W, const double *F, int64_t ldf,

@@ -1,0 +1,382 @@
+// hz_kernels_real.h -- FP64 device bodies shared by the single-pair kernels
+// (hz_real.hip) and the batched kernels (hz_batched.hip): the pivot Gram
+// block of a block-column pair, the inner solve of one pivot block pair and
+// the in-place block update of a row range.
+#pragma once
+#include "hz_device.h"
+#include "hz_internal.h"
+
+namespace hz {
+
+// Device body: one workgroup of 256 threads forms the Gram block of the
+// block-column pair (p, q) of Y (m rows, ld m) over the 64-row chunks
+// [c0, c1) and writes it to out (column-major W2 x W2, lower tiles).
+template <int W2>
+__device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t m, int p, int q,
+                                           int64_t c0, int64_t c1, double *__restrict__ out)
+{
+    constexpr int W = W2 / 2, NB = W2 / 16, LDT = 66, NLD = W2 / 8;
+    constexpr int NT = NB * (NB + 1) / 2;    // lower-triangle tiles
+    __shared__ __attribute__((aligned(16))) double tile[W2 * LDT];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lrow = 2 * (tid & 31), lcol = tid >> 5;
+
+    d4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const double *colp[NLD];
+#pragma unroll
+    for (int t = 0; t < NLD; ++t) {
+        const int cc = lcol + 8 * t;
+        const int gc = (cc < W) ? p * W + cc : q * W + (cc - W);
+        colp[t] = Y + (int64_t)gc * m + lrow;
+    }
+    d2 buf[NLD];
+    if (c0 < c1) {
+#pragma unroll
+        for (int t = 0; t < NLD; ++t) buf[t] = *(const d2 *)(colp[t] + c0 * 64);
+    }
+    for (int64_t c = c0; c < c1; ++c) {
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < NLD; ++t) *(d2 *)(tile + (lcol + 8 * t) * LDT + lrow) = buf[t];
+        __syncthreads();
+        if (c + 1 < c1) {
+#pragma unroll
+            for (int t = 0; t < NLD; ++t) buf[t] = *(const d2 *)(colp[t] + (c + 1) * 64);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int ks = wave + 4 * s;
+            double fr[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                fr[b] = tile[(16 * b + (lane & 15)) * LDT + 4 * ks + (lane >> 4)];
+            int t = 0;
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+                for (int b = 0; b <= a; ++b, ++t) acc[t] = mfma16(fr[a], fr[b], acc[t]);
+        }
+    }
+    // Sum the four waves' partial tiles in wave order (tile reused, ld W2).
+    for (int wv = 0; wv < 4; ++wv) {
+        __syncthreads();
+        if (wave == wv) {
+            int t = 0;
+#pragma unroll
+            for (int a = 0; a < NB; ++a)
+#pragma unroll
+                for (int b = 0; b <= a; ++b, ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int gi = 16 * a + 4 * r + (lane >> 4), gj = 16 * b + (lane & 15);
+                        double *dst = tile + gj * W2 + gi;
+                        *dst = (wv == 0) ? acc[t][r] : *dst + acc[t][r];
+                    }
+        }
+    }
+    __syncthreads();
+    // Only lower-triangle tiles are meaningful; upper ones are not written.
+    for (int e = 2 * tid; e < W2 * W2; e += 512) *(d2 *)(out + e) = *(const d2 *)(tile + e);
+}
+
+// Device body: the workgroup (NT threads) solves the block pair whose Gram
+// blocks are pa (F) and pb (G) (column-major W2 x W2, lower triangles),
+// writes Z_tilde to zt, the counters (transformations, big ones, inner
+// sweeps) to myc[0..2], and on a non-positive pivot sets FLAG_CHOL in
+// status[ST_FLAGS] and failcode into status[ST_FAILPAIR] (minimum kept).
+template <int W2, int LP>
+__device__ __forceinline__ void inner_solve(
+    const double *__restrict__ pa, const double *__restrict__ pb,
+    const int16_t *__restrict__ itab, int isteps, int inner_max, double tol, int sort,
+    double *__restrict__ zt, unsigned long long *__restrict__ myc, int *__restrict__ status,
+    int failcode, unsigned long long *__restrict__ ph)
+{
+    constexpr int W = W2 / 2;         // column pairs per inner step
+    constexpr int NT = W * LP;
+    constexpr int RPL = W2 / LP;      // rows per lane
+    constexpr int LDI = W2 + 2;
+    static_assert(RPL >= 2 && RPL % 2 == 0 && NT >= 64, "bad inner geometry");
+    __shared__ __attribute__((aligned(16))) double sF[W2 * LDI];
+    __shared__ __attribute__((aligned(16))) double sG[W2 * LDI];
+    __shared__ __attribute__((aligned(16))) double sZ[W2 * LDI];
+    __shared__ int16_t stab[W2 * W2];
+    __shared__ __attribute__((aligned(16))) double lbuf[2][64];
+    __shared__ int s_fail;
+    __shared__ unsigned s_cnt[3 * W];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (ph && tid == 0) ph[0] = wall_clock64();
+    // 1. load the Gram blocks (lower triangles) into LDS
+    {
+        for (int e = 2 * tid; e < W2 * W2; e += 2 * NT) {
+            const d2 a = *(const d2 *)(pa + e), b = *(const d2 *)(pb + e);
+            const int col = e / W2, row = e % W2;
+            *(d2 *)(sF + col * LDI + row) = a;
+            *(d2 *)(sG + col * LDI + row) = b;
+        }
+        for (int e = tid; e < isteps * W * 2; e += NT) stab[e] = itab[e];
+        if (tid == 0) s_fail = 0;
+    }
+    __syncthreads();
+    if (ph && tid == 0) ph[1] = wall_clock64();
+
+    // 2. Cholesky factorizations, lane = row, one wave per matrix.
+    {
+        constexpr bool two = (W2 == 64);
+        const int mat = two ? wave : (lane >> 5);
+        const int i = two ? lane : (lane & 31);
+        if ((two ? (wave < 2) : (wave == 0)) && i < W2) {
+            double *M = mat ? sG : sF;
+            double *lb = lbuf[mat];
+            double a[W2];
+#pragma unroll
+            for (int k = 0; k < W2; ++k) a[k] = M[k * LDI + i];
+            bool ok = true;
+#pragma unroll
+            for (int j = 0; j < W2; ++j) {
+                double piv;
+                if (two) {
+                    piv = readlane_d(a[j], j);
+                } else {
+                    const double p0 = readlane_d(a[j], j), p1 = readlane_d(a[j], 32 + j);
+                    piv = mat ? p1 : p0;
+                }
+                ok = ok && (piv > 0.0) && (piv < INFINITY);
+                const double inv = rsqrt_nr(piv);
+                const double l = (i >= j) ? a[j] * inv : 0.0;
+                a[j] = l;
+                lb[i] = l;
+                wave_fence();
+#pragma unroll
+                for (int k = j + 1; k < W2; k += 2) {
+                    const d2 lk = *(const d2 *)(lb + k - (k & 1));
+                    if (k & 1) {
+                        a[k] = fma(-l, lk[1], a[k]);
+                        if (k + 1 < W2) a[k + 1] = fma(-l, (*(const d2 *)(lb + k + 1))[0], a[k + 1]);
+                    } else {
+                        a[k] = fma(-l, lk[0], a[k]);
+                        if (k + 1 < W2) a[k + 1] = fma(-l, lk[1], a[k + 1]);
+                    }
+                }
+                wave_fence();
+            }
+            // F_hat = L^T: column i of F_hat is row i of L.
+#pragma unroll
+            for (int k = 0; k < W2; ++k) M[i * LDI + k] = (k <= i) ? a[k] : 0.0;
+            if (!ok) s_fail = 1;
+        }
+    }
+    __syncthreads();
+    if (ph && tid == 0) ph[2] = wall_clock64();
+    if (s_fail) {
+        for (int e = tid; e < W2 * W2; e += NT) zt[e] = (e % W2 == e / W2) ? 1.0 : 0.0;
+        if (tid == 0) {
+            myc[0] = 0;
+            myc[1] = 0;
+            myc[2] = 0;
+            atomicOr(status + ST_FLAGS, FLAG_CHOL);
+            atomicMin(status + ST_FAILPAIR, failcode);
+        }
+        return;
+    }
+
+    const int grp = tid / LP, gl = tid % LP, r0 = gl * RPL;
+    // 3. prescale the factor pair: columns 2*grp and 2*grp+1 per group.
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = 2 * grp + h;
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const double g = sG[c * LDI + r0 + r];
+            s = fma(g, g, s);
+        }
+        s = dpp_group_sum<LP>(s);
+        const double d = rsqrt_nr(s);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            sF[c * LDI + r0 + r] *= d;
+            sG[c * LDI + r0 + r] *= d;
+            sZ[c * LDI + r0 + r] = (r0 + r == c) ? d : 0.0;
+        }
+    }
+    __syncthreads();
+    if (ph && tid == 0) ph[3] = wall_clock64();
+
+    // 4. inner sweeps
+    const double tol2 = tol * tol;
+    unsigned my_all = 0, my_big = 0;
+    int nsw = 0;
+    for (int sw = 0; sw < inner_max; ++sw) {
+        unsigned sw_all = 0, sw_big = 0;
+        ++nsw;
+        for (int st = 0; st < isteps; ++st) {
+            const int ci = stab[(st * W + grp) * 2], cj = stab[(st * W + grp) * 2 + 1];
+            double fi[RPL], fj[RPL], gi[RPL], gj[RPL], zi[RPL], zj[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; r += 2) {
+                const d2 a0 = *(const d2 *)(sF + ci * LDI + r0 + r);
+                const d2 a1 = *(const d2 *)(sF + cj * LDI + r0 + r);
+                const d2 b0 = *(const d2 *)(sG + ci * LDI + r0 + r);
+                const d2 b1 = *(const d2 *)(sG + cj * LDI + r0 + r);
+                const d2 c0 = *(const d2 *)(sZ + ci * LDI + r0 + r);
+                const d2 c1 = *(const d2 *)(sZ + cj * LDI + r0 + r);
+                fi[r] = a0[0]; fi[r + 1] = a0[1];
+                fj[r] = a1[0]; fj[r + 1] = a1[1];
+                gi[r] = b0[0]; gi[r + 1] = b0[1];
+                gj[r] = b1[0]; gj[r + 1] = b1[1];
+                zi[r] = c0[0]; zi[r + 1] = c0[1];
+                zj[r] = c1[0]; zj[r + 1] = c1[1];
+            }
+            double aii = 0.0, ajj = 0.0, aij = 0.0, bij = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                aii = fma(fi[r], fi[r], aii);
+                ajj = fma(fj[r], fj[r], ajj);
+                aij = fma(fi[r], fj[r], aij);
+                bij = fma(gi[r], gj[r], bij);
+            }
+            aii = dpp_group_sum<LP>(aii);
+            ajj = dpp_group_sum<LP>(ajj);
+            aij = dpp_group_sum<LP>(aij);
+            bij = dpp_group_sum<LP>(bij);
+            double z11 = 1.0, z21 = 0.0, z12 = 0.0, z22 = 1.0;
+            bool swap;
+            const bool orth = (aij * aij < aii * ajj * tol2) && (fabs(bij) < tol);
+            if (orth) {
+                swap = sort && (aii < ajj);
+            } else {
+                hz_real_2x2_fast(aii, ajj, aij, bij, z11, z21, z12, z22);
+                sw_all += 1;
+                if (!(z11 == 1.0 && z22 == 1.0)) sw_big += 1;
+                swap = false;
+                if (sort) {
+                    const double a11 = fma(z11 * z11, aii, fma(2.0 * z11 * z21, aij, z21 * z21 * ajj));
+                    const double a22 = fma(z12 * z12, aii, fma(2.0 * z22 * z12, aij, z22 * z22 * ajj));
+                    swap = a11 < a22;
+                }
+            }
+            if (swap) {
+                double t;
+                t = z11; z11 = z12; z12 = t;
+                t = z21; z21 = z22; z22 = t;
+            }
+            if (!orth || swap) {
+#pragma unroll
+                for (int r = 0; r < RPL; r += 2) {
+                    d2 nfi, nfj, ngi, ngj, nzi, nzj;
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        nfi[u] = fma(fj[r + u], z21, fi[r + u] * z11);
+                        nfj[u] = fma(fi[r + u], z12, fj[r + u] * z22);
+                        ngi[u] = fma(gj[r + u], z21, gi[r + u] * z11);
+                        ngj[u] = fma(gi[r + u], z12, gj[r + u] * z22);
+                        nzi[u] = fma(zj[r + u], z21, zi[r + u] * z11);
+                        nzj[u] = fma(zi[r + u], z12, zj[r + u] * z22);
+                    }
+                    *(d2 *)(sF + ci * LDI + r0 + r) = nfi;
+                    *(d2 *)(sF + cj * LDI + r0 + r) = nfj;
+                    *(d2 *)(sG + ci * LDI + r0 + r) = ngi;
+                    *(d2 *)(sG + cj * LDI + r0 + r) = ngj;
+                    *(d2 *)(sZ + ci * LDI + r0 + r) = nzi;
+                    *(d2 *)(sZ + cj * LDI + r0 + r) = nzj;
+                }
+            }
+            __syncthreads();
+        }
+        my_all += sw_all;
+        my_big += sw_big;
+        const int any = __syncthreads_count(gl == 0 && sw_all > 0);
+        if (any == 0) break;
+    }
+
+    if (ph && tid == 0) ph[4] = wall_clock64();
+    // 5. Theta rescale and write Z_tilde (column-major W2 x W2).
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int c = 2 * grp + h;
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const double f = sF[c * LDI + r0 + r], g = sG[c * LDI + r0 + r];
+            s = fma(f, f, s);
+            s = fma(g, g, s);
+        }
+        s = dpp_group_sum<LP>(s);
+        const double th = rsqrt_nr(s);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) zt[c * W2 + r0 + r] = sZ[c * LDI + r0 + r] * th;
+    }
+    // counters: the groups' totals summed in group order
+    if (gl == 0) {
+        s_cnt[3 * grp] = my_all;
+        s_cnt[3 * grp + 1] = my_big;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long ta = 0, tb = 0;
+        for (int g = 0; g < W; ++g) {
+            ta += s_cnt[3 * g];
+            tb += s_cnt[3 * g + 1];
+        }
+        myc[0] = ta;
+        myc[1] = tb;
+        myc[2] = (unsigned long long)nsw;
+        if (ph) ph[5] = wall_clock64();
+    }
+}
+
+// Device body: one workgroup (256 threads) updates rows [rb, re) of the
+// block-column pair (p, q) of Y (ld m) by zt (column-major W2 x W2).
+template <int W2>
+__device__ __forceinline__ void update_rows(double *__restrict__ Y, int64_t m, int p, int q,
+                                            int64_t rb, int64_t re,
+                                            const double *__restrict__ zt)
+{
+    constexpr int W = W2 / 2, NB = W2 / 16, KS = W2 / 4, LDZ = W2 + 1;
+    __shared__ double sz[W2 * LDZ];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < W2 * W2; e += 256) sz[(e / W2) * LDZ + (e % W2)] = zt[e];
+    __syncthreads();
+    // Lane (i, k) = (lane % 16, lane / 16).  Columns 0..W-1 of the pair are
+    // block column p, W..2W-1 block column q; every k-step's column offset
+    // is a uniform multiple of m.
+    const int k4 = lane >> 4, i16 = lane & 15;
+    const double *bp = Y + ((int64_t)p * W + k4) * m + i16;
+    const double *bq = Y + ((int64_t)q * W + k4) * m + i16;
+    for (int64_t r0 = rb + 16 * wave; r0 < re; r0 += 64) {
+        // keep the Z_tilde fragment reads inside the loop (in LDS, not in
+        // 128 registers hoisted out of it)
+        __asm__ volatile("" ::: "memory");
+        double xb[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            xb[s] = (4 * s < W) ? bp[(int64_t)(4 * s) * m + r0] : bq[(int64_t)(4 * s - W) * m + r0];
+        d4 acc[NB];
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) acc[jb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+                // A'[j][k] = Z_tilde[4s+k][16jb+j], lane j + 16k
+                const double za = sz[(16 * jb + i16) * LDZ + 4 * s + k4];
+                acc[jb] = mfma16(za, xb[s], acc[jb]);
+            }
+        // element r of acc[jb] in lane l is output column 16jb + 4r + l/16, row l%16
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c0 = 16 * jb + 4 * r;
+                double *dst = (c0 < W) ? (double *)bp + (int64_t)c0 * m + r0
+                                       : (double *)bq + (int64_t)(c0 - W) * m + r0;
+                *dst = acc[jb][r];
+            }
+    }
+}
+
+}  // namespace hz

@@ -134,3 +134,53 @@ def test_product_path_does_not_reach_the_oracle():
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "hz_oracle" not in src, f
                 assert "oracle/" not in src, f
+
+
+def _bcall(hz, batch, mf, mg, n, ptr=8, ld=None, arrays=None, work=None, wb=0):
+    """hz_dgsvd_batched with fake (aligned, never dereferenced) device
+    pointers: only argument checks run, so no GPU is touched."""
+    L = hz.lib()
+    p = hz.params()
+    i64 = lambda v: (ctypes.c_int64 * len(v))(*v) if v is not None else None
+    pv = lambda: (ctypes.c_void_p * max(batch, 1))(*([ptr] * max(batch, 1)))
+    a = dict(mf=i64(mf), mg=i64(mg), n=i64(n), F=pv(), ldf=i64(ld or mf), G=pv(),
+             ldg=i64(ld or mg), Z=pv(), ldz=i64(ld or n), s=pv(), sf=pv(), sg=pv())
+    if arrays:
+        a.update(arrays)
+    return L.hz_dgsvd_batched(ctypes.byref(p), batch, a["mf"], a["mg"], a["n"], a["F"],
+                              a["ldf"], a["G"], a["ldg"], a["Z"], a["ldz"], a["s"], a["sf"],
+                              a["sg"], work, wb, None, None)
+
+
+def test_batched_argument_validation(hz):
+    assert _bcall(hz, -1, [4], [4], [2]) == -2
+    assert _bcall(hz, 70000, [4], [4], [2]) == -2
+    assert _bcall(hz, 0, [4], [4], [2]) == 0          # empty batch: nothing to do
+    assert _bcall(hz, 2, [4, 4], [4, 4], [2, 2], arrays=dict(mf=None)) == -3
+    assert _bcall(hz, 2, [4, 4], [4, 4], [2, 2], arrays=dict(n=None)) == -5
+    assert _bcall(hz, 2, [4, 4], [4, 4], [2, 2], arrays=dict(G=None)) == -8
+    assert _bcall(hz, 2, [4, 4], [4, 4], [2, 2], arrays=dict(sg=None)) == -14
+    # per-pair checks take the single-pair argument index + 1
+    assert _bcall(hz, 2, [4, 0], [4, 4], [2, 2]) == -3     # m_f < 1
+    assert _bcall(hz, 2, [4, 4], [4, 1], [2, 2]) == -5     # n > m_g
+    assert _bcall(hz, 2, [4, 4], [4, 4], [2, 2], ptr=12) == -6   # misaligned F
+    assert _bcall(hz, 2, [4, 4], [4, 4], [2, 2], arrays=dict(
+        ldz=(ctypes.c_int64 * 2)(2, 1))) == -11
+    assert _bcall(hz, 2, [4, 4], [4, 4], [2, 2], work=ctypes.c_void_p(8)) == -15
+    assert _bcall(hz, 2, [4, 4], [4, 4], [2, 2], work=ctypes.c_void_p(256), wb=16) == -16
+
+
+def test_batched_work_size(hz):
+    L = hz.lib()
+    i64 = lambda v: (ctypes.c_int64 * len(v))(*v)
+    p = hz.params()
+    one = [L.hz_dgsvd_work_size(ctypes.byref(hz.params(w=16)), m, g, k)
+           for m, g, k in ((300, 256, 200), (90, 60, 40))]
+    both = L.hz_dgsvd_batched_work_size(ctypes.byref(p), 2, i64([300, 90]), i64([256, 60]),
+                                        i64([200, 40]))
+    assert both > 0 and both % 256 == 0
+    # at least the working copies of both pairs
+    assert both > 8 * (320 + 256 + 256) * 224
+    assert L.hz_dgsvd_batched_work_size(ctypes.byref(p), 1, i64([3]), i64([3]), i64([4])) == 0
+    assert L.hz_dgsvd_batched_work_size(ctypes.byref(p), 0, None, None, None) == 256
+    assert min(one) > 0
