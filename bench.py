@@ -12,7 +12,11 @@ device-to-device copies, inside the timed region, <0.1% of a solve).
 Prints one JSON line: solves/s, the measured per-kernel split, the roofline
 entry of the dominant kernel (algorithmic bytes or flops per launch over its
 average launch time, measured with HIP events on the solve's stream) and the
-CPU oracle timed on a bounded sample on the host.
+CPU oracle timed on a bounded sample on the host.  Unless --no-forms is
+given, the line also carries the mixed-precision form against plain FP64 on
+the 8192 x 2048 pair and the batched form against a loop of single-pair
+solves on the 512-pair ensemble (wall time of each, same parameters, with
+the accuracy each reaches).
 """
 
 import argparse
@@ -74,6 +78,93 @@ def cpu_baseline(F, G, tol, golden_sweeps):
                        f"scaled by the {sweeps} sweeps the oracle needs on this pair")
 
 
+def _timed(fn, reps):
+    import torch
+    best, out = None, None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    return best, out
+
+
+def mixed_vs_plain(reps=2):
+    """hz_dgsvd_mixed against hz_dgsvd on the seeded 8192 x 2048 pair (w = 32,
+    one inner sweep, tol = n eps); both restore the pair from device copies
+    inside the timed call (two 128 MiB copies)."""
+    import torch
+    import gsvd_inputs as gi
+    import paper_1909_00101_amd as hz
+    spec = gi.CONFIGS[4]
+    F, G, s_true = gi.config_pair(4)
+    dev = torch.device("cuda:0")
+    F0, G0 = torch.from_numpy(F).to(dev), torch.from_numpy(G).to(dev)
+    Fw, Gw = F0.clone(), G0.clone()
+    kw = dict(w=32, inner_max_sweeps=1, tol=spec.n * np.finfo(np.float64).eps)
+    res = {}
+    for name, mixed in (("plain", False), ("mixed", True)):
+        def run():
+            Fw.copy_(F0)
+            Gw.copy_(G0)
+            return hz.gsvd(Fw, Gw, overwrite=True, mixed=mixed, **kw)
+        run()
+        dt, r = _timed(run, reps)
+        err = float(np.max(np.abs(r["sigma"].cpu().numpy() - s_true) / s_true))
+        res[name] = dict(ms=round(dt * 1e3, 2), sweeps_fp64=r["sweeps"],
+                         sweeps_fp32=r["sweeps_fp32"], max_rel_sigma_err=err, status=r["status"])
+    del F0, G0, Fw, Gw
+    torch.cuda.empty_cache()
+    return dict(workload=f"seeded {spec.m_f}x{spec.n} real pair, kappa(X)=1e2, w=32, "
+                         f"one inner sweep, tol=n*eps",
+                speedup=round(res["plain"]["ms"] / res["mixed"]["ms"], 3), **res)
+
+
+def batched_vs_plain(tune_cache=None, reps=3):
+    """hz_dgsvd_batched on the 512-pair ensemble (n ~ U{16..256}, m ~ U{n..2n})
+    against hz_dgsvd called on each pair in turn, both with the parameters
+    the batched autotuner picks (or its defaults with one inner sweep); the
+    pairs are restored from device copies in both."""
+    import torch
+    import gsvd_inputs as gi
+    import paper_1909_00101_amd as hz
+    pairs = gi.make_batch()
+    dev = torch.device("cuda:0")
+    D = [(torch.from_numpy(F).to(dev), torch.from_numpy(G).to(dev)) for F, G, _ in pairs]
+    W = [(F.clone(), G.clone()) for F, G in D]
+    S = [s for _, _, s in pairs]
+    kw = dict(inner_max_sweeps=1)
+    if tune_cache is not None:
+        kw, _ = hz.tune_batched(D, cache=tune_cache)
+
+    def restore():
+        for (f0, g0), (f, g) in zip(D, W):
+            f.copy_(f0)
+            g.copy_(g0)
+
+    def batched():
+        restore()
+        return hz.gsvd_batched(W, overwrite=True, **kw)
+
+    def loop():
+        restore()
+        return [hz.gsvd(f, g, overwrite=True, **kw) for f, g in W]
+
+    batched()
+    tb, (st, outs) = _timed(batched, reps)
+    eb = max(float(np.max(np.abs(o["sigma"].cpu().numpy() - s) / s)) for o, s in zip(outs, S))
+    tl, louts = _timed(loop, 1)
+    el = max(float(np.max(np.abs(o["sigma"].cpu().numpy() - s) / s)) for o, s in zip(louts, S))
+    return dict(workload="512 seeded real pairs, n~U{16..256}, m_F,m_G~U{n..2n}, "
+                         "kappa log-uniform in [1,1e2]", params=kw,
+                batched_ms=round(tb * 1e3, 2), loop_ms=round(tl * 1e3, 2),
+                speedup=round(tl / tb, 2), pairs_per_s=round(len(pairs) / tb, 1),
+                status=st, max_sweeps=max(o["sweeps"] for o in outs),
+                max_rel_sigma_err_batched=eb, max_rel_sigma_err_loop=el)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +173,13 @@ def main():
     ap.add_argument("--w", type=int, default=32)
     ap.add_argument("--inner-max-sweeps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the mixed-precision and batched comparisons")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use --w/--inner-max-sweeps and library defaults, no autotuner")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1909_00101_amd",
+                                                         "tune_cache.txt"),
+                    help="autotuner cache file (read, and appended to on a miss)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
@@ -103,6 +201,12 @@ def main():
     Fw = F0.clone()
     Gw = G0.clone()
     kw = dict(w=args.w, ordering=hz.HZ_ORD_MM, tol=tol, inner_max_sweeps=args.inner_max_sweeps)
+    tune_cache = None if args.no_tune else args.tune_cache
+    if tune_cache is not None:
+        # block width, ordering and tolerance are the workload's; the tuner
+        # picks the inner sweep cap, Gram splits, update rows and inner lanes
+        best, _ = hz.tune(F0, G0, cache=tune_cache, w=args.w, ordering=hz.HZ_ORD_MM, tol=tol)
+        kw.update(best)
     p = hz.params(**kw)
     nbytes = hz.lib().hz_dgsvd_work_size(ctypes.byref(p), spec.m_f, spec.m_g, spec.n)
     work = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
@@ -187,11 +291,14 @@ def main():
                config=dict(workload="blocked real FP64 GSVD of a seeded 4096x1024 pair "
                                     "(kappa(X)=1e2, sigma log-uniform in [1e-3,1e3])",
                            m_f=spec.m_f, m_g=spec.m_g, n=spec.n, w=args.w, ordering="MM",
-                           inner_max_sweeps=args.inner_max_sweeps, tol="1024*eps",
-                           parallelism="single GPU"),
+                           tol="1024*eps", parallelism="single GPU",
+                           launch={k: kw[k] for k in ("inner_max_sweeps", "inner_lanes",
+                                                      "gram_splits", "update_rows") if k in kw}),
                sweeps=sweeps, max_rel_sigma_err_vs_prescribed=err,
                fp64_mfma_util_solve=round(mfma_util, 4),
                kernel_time_split=split, kernels=per_kernel, roofline=roof)
+    if not args.no_forms:
+        out["forms"] = dict(mixed=mixed_vs_plain(), batched=batched_vs_plain(tune_cache))
     if not args.no_cpu_baseline:
         golden = os.path.join(ROOT, "tests", "golden", "oracle_config2.json")
         gs = None

@@ -230,6 +230,38 @@ int hz_dgsvd_batched(const hz_params *p, int batch, const int64_t *m_f, const in
 size_t hz_dgsvd_batched_work_size(const hz_params *p, int batch, const int64_t *m_f,
                                   const int64_t *m_g, const int64_t *n);
 
+/* Autotuner (the launch-parameter search the batched and single-pair
+ * forms use).  Starting from p (NULL = defaults), every tunable field that
+ * p leaves at 0 -- w, gram_splits, update_rows, inner_lanes -- and the
+ * choice between one inner sweep and p->inner_max_sweeps (block-oriented
+ * or full-block inner level, Section 3.5) is varied in turn with the
+ * others held at the best so far; each candidate is timed as a complete
+ * solve up to, not including, the final extraction, which reads F and G
+ * (device, caller-owned, left unmodified) and writes only a scratch
+ * workspace the tuner allocates.  Only candidates that converge count.
+ * The fastest is written to *best (host) and its time in milliseconds to
+ * *best_ms (host, may be NULL), and appended to the text file cache_path
+ * (may be NULL) under a key of the sizes, the fixed parameters, the device
+ * and the library version; a later call with the same key returns the
+ * cached choice without timing, so the parameters -- and hence the
+ * results, which depend on w and the Gram splits -- stay the same from run
+ * to run.  Returns HZ_OK, HZ_ENOCONV (no candidate converged), HZ_EHIP, or
+ * -(argument index): hz_dgsvd_tune 1 p, 2 m_f, 3 m_g, 4 n, 5 F, 6 ldf,
+ * 7 G, 8 ldg, 9 cache_path, 10 best, 11 best_ms, 12 stream. */
+int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const double *F,
+                  int64_t ldf, const double *G, int64_t ldg, const char *cache_path,
+                  hz_params *best, double *best_ms, void *stream);
+
+/* Autotuner of the batched form: as hz_dgsvd_tune over w, inner_lanes and
+ * the inner sweep cap, timing hz_dgsvd_batched without the extraction.
+ * Arguments: 1 p, 2 batch (1..65535), 3 m_f, 4 m_g, 5 n (host arrays),
+ * 6 F, 7 ldf, 8 G, 9 ldg (host arrays; device matrices left unmodified),
+ * 10 cache_path, 11 best, 12 best_ms, 13 stream. */
+int hz_dgsvd_batched_tune(const hz_params *p, int batch, const int64_t *m_f, const int64_t *m_g,
+                          const int64_t *n, const double *const *F, const int64_t *ldf,
+                          const double *const *G, const int64_t *ldg, const char *cache_path,
+                          hz_params *best, double *best_ms, void *stream);
+
 /* Short English description of a status code. */
 const char *hz_strerror(int status);
 

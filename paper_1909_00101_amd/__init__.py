@@ -122,6 +122,15 @@ def lib():
                                        pp, pa, pp, pa, pp, pa, pp, pp, pp, vp, ctypes.c_size_t,
                                        ctypes.POINTER(HzInfo), vp]
         L.hz_dgsvd_batched.restype = ctypes.c_int
+        L.hz_dgsvd_tune.argtypes = [ctypes.POINTER(HzParams), i64, i64, i64, dp, i64, dp, i64,
+                                    ctypes.c_char_p, ctypes.POINTER(HzParams),
+                                    ctypes.POINTER(ctypes.c_double), vp]
+        L.hz_dgsvd_tune.restype = ctypes.c_int
+        L.hz_dgsvd_batched_tune.argtypes = [ctypes.POINTER(HzParams), ctypes.c_int, pa, pa, pa,
+                                            pp, pa, pp, pa, ctypes.c_char_p,
+                                            ctypes.POINTER(HzParams),
+                                            ctypes.POINTER(ctypes.c_double), vp]
+        L.hz_dgsvd_batched_tune.restype = ctypes.c_int
         L.hz_version.argtypes = []
         L.hz_version.restype = ctypes.c_char_p
         _lib = L
@@ -301,3 +310,52 @@ def gsvd_batched(pairs, *, overwrite=False, workspace=None, **kw):
                         converged=bool(f.converged), w=f.w, rot_total=f.rot_total,
                         rot_big=f.rot_big, inner_sweeps=f.inner_sweeps))
     return st, out
+
+
+_TUNED = ("w", "inner_max_sweeps", "inner_lanes", "gram_splits", "update_rows")
+
+
+def tune(F, G, *, cache=None, **kw):
+    """Autotune the single-pair real solver on (F, G) (float64 CUDA tensors,
+    not modified) with hz_dgsvd_tune.  Fields given in ``kw`` stay fixed;
+    returns (dict of the chosen parameters, milliseconds of the timed
+    solve).  ``cache`` names the text file that persists the choice."""
+    import torch
+    L = lib()
+    F = _colmajor(F)
+    G = _colmajor(G)
+    if F.dtype != torch.float64 or G.dtype != torch.float64:
+        raise TypeError("the tuner takes float64 pairs")
+    p = params(**kw)
+    best = HzParams()
+    ms = ctypes.c_double()
+    stream = torch.cuda.current_stream(F.device).cuda_stream
+    st = L.hz_dgsvd_tune(ctypes.byref(p), F.shape[0], G.shape[0], F.shape[1], _ptr(F), _ld(F),
+                         _ptr(G), _ld(G), cache.encode() if cache else None, ctypes.byref(best),
+                         ctypes.byref(ms), ctypes.c_void_p(stream))
+    if st != 0:
+        raise GsvdError(st, None) if st > 0 else ValueError(f"hz_dgsvd_tune rejected argument {-st}")
+    return {k: getattr(best, k) for k in _TUNED}, ms.value
+
+
+def tune_batched(pairs, *, cache=None, **kw):
+    """Autotune the batched solver on [(F_i, G_i), ...] (not modified) with
+    hz_dgsvd_batched_tune; returns (chosen parameters, milliseconds)."""
+    import torch
+    L = lib()
+    Fs = [_colmajor(F) for F, _ in pairs]
+    Gs = [_colmajor(G) for _, G in pairs]
+    batch = len(pairs)
+    p = params(**kw)
+    best = HzParams()
+    ms = ctypes.c_double()
+    stream = torch.cuda.current_stream(Fs[0].device).cuda_stream
+    st = L.hz_dgsvd_batched_tune(ctypes.byref(p), batch, _i64s([f.shape[0] for f in Fs]),
+                                 _i64s([g.shape[0] for g in Gs]), _i64s([f.shape[1] for f in Fs]),
+                                 _ptrs(Fs), _i64s([_ld(f) for f in Fs]), _ptrs(Gs),
+                                 _i64s([_ld(g) for g in Gs]), cache.encode() if cache else None,
+                                 ctypes.byref(best), ctypes.byref(ms), ctypes.c_void_p(stream))
+    if st != 0:
+        raise GsvdError(st, None) if st > 0 else ValueError(
+            f"hz_dgsvd_batched_tune rejected argument {-st}")
+    return {k: getattr(best, k) for k in _TUNED}, ms.value

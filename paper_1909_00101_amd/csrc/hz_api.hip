@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <mutex>
 #include <vector>
 
@@ -256,7 +257,7 @@ enum { KIND_REAL = 0, KIND_COMPLEX = 1, KIND_MIXED = 2 };
 static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t work_bytes,
                      hz_info *info, hipStream_t st, int kind, const void *F, int64_t ldf,
                      const void *G, int64_t ldg, void *U, void *V, void *Z, int64_t ldz,
-                     double *sigma, double *sigma_f, double *sigma_g);
+                     double *sigma, double *sigma_f, double *sigma_g, bool finish = true);
 
 }  // namespace hz
 
@@ -464,7 +465,7 @@ namespace hz {
 static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t work_bytes,
                      hz_info *info, hipStream_t st, int kind, const void *F, int64_t ldf,
                      const void *G, int64_t ldg, void *U, void *V, void *Z, int64_t ldz,
-                     double *sigma, double *sigma_f, double *sigma_g)
+                     double *sigma, double *sigma_f, double *sigma_g, bool finish)
 {
     (void)work_bytes;
     int rc = HZ_OK;
@@ -589,7 +590,7 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
                 }
             }
         }
-        if (!(hs[ST_FLAGS] & FLAG_CHOL)) {
+        if (finish && !(hs[ST_FLAGS] & FLAG_CHOL)) {
             if (kind == KIND_COMPLEX)
                 launch_finish_cplx(P, W, (double *)U, ldf, (double *)V, ldg, (double *)Z, ldz,
                                    sigma, sigma_f, sigma_g, st);
@@ -776,7 +777,8 @@ static int run_batched(const hz_params &prm, int batch, const int64_t *mf, const
                        const int64_t *n, double *const *F, const int64_t *ldf, double *const *G,
                        const int64_t *ldg, double *const *Z, const int64_t *ldz,
                        double *const *sigma, double *const *sigma_f, double *const *sigma_g,
-                       const BLayout &L, void *work, hz_info *infos, hipStream_t st)
+                       const BLayout &L, void *work, hz_info *infos, hipStream_t st,
+                       bool finish = true)
 {
     int rc = HZ_OK;
     bool own = false;
@@ -881,7 +883,7 @@ static int run_batched(const hz_params &prm, int batch, const int64_t *mf, const
             }
         }
         HZ_CHECK(hipMemcpyAsync(base, hm, L.meta, hipMemcpyHostToDevice, st));
-        for (int i = 0; i < batch; ++i) {
+        for (int i = 0; i < batch && finish; ++i) {
             if (n[i] != 1) continue;
             launch_n1_real(mf[i], mg[i], F[i], G[i], Z[i], sigma[i], sigma_f[i], sigma_g[i],
                            B.pstatus + (size_t)i * ST_NSLOTS, st);
@@ -908,7 +910,7 @@ static int run_batched(const hz_params &prm, int batch, const int64_t *mf, const
             ++sweeps;
             if (nact == 0) break;
         }
-        launchb_finish(B, st);
+        if (finish) launchb_finish(B, st);
         HZ_CHECK(hipGetLastError());
         HZ_CHECK(hipMemcpyAsync(hinfo.data(), B.pinfo, hinfo.size() * sizeof(int),
                                 hipMemcpyDeviceToHost, st));
@@ -991,6 +993,267 @@ int hz_dgsvd_batched(const hz_params *p, int batch, const int64_t *m_f, const in
     if (work && work_bytes < L.total) return -16;
     return run_batched(prm, batch, m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g,
                        L, work, infos, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ autotuner
+// Chooses launch parameters by timing complete solves without the final
+// extraction (prescale and sweeps to convergence read F and G and write
+// only the workspace, so the caller's data are left as they were).  The
+// choice is appended to a plain-text cache file keyed by the problem
+// sizes, the fixed parameters and the device, so later runs -- and with
+// them the results, which depend on the block width and the reduction
+// splits -- are reproducible without timing again.
+namespace hz {
+
+static uint64_t fnv(uint64_t h, const void *p, size_t n)
+{
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+static uint64_t tune_key(const char *kind, const hz_params &p, int batch, const int64_t *mf,
+                         const int64_t *mg, const int64_t *n)
+{
+    uint64_t h = 14695981039346656037ull;
+    h = fnv(h, kind, strlen(kind));
+    const int fixed[] = {p.variant, p.ordering, p.inner_ordering, p.w, p.max_sweeps, p.sort,
+                         p.inner_lanes, p.gram_splits, p.update_rows};
+    h = fnv(h, fixed, sizeof(fixed));
+    h = fnv(h, &p.tol, sizeof(p.tol));
+    h = fnv(h, &batch, sizeof(batch));
+    h = fnv(h, mf, sizeof(int64_t) * batch);
+    h = fnv(h, mg, sizeof(int64_t) * batch);
+    h = fnv(h, n, sizeof(int64_t) * batch);
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        h = fnv(h, prop.gcnArchName, strlen(prop.gcnArchName));
+        h = fnv(h, &prop.multiProcessorCount, sizeof(int));
+    }
+    const char *ver = hz_version();
+    return fnv(h, ver, strlen(ver));
+}
+
+static std::mutex g_tune_mu;
+
+// Cache line: "<key hex> w inner_max_sweeps inner_lanes gram_splits update_rows ms".
+static bool cache_lookup(const char *path, uint64_t key, hz_params &p, double &ms)
+{
+    if (!path || !*path) return false;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[256];
+    bool hit = false;
+    while (fgets(line, sizeof(line), f)) {
+        unsigned long long k;
+        int w, ims, lp, gs, ur;
+        double t;
+        if (sscanf(line, "%llx %d %d %d %d %d %lf", &k, &w, &ims, &lp, &gs, &ur, &t) == 7 &&
+            k == key) {
+            p.w = w;
+            p.inner_max_sweeps = ims;
+            p.inner_lanes = lp;
+            p.gram_splits = gs;
+            p.update_rows = ur;
+            ms = t;
+            hit = true;     // the last matching line wins
+        }
+    }
+    fclose(f);
+    return hit && params_ok(p);
+}
+
+static void cache_store(const char *path, uint64_t key, const hz_params &p, double ms)
+{
+    if (!path || !*path) return;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%016llx %d %d %d %d %d %.4f\n", (unsigned long long)key, p.w, p.inner_max_sweeps,
+            p.inner_lanes, p.gram_splits, p.update_rows, ms);
+    fclose(f);
+}
+
+static double now_ms()
+{
+    return std::chrono::duration<double, std::milli>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// Coordinate search: each tunable that the caller left at 0 is varied in
+// turn with the others held at the best values so far; a candidate counts
+// only if it converges.  Returns the best time (ms) or a negative status.
+template <typename Solve>
+static double coordinate_search(hz_params &best, const std::vector<std::vector<int>> &axes,
+                                const std::vector<int *> &fields, Solve solve)
+{
+    double best_ms = -1.0;
+    {
+        const double t = solve(best);
+        if (t >= 0.0) best_ms = t;
+    }
+    for (size_t a = 0; a < axes.size(); ++a) {
+        const int keep = *fields[a];
+        int arg = keep;
+        for (int v : axes[a]) {
+            if (v == keep) continue;
+            hz_params c = best;
+            // the field pointers address `best`; write into the copy instead
+            *(int *)((char *)&c + ((char *)fields[a] - (char *)&best)) = v;
+            if (!params_ok(c)) continue;
+            const double t = solve(c);
+            if (t >= 0.0 && (best_ms < 0.0 || t < best_ms)) {
+                best_ms = t;
+                arg = v;
+            }
+        }
+        *fields[a] = arg;
+    }
+    return best_ms;
+}
+
+}  // namespace hz
+
+extern "C" {
+
+int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const double *F,
+                  int64_t ldf, const double *G, int64_t ldg, const char *cache_path,
+                  hz_params *best, double *best_ms, void *stream)
+{
+    hz_params base;
+    if (p) base = *p; else hz_default_params(&base);
+    if (!params_ok(base)) return -1;
+    const double dummy = 0.0;
+    const int a = check_args(m_f, m_g, n, F, ldf, G, ldg, &dummy, n, &dummy, &dummy, &dummy);
+    if (a) return a;
+    if (!best) return -10;
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t key = tune_key("dgsvd", base, 1, &m_f, &m_g, &n);
+    hz_params cur = base;
+    double ms = 0.0;
+    if (cache_lookup(cache_path, key, cur, ms)) {
+        *best = cur;
+        if (best_ms) *best_ms = ms;
+        return HZ_OK;
+    }
+    if (n < 2) {
+        *best = base;
+        if (best_ms) *best_ms = 0.0;
+        return HZ_OK;
+    }
+    int herr = 0;
+    auto solve = [&](const hz_params &c) -> double {
+        Plan P;
+        if (!make_plan(c, m_f, m_g, n, 0, P)) return -1.0;
+        void *work = nullptr;
+        if (hipMalloc(&work, P.total) != hipSuccess) { herr = 1; return -1.0; }
+        hz_info info;
+        memset(&info, 0, sizeof(info));
+        (void)hipStreamSynchronize(st);
+        const double t0 = now_ms();
+        const int rc = run_solve(c, P, work, P.total, &info, st, KIND_REAL, F, ldf, G, ldg,
+                                 nullptr, nullptr, nullptr, n, nullptr, nullptr, nullptr, false);
+        const double t = now_ms() - t0;
+        (void)hipFree(work);
+        if (rc == HZ_EHIP) herr = 1;
+        return rc == HZ_OK ? t : -1.0;
+    };
+    if (!base.w) cur.w = default_w(n, 0);
+    if (!base.gram_splits) cur.gram_splits = 8;
+    if (!base.update_rows) cur.update_rows = 64;
+    if (!base.inner_lanes) cur.inner_lanes = 0;
+    std::vector<std::vector<int>> axes;
+    std::vector<int *> fields;
+    if (!base.w) { axes.push_back({8, 16, 32}); fields.push_back(&cur.w); }
+    axes.push_back({1, base.inner_max_sweeps});
+    fields.push_back(&cur.inner_max_sweeps);
+    if (!base.gram_splits) { axes.push_back({4, 8, 16}); fields.push_back(&cur.gram_splits); }
+    if (!base.update_rows) { axes.push_back({32, 64, 128}); fields.push_back(&cur.update_rows); }
+    if (!base.inner_lanes) { axes.push_back({8, 16}); fields.push_back(&cur.inner_lanes); }
+    ms = coordinate_search(cur, axes, fields, solve);
+    if (herr) return HZ_EHIP;
+    if (ms < 0.0) return HZ_ENOCONV;
+    *best = cur;
+    if (best_ms) *best_ms = ms;
+    cache_store(cache_path, key, cur, ms);
+    return HZ_OK;
+}
+
+int hz_dgsvd_batched_tune(const hz_params *p, int batch, const int64_t *m_f, const int64_t *m_g,
+                          const int64_t *n, const double *const *F, const int64_t *ldf,
+                          const double *const *G, const int64_t *ldg, const char *cache_path,
+                          hz_params *best, double *best_ms, void *stream)
+{
+    hz_params base;
+    if (p) base = *p; else hz_default_params(&base);
+    if (!params_ok(base)) return -1;
+    if (batch < 1 || batch > 65535) return -2;
+    if (!m_f) return -3;
+    if (!m_g) return -4;
+    if (!n) return -5;
+    if (!F) return -6;
+    if (!ldf) return -7;
+    if (!G) return -8;
+    if (!ldg) return -9;
+    const double dummy = 0.0;
+    for (int i = 0; i < batch; ++i) {
+        const int a = check_args(m_f[i], m_g[i], n[i], F[i], ldf[i], G[i], ldg[i], &dummy, n[i],
+                                 &dummy, &dummy, &dummy);
+        if (a) return a - 1;
+    }
+    if (!best) return -11;
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t key = tune_key("dgsvd_batched", base, batch, m_f, m_g, n);
+    hz_params cur = base;
+    double ms = 0.0;
+    if (cache_lookup(cache_path, key, cur, ms)) {
+        *best = cur;
+        if (best_ms) *best_ms = ms;
+        return HZ_OK;
+    }
+    std::vector<double *> nul((size_t)batch, nullptr);
+    std::vector<int64_t> ldz(n, n + batch);
+    int herr = 0;
+    auto solve = [&](const hz_params &c) -> double {
+        BLayout L;
+        if (!plan_batched(c, batch, m_f, m_g, n, L)) return -1.0;
+        void *work = nullptr;
+        if (hipMalloc(&work, L.total) != hipSuccess) { herr = 1; return -1.0; }
+        std::vector<hz_info> infos((size_t)batch);
+        (void)hipStreamSynchronize(st);
+        const double t0 = now_ms();
+        const int rc = run_batched(c, batch, m_f, m_g, n, (double *const *)F, ldf,
+                                   (double *const *)G, ldg, nul.data(), ldz.data(), nul.data(),
+                                   nul.data(), nul.data(), L, work, infos.data(), st, false);
+        const double t = now_ms() - t0;
+        (void)hipFree(work);
+        if (rc == HZ_EHIP) herr = 1;
+        return rc == HZ_OK ? t : -1.0;
+    };
+    int64_t nmax = 1;
+    for (int i = 0; i < batch; ++i) nmax = n[i] > nmax ? n[i] : nmax;
+    if (!base.w) cur.w = nmax <= 32 ? 8 : 16;
+    std::vector<std::vector<int>> axes;
+    std::vector<int *> fields;
+    if (!base.w) { axes.push_back({8, 16, 32}); fields.push_back(&cur.w); }
+    axes.push_back({1, base.inner_max_sweeps});
+    fields.push_back(&cur.inner_max_sweeps);
+    if (!base.inner_lanes) { axes.push_back({8, 16}); fields.push_back(&cur.inner_lanes); }
+    ms = coordinate_search(cur, axes, fields, solve);
+    if (herr) return HZ_EHIP;
+    if (ms < 0.0) return HZ_ENOCONV;
+    *best = cur;
+    if (best_ms) *best_ms = ms;
+    cache_store(cache_path, key, cur, ms);
+    return HZ_OK;
 }
 
 }  // extern "C"

@@ -184,3 +184,28 @@ def test_batched_work_size(hz):
     assert L.hz_dgsvd_batched_work_size(ctypes.byref(p), 1, i64([3]), i64([3]), i64([4])) == 0
     assert L.hz_dgsvd_batched_work_size(ctypes.byref(p), 0, None, None, None) == 256
     assert min(one) > 0
+
+
+def test_tuner_argument_validation(hz):
+    L = hz.lib()
+    p = hz.params()
+    best = hz.HzParams()
+    v = ctypes.c_void_p(8)
+    assert L.hz_dgsvd_tune(ctypes.byref(p), 0, 4, 2, v, 4, v, 4, None, ctypes.byref(best),
+                           None, None) == -2
+    assert L.hz_dgsvd_tune(ctypes.byref(p), 4, 4, 5, v, 4, v, 4, None, ctypes.byref(best),
+                           None, None) == -4
+    assert L.hz_dgsvd_tune(ctypes.byref(p), 4, 4, 2, v, 4, v, 4, None, None, None, None) == -10
+    bad = hz.params(w=12)
+    assert L.hz_dgsvd_tune(ctypes.byref(bad), 4, 4, 2, v, 4, v, 4, None, ctypes.byref(best),
+                           None, None) == -1
+    i64 = lambda vals: (ctypes.c_int64 * len(vals))(*vals)
+    pv = (ctypes.c_void_p * 1)(8)
+    assert L.hz_dgsvd_batched_tune(ctypes.byref(p), 0, i64([4]), i64([4]), i64([2]), pv,
+                                   i64([4]), pv, i64([4]), None, ctypes.byref(best), None,
+                                   None) == -2
+    assert L.hz_dgsvd_batched_tune(ctypes.byref(p), 1, i64([4]), i64([4]), i64([2]), pv,
+                                   i64([3]), pv, i64([4]), None, ctypes.byref(best), None,
+                                   None) == -7
+    assert L.hz_dgsvd_batched_tune(ctypes.byref(p), 1, i64([4]), i64([4]), i64([2]), pv,
+                                   i64([4]), pv, i64([4]), None, None, None, None) == -11
