@@ -78,6 +78,33 @@ def cpu_baseline(F, G, tol, golden_sweeps):
                        f"scaled by the {sweeps} sweeps the oracle needs on this pair")
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gsvd_real_4096x1024_w32_bo_traffic.txt")
+KERNEL_SOURCES = ["paper_1909_00101_amd/csrc/hz_real.hip", "paper_1909_00101_amd/csrc/hz_kernels_real.h",
+                  "paper_1909_00101_amd/csrc/hz_device.h"]
+
+
+def measured_traffic():
+    """HBM bytes per dispatch of each kernel of the 4096x1024 workload, from
+    the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (each counter
+    scaled by its reading for a 32 MiB device copy).  Empty when the kernel
+    sources have changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return {}
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read()
+                                for f in KERNEL_SOURCES)).hexdigest()[:16]
+    out, sha = {}, None
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("#") or not line.strip():
+            continue
+        t = line.split()
+        if t[0] == "source_sha":
+            sha = t[1]
+        elif len(t) == 7:
+            out[t[0]] = (float(t[5]) + float(t[6])) * 2.0 ** 20
+    return out if sha == h else {}
+
+
 def _timed(fn, reps):
     import torch
     best, out = None, None
@@ -266,12 +293,22 @@ def main():
             roof = dict(bound="mfma", achieved=round(achieved, 2), peak=FP64_MFMA_PEAK_TFS,
                         unit="TFLOP/s", frac=round(achieved / FP64_MFMA_PEAK_TFS, 4),
                         traffic=None)
-    roof["kernel"] = f"k_{dom}<W2={2 * args.w}>"
+    lp = kw.get("inner_lanes") or (16 if args.w == 32 else 8)
+    names = {"gram": [f"hz::k_gram<{2 * args.w}>", f"hz::k_gram_sum<{2 * args.w}>"],
+             "inner": [f"hz::k_inner<{2 * args.w},{lp}>"],
+             "update": [f"hz::k_update<{2 * args.w}>"]}
+    traffic = measured_traffic()
+    tr = {k: (sum(traffic[n] for n in v) if all(n in traffic for n in v) else None)
+          for k, v in names.items()}
+    roof["traffic"] = tr[dom]
+    roof["kernel"] = "+".join(names[dom])
     roof["avg_launch_us"] = round(t_launch * 1e6, 2)
     if intensity is not None:
         roof["intensity_flop_per_byte"] = round(intensity, 2)
     per_kernel = {k: dict(avg_us=round(v[0] / max(1, v[1]) * 1e3, 2), launches=int(v[1]))
                   for k, v in kinds.items()}
+    for k in kinds:
+        per_kernel[k]["traffic_bytes"] = tr[k]
     for k in ("gram", "update"):
         wd = kinds[k][2]
         t = kinds[k][0] / max(1, kinds[k][1]) * 1e-3

@@ -32,12 +32,15 @@ __device__ __forceinline__ double group_sum(double v)
 __device__ __forceinline__ double wave_sum(double v) { return group_sum<64>(v); }
 
 // DPP lane exchange of a double within a row of 16 lanes (two 32-bit moves).
+// Every pattern used here reads a lane of the same row, so bound_ctrl (read
+// 0 from an invalid source lane) never applies; it lets the move write a
+// fresh register instead of one tied to, and first copied from, the source.
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v)
 {
     const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp((int)b, (int)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
