@@ -209,9 +209,8 @@ def main():
                     help="autotuner cache file (read, and appended to on a miss)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the solver runs on a single MI355X "
-              "(see DESIGN.md for how the path would shard); run with --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the solver runs on a single MI355X; "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -247,7 +246,20 @@ def main():
         r = solve()
     torch.cuda.synchronize()
     L = hz.lib()
+    # untimed pass with events around every launch: the per-kernel split
     L.hz_profile_enable(1)
+    solve()
+    torch.cuda.synchronize()
+    ms = (ctypes.c_double * 4)()
+    cnt = (ctypes.c_int64 * 4)()
+    L.hz_profile_read(ms, cnt, 4)
+    kind_index = {"gram": 0, "inner": 1, "update": 2}
+    dom = max(kind_index, key=lambda k: ms[kind_index[k]])
+    split_ms = {k: (ms[i], cnt[i]) for k, i in kind_index.items()}
+    split_pass = dict(split_ms)
+    # timed region: events only around the dominant kernel's launches (events
+    # around every launch would stretch the solve by about 10 %)
+    L.hz_profile_enable(4 + kind_index[dom])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sweeps, isw, rots = [], 0, 0
@@ -258,20 +270,19 @@ def main():
         rots += r["rot_total"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms = (ctypes.c_double * 4)()
-    cnt = (ctypes.c_int64 * 4)()
     L.hz_profile_read(ms, cnt, 4)
     L.hz_profile_enable(0)
+    split_ms[dom] = (ms[kind_index[dom]], cnt[kind_index[dom]])
     err = float(np.max(np.abs(r["sigma"].cpu().numpy() - s_true) / s_true))
 
     gram, upd = algorithmic(spec.m_f, spec.m_g, spec.n, args.w)
     npairs = spec.n // (2 * args.w)
-    inner = dict(flops=inner_flops(args.w, cnt[1], isw, rots, npairs), bytes=None)
-    kinds = {"gram": (ms[0], cnt[0], gram), "inner": (ms[1], cnt[1], inner),
-             "update": (ms[2], cnt[2], upd)}
-    split = {k: round(v[0] / max(1e-9, sum(x[0] for x in kinds.values())), 4)
-             for k, v in kinds.items()}
-    dom = max(kinds, key=lambda k: kinds[k][0])
+    launches_timed = sum(sweeps) * (spec.n // args.w)     # inner launches in the timed solves
+    inner = dict(flops=inner_flops(args.w, launches_timed, isw, rots, npairs), bytes=None)
+    kinds = {"gram": (*split_ms["gram"], gram), "inner": (*split_ms["inner"], inner),
+             "update": (*split_ms["update"], upd)}
+    split = {k: round(v[0] / max(1e-9, sum(x[0] for x in split_pass.values())), 4)
+             for k, v in split_pass.items()}
     t_launch = kinds[dom][0] / max(1, kinds[dom][1]) * 1e-3
     work_d = kinds[dom][2]
     ridge = FP64_MFMA_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)

@@ -152,10 +152,12 @@ int hz_eval_2x2(int64_t count, const double *in, double *out, void *stream);
 int hz_eval_2x2_z(int64_t count, const double *in, double *out, void *stream);
 
 /* Per-kernel timing of later solves in this process, for measurement:
- * with enable = 1 (or 2, see below) every Gram, inner-solve and update launch is bracketed by
- * HIP events on the solve's stream (resolved at the host syncs each sweep
- * already makes), and the sums are cleared; enable = 0 stops collecting.
- * Not for concurrent solves. */
+ * with enable = 1 (or 2, see below) every Gram, inner-solve and update
+ * launch is bracketed by HIP events on the solve's stream (resolved at the
+ * host syncs each sweep already makes), and the sums are cleared; enable =
+ * 3 brackets only the inner-solve launches; enable = 0 stops collecting.
+ * While collecting, sweeps are launched directly instead of replayed from
+ * a captured hipGraph.  Not for concurrent solves. */
 void hz_profile_enable(int enable);
 
 /* With hz_profile_enable(2), the inner solver also stamps the device wall

@@ -132,6 +132,7 @@ static bool make_plan(const hz_params &prm, int64_t mf, int64_t mg, int64_t n, i
     P.o_itab = o; o = align256(o + sizeof(int16_t) * (size_t)P.isteps * P.w * 2);
     P.o_cnt = o; o = align256(o + sizeof(unsigned long long) * (size_t)P.steps * P.npairs * 4);
     P.o_status = o; o = align256(o + sizeof(int) * ST_NSLOTS);
+    P.o_tot = o; o = align256(o + sizeof(unsigned long long) * SWEEP_TOT_N);
     P.o_sf = o; o = align256(o + sizeof(double) * (size_t)P.nw);
     P.o_sg = o; o = align256(o + sizeof(double) * (size_t)P.nw);
     P.o_sig = o; o = align256(o + sizeof(double) * (size_t)P.nw);
@@ -165,6 +166,7 @@ static Ptrs make_ptrs(const Plan &P, void *work)
     W.itab = (int16_t *)(b + P.o_itab);
     W.cnt = (unsigned long long *)(b + P.o_cnt);
     W.status = (int *)(b + P.o_status);
+    W.tot = (unsigned long long *)(b + P.o_tot);
     W.sf = (double *)(b + P.o_sf);
     W.sg = (double *)(b + P.o_sg);
     W.sig = (double *)(b + P.o_sig);
@@ -218,6 +220,7 @@ struct Prof {
     double ms[K_NKINDS] = {0, 0, 0, 0};
     int64_t launches[K_NKINDS] = {0, 0, 0, 0};
     bool phases = false;           // also time the inner solver's phases
+    int only = -1;                 // >= 0: events around launches of this kind only
     double phase_us[5] = {0, 0, 0, 0, 0};
     int64_t phase_n = 0;
 };
@@ -225,7 +228,7 @@ static Prof g_prof;
 
 void prof_mark(int kind, bool begin, hipStream_t s)
 {
-    if (!g_prof.on) return;
+    if (!g_prof.on || (g_prof.only >= 0 && kind != g_prof.only)) return;
     if (g_prof.used == g_prof.pool.size()) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return;
@@ -249,6 +252,21 @@ static void prof_flush()
     }
     g_prof.used = 0;
     g_prof.kind.clear();
+}
+
+// One private non-blocking stream per device to capture the sweep graphs on
+// (the caller's stream may be the null stream, which cannot be captured).
+static hipStream_t capture_stream()
+{
+    static std::mutex mu;
+    static std::vector<hipStream_t> streams;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+        streams[dev] = nullptr;
+    return streams[dev];
 }
 
 enum { KIND_REAL = 0, KIND_COMPLEX = 1, KIND_MIXED = 2 };
@@ -319,6 +337,7 @@ void hz_profile_enable(int enable)
     std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.on = enable != 0;
     g_prof.phases = enable == 2;
+    g_prof.only = (enable >= 4 && enable < 4 + K_NKINDS) ? enable - 4 : -1;
     for (int k = 0; k < 5; ++k) g_prof.phase_us[k] = 0.0;
     g_prof.phase_n = 0;
     g_prof.used = 0;
@@ -470,13 +489,16 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
     (void)work_bytes;
     int rc = HZ_OK;
     bool own = false;
+    hipGraph_t graphs[2] = {nullptr, nullptr};
+    hipGraphExec_t execs[2] = {nullptr, nullptr};
+    unsigned long long *hpin = nullptr;
+    unsigned long long *dphase = nullptr;
     if (!work) {
         if (hipMalloc(&work, P.total) != hipSuccess) return HZ_EHIP;
         own = true;
     }
     {
         Ptrs W = make_ptrs(P, work);
-        unsigned long long *dphase = nullptr;
         std::vector<unsigned long long> hph;
         double clk_khz = 0.0;
         if (g_prof.on && g_prof.phases && kind != KIND_COMPLEX) {
@@ -495,8 +517,6 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
         std::vector<int16_t> itab;
         build_ordering<int>(prm.ordering, P.nblk, otab);
         build_ordering<int16_t>(prm.inner_ordering, P.W2, itab);
-        std::vector<unsigned long long> hc((size_t)P.steps * P.npairs * 4);
-        std::vector<double> hoff;
         int hs[ST_NSLOTS] = {0, INT_MAX, 0, 0};
         uint64_t tot_all = 0, tot_big = 0, tot_isw = 0;
         int sweeps = 0, sweeps32 = 0, converged = 0;
@@ -514,27 +534,41 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
             launch_prescale_real(P, W, (const double *)F, ldf, (const double *)G, ldg, st);
         HZ_CHECK(hipGetLastError());
 
-        // One outer sweep: all block steps, then the counters (and the
-        // off-diagonal measure of an FP32 sweep) read back once (Algorithm 1).
-        auto sweep = [&](bool fp32, uint64_t &s_all, uint64_t &s_big) -> hipError_t {
+        // One outer sweep: all block steps and the end-of-sweep summary,
+        // then SWEEP_TOT_N words read back once (Algorithm 1).  Without the
+        // profiler the sweep is captured once as a hipGraph (per precision)
+        // and replayed.
+        const bool use_graph = !g_prof.on;
+        auto enqueue = [&](bool fp32, hipStream_t s) {
             for (int k = 0; k < P.steps; ++k) {
-                if (fp32) launch_step_mixed32(P, W, k, prm, tol, st);
-                else if (kind == KIND_COMPLEX) launch_step_cplx(P, W, k, prm, tol, st);
-                else launch_step_real(P, W, k, prm, tol, st);
+                if (fp32) launch_step_mixed32(P, W, k, prm, tol, s);
+                else if (kind == KIND_COMPLEX) launch_step_cplx(P, W, k, prm, tol, s);
+                else launch_step_real(P, W, k, prm, tol, s);
             }
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            e = hipMemcpyAsync(hc.data(), W.cnt, hc.size() * sizeof(unsigned long long),
-                               hipMemcpyDeviceToHost, st);
-            if (e != hipSuccess) return e;
-            e = hipMemcpyAsync(hs, W.status, sizeof(hs), hipMemcpyDeviceToHost, st);
-            if (e != hipSuccess) return e;
-            if (fp32) {
-                hoff.resize((size_t)P.steps * P.npairs * 2);
-                e = hipMemcpyAsync(hoff.data(), W.offd, hoff.size() * sizeof(double),
-                                   hipMemcpyDeviceToHost, st);
+            launch_sweep_totals(P, W, s);
+        };
+        auto sweep = [&](bool fp32, uint64_t &s_all, uint64_t &s_big) -> hipError_t {
+            hipError_t e = hipSuccess;
+            const int g = fp32 ? 1 : 0;
+            if (use_graph && !execs[g]) {
+                hipStream_t cs = capture_stream();
+                if (!cs) return hipErrorInvalidValue;
+                e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) return e;
+                enqueue(fp32, cs);
+                e = hipStreamEndCapture(cs, &graphs[g]);
+                if (e != hipSuccess) return e;
+                e = hipGraphInstantiate(&execs[g], graphs[g], nullptr, nullptr, 0);
                 if (e != hipSuccess) return e;
             }
+            if (use_graph) e = hipGraphLaunch(execs[g], st);
+            else enqueue(fp32, st);
+            if (e != hipSuccess) return e;
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            e = hipMemcpyAsync(hpin, W.tot, SWEEP_TOT_N * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, st);
+            if (e != hipSuccess) return e;
             if (dphase) {
                 e = hipMemcpyAsync(hph.data(), dphase, hph.size() * 8, hipMemcpyDeviceToHost, st);
                 if (e != hipSuccess) return e;
@@ -549,16 +583,17 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
                     g_prof.phase_n += 1;
                 }
             }
-            s_all = s_big = 0;
-            for (size_t i = 0; i < hc.size(); i += 4) {
-                s_all += hc[i];
-                s_big += hc[i + 1];
-                tot_isw += hc[i + 2];
-            }
+            s_all = hpin[TOT_ALL];
+            s_big = hpin[TOT_BIG];
+            tot_isw += hpin[TOT_ISW];
+            hs[ST_FLAGS] = (int)hpin[TOT_FLAGS];
+            hs[ST_FAILPAIR] = (int)hpin[TOT_FAILPAIR];
+            if (fp32) last_off = __builtin_bit_cast(double, hpin[TOT_OFFD]);
             tot_all += s_all;
             tot_big += s_big;
             return hipSuccess;
         };
+        HZ_CHECK(hipHostMalloc((void **)&hpin, SWEEP_TOT_N * sizeof(unsigned long long), 0));
 
         if (kind == KIND_MIXED) {
             // FP32 sweeps until the largest scaled off-diagonal Gram entry of a
@@ -568,8 +603,6 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
                 uint64_t s_all, s_big;
                 HZ_CHECK(sweep(true, s_all, s_big));
                 ++sweeps32;
-                last_off = 0.0;
-                for (double v : hoff) last_off = (v > last_off) ? v : last_off;
                 if (hs[ST_FLAGS]) break;
                 if (s_big == 0 || last_off < prm.mixed_switch) break;
             }
@@ -616,16 +649,16 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
             info->last_offdiag = last_off;
             info->status = rc;
         }
-        if (dphase) {
-            (void)hipStreamSynchronize(st);
-            (void)hipFree(dphase);
-        }
     }
 done:
-    if (own) {
-        (void)hipStreamSynchronize(st);
-        (void)hipFree(work);
+    (void)hipStreamSynchronize(st);
+    for (int g = 0; g < 2; ++g) {
+        if (execs[g]) (void)hipGraphExecDestroy(execs[g]);
+        if (graphs[g]) (void)hipGraphDestroy(graphs[g]);
     }
+    if (hpin) (void)hipHostFree(hpin);
+    if (dphase) (void)hipFree(dphase);
+    if (own) (void)hipFree(work);
     return rc;
 }
 
@@ -756,21 +789,6 @@ static int check_batched(int batch, const int64_t *mf, const int64_t *mg, const 
         if (a) return a - 1;
     }
     return 0;
-}
-
-// One private non-blocking stream per device to capture the sweep graph on
-// (the caller's stream may be the null stream, which cannot be captured).
-static hipStream_t capture_stream()
-{
-    static std::mutex mu;
-    static std::vector<hipStream_t> streams;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    std::lock_guard<std::mutex> lk(mu);
-    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
-    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
-        streams[dev] = nullptr;
-    return streams[dev];
 }
 
 static int run_batched(const hz_params &prm, int batch, const int64_t *mf, const int64_t *mg,

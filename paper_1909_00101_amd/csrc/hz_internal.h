@@ -29,7 +29,7 @@ struct Plan {
     int is_complex;
     size_t esz;               // bytes per matrix element (8 or 16)
     // workspace offsets (bytes)
-    size_t o_fw, o_gw, o_zw, o_part, o_gram, o_arrive, o_zt, o_otab, o_itab, o_cnt, o_status;
+    size_t o_fw, o_gw, o_zw, o_part, o_gram, o_arrive, o_zt, o_otab, o_itab, o_cnt, o_status, o_tot;
     size_t o_sf, o_sg, o_sig, o_rank, o_border;
     size_t o_fs, o_gs, o_zs, o_offd;   // mixed form only (FP32 copies, off-diagonal measure)
     int mixed;
@@ -49,6 +49,7 @@ struct Ptrs {
     int *rank, *border;
     float *Fs, *Gs, *Zs;         // mixed form: FP32 working copies
     double *offd;                // mixed form: per (step, pair, matrix) off-diagonal measure
+    unsigned long long *tot;   // per-sweep summary (SWEEP_TOT_N words)
 };
 
 // One pair of a batched solve, as the batched kernels see it.
@@ -104,6 +105,13 @@ void launch_rank(const Plan &P, const Ptrs &W, hipStream_t s);
 void launch_gram_sum(const Plan &P, const Ptrs &W, hipStream_t s);
 void launch_inner_real(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
                        hipStream_t s);
+
+// Per-sweep summary written by k_sweep_totals: sums of the per-(step, pair)
+// counters, the largest off-diagonal measure (mixed form, as bits of a
+// double) and the status words.
+enum { TOT_ALL = 0, TOT_BIG = 1, TOT_ISW = 2, TOT_OFFD = 3, TOT_FLAGS = 4, TOT_FAILPAIR = 5,
+       SWEEP_TOT_N = 8 };
+void launch_sweep_totals(const Plan &P, const Ptrs &W, hipStream_t s);
 
 // launchers (batched), hz_batched.hip
 void launchb_prescale(const BPlan &B, hipStream_t s);

@@ -313,7 +313,58 @@ void launch_eval_2x2(int64_t count, const double *in, double *out, hipStream_t s
                        in, out);
 }
 
+// End-of-sweep summary (one workgroup): totals of the per-(step, pair)
+// counters (integer sums: order-independent), the largest off-diagonal
+// measure of the sweep when offd is given, and the status words, so the
+// host reads SWEEP_TOT_N words per sweep.
+__global__ __launch_bounds__(256) void k_sweep_totals(const unsigned long long *__restrict__ cnt,
+                                                      int n, const double *__restrict__ offd,
+                                                      int noffd, const int *__restrict__ status,
+                                                      unsigned long long *__restrict__ tot)
+{
+    __shared__ unsigned long long s3[3][256];
+    __shared__ double so[256];
+    const int t = threadIdx.x;
+    unsigned long long a = 0, b = 0, c = 0;
+    for (int i = t; i < n; i += 256) {
+        a += cnt[4 * (size_t)i];
+        b += cnt[4 * (size_t)i + 1];
+        c += cnt[4 * (size_t)i + 2];
+    }
+    double m = 0.0;
+    if (offd)
+        for (int i = t; i < noffd; i += 256) m = fmax(m, offd[i]);
+    s3[0][t] = a;
+    s3[1][t] = b;
+    s3[2][t] = c;
+    so[t] = m;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            s3[0][t] += s3[0][t + h];
+            s3[1][t] += s3[1][t + h];
+            s3[2][t] += s3[2][t + h];
+            so[t] = fmax(so[t], so[t + h]);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        tot[TOT_ALL] = s3[0][0];
+        tot[TOT_BIG] = s3[1][0];
+        tot[TOT_ISW] = s3[2][0];
+        tot[TOT_OFFD] = __builtin_bit_cast(unsigned long long, so[0]);
+        tot[TOT_FLAGS] = (unsigned long long)(unsigned)status[ST_FLAGS];
+        tot[TOT_FAILPAIR] = (unsigned long long)(unsigned)status[ST_FAILPAIR];
+    }
+}
+
 // ------------------------------------------------------------------ launchers
+
+void launch_sweep_totals(const Plan &P, const Ptrs &W, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sweep_totals, dim3(1), dim3(256), 0, s, W.cnt, P.steps * P.npairs,
+                       P.mixed ? W.offd : nullptr, P.steps * P.npairs * 2, W.status, W.tot);
+}
 
 void launch_prescale_real(const Plan &P, const Ptrs &W, const double *F, int64_t ldf,
                           const double *G, int64_t ldg, hipStream_t s)
