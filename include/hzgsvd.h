@@ -74,6 +74,10 @@ extern "C" {
 #define HZ_ORD_MM 1
 #define HZ_ORD_RR 2
 
+/* hz_params.schedule */
+#define HZ_SCHED_STEPS 1
+#define HZ_SCHED_DATAFLOW 2
+
 typedef struct hz_params {
     int variant;          /* 0 only: criterion C1, prescaled, ordinary dots (Table 1) */
     int ordering;         /* outer block ordering, HZ_ORD_MM (default) or HZ_ORD_RR */
@@ -93,6 +97,10 @@ typedef struct hz_params {
     int inner_lanes;      /* lanes per column pair in the inner solver: 8 or 16 */
     int gram_splits;      /* row splits of the Gram kernel (1..16) */
     int update_rows;      /* rows per wave in the update kernel (multiple of 16) */
+    int schedule;         /* real FP64 path: 0 = default, HZ_SCHED_STEPS = one launch per
+                             phase and block step, HZ_SCHED_DATAFLOW = one persistent
+                             launch per sweep whose workgroups take Gram, inner-solve and
+                             update tasks from a dependency-ordered queue (w = 32 only) */
 } hz_params;
 
 typedef struct hz_info {
@@ -136,6 +144,17 @@ int hz_dgsvd(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n,
  * number of steps (N or N - 1), or -1 for a bad kind or N.  table may be
  * NULL to query the step count. */
 int hz_ordering(int kind, int N, int *table);
+
+/* Diagnostic: the task list of one sweep of the dataflow schedule
+ * (HZ_SCHED_DATAFLOW) for these sizes and parameters (w must be 32).
+ * Returns the number of tasks, or -1 if the schedule does not apply.
+ * tasks (host, 4 ints per task: kind 0 = Gram / 1 = inner / 2 = update,
+ * step, pair, sub-index), parents (host, 2 ints per (step, pair): the pairs
+ * of the previous step holding its two block columns) and info (host,
+ * 4 ints: steps, pairs per step, Gram splits per matrix, update tiles per
+ * pair) may each be NULL. */
+int hz_dataflow_tasks(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, int *tasks,
+                      int *parents, int *info);
 
 /* Diagnostic: evaluate the device's real 2x2 transformation (the one the
  * inner solver uses, Section 2.1.2) on `count` pivot pairs.  in (device,

@@ -18,6 +18,9 @@
 namespace hz {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Largest persistent grid of the dataflow schedule.
+static constexpr int DF_MAX_WG = 1024;
 static int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 // Parallel orderings of Section 2.2 on N (even) indices; table[k][l] = (p, q).
@@ -66,6 +69,7 @@ static int build_ordering(int kind, int N, std::vector<T> &tab)
 static int params_ok(const hz_params &p)
 {
     if (p.variant != 0) return 0;
+    if (p.schedule != 0 && p.schedule != HZ_SCHED_STEPS && p.schedule != HZ_SCHED_DATAFLOW) return 0;
     if (p.ordering != HZ_ORD_MM && p.ordering != HZ_ORD_RR) return 0;
     if (p.inner_ordering != HZ_ORD_MM && p.inner_ordering != HZ_ORD_RR) return 0;
     if (p.w != 0 && p.w != 8 && p.w != 16 && p.w != 32) return 0;
@@ -138,6 +142,22 @@ static bool make_plan(const hz_params &prm, int64_t mf, int64_t mg, int64_t n, i
     P.o_sig = o; o = align256(o + sizeof(double) * (size_t)P.nw);
     P.o_rank = o; o = align256(o + sizeof(int) * (size_t)P.nw);
     P.o_border = o; o = align256(o + sizeof(int) * (size_t)P.nw);
+    P.dataflow = !is_complex && !mixed && P.W2 == 64 && P.inner_lp == 16 &&
+                 prm.schedule == HZ_SCHED_DATAFLOW;
+    if (P.dataflow) {
+        P.df_tile_rows = 4 * (int64_t)P.upd_rows;
+        P.df_tiles_f = (int)((P.mfw + P.df_tile_rows - 1) / P.df_tile_rows);
+        P.df_tiles_g = (int)((P.mgw + P.df_tile_rows - 1) / P.df_tile_rows);
+        P.df_tiles_z = (int)((P.nzw + P.df_tile_rows - 1) / P.df_tile_rows);
+        const size_t kl = (size_t)P.steps * P.npairs;
+        P.df_ntasks = (int)(kl * (2 * P.splits + 1 + P.df_tiles_f + P.df_tiles_g + P.df_tiles_z));
+        P.o_dpart = o; o = align256(o + 8 * kl * 2 * P.splits * P.W2 * P.W2);
+        P.o_dzt = o; o = align256(o + 8 * kl * P.W2 * P.W2);
+        P.o_dtask = o; o = align256(o + 16 * (size_t)P.df_ntasks);
+        P.o_dpar = o; o = align256(o + 8 * kl);
+        P.o_ddep = o; o = align256(o + 4 * (3 * kl + 4));
+        P.o_dwg = o; o = align256(o + 4 * ((size_t)DF_MAX_WG + 1 + P.df_ntasks));
+    }
     P.mixed = mixed;
     if (mixed) {
         P.o_fs = o; o = align256(o + sizeof(float) * (size_t)P.mfw * P.nw);
@@ -269,6 +289,69 @@ static hipStream_t capture_stream()
     return streams[dev];
 }
 
+// Task list of one dataflow sweep (hz_dataflow.hip), in dependency order.
+// Step 0: every pair's Gram tasks then its inner task.  Step k > 0: the
+// pairs ordered by the later of their two parents' inner tasks; before a
+// pair's Gram tasks come the update tiles of any parent not yet listed.
+// The last step's update tiles close the list.  parents[k][l] holds the
+// step-(k-1) pairs that held the block columns of pair l of step k.
+static void build_df_tasks(const Plan &P, const std::vector<int> &otab, std::vector<int4> &tasks,
+                           std::vector<int2> &parents)
+{
+    const int NP = P.npairs, NS = P.steps, S = P.splits;
+    const int T = P.df_tiles_f + P.df_tiles_g + P.df_tiles_z;
+    tasks.clear();
+    tasks.reserve(P.df_ntasks);
+    parents.assign((size_t)NS * NP, make_int2(0, 0));
+    std::vector<int> owner(P.nblk), inner_pos((size_t)NS * NP, 0);
+    std::vector<char> upd_listed((size_t)NS * NP, 0);
+    auto emit_pair = [&](int k, int l) {
+        for (int sub = 0; sub < 2 * S; ++sub) tasks.push_back(make_int4(DF_GRAM, k, l, sub));
+        inner_pos[(size_t)k * NP + l] = (int)tasks.size();
+        tasks.push_back(make_int4(DF_INNER, k, l, 0));
+    };
+    auto emit_update = [&](int k, int l) {
+        if (upd_listed[(size_t)k * NP + l]) return;
+        upd_listed[(size_t)k * NP + l] = 1;
+        for (int t = 0; t < T; ++t) tasks.push_back(make_int4(DF_UPDATE, k, l, t));
+    };
+    for (int l = 0; l < NP; ++l) emit_pair(0, l);
+    for (int k = 1; k < NS; ++k) {
+        for (int l = 0; l < NP; ++l) {
+            owner[otab[((size_t)(k - 1) * NP + l) * 2]] = l;
+            owner[otab[((size_t)(k - 1) * NP + l) * 2 + 1]] = l;
+        }
+        std::vector<int> order(NP);
+        std::vector<int> key(NP);
+        for (int l = 0; l < NP; ++l) {
+            const int a = owner[otab[((size_t)k * NP + l) * 2]];
+            const int b = owner[otab[((size_t)k * NP + l) * 2 + 1]];
+            parents[(size_t)k * NP + l] = make_int2(a, b);
+            const int pa = inner_pos[(size_t)(k - 1) * NP + a];
+            const int pb = inner_pos[(size_t)(k - 1) * NP + b];
+            key[l] = pa > pb ? pa : pb;
+            order[l] = l;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key[x] < key[y]; });
+        for (int l : order) {
+            const int2 par = parents[(size_t)k * NP + l];
+            const int pa = inner_pos[(size_t)(k - 1) * NP + par.x];
+            const int pb = inner_pos[(size_t)(k - 1) * NP + par.y];
+            if (pa <= pb) { emit_update(k - 1, par.x); emit_update(k - 1, par.y); }
+            else { emit_update(k - 1, par.y); emit_update(k - 1, par.x); }
+            emit_pair(k, l);
+        }
+    }
+    std::vector<int> last(NP);
+    for (int l = 0; l < NP; ++l) last[l] = l;
+    std::stable_sort(last.begin(), last.end(), [&](int x, int y) {
+        return inner_pos[(size_t)(NS - 1) * NP + x] < inner_pos[(size_t)(NS - 1) * NP + y];
+    });
+    for (int l : last) emit_update(NS - 1, l);
+    for (int k = 0; k + 1 < NS; ++k)
+        for (int l = 0; l < NP; ++l) emit_update(k, l);   // pairs that parent nothing (none in MM)
+}
+
 enum { KIND_REAL = 0, KIND_COMPLEX = 1, KIND_MIXED = 2 };
 
 // The host sweep loop shared by the real, complex and mixed solvers.
@@ -330,6 +413,33 @@ int hz_ordering(int kind, int N, int *table)
     const int steps = build_ordering<int>(kind, N, t);
     if (table) memcpy(table, t.data(), t.size() * sizeof(int));
     return steps;
+}
+
+int hz_dataflow_tasks(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, int *tasks,
+                      int *parents, int *info)
+{
+    hz_params prm;
+    if (p) prm = *p; else hz_default_params(&prm);
+    prm.schedule = HZ_SCHED_DATAFLOW;
+    if (!params_ok(prm) || m_f < n || m_g < n || n < 2) return -1;
+    Plan P;
+    if (!make_plan(prm, m_f, m_g, n, 0, P) || !P.dataflow) return -1;
+    if (info) {
+        info[0] = P.steps;
+        info[1] = P.npairs;
+        info[2] = P.splits;
+        info[3] = P.df_tiles_f + P.df_tiles_g + P.df_tiles_z;
+    }
+    if (tasks || parents) {
+        std::vector<int> otab;
+        build_ordering<int>(prm.ordering, P.nblk, otab);
+        std::vector<int4> t;
+        std::vector<int2> par;
+        build_df_tasks(P, otab, t, par);
+        if (tasks) memcpy(tasks, t.data(), t.size() * sizeof(int4));
+        if (parents) memcpy(parents, par.data(), par.size() * sizeof(int2));
+    }
+    return P.df_ntasks;
 }
 
 void hz_profile_enable(int enable)
@@ -526,6 +636,81 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
         HZ_CHECK(hipMemcpyAsync(W.itab, itab.data(), itab.size() * sizeof(int16_t),
                                 hipMemcpyHostToDevice, st));
         HZ_CHECK(hipMemcpyAsync(W.status, hs, sizeof(hs), hipMemcpyHostToDevice, st));
+        DFArgs dfa;
+        int df_wg = 0;
+        std::vector<int4> dtasks;
+        std::vector<int2> dpar;
+        std::vector<int> dwl;
+        hipError_t df_err = hipSuccess;
+        if (P.dataflow) {
+            build_df_tasks(P, otab, dtasks, dpar);
+            char *b = (char *)work;
+            HZ_CHECK(hipMemcpyAsync(b + P.o_dtask, dtasks.data(), dtasks.size() * sizeof(int4),
+                                    hipMemcpyHostToDevice, st));
+            HZ_CHECK(hipMemcpyAsync(b + P.o_dpar, dpar.data(), dpar.size() * sizeof(int2),
+                                    hipMemcpyHostToDevice, st));
+            memset(&dfa, 0, sizeof(dfa));
+            dfa.Fw = W.Fw;
+            dfa.Gw = W.Gw;
+            dfa.Zw = W.Zw;
+            dfa.mfw = P.mfw;
+            dfa.mgw = P.mgw;
+            dfa.nzw = P.nzw;
+            dfa.otab = W.otab;
+            dfa.npairs = P.npairs;
+            dfa.steps = P.steps;
+            dfa.splits = P.splits;
+            dfa.tiles_f = P.df_tiles_f;
+            dfa.tiles_g = P.df_tiles_g;
+            dfa.tiles_z = P.df_tiles_z;
+            dfa.tiles = P.df_tiles_f + P.df_tiles_g + P.df_tiles_z;
+            dfa.tile_rows = P.df_tile_rows;
+            dfa.part = (double *)(b + P.o_dpart);
+            dfa.Zt = (double *)(b + P.o_dzt);
+            dfa.itab = W.itab;
+            dfa.isteps = P.isteps;
+            dfa.inner_max = prm.inner_max_sweeps;
+            dfa.sort = prm.sort;
+            dfa.tol = tol;
+            dfa.cnt = W.cnt;
+            dfa.status = W.status;
+            dfa.tasks = (const int4 *)(b + P.o_dtask);
+            dfa.ntasks = P.df_ntasks;
+            dfa.parents = (const int2 *)(b + P.o_dpar);
+            dfa.dep = (unsigned *)(b + P.o_ddep);
+            dfa.head = dfa.dep + 3 * (size_t)P.steps * P.npairs;
+            dfa.spin_limit = 1u << 20;
+            dfa.err = W.status + ST_FLAGS;
+            int dev = 0, per_cu = 0;
+            HZ_CHECK(hipGetDevice(&dev));
+            HZ_CHECK(hipDeviceGetAttribute(&df_wg, hipDeviceAttributeMultiprocessorCount, dev));
+            HZ_CHECK(df_occupancy(&per_cu));
+            df_wg = df_wg * (per_cu > 0 ? per_cu : 1);
+            if (df_wg > DF_MAX_WG) df_wg = DF_MAX_WG;
+            // per-workgroup task lists: inner tasks round-robin over the
+            // first NI workgroups, Gram and update tasks over the others,
+            // each list in ascending (dependency) order
+            const int NI = df_wg < 8 ? 0 : (P.npairs < df_wg / 4 ? P.npairs : df_wg / 4);
+            std::vector<std::vector<int>> per((size_t)df_wg);
+            int ci = 0, cm = 0;
+            for (int i = 0; i < P.df_ntasks; ++i) {
+                if (NI > 0 && dtasks[i].x == DF_INNER) per[(size_t)(ci++ % NI)].push_back(i);
+                else per[(size_t)(NI + cm++ % (df_wg - NI))].push_back(i);
+            }
+            std::vector<int> wl((size_t)df_wg + 1 + P.df_ntasks);
+            int o = 0;
+            for (int w = 0; w < df_wg; ++w) {
+                wl[w] = o;
+                for (int i : per[w]) wl[(size_t)df_wg + 1 + o++] = i;
+            }
+            wl[df_wg] = o;
+            dwl.swap(wl);
+            int *dw = (int *)(b + P.o_dwg);
+            HZ_CHECK(hipMemcpyAsync(dw, dwl.data(), dwl.size() * sizeof(int), hipMemcpyHostToDevice,
+                                    st));
+            dfa.wg_off = dw;
+            dfa.wg_list = dw + df_wg + 1;
+        }
         if (kind == KIND_COMPLEX)
             launch_prescale_cplx(P, W, (const double *)F, ldf, (const double *)G, ldg, st);
         else if (kind == KIND_MIXED)
@@ -538,8 +723,14 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
         // then SWEEP_TOT_N words read back once (Algorithm 1).  Without the
         // profiler the sweep is captured once as a hipGraph (per precision)
         // and replayed.
-        const bool use_graph = !g_prof.on;
+        // the dataflow sweep is a cooperative launch, which is not captured
+        const bool use_graph = !g_prof.on && !P.dataflow;
         auto enqueue = [&](bool fp32, hipStream_t s) {
+            if (P.dataflow && !fp32) {
+                df_err = launch_sweep_df(dfa, df_wg, s);
+                if (df_err == hipSuccess) launch_sweep_totals(P, W, s);
+                return;
+            }
             for (int k = 0; k < P.steps; ++k) {
                 if (fp32) launch_step_mixed32(P, W, k, prm, tol, s);
                 else if (kind == KIND_COMPLEX) launch_step_cplx(P, W, k, prm, tol, s);
@@ -564,6 +755,7 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
             if (use_graph) e = hipGraphLaunch(execs[g], st);
             else enqueue(fp32, st);
             if (e != hipSuccess) return e;
+            if (df_err != hipSuccess) return df_err;
             e = hipGetLastError();
             if (e != hipSuccess) return e;
             e = hipMemcpyAsync(hpin, W.tot, SWEEP_TOT_N * sizeof(unsigned long long),
@@ -634,7 +826,8 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
             HZ_CHECK(hipMemcpyAsync(hs, W.status, sizeof(hs), hipMemcpyDeviceToHost, st));
         }
         HZ_CHECK(hipStreamSynchronize(st));
-        if (hs[ST_FLAGS] & FLAG_NONFINITE) rc = HZ_ENONFINITE;
+        if (hs[ST_FLAGS] & FLAG_STALL) rc = HZ_EHIP;
+        else if (hs[ST_FLAGS] & FLAG_NONFINITE) rc = HZ_ENONFINITE;
         else if (hs[ST_FLAGS] & FLAG_CHOL) rc = HZ_ECHOL;
         else if (!converged) rc = HZ_ENOCONV;
         if (info) {
@@ -1094,7 +1287,7 @@ static void cache_store(const char *path, uint64_t key, const hz_params &p, doub
     std::lock_guard<std::mutex> lk(g_tune_mu);
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%016llx %d %d %d %d %d %.4f\n", (unsigned long long)key, p.w, p.inner_max_sweeps,
+    fprintf(f, "%016llx %d %d %d %d %d %.6f\n", (unsigned long long)key, p.w, p.inner_max_sweeps,
             p.inner_lanes, p.gram_splits, p.update_rows, ms);
     fclose(f);
 }

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void kb_prescale(const BProb *__restrict__ pro
 
 // Gram blocks of step k: task t = (pair i, block pair l), blockIdx.y = matrix.
 template <int W2>
-__global__ __launch_bounds__(256) void kb_gram(const BProb *__restrict__ probs,
+__global__ __launch_bounds__(512) void kb_gram(const BProb *__restrict__ probs,
                                                const int2 *__restrict__ tasks,
                                                const int *__restrict__ active, int step)
 {
@@ -56,8 +56,9 @@ __global__ __launch_bounds__(256) void kb_gram(const BProb *__restrict__ probs,
     const int mat = blockIdx.y;
     const int *pr = P.otab + ((size_t)step * P.npairs + tk.y) * 2;
     const int64_t m = mat ? P.mgw : P.mfw;
-    gram_block<W2>(mat ? P.Gw : P.Fw, m, pr[0], pr[1], 0, m / 64,
-                   P.gram + ((size_t)tk.y * 2 + mat) * (W2 * W2));
+    __shared__ __attribute__((aligned(16))) double tile[gram_lds<W2>()];
+    gram_block<W2, 8>(mat ? P.Gw : P.Fw, m, pr[0], pr[1], 0, m / 64,
+                   P.gram + ((size_t)tk.y * 2 + mat) * (W2 * W2), tile);
 }
 
 template <int W2, int LP>
@@ -71,9 +72,10 @@ __global__ __launch_bounds__((W2 / 2) * LP) void kb_inner(
     if (!active[tk.x]) return;
     const BProb &P = probs[tk.x];
     const double *pa = P.gram + (size_t)tk.y * 2 * (W2 * W2);
-    inner_solve<W2, LP>(pa, pa + W2 * W2, itab, isteps, inner_max, P.tol, sort,
+    __shared__ __attribute__((aligned(16))) double lds[inner_lds<W2>()];
+    inner_solve<W2, LP>(pa, pa + W2 * W2, 1, 0, itab, isteps, inner_max, P.tol, sort,
                         P.Zt + (size_t)tk.y * (W2 * W2), c,
-                        pstatus + (size_t)tk.x * ST_NSLOTS, step * 65536 + tk.y, nullptr);
+                        pstatus + (size_t)tk.x * ST_NSLOTS, step * 65536 + tk.y, nullptr, lds);
     __syncthreads();
     if (threadIdx.x == 0) {
         // integer sums: the result does not depend on the order of arrival
@@ -95,7 +97,8 @@ __global__ __launch_bounds__(256) void kb_update(const BProb *__restrict__ probs
     const int part = blockIdx.y;
     double *Y = part == 0 ? P.Fw : (part == 1 ? P.Gw : P.Zw);
     const int64_t m = part == 0 ? P.mfw : (part == 1 ? P.mgw : P.nzw);
-    update_rows<W2>(Y, m, pr[0], pr[1], 0, m, P.Zt + (size_t)tk.y * (W2 * W2));
+    __shared__ double sz[update_lds<W2>()];
+    update_rows<W2, 4>(Y, m, pr[0], pr[1], 0, m, P.Zt + (size_t)tk.y * (W2 * W2), sz);
 }
 
 // End of a sweep, one workgroup: per pair, add the sweep's counters to the
@@ -225,7 +228,7 @@ static void stepb_impl(const BPlan &B, int k, const hz_params &prm, hipStream_t 
     if (nt == 0) return;
     const int2 *tasks = B.tasks + B.task_off[k];
     prof_mark(K_GRAM, true, s);
-    hipLaunchKernelGGL(kb_gram<W2>, dim3(nt, 2), dim3(256), 0, s, B.probs, tasks, B.active, k);
+    hipLaunchKernelGGL(kb_gram<W2>, dim3(nt, 2), dim3(512), 0, s, B.probs, tasks, B.active, k);
     prof_mark(K_GRAM, false, s);
     prof_mark(K_INNER, true, s);
     if constexpr (W2 == 16) {

@@ -201,7 +201,13 @@ __device__ __forceinline__ void hz_real_2x2_fast(double aii, double ajj, double 
     const bool tiny = (qd == q2);
     const double c = tiny ? 1.0 : q * r;
     const double s = sD * r;
-    const double sp = sqrt_nr(1.0 + x), sm = sqrt_nr(1.0 - x);
+    // sqrt(1 + x) from one reciprocal square root and sqrt(1 - x) =
+    // t/sqrt(1 + x) with t = t2 * (1/t), both to a few ulps.  xi is divided
+    // out rather than taken as (sqrt(1+x) - sqrt(1-x))/2: for tiny x that
+    // difference cancels, and xi enters the sines of tiny transformations
+    // directly, so it needs relative accuracy.
+    const double rp = rsqrt_nr(1.0 + x);
+    const double sp = (1.0 + x) * rp, sm = (t2 * rt) * rp;
     const double xi = div_nr(x, sp + sm);
     const double eta = div_nr(x, (1.0 + sp) * (1.0 + sm));
     const double cphi = fma(xi, fma(-eta, c, s), c);

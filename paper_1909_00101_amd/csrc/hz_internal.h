@@ -32,6 +32,11 @@ struct Plan {
     size_t o_fw, o_gw, o_zw, o_part, o_gram, o_arrive, o_zt, o_otab, o_itab, o_cnt, o_status, o_tot;
     size_t o_sf, o_sg, o_sig, o_rank, o_border;
     size_t o_fs, o_gs, o_zs, o_offd;   // mixed form only (FP32 copies, off-diagonal measure)
+    int dataflow;                      // one persistent launch per sweep (hz_dataflow.hip)
+    int df_tiles_f, df_tiles_g, df_tiles_z, df_ntasks;
+    int64_t df_tile_rows;
+    size_t o_dpart, o_dzt, o_dtask, o_dpar, o_ddep, o_dwg;
+    int df_nwg, df_inner_wg;
     int mixed;
     size_t total;
 };
@@ -83,7 +88,7 @@ struct BPlan {
 
 // status[] slots written by kernels (integer atomics only)
 enum { ST_FLAGS = 0, ST_FAILPAIR = 1, ST_NSLOTS = 4 };
-enum { FLAG_NONFINITE = 1, FLAG_CHOL = 2 };
+enum { FLAG_NONFINITE = 1, FLAG_CHOL = 2, FLAG_STALL = 4 };
 
 // Kernel kinds timed by the optional per-launch profiler.
 enum { K_GRAM = 0, K_INNER = 1, K_UPDATE = 2, K_OTHER = 3, K_NKINDS = 4 };
@@ -112,6 +117,35 @@ void launch_inner_real(const Plan &P, const Ptrs &W, int step, const hz_params &
 enum { TOT_ALL = 0, TOT_BIG = 1, TOT_ISW = 2, TOT_OFFD = 3, TOT_FLAGS = 4, TOT_FAILPAIR = 5,
        SWEEP_TOT_N = 8 };
 void launch_sweep_totals(const Plan &P, const Ptrs &W, hipStream_t s);
+
+// Persistent dataflow sweep (hz_dataflow.hip), real FP64, pivot blocks of 64.
+enum { DF_GRAM = 0, DF_INNER = 1, DF_UPDATE = 2 };
+struct DFArgs {
+    double *Fw, *Gw, *Zw;
+    int64_t mfw, mgw, nzw;
+    const int *otab;             // steps x npairs x 2
+    int npairs, steps, splits;   // splits: Gram row splits per matrix
+    int tiles_f, tiles_g, tiles_z, tiles;
+    int64_t tile_rows;
+    double *part;                // steps x npairs x 2 x splits x 64 x 64
+    double *Zt;                  // steps x npairs x 64 x 64
+    const int16_t *itab;
+    int isteps, inner_max, sort;
+    double tol;
+    unsigned long long *cnt;     // steps x npairs x 4 (as the per-step kernels)
+    int *status;
+    const int4 *tasks;           // (kind, step, pair, sub) in dependency order
+    int ntasks;
+    const int *wg_off;           // per workgroup: its task indices (into tasks), ascending,
+    const int *wg_list;          //   wg_list[wg_off[w] .. wg_off[w + 1])
+    const int2 *parents;         // per (step, pair): the two step-1 pairs holding its blocks
+    unsigned *dep;               // 3 x steps x npairs completion counters
+    unsigned *head;              // (unused with static assignment)
+    unsigned spin_limit;
+    int *err;
+};
+hipError_t launch_sweep_df(const DFArgs &A, int nwg, hipStream_t s);
+hipError_t df_occupancy(int *per_cu);   // resident sweep workgroups per compute unit
 
 // launchers (batched), hz_batched.hip
 void launchb_prescale(const BPlan &B, hipStream_t s);

@@ -8,27 +8,42 @@
 
 namespace hz {
 
-// Device body: one workgroup of 256 threads forms the Gram block of the
-// block-column pair (p, q) of Y (m rows, ld m) over the 64-row chunks
-// [c0, c1) and writes it to out (column-major W2 x W2, lower tiles).
-template <int W2>
-__device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t m, int p, int q,
-                                           int64_t c0, int64_t c1, double *__restrict__ out)
+// LDS (doubles) each body needs; the caller provides it, so one kernel can
+// run several bodies over a single allocation.
+template <int W2> constexpr int gram_lds() { return W2 * 66; }
+template <int W2> constexpr int update_lds() { return W2 * (W2 + 1); }
+template <int W2> constexpr int inner_lds()
 {
-    constexpr int W = W2 / 2, NB = W2 / 16, LDT = 66, NLD = W2 / 8;
-    constexpr int NT = NB * (NB + 1) / 2;    // lower-triangle tiles
-    __shared__ __attribute__((aligned(16))) double tile[W2 * LDT];
+    return 3 * W2 * (W2 + 2) + 128 + W2 * W2 / 4 + (3 * (W2 / 2) + 1) / 2 + 2;
+}
+
+// Device body: one workgroup of NW waves forms the Gram block of the
+// block-column pair (p, q) of Y (m rows, ld m) over the 64-row chunks
+// [c0, c1) and writes it to out (column-major W2 x W2, lower tiles).  Each
+// chunk is staged in LDS (tile, gram_lds<W2>() doubles) with the next one
+// prefetched into registers; wave w takes the k-steps w, w + NW, ... of
+// every chunk, and the waves' partial tiles are summed in wave order.
+template <int W2, int NW>
+__device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t m, int p, int q,
+                                           int64_t c0, int64_t c1, double *__restrict__ out,
+                                           double *__restrict__ tile)
+{
+    constexpr int W = W2 / 2, NB = W2 / 16, LDT = 66, NT = 64 * NW;
+    constexpr int CPP = NT / 32;             // columns loaded per pass (32 lanes per column)
+    constexpr int NLD = W2 / CPP;            // columns per thread
+    constexpr int NTL = NB * (NB + 1) / 2;   // lower-triangle tiles
+    static_assert(W2 % CPP == 0 && 16 % NW == 0, "bad Gram geometry");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lrow = 2 * (tid & 31), lcol = tid >> 5;
 
-    d4 acc[NT];
+    d4 acc[NTL];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < NTL; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
     const double *colp[NLD];
 #pragma unroll
     for (int t = 0; t < NLD; ++t) {
-        const int cc = lcol + 8 * t;
+        const int cc = lcol + CPP * t;
         const int gc = (cc < W) ? p * W + cc : q * W + (cc - W);
         colp[t] = Y + (int64_t)gc * m + lrow;
     }
@@ -40,15 +55,15 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
     for (int64_t c = c0; c < c1; ++c) {
         __syncthreads();
 #pragma unroll
-        for (int t = 0; t < NLD; ++t) *(d2 *)(tile + (lcol + 8 * t) * LDT + lrow) = buf[t];
+        for (int t = 0; t < NLD; ++t) *(d2 *)(tile + (lcol + CPP * t) * LDT + lrow) = buf[t];
         __syncthreads();
         if (c + 1 < c1) {
 #pragma unroll
             for (int t = 0; t < NLD; ++t) buf[t] = *(const d2 *)(colp[t] + (c + 1) * 64);
         }
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int ks = wave + 4 * s;
+        for (int s = 0; s < 16 / NW; ++s) {
+            const int ks = wave + NW * s;
             double fr[NB];
 #pragma unroll
             for (int b = 0; b < NB; ++b)
@@ -60,8 +75,8 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
                 for (int b = 0; b <= a; ++b, ++t) acc[t] = mfma16(fr[a], fr[b], acc[t]);
         }
     }
-    // Sum the four waves' partial tiles in wave order (tile reused, ld W2).
-    for (int wv = 0; wv < 4; ++wv) {
+    // Sum the waves' partial tiles in wave order (tile reused, ld W2).
+    for (int wv = 0; wv < NW; ++wv) {
         __syncthreads();
         if (wave == wv) {
             int t = 0;
@@ -79,7 +94,7 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
     }
     __syncthreads();
     // Only lower-triangle tiles are meaningful; upper ones are not written.
-    for (int e = 2 * tid; e < W2 * W2; e += 512) *(d2 *)(out + e) = *(const d2 *)(tile + e);
+    for (int e = 2 * tid; e < W2 * W2; e += 2 * NT) *(d2 *)(out + e) = *(const d2 *)(tile + e);
 }
 
 // Device body: the workgroup (NT threads) solves the block pair whose Gram
@@ -89,30 +104,38 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
 // status[ST_FLAGS] and failcode into status[ST_FAILPAIR] (minimum kept).
 template <int W2, int LP>
 __device__ __forceinline__ void inner_solve(
-    const double *__restrict__ pa, const double *__restrict__ pb,
+    const double *__restrict__ pa, const double *__restrict__ pb, int nsplit, size_t sstride,
     const int16_t *__restrict__ itab, int isteps, int inner_max, double tol, int sort,
     double *__restrict__ zt, unsigned long long *__restrict__ myc, int *__restrict__ status,
-    int failcode, unsigned long long *__restrict__ ph)
+    int failcode, unsigned long long *__restrict__ ph, double *__restrict__ lds)
 {
     constexpr int W = W2 / 2;         // column pairs per inner step
     constexpr int NT = W * LP;
     constexpr int RPL = W2 / LP;      // rows per lane
     constexpr int LDI = W2 + 2;
     static_assert(RPL >= 2 && RPL % 2 == 0 && NT >= 64, "bad inner geometry");
-    __shared__ __attribute__((aligned(16))) double sF[W2 * LDI];
-    __shared__ __attribute__((aligned(16))) double sG[W2 * LDI];
-    __shared__ __attribute__((aligned(16))) double sZ[W2 * LDI];
-    __shared__ int16_t stab[W2 * W2];
-    __shared__ __attribute__((aligned(16))) double lbuf[2][64];
-    __shared__ int s_fail;
-    __shared__ unsigned s_cnt[3 * W];
+    double *const sF = lds;
+    double *const sG = lds + W2 * LDI;
+    double *const sZ = lds + 2 * W2 * LDI;
+    double *const lbuf0 = lds + 3 * W2 * LDI;                 // 2 x 64 doubles
+    int16_t *const stab = (int16_t *)(lbuf0 + 128);           // W2 * W2 entries
+    unsigned *const s_cnt = (unsigned *)(lbuf0 + 128 + W2 * W2 / 4);
+    int *const s_failp = (int *)(s_cnt + 3 * W);
+#define s_fail (*s_failp)
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (ph && tid == 0) ph[0] = wall_clock64();
-    // 1. load the Gram blocks (lower triangles) into LDS
+    // 1. load the Gram blocks (lower triangles) into LDS; with nsplit > 1 the
+    // blocks arrive as nsplit row-split partials (stride sstride), added in
+    // split order.
     {
         for (int e = 2 * tid; e < W2 * W2; e += 2 * NT) {
-            const d2 a = *(const d2 *)(pa + e), b = *(const d2 *)(pb + e);
+            if ((e / W2) / 16 > (e % W2) / 16) continue;      // upper tiles are never read
+            d2 a = *(const d2 *)(pa + e), b = *(const d2 *)(pb + e);
+            for (int sp = 1; sp < nsplit; ++sp) {
+                a += *(const d2 *)(pa + sp * sstride + e);
+                b += *(const d2 *)(pb + sp * sstride + e);
+            }
             const int col = e / W2, row = e % W2;
             *(d2 *)(sF + col * LDI + row) = a;
             *(d2 *)(sG + col * LDI + row) = b;
@@ -130,7 +153,7 @@ __device__ __forceinline__ void inner_solve(
         const int i = two ? lane : (lane & 31);
         if ((two ? (wave < 2) : (wave == 0)) && i < W2) {
             double *M = mat ? sG : sF;
-            double *lb = lbuf[mat];
+            double *lb = lbuf0 + 64 * mat;
             double a[W2];
 #pragma unroll
             for (int k = 0; k < W2; ++k) a[k] = M[k * LDI + i];
@@ -171,7 +194,7 @@ __device__ __forceinline__ void inner_solve(
     }
     __syncthreads();
     if (ph && tid == 0) ph[2] = wall_clock64();
-    if (s_fail) {
+    if (__builtin_amdgcn_readfirstlane(s_fail)) {      // uniform: every lane read the same word
         for (int e = tid; e < W2 * W2; e += NT) zt[e] = (e % W2 == e / W2) ? 1.0 : 0.0;
         if (tid == 0) {
             myc[0] = 0;
@@ -289,7 +312,7 @@ __device__ __forceinline__ void inner_solve(
         }
         my_all += sw_all;
         my_big += sw_big;
-        const int any = __syncthreads_count(gl == 0 && sw_all > 0);
+        const int any = __builtin_amdgcn_readfirstlane(__syncthreads_count(gl == 0 && sw_all > 0));
         if (any == 0) break;
     }
 
@@ -327,19 +350,21 @@ __device__ __forceinline__ void inner_solve(
         myc[2] = (unsigned long long)nsw;
         if (ph) ph[5] = wall_clock64();
     }
+#undef s_fail
 }
 
-// Device body: one workgroup (256 threads) updates rows [rb, re) of the
-// block-column pair (p, q) of Y (ld m) by zt (column-major W2 x W2).
-template <int W2>
+// Device body: one workgroup of NW waves updates rows [rb, re) (a multiple
+// of 16 rows) of the block-column pair (p, q) of Y (ld m) by zt
+// (column-major W2 x W2), staged in LDS (sz, update_lds<W2>() doubles).
+template <int W2, int NW>
 __device__ __forceinline__ void update_rows(double *__restrict__ Y, int64_t m, int p, int q,
                                             int64_t rb, int64_t re,
-                                            const double *__restrict__ zt)
+                                            const double *__restrict__ zt,
+                                            double *__restrict__ sz)
 {
     constexpr int W = W2 / 2, NB = W2 / 16, KS = W2 / 4, LDZ = W2 + 1;
-    __shared__ double sz[W2 * LDZ];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < W2 * W2; e += 256) sz[(e / W2) * LDZ + (e % W2)] = zt[e];
+    for (int e = tid; e < W2 * W2; e += 64 * NW) sz[(e / W2) * LDZ + (e % W2)] = zt[e];
     __syncthreads();
     // Lane (i, k) = (lane % 16, lane / 16).  Columns 0..W-1 of the pair are
     // block column p, W..2W-1 block column q; every k-step's column offset
@@ -347,7 +372,7 @@ __device__ __forceinline__ void update_rows(double *__restrict__ Y, int64_t m, i
     const int k4 = lane >> 4, i16 = lane & 15;
     const double *bp = Y + ((int64_t)p * W + k4) * m + i16;
     const double *bq = Y + ((int64_t)q * W + k4) * m + i16;
-    for (int64_t r0 = rb + 16 * wave; r0 < re; r0 += 64) {
+    for (int64_t r0 = rb + 16 * wave; r0 < re; r0 += 16 * NW) {
         // keep the Z_tilde fragment reads inside the loop (in LDS, not in
         // 128 registers hoisted out of it)
         __asm__ volatile("" ::: "memory");

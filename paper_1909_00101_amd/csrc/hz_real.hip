@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_prescale_copy(
 // no floating-point atomics, so the result is reproducible bit for bit.
 // ------------------------------------------------------------------------
 template <int W2>
-__global__ __launch_bounds__(256) void k_gram(const double *__restrict__ Fw,
+__global__ __launch_bounds__(512) void k_gram(const double *__restrict__ Fw,
                                               const double *__restrict__ Gw, int64_t mfw,
                                               int64_t mgw, const int *__restrict__ pairs,
                                               int splits, double *__restrict__ part)
@@ -71,9 +71,10 @@ __global__ __launch_bounds__(256) void k_gram(const double *__restrict__ Fw,
     const int split = blockIdx.x, pr = blockIdx.y, mat = blockIdx.z;
     const int64_t m = mat ? mgw : mfw;
     const int64_t nch = m / 64;
-    gram_block<W2>(mat ? Gw : Fw, m, pairs[2 * pr], pairs[2 * pr + 1], nch * split / splits,
+    __shared__ __attribute__((aligned(16))) double tile[gram_lds<W2>()];
+    gram_block<W2, 8>(mat ? Gw : Fw, m, pairs[2 * pr], pairs[2 * pr + 1], nch * split / splits,
                    nch * (split + 1) / splits,
-                   part + ((size_t)(pr * 2 + mat) * splits + split) * (W2 * W2));
+                   part + ((size_t)(pr * 2 + mat) * splits + split) * (W2 * W2), tile);
 }
 
 // Sum of the Gram split partials in split order (fixed association, so the
@@ -129,10 +130,11 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner(
 {
     const int pr = blockIdx.x;
     const double *pa = gram + (size_t)(pr * 2) * (W2 * W2);
-    inner_solve<W2, LP>(pa, pa + W2 * W2, itab, isteps, inner_max, tol, sort,
+    __shared__ __attribute__((aligned(16))) double lds[inner_lds<W2>()];
+    inner_solve<W2, LP>(pa, pa + W2 * W2, 1, 0, itab, isteps, inner_max, tol, sort,
                         Zt + (size_t)pr * (W2 * W2), cnt + ((size_t)step * npairs + pr) * 4,
                         status, step * 65536 + pr,
-                        phase ? phase + ((size_t)step * npairs + pr) * 8 : nullptr);
+                        phase ? phase + ((size_t)step * npairs + pr) * 8 : nullptr, lds);
 }
 
 // ------------------------------------------------------------------------
@@ -174,7 +176,9 @@ __global__ __launch_bounds__(256) void k_update(double *__restrict__ Fw, double 
     }
     const int64_t rb = t * 4 * (int64_t)rows_per_wave;
     const int64_t re = (rb + 4 * (int64_t)rows_per_wave < m) ? rb + 4 * (int64_t)rows_per_wave : m;
-    update_rows<W2>(Y, m, pairs[2 * pr], pairs[2 * pr + 1], rb, re, Zt + (size_t)pr * (W2 * W2));
+    __shared__ double sz[update_lds<W2>()];
+    update_rows<W2, 4>(Y, m, pairs[2 * pr], pairs[2 * pr + 1], rb, re, Zt + (size_t)pr * (W2 * W2),
+                       sz);
 }
 
 // ------------------------------------------------------------------------
@@ -431,7 +435,7 @@ static void step_impl(const Plan &P, const Ptrs &W, int step, const hz_params &p
 {
     const int *pairs = W.otab + (size_t)step * P.npairs * 2;
     prof_mark(K_GRAM, true, s);
-    hipLaunchKernelGGL(k_gram<W2>, dim3(P.splits, P.npairs, 2), dim3(256), 0, s, W.Fw, W.Gw,
+    hipLaunchKernelGGL(k_gram<W2>, dim3(P.splits, P.npairs, 2), dim3(512), 0, s, W.Fw, W.Gw,
                        P.mfw, P.mgw, pairs, P.splits, W.part);
     launch_gram_sum(P, W, s);
     prof_mark(K_GRAM, false, s);

@@ -209,3 +209,52 @@ def test_tuner_argument_validation(hz):
                                    None) == -7
     assert L.hz_dgsvd_batched_tune(ctypes.byref(p), 1, i64([4]), i64([4]), i64([2]), pv,
                                    i64([4]), pv, i64([4]), None, None, None, None) == -11
+
+
+@pytest.mark.parametrize("shape", [(4096, 4096, 1024, 8, 64), (700, 520, 256, 4, 32),
+                                   (333, 200, 130, 2, 16), (64, 64, 64, 1, 16)],
+                         ids=lambda s: "x".join(map(str, s[:3])))
+def test_dataflow_task_list_is_a_dependency_order(hz, shape):
+    """The persistent sweep kernel takes tasks in list order and waits for
+    their inputs; it can only drain if every task comes after everything it
+    waits for.  Checks that, that every task appears once, and that the
+    parents of a pair are the previous step's pairs holding its blocks."""
+    m_f, m_g, n, splits, urows = shape
+    L = hz.lib()
+    L.hz_dataflow_tasks.argtypes = [ctypes.POINTER(hz.HzParams), ctypes.c_int64, ctypes.c_int64,
+                                    ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p]
+    p = hz.params(w=32, gram_splits=splits, update_rows=urows)
+    info = np.zeros(4, dtype=np.int32)
+    nt = L.hz_dataflow_tasks(ctypes.byref(p), m_f, m_g, n, None, None, info.ctypes.data)
+    steps, npairs, S, T = (int(v) for v in info)
+    assert nt == steps * npairs * (2 * S + 1 + T)
+    tasks = np.zeros((nt, 4), dtype=np.int32)
+    par = np.zeros((steps * npairs, 2), dtype=np.int32)
+    assert L.hz_dataflow_tasks(ctypes.byref(p), m_f, m_g, n, tasks.ctypes.data,
+                               par.ctypes.data, None) == nt
+    seen = {}
+    for i, (kind, k, l, sub) in enumerate(tasks.tolist()):
+        key = (kind, k, l, sub)
+        assert key not in seen
+        seen[key] = i
+    assert len(seen) == nt
+    nblk = 2 * npairs
+    tab = np.zeros(steps * npairs * 2, dtype=np.int32)
+    L.hz_ordering(hz.HZ_ORD_MM, nblk, tab.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    tab = tab.reshape(steps, npairs, 2)
+    for k in range(1, steps):
+        for l in range(npairs):
+            a, b = par[k * npairs + l]
+            assert set(tab[k, l]) <= set(tab[k - 1, a]) | set(tab[k - 1, b])
+            assert tab[k, l, 0] in tab[k - 1, a] and tab[k, l, 1] in tab[k - 1, b]
+    for (kind, k, l, sub), i in seen.items():
+        if kind == 0 and k > 0:
+            for q in par[k * npairs + l]:
+                for t in range(T):
+                    assert seen[(2, k - 1, int(q), t)] < i
+        elif kind == 1:
+            for s_ in range(2 * S):
+                assert seen[(0, k, l, s_)] < i
+        elif kind == 2:
+            assert seen[(1, k, l, 0)] < i
