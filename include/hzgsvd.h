@@ -94,7 +94,9 @@ typedef struct hz_params {
     int max_fp32_sweeps;  /* mixed form: cap on FP32 sweeps (default 20) */
     /* kernel tunables (0 = built-in choice); they change rounding order, so a
        fixed setting gives bitwise-reproducible results */
-    int inner_lanes;      /* lanes per column pair in the inner solver: 8 or 16 */
+    int inner_lanes;      /* lanes per column pair in the inner solver: 4, 8 or 16 (0 = 16 for
+                             2w = 64, else 8; 2w = 16 always uses 8; the complex solver
+                             runs 4 as 8) */
     int gram_splits;      /* row splits of the Gram kernel (1..16) */
     int update_rows;      /* rows per wave in the update kernel (multiple of 16) */
     int schedule;         /* real FP64 path: 0 = default, HZ_SCHED_STEPS = one launch per

@@ -74,7 +74,8 @@ static int params_ok(const hz_params &p)
     if (p.inner_ordering != HZ_ORD_MM && p.inner_ordering != HZ_ORD_RR) return 0;
     if (p.w != 0 && p.w != 8 && p.w != 16 && p.w != 32) return 0;
     if (p.inner_max_sweeps < 1 || p.max_sweeps < 1) return 0;
-    if (p.inner_lanes != 0 && p.inner_lanes != 8 && p.inner_lanes != 16) return 0;
+    if (p.inner_lanes != 0 && p.inner_lanes != 4 && p.inner_lanes != 8 && p.inner_lanes != 16)
+        return 0;
     if (p.gram_splits < 0 || p.gram_splits > 16 || p.update_rows < 0 || (p.update_rows % 16) != 0) return 0;
     return 1;
 }
@@ -122,7 +123,7 @@ static bool make_plan(const hz_params &prm, int64_t mf, int64_t mg, int64_t n, i
     P.splits = (int)sp;
     P.upd_rows = prm.update_rows ? prm.update_rows : 128;
     P.inner_lp = prm.inner_lanes ? prm.inner_lanes : ((P.W2 == 64) ? 16 : 8);
-    if (P.W2 == 16) P.inner_lp = 8;
+    if (P.W2 == 16) P.inner_lp = 8;       // 8 column pairs x 8 lanes: one wave
     const size_t es = P.esz;
     size_t o = 0;
     P.o_fw = o; o = align256(o + es * (size_t)P.mfw * P.nw);
@@ -1388,7 +1389,7 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
     fields.push_back(&cur.inner_max_sweeps);
     if (!base.gram_splits) { axes.push_back({4, 8, 16}); fields.push_back(&cur.gram_splits); }
     if (!base.update_rows) { axes.push_back({32, 64, 128}); fields.push_back(&cur.update_rows); }
-    if (!base.inner_lanes) { axes.push_back({8, 16}); fields.push_back(&cur.inner_lanes); }
+    if (!base.inner_lanes) { axes.push_back({4, 8, 16}); fields.push_back(&cur.inner_lanes); }
     ms = coordinate_search(cur, axes, fields, solve);
     if (herr) return HZ_EHIP;
     if (ms < 0.0) return HZ_ENOCONV;
@@ -1457,7 +1458,7 @@ int hz_dgsvd_batched_tune(const hz_params *p, int batch, const int64_t *m_f, con
     if (!base.w) { axes.push_back({8, 16, 32}); fields.push_back(&cur.w); }
     axes.push_back({1, base.inner_max_sweeps});
     fields.push_back(&cur.inner_max_sweeps);
-    if (!base.inner_lanes) { axes.push_back({8, 16}); fields.push_back(&cur.inner_lanes); }
+    if (!base.inner_lanes) { axes.push_back({4, 8, 16}); fields.push_back(&cur.inner_lanes); }
     ms = coordinate_search(cur, axes, fields, solve);
     if (herr) return HZ_EHIP;
     if (ms < 0.0) return HZ_ENOCONV;

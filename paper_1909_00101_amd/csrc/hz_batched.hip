@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void kb_prescale(const BProb *__restrict__ pro
 
 // Gram blocks of step k: task t = (pair i, block pair l), blockIdx.y = matrix.
 template <int W2>
-__global__ __launch_bounds__(512) void kb_gram(const BProb *__restrict__ probs,
+__global__ __launch_bounds__(256) void kb_gram(const BProb *__restrict__ probs,
                                                const int2 *__restrict__ tasks,
                                                const int *__restrict__ active, int step)
 {
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(512) void kb_gram(const BProb *__restrict__ probs,
     const int *pr = P.otab + ((size_t)step * P.npairs + tk.y) * 2;
     const int64_t m = mat ? P.mgw : P.mfw;
     __shared__ __attribute__((aligned(16))) double tile[gram_lds<W2>()];
-    gram_block<W2, 8>(mat ? P.Gw : P.Fw, m, pr[0], pr[1], 0, m / 64,
+    gram_block<W2, 4>(mat ? P.Gw : P.Fw, m, pr[0], pr[1], 0, m / 64,
                    P.gram + ((size_t)tk.y * 2 + mat) * (W2 * W2), tile);
 }
 
@@ -228,7 +228,7 @@ static void stepb_impl(const BPlan &B, int k, const hz_params &prm, hipStream_t 
     if (nt == 0) return;
     const int2 *tasks = B.tasks + B.task_off[k];
     prof_mark(K_GRAM, true, s);
-    hipLaunchKernelGGL(kb_gram<W2>, dim3(nt, 2), dim3(512), 0, s, B.probs, tasks, B.active, k);
+    hipLaunchKernelGGL(kb_gram<W2>, dim3(nt, 2), dim3(256), 0, s, B.probs, tasks, B.active, k);
     prof_mark(K_GRAM, false, s);
     prof_mark(K_INNER, true, s);
     if constexpr (W2 == 16) {
@@ -236,7 +236,11 @@ static void stepb_impl(const BPlan &B, int k, const hz_params &prm, hipStream_t 
                            B.active, k, B.itab, B.isteps, prm.inner_max_sweeps, prm.sort, B.pcnt,
                            B.pstatus);
     } else {
-        if (B.inner_lp == 16)
+        if (B.inner_lp == 4)
+            hipLaunchKernelGGL((kb_inner<W2, 4>), dim3(nt), dim3((W2 / 2) * 4), 0, s, B.probs,
+                               tasks, B.active, k, B.itab, B.isteps, prm.inner_max_sweeps,
+                               prm.sort, B.pcnt, B.pstatus);
+        else if (B.inner_lp == 16)
             hipLaunchKernelGGL((kb_inner<W2, 16>), dim3(nt), dim3((W2 / 2) * 16), 0, s, B.probs,
                                tasks, B.active, k, B.itab, B.isteps, prm.inner_max_sweeps,
                                prm.sort, B.pcnt, B.pstatus);

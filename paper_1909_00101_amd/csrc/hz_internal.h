@@ -109,7 +109,7 @@ void launch_eval_2x2(int64_t count, const double *in, double *out, hipStream_t s
 void launch_rank(const Plan &P, const Ptrs &W, hipStream_t s);
 void launch_gram_sum(const Plan &P, const Ptrs &W, hipStream_t s);
 void launch_inner_real(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
-                       hipStream_t s);
+                       bool partials, hipStream_t s);
 
 // Per-sweep summary written by k_sweep_totals: sums of the per-(step, pair)
 // counters, the largest off-diagonal measure (mixed form, as bits of a

@@ -17,12 +17,14 @@ template <int W2> constexpr int inner_lds()
     return 3 * W2 * (W2 + 2) + 128 + W2 * W2 / 4 + (3 * (W2 / 2) + 1) / 2 + 2;
 }
 
-// Device body: one workgroup of NW waves forms the Gram block of the
-// block-column pair (p, q) of Y (m rows, ld m) over the 64-row chunks
-// [c0, c1) and writes it to out (column-major W2 x W2, lower tiles).  Each
-// chunk is staged in LDS (tile, gram_lds<W2>() doubles) with the next one
-// prefetched into registers; wave w takes the k-steps w, w + NW, ... of
-// every chunk, and the waves' partial tiles are summed in wave order.
+// Device body: NW waves form the Gram block of the block-column pair (p, q)
+// of Y (m rows, ld m) over the 64-row chunks [c0, c1) and write it to out
+// (column-major W2 x W2, lower tiles).  Each chunk is staged in LDS (tile,
+// gram_lds<W2>() doubles) with the next one prefetched into registers; wave
+// w takes the k-steps w, w + NW, ... of every chunk, and the waves' partial
+// tiles are summed in wave order.  Further waves of a larger workgroup only
+// take part in the barriers, so the sums do not depend on the workgroup
+// size.
 template <int W2, int NW>
 __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t m, int p, int q,
                                            int64_t c0, int64_t c1, double *__restrict__ out,
@@ -34,7 +36,8 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
     constexpr int NTL = NB * (NB + 1) / 2;   // lower-triangle tiles
     static_assert(W2 % CPP == 0 && 16 % NW == 0, "bad Gram geometry");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lrow = 2 * (tid & 31), lcol = tid >> 5;
+    const bool act = tid < NT;
+    const int lrow = 2 * (tid & 31), lcol = (tid >> 5) % CPP;
 
     d4 acc[NTL];
 #pragma unroll
@@ -48,31 +51,35 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
         colp[t] = Y + (int64_t)gc * m + lrow;
     }
     d2 buf[NLD];
-    if (c0 < c1) {
+    if (act && c0 < c1) {
 #pragma unroll
         for (int t = 0; t < NLD; ++t) buf[t] = *(const d2 *)(colp[t] + c0 * 64);
     }
     for (int64_t c = c0; c < c1; ++c) {
         __syncthreads();
+        if (act) {
 #pragma unroll
-        for (int t = 0; t < NLD; ++t) *(d2 *)(tile + (lcol + CPP * t) * LDT + lrow) = buf[t];
-        __syncthreads();
-        if (c + 1 < c1) {
-#pragma unroll
-            for (int t = 0; t < NLD; ++t) buf[t] = *(const d2 *)(colp[t] + (c + 1) * 64);
+            for (int t = 0; t < NLD; ++t) *(d2 *)(tile + (lcol + CPP * t) * LDT + lrow) = buf[t];
         }
+        __syncthreads();
+        if (act) {
+            if (c + 1 < c1) {
 #pragma unroll
-        for (int s = 0; s < 16 / NW; ++s) {
-            const int ks = wave + NW * s;
-            double fr[NB];
+                for (int t = 0; t < NLD; ++t) buf[t] = *(const d2 *)(colp[t] + (c + 1) * 64);
+            }
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
-                fr[b] = tile[(16 * b + (lane & 15)) * LDT + 4 * ks + (lane >> 4)];
-            int t = 0;
+            for (int s = 0; s < 16 / NW; ++s) {
+                const int ks = wave + NW * s;
+                double fr[NB];
 #pragma unroll
-            for (int a = 0; a < NB; ++a)
+                for (int b = 0; b < NB; ++b)
+                    fr[b] = tile[(16 * b + (lane & 15)) * LDT + 4 * ks + (lane >> 4)];
+                int t = 0;
 #pragma unroll
-                for (int b = 0; b <= a; ++b, ++t) acc[t] = mfma16(fr[a], fr[b], acc[t]);
+                for (int a = 0; a < NB; ++a)
+#pragma unroll
+                    for (int b = 0; b <= a; ++b, ++t) acc[t] = mfma16(fr[a], fr[b], acc[t]);
+            }
         }
     }
     // Sum the waves' partial tiles in wave order (tile reused, ld W2).
@@ -94,7 +101,8 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
     }
     __syncthreads();
     // Only lower-triangle tiles are meaningful; upper ones are not written.
-    for (int e = 2 * tid; e < W2 * W2; e += 2 * NT) *(d2 *)(out + e) = *(const d2 *)(tile + e);
+    if (act)
+        for (int e = 2 * tid; e < W2 * W2; e += 2 * NT) *(d2 *)(out + e) = *(const d2 *)(tile + e);
 }
 
 // Device body: the workgroup (NT threads) solves the block pair whose Gram

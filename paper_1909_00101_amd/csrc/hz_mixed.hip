@@ -335,7 +335,7 @@ static void step32_impl(const Plan &P, const Ptrs &W, int step, const hz_params 
                        P.npairs, W.offd);
     prof_mark(K_GRAM, false, s);
     prof_mark(K_INNER, true, s);
-    launch_inner_real(P, W, step, prm, tol, s);
+    launch_inner_real(P, W, step, prm, tol, false, s);
     prof_mark(K_INNER, false, s);
     const int64_t rpt = 4 * (int64_t)P.upd_rows;
     const int tf = (int)((P.mfw + rpt - 1) / rpt), tg = (int)((P.mgw + rpt - 1) / rpt),

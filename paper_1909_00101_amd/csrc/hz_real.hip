@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_prescale_copy(
 // no floating-point atomics, so the result is reproducible bit for bit.
 // ------------------------------------------------------------------------
 template <int W2>
-__global__ __launch_bounds__(512) void k_gram(const double *__restrict__ Fw,
+__global__ __launch_bounds__(256) void k_gram(const double *__restrict__ Fw,
                                               const double *__restrict__ Gw, int64_t mfw,
                                               int64_t mgw, const int *__restrict__ pairs,
                                               int splits, double *__restrict__ part)
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(512) void k_gram(const double *__restrict__ Fw,
     const int64_t m = mat ? mgw : mfw;
     const int64_t nch = m / 64;
     __shared__ __attribute__((aligned(16))) double tile[gram_lds<W2>()];
-    gram_block<W2, 8>(mat ? Gw : Fw, m, pairs[2 * pr], pairs[2 * pr + 1], nch * split / splits,
+    gram_block<W2, 4>(mat ? Gw : Fw, m, pairs[2 * pr], pairs[2 * pr + 1], nch * split / splits,
                    nch * (split + 1) / splits,
                    part + ((size_t)(pr * 2 + mat) * splits + split) * (W2 * W2), tile);
 }
@@ -123,15 +123,16 @@ __global__ __launch_bounds__(256) void k_gram_sum(const double *__restrict__ par
 // ------------------------------------------------------------------------
 template <int W2, int LP>
 __global__ __launch_bounds__((W2 / 2) * LP) void k_inner(
-    const double *__restrict__ gram, int npairs, int step,
+    const double *__restrict__ gram, int nsplit, int npairs, int step,
     const int16_t *__restrict__ itab, int isteps, int inner_max, double tol, int sort,
     double *__restrict__ Zt, unsigned long long *__restrict__ cnt, int *__restrict__ status,
     unsigned long long *__restrict__ phase)
 {
     const int pr = blockIdx.x;
-    const double *pa = gram + (size_t)(pr * 2) * (W2 * W2);
+    const double *pa = gram + (size_t)(pr * 2) * nsplit * (W2 * W2);
     __shared__ __attribute__((aligned(16))) double lds[inner_lds<W2>()];
-    inner_solve<W2, LP>(pa, pa + W2 * W2, 1, 0, itab, isteps, inner_max, tol, sort,
+    inner_solve<W2, LP>(pa, pa + (size_t)nsplit * (W2 * W2), nsplit, W2 * W2, itab, isteps,
+                        inner_max, tol, sort,
                         Zt + (size_t)pr * (W2 * W2), cnt + ((size_t)step * npairs + pr) * 4,
                         status, step * 65536 + pr,
                         phase ? phase + ((size_t)step * npairs + pr) * 8 : nullptr, lds);
@@ -380,33 +381,40 @@ void launch_prescale_real(const Plan &P, const Ptrs &W, const double *F, int64_t
 
 template <int W2>
 static void inner_impl(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
-                       hipStream_t s)
+                       bool partials, hipStream_t s)
 {
+    const double *src = partials ? W.part : W.gram;
+    const int ns = partials ? P.splits : 1;
     if constexpr (W2 == 16) {
-        hipLaunchKernelGGL((k_inner<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s, W.gram,
+        hipLaunchKernelGGL((k_inner<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s, src, ns,
                            P.npairs, step, W.itab, P.isteps, prm.inner_max_sweeps, tol, prm.sort,
                            W.Zt, W.cnt, W.status, W.phase);
     } else {
-        if (P.inner_lp == 8)
+        if (P.inner_lp == 4)
+            hipLaunchKernelGGL((k_inner<W2, 4>), dim3(P.npairs), dim3((W2 / 2) * 4), 0, s,
+                               src, ns, P.npairs, step, W.itab, P.isteps,
+                               prm.inner_max_sweeps, tol, prm.sort, W.Zt, W.cnt, W.status,
+                               W.phase);
+        else if (P.inner_lp == 8)
             hipLaunchKernelGGL((k_inner<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s,
-                               W.gram, P.npairs, step, W.itab, P.isteps,
+                               src, ns, P.npairs, step, W.itab, P.isteps,
                                prm.inner_max_sweeps, tol, prm.sort, W.Zt, W.cnt, W.status,
                                W.phase);
         else
             hipLaunchKernelGGL((k_inner<W2, 16>), dim3(P.npairs), dim3((W2 / 2) * 16), 0, s,
-                               W.gram, P.npairs, step, W.itab, P.isteps,
+                               src, ns, P.npairs, step, W.itab, P.isteps,
                                prm.inner_max_sweeps, tol, prm.sort, W.Zt, W.cnt, W.status,
                                W.phase);
     }
 }
 
 void launch_inner_real(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
-                       hipStream_t s)
+                       bool partials, hipStream_t s)
 {
     switch (P.W2) {
-    case 16: inner_impl<16>(P, W, step, prm, tol, s); break;
-    case 32: inner_impl<32>(P, W, step, prm, tol, s); break;
-    default: inner_impl<64>(P, W, step, prm, tol, s); break;
+    case 16: inner_impl<16>(P, W, step, prm, tol, partials, s); break;
+    case 32: inner_impl<32>(P, W, step, prm, tol, partials, s); break;
+    default: inner_impl<64>(P, W, step, prm, tol, partials, s); break;
     }
 }
 
@@ -435,12 +443,12 @@ static void step_impl(const Plan &P, const Ptrs &W, int step, const hz_params &p
 {
     const int *pairs = W.otab + (size_t)step * P.npairs * 2;
     prof_mark(K_GRAM, true, s);
-    hipLaunchKernelGGL(k_gram<W2>, dim3(P.splits, P.npairs, 2), dim3(512), 0, s, W.Fw, W.Gw,
+    hipLaunchKernelGGL(k_gram<W2>, dim3(P.splits, P.npairs, 2), dim3(256), 0, s, W.Fw, W.Gw,
                        P.mfw, P.mgw, pairs, P.splits, W.part);
     launch_gram_sum(P, W, s);
     prof_mark(K_GRAM, false, s);
     prof_mark(K_INNER, true, s);
-    inner_impl<W2>(P, W, step, prm, tol, s);
+    inner_impl<W2>(P, W, step, prm, tol, false, s);
     prof_mark(K_INNER, false, s);
     const int64_t rpt = 4 * (int64_t)P.upd_rows;
     const int tf = (int)((P.mfw + rpt - 1) / rpt), tg = (int)((P.mgw + rpt - 1) / rpt),

@@ -67,10 +67,10 @@ def _small_batch():
     return pairs
 
 
-@pytest.mark.parametrize("w", [8, 16])
-def test_small_batch_vs_oracle(w):
+@pytest.mark.parametrize("w,lanes", [(8, 0), (16, 0), (16, 4)])
+def test_small_batch_vs_oracle(w, lanes):
     pairs = _small_batch()
-    st, res = _run_batch(pairs, w=w)
+    st, res = _run_batch(pairs, w=w, inner_lanes=lanes)
     assert st == 0, [r["status"] for r in res]
     worst = 0.0
     for i, ((F, G, s_true), r) in enumerate(zip(pairs, res)):

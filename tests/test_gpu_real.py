@@ -101,12 +101,16 @@ def test_n1_closed_form():
 
 
 @pytest.mark.parametrize("kw", [dict(ordering=2), dict(inner_ordering=1),
-                                dict(inner_max_sweeps=1), dict(sort=0)],
-                         ids=["outerRR", "innerMM", "BO", "nosort"])
+                                dict(inner_max_sweeps=1), dict(sort=0),
+                                dict(w=16, inner_lanes=4), dict(w=32, inner_lanes=4),
+                                dict(w=32, inner_lanes=8)],
+                         ids=["outerRR", "innerMM", "BO", "nosort", "w16lanes4", "w32lanes4",
+                              "w32lanes8"])
 def test_variants_parity(kw):
     F, G, _ = gi.custom_pair(200, 180, 64, kappa=1e2, seed=77)
     o = _oracle(F, G)
-    r = _run(F, G, w=8, **kw)
+    kw = dict(kw)
+    r = _run(F, G, w=kw.pop("w", 8), **kw)
     assert r["status"] == 0
     assert max_rel(r["sigma"], o["sigma"]) < SIG_TOL
     _check(F, G, r)
