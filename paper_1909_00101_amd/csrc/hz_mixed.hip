@@ -13,6 +13,7 @@
 namespace hz {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
 
 // v_mfma_f32_16x16x4_f32: A[i][k] lane i + 16k, B[k][j] lane j + 16k,
 // C[i][j] lane j + 16*(i/4), element i%4 (checked on gfx950).
@@ -137,8 +138,11 @@ __global__ __launch_bounds__(256) void k_gram32(const float *__restrict__ Fs,
 }
 
 // Block update of the FP32 copies, [Y_p Y_q] <- [Y_p Y_q] fl32(Z_tilde), FP32
-// MFMA with D' = Z^T X^T (see k_update).  Element r of the accumulator in
-// lane l is output column 16jb + 4(l/16) + r, row l%16.
+// MFMA with D' = Z^T X^T (see k_update).  Each wave takes 32 rows at a time
+// as 16 row pairs: a lane loads (and stores) two consecutive rows of a
+// column as one 8-byte access, and two MFMA chains handle the even and the
+// odd rows.  Element r of an accumulator in lane l is output column
+// 16jb + 4(l/16) + r of row 2(l%16) (even chain) or 2(l%16) + 1 (odd).
 template <int W2>
 __global__ __launch_bounds__(256) void k_update32(float *__restrict__ Fs, float *__restrict__ Gs,
                                                   float *__restrict__ Zs, int64_t mfw,
@@ -169,30 +173,36 @@ __global__ __launch_bounds__(256) void k_update32(float *__restrict__ Fs, float 
         m = nzw;
         t -= tiles_f + tiles_g;
     }
+    // tiles are 4 * rows_per_wave rows (a multiple of 64), m a multiple of 64
     const int64_t rb = t * 4 * (int64_t)rows_per_wave;
     const int64_t re = (rb + 4 * (int64_t)rows_per_wave < m) ? rb + 4 * (int64_t)rows_per_wave : m;
     __syncthreads();
     const int k4 = lane >> 4, i16 = lane & 15;
-    float *bp = Y + ((int64_t)p * W + k4) * m + i16;
-    float *bq = Y + ((int64_t)q * W + k4) * m + i16;
-    for (int64_t r0 = rb + 16 * wave; r0 < re; r0 += 64) {
+    float *bp = Y + ((int64_t)p * W + k4) * m + 2 * i16;
+    float *bq = Y + ((int64_t)q * W + k4) * m + 2 * i16;
+    for (int64_t r0 = rb + 32 * wave; r0 < re; r0 += 128) {
         __asm__ volatile("" ::: "memory");
-        float xb[KS];
+        f2 xb[KS];
 #pragma unroll
         for (int s = 0; s < KS; ++s)
-            xb[s] = (4 * s < W) ? bp[(int64_t)(4 * s) * m + r0] : bq[(int64_t)(4 * s - W) * m + r0];
-        f4 acc[NB];
+            xb[s] = (4 * s < W) ? *(const f2 *)(bp + (int64_t)(4 * s) * m + r0)
+                                : *(const f2 *)(bq + (int64_t)(4 * s - W) * m + r0);
+        f4 ae[NB], ao[NB];
 #pragma unroll
-        for (int jb = 0; jb < NB; ++jb) acc[jb] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int jb = 0; jb < NB; ++jb) {
+            ae[jb] = f4{0.f, 0.f, 0.f, 0.f};
+            ao[jb] = f4{0.f, 0.f, 0.f, 0.f};
+        }
 #pragma unroll
         for (int s = 0; s < KS; ++s)
 #pragma unroll
             for (int jb = 0; jb < NB; ++jb) {
                 const float za = sz[(16 * jb + i16) * LDZ + 4 * s + k4];
-                acc[jb] = mfma16f(za, xb[s], acc[jb]);
+                ae[jb] = mfma16f(za, xb[s][0], ae[jb]);
+                ao[jb] = mfma16f(za, xb[s][1], ao[jb]);
             }
-        // output column 16jb + 4*k4 + r, row r0 + i16: stored through the
-        // base pointers (which already carry the k4 column offset)
+        // output column 16jb + 4*k4 + r, rows r0 + 2*i16 (+1): stored through
+        // the base pointers (which already carry the k4 column offset)
 #pragma unroll
         for (int jb = 0; jb < NB; ++jb)
 #pragma unroll
@@ -200,7 +210,7 @@ __global__ __launch_bounds__(256) void k_update32(float *__restrict__ Fs, float 
                 const int c0 = 16 * jb + 3 * k4 + r;   // + k4 via the base pointer
                 const int cabs = 16 * jb + 4 * k4 + r;
                 float *dst = (cabs < W) ? bp + (int64_t)c0 * m + r0 : bq + (int64_t)(c0 - W) * m + r0;
-                *dst = acc[jb][r];
+                *(f2 *)dst = f2{ae[jb][r], ao[jb][r]};
             }
     }
 }
