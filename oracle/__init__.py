@@ -43,15 +43,18 @@ def _load():
         i64, dp = ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
         sig = [i64, i64, i64, dp, i64, dp, i64, dp, i64, dp, dp, dp,
                ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-               ctypes.POINTER(ctypes.c_int64)]
+               ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
         for name in ("hzo_dgsvd", "hzo_zgsvd"):
             f = getattr(lib, name)
             f.argtypes = sig
             f.restype = ctypes.c_int
         lib.hzo_real_2x2.argtypes = [ctypes.c_double] * 4 + [dp, ctypes.POINTER(ctypes.c_int)]
         lib.hzo_real_2x2.restype = None
+        lib.hzo_real_2x2_c.argtypes = [ctypes.c_double] * 4 + [dp, ctypes.POINTER(ctypes.c_int),
+                                                               dp]
+        lib.hzo_real_2x2_c.restype = None
         lib.hzo_cplx_2x2_v.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp, dp,
-                                       ctypes.POINTER(ctypes.c_int)]
+                                       ctypes.POINTER(ctypes.c_int), dp]
         lib.hzo_cplx_2x2_v.restype = None
         lib.hzo_ordering.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         lib.hzo_ordering.restype = ctypes.c_int
@@ -63,12 +66,15 @@ def _dptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def gsvd(F, G, *, ordering=ORD_ROWCYCLIC, tol=0.0, max_sweeps=30, sort=True, threads=0):
+def gsvd(F, G, *, ordering=ORD_ROWCYCLIC, tol=0.0, max_sweeps=30, sort=True, threads=0,
+         variant=0):
     """GSVD of the pair (F, G) by the unblocked oracle.
 
     Returns a dict with U, V, Z (Fortran-ordered), sigma, sigma_f, sigma_g
     (descending in sigma), sweeps, rot_all, rot_big, converged, status.
-    tol <= 0 selects sqrt(n)*eps.  F and G are copied, not modified.
+    tol <= 0 selects sqrt(n)*eps.  variant 0 classifies small transformations
+    by criterion C1, variant 4 by criterion C2 (Section 2.5, Table 1).
+    F and G are copied, not modified.
     """
     lib = _load()
     is_c = np.iscomplexobj(F) or np.iscomplexobj(G)
@@ -87,31 +93,40 @@ def gsvd(F, G, *, ordering=ORD_ROWCYCLIC, tol=0.0, max_sweeps=30, sort=True, thr
     fn = lib.hzo_zgsvd if is_c else lib.hzo_dgsvd
     st = fn(m_f, m_g, n, _dptr(U), m_f, _dptr(V), m_g, _dptr(Z), n,
             _dptr(s), _dptr(sf), _dptr(sg), int(ordering), float(tol), int(max_sweeps),
-            1 if sort else 0, int(threads), info.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+            1 if sort else 0, int(variant), int(threads),
+            info.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
     if st < 0:
         raise ValueError("oracle rejected the arguments")
     return dict(U=U, V=V, Z=Z, sigma=s, sigma_f=sf, sigma_g=sg, sweeps=int(info[0]),
                 rot_all=int(info[1]), rot_big=int(info[2]), converged=bool(info[3]), status=st)
 
 
-def real_2x2(aii, ajj, aij, x):
-    """The oracle's real 2x2 transformation (Section 2.1.2) as a 2x2 array."""
+def real_2x2(aii, ajj, aij, x, cosines=False):
+    """The oracle's real 2x2 transformation (Section 2.1.2) as a 2x2 array
+    and the exception flag; with cosines=True also (cos phi, cos psi)."""
     lib = _load()
     z = np.zeros(4)
+    cc = np.zeros(2)
     e = ctypes.c_int(0)
-    lib.hzo_real_2x2(aii, ajj, aij, x, _dptr(z), ctypes.byref(e))
+    lib.hzo_real_2x2_c(aii, ajj, aij, x, _dptr(z), ctypes.byref(e), _dptr(cc))
+    if cosines:
+        return z.reshape(2, 2, order="F"), bool(e.value), cc
     return z.reshape(2, 2, order="F"), bool(e.value)
 
 
-def cplx_2x2(aii, ajj, aij, b):
-    """The oracle's complex 2x2 transformation (Section 2.1.1)."""
+def cplx_2x2(aii, ajj, aij, b, cosines=False):
+    """The oracle's complex 2x2 transformation (Section 2.1.1) and the
+    exception flag; with cosines=True also (cos phi, cos psi)."""
     lib = _load()
     a = np.array([complex(aij).real, complex(aij).imag])
     bb = np.array([complex(b).real, complex(b).imag])
     z = np.zeros(8)
+    cc = np.zeros(2)
     e = ctypes.c_int(0)
-    lib.hzo_cplx_2x2_v(aii, ajj, _dptr(a), _dptr(bb), _dptr(z), ctypes.byref(e))
+    lib.hzo_cplx_2x2_v(aii, ajj, _dptr(a), _dptr(bb), _dptr(z), ctypes.byref(e), _dptr(cc))
     zc = z[0::2] + 1j * z[1::2]
+    if cosines:
+        return zc.reshape(2, 2, order="F"), bool(e.value), cc
     return zc.reshape(2, 2, order="F"), bool(e.value)
 
 

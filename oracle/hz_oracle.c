@@ -23,9 +23,10 @@
  *   Section 2.2 : sweeps under a sequential or parallel strategy.
  *   Section 2.4 : final rescaling and extraction of U, V, Sigma_F, Sigma_G,
  *                 Sigma, Z.
- *   Section 2.5 : big/small classification (criterion C1) and the stop rule
+ *   Section 2.5 : big/small classification (criteria C1 and C2) and the stop rule
  *                 "no big transformation in a sweep".
- *   Table 1     : variant 0 (C1, prescaled, ordinary dot products).
+ *   Table 1     : variant 0 (C1, prescaled, ordinary dot products) and
+ *                 variant 4 (the same with criterion C2).
  *
  * Readings of passages that are silent, garbled or inconsistent (each one is
  * also listed in the design notes of the repository):
@@ -115,7 +116,22 @@ static void cos_sin_from_tan(double tn, double *c, double *s)
  * Z[2]=Z12, Z[3]=Z22.  *exc is set when the exception (A' proportional to B')
  * is taken.
  */
+void hzo_real_2x2_c(double aii, double ajj, double aij, double x, double Z[4], int *exc,
+                    double cc[2]);
+
 void hzo_real_2x2(double aii, double ajj, double aij, double x, double Z[4], int *exc)
+{
+    double cc[2];
+    hzo_real_2x2_c(aii, ajj, aij, x, Z, exc, cc);
+}
+
+/*
+ * As hzo_real_2x2, also returning the unscaled cosines cc = (cos phi,
+ * cos psi) that criterion C2 of Section 2.5 tests (both NaN for the
+ * exception, whose matrix is not of that form).
+ */
+void hzo_real_2x2_c(double aii, double ajj, double aij, double x, double Z[4], int *exc,
+                    double cc[2])
 {
     const double t = sqrt(fma(-x, x, 1.0));
     const double num = t * (ajj - aii);
@@ -132,6 +148,7 @@ void hzo_real_2x2(double aii, double ajj, double aij, double x, double Z[4], int
         Z[2] = -r2 * s * q;
         Z[3] = r2 * q;
         *exc = 1;
+        cc[0] = cc[1] = NAN;
         return;
     }
     const double xi = x / (sqrt(1.0 + x) + sqrt(1.0 - x));
@@ -148,6 +165,8 @@ void hzo_real_2x2(double aii, double ajj, double aij, double x, double Z[4], int
     Z[1] = -spsi / t;
     Z[2] = sphi / t;
     Z[3] = cpsi / t;
+    cc[0] = cphi;
+    cc[1] = cpsi;
 }
 
 /* ---------------------------------------------------- 2x2, complex case */
@@ -157,7 +176,19 @@ void hzo_real_2x2(double aii, double ajj, double aij, double x, double Z[4], int
  * [-e^{-i beta} sin psi, cos psi]] for A' = [[aii, aij], [conj(aij), ajj]],
  * B' = [[1, b], [conj(b), 1]].  Column-major Z as in the real case.
  */
+void hzo_cplx_2x2_c(double aii, double ajj, zdouble aij, zdouble b, zdouble Z[4], int *exc,
+                    double cc[2]);
+
 void hzo_cplx_2x2(double aii, double ajj, zdouble aij, zdouble b, zdouble Z[4], int *exc)
+{
+    double cc[2];
+    hzo_cplx_2x2_c(aii, ajj, aij, b, Z, exc, cc);
+}
+
+/* As hzo_cplx_2x2, also returning cc = (cos phi, cos psi) (NaN for the
+ * exception). */
+void hzo_cplx_2x2_c(double aii, double ajj, zdouble aij, zdouble b, zdouble Z[4], int *exc,
+                    double cc[2])
 {
     const double x = hypot(creal(b), cimag(b));
     const double zeta = (b == 0.0) ? 0.0 : carg(b);
@@ -176,6 +207,7 @@ void hzo_cplx_2x2(double aii, double ajj, zdouble aij, zdouble b, zdouble Z[4], 
         Z[2] = -r2 * ez * q;
         Z[3] = r2 * q;
         *exc = 1;
+        cc[0] = cc[1] = NAN;
         return;
     }
     const double tau = sign1(h);
@@ -193,14 +225,16 @@ void hzo_cplx_2x2(double aii, double ajj, zdouble aij, zdouble b, zdouble Z[4], 
     Z[1] = -eb_spsi / t;
     Z[2] = ea_sphi / t;
     Z[3] = cpsi / t;
+    cc[0] = cphi;
+    cc[1] = cpsi;
 }
 
-/* Interleaved-argument wrapper of hzo_cplx_2x2 for foreign callers. */
+/* Interleaved-argument wrapper of hzo_cplx_2x2_c for foreign callers. */
 void hzo_cplx_2x2_v(double aii, double ajj, const double *aij, const double *b,
-                    double *Zout, int *exc)
+                    double *Zout, int *exc, double cc[2])
 {
     zdouble Z[4];
-    hzo_cplx_2x2(aii, ajj, aij[0] + I * aij[1], b[0] + I * b[1], Z, exc);
+    hzo_cplx_2x2_c(aii, ajj, aij[0] + I * aij[1], b[0] + I * b[1], Z, exc, cc);
     for (int k = 0; k < 4; ++k) {
         Zout[2 * k] = creal(Z[k]);
         Zout[2 * k + 1] = cimag(Z[k]);
@@ -343,12 +377,24 @@ static void rot_cols_r(double *Y, int64_t ld, int64_t m, int64_t i, int64_t j, c
 }
 
 /*
+ * Section 2.5: a transformation is small under criterion C1 (variant 0)
+ * when both scaled cosines (cos phi)/t and (cos psi)/t, the diagonal of
+ * Zhat', equal 1, and under criterion C2 (variant 4) when the unscaled
+ * cosines cos phi and cos psi equal 1; every other transformation is big.
+ */
+static int is_big(int variant, double z11, double z22, const double cc[2])
+{
+    if (variant == 4) return !(cc[0] == 1.0 && cc[1] == 1.0);
+    return !(z11 == 1.0 && z22 == 1.0);
+}
+
+/*
  * One pointwise step on the pivot pair (i, j), i < j (Section 2.1, variant
- * 0).  Adds to *all and *big and returns nothing else.
+ * 0 or 4).  Adds to *all and *big and returns nothing else.
  */
 static void step_real(int64_t m_f, int64_t m_g, int64_t n, double *F, int64_t ldf,
                       double *G, int64_t ldg, double *Z, int64_t ldz,
-                      int64_t i, int64_t j, double tol, int sort,
+                      int64_t i, int64_t j, double tol, int sort, int variant,
                       int64_t *all, int64_t *big)
 {
     const double *fi = F + i * ldf, *fj = F + j * ldf;
@@ -364,11 +410,11 @@ static void step_real(int64_t m_f, int64_t m_g, int64_t n, double *F, int64_t ld
         }
         return;
     }
-    double Zh[4];
+    double Zh[4], cc[2];
     int exc;
-    hzo_real_2x2(aii, ajj, aij, bij, Zh, &exc);
+    hzo_real_2x2_c(aii, ajj, aij, bij, Zh, &exc, cc);
     *all += 1;
-    if (!(Zh[0] == 1.0 && Zh[3] == 1.0))
+    if (is_big(variant, Zh[0], Zh[3], cc))
         *big += 1;
     if (sort) {
         const double a11 = Zh[0] * Zh[0] * aii + 2.0 * Zh[0] * Zh[1] * aij + Zh[1] * Zh[1] * ajj;
@@ -395,10 +441,11 @@ static void step_real(int64_t m_f, int64_t m_g, int64_t n, double *F, int64_t ld
 int hzo_dgsvd(int64_t m_f, int64_t m_g, int64_t n,
               double *F, int64_t ldf, double *G, int64_t ldg, double *Z, int64_t ldz,
               double *sigma, double *sigma_f, double *sigma_g,
-              int ordering, double tol, int max_sweeps, int sort, int threads,
+              int ordering, double tol, int max_sweeps, int sort, int variant, int threads,
               int64_t *info)
 {
-    if (n < 1 || m_f < n || m_g < n || ldf < m_f || ldg < m_g || ldz < n)
+    if (n < 1 || m_f < n || m_g < n || ldf < m_f || ldg < m_g || ldz < n ||
+        (variant != 0 && variant != 4))
         return -1;
     info[0] = info[1] = info[2] = 0;
     info[3] = 1;
@@ -438,7 +485,7 @@ int hzo_dgsvd(int64_t m_f, int64_t m_g, int64_t n,
             for (int l = 0; l < ppairs; ++l) {
                 const int64_t i = row[2 * l], j = row[2 * l + 1];
                 if (j >= n) continue;   /* padding index of odd n */
-                step_real(m_f, m_g, n, F, ldf, G, ldg, Z, ldz, i, j, tol, sort, &all, &big);
+                step_real(m_f, m_g, n, F, ldf, G, ldg, Z, ldz, i, j, tol, sort, variant, &all, &big);
             }
         }
         ++sw;
@@ -490,7 +537,7 @@ static void rot_cols_z(zdouble *Y, int64_t ld, int64_t m, int64_t i, int64_t j, 
 
 static void step_cplx(int64_t m_f, int64_t m_g, int64_t n, zdouble *F, int64_t ldf,
                       zdouble *G, int64_t ldg, zdouble *Z, int64_t ldz,
-                      int64_t i, int64_t j, double tol, int sort,
+                      int64_t i, int64_t j, double tol, int sort, int variant,
                       int64_t *all, int64_t *big)
 {
     zdouble *fi = F + i * ldf, *fj = F + j * ldf;
@@ -509,10 +556,11 @@ static void step_cplx(int64_t m_f, int64_t m_g, int64_t n, zdouble *F, int64_t l
         return;
     }
     zdouble Zh[4];
+    double cc[2];
     int exc;
-    hzo_cplx_2x2(aii, ajj, aij, bij, Zh, &exc);
+    hzo_cplx_2x2_c(aii, ajj, aij, bij, Zh, &exc, cc);
     *all += 1;
-    if (!(Zh[0] == 1.0 && Zh[3] == 1.0))
+    if (is_big(variant, creal(Zh[0]), creal(Zh[3]), cc))   /* the diagonal of Zhat' is real */
         *big += 1;
     rot_cols_z(F, ldf, m_f, i, j, Zh);
     rot_cols_z(G, ldg, m_g, i, j, Zh);
@@ -530,11 +578,12 @@ static void step_cplx(int64_t m_f, int64_t m_g, int64_t n, zdouble *F, int64_t l
 int hzo_zgsvd(int64_t m_f, int64_t m_g, int64_t n,
               double *Fd, int64_t ldf, double *Gd, int64_t ldg, double *Zd, int64_t ldz,
               double *sigma, double *sigma_f, double *sigma_g,
-              int ordering, double tol, int max_sweeps, int sort, int threads,
+              int ordering, double tol, int max_sweeps, int sort, int variant, int threads,
               int64_t *info)
 {
     zdouble *F = (zdouble *)Fd, *G = (zdouble *)Gd, *Z = (zdouble *)Zd;
-    if (n < 1 || m_f < n || m_g < n || ldf < m_f || ldg < m_g || ldz < n)
+    if (n < 1 || m_f < n || m_g < n || ldf < m_f || ldg < m_g || ldz < n ||
+        (variant != 0 && variant != 4))
         return -1;
     info[0] = info[1] = info[2] = 0;
     info[3] = 1;
@@ -572,7 +621,7 @@ int hzo_zgsvd(int64_t m_f, int64_t m_g, int64_t n,
             for (int l = 0; l < ppairs; ++l) {
                 const int64_t i = row[2 * l], j = row[2 * l + 1];
                 if (j >= n) continue;
-                step_cplx(m_f, m_g, n, F, ldf, G, ldg, Z, ldz, i, j, tol, sort, &all, &big);
+                step_cplx(m_f, m_g, n, F, ldf, G, ldg, Z, ldz, i, j, tol, sort, variant, &all, &big);
             }
         }
         ++sw;

@@ -329,3 +329,91 @@ def test_sweep_cap_reports_not_converged():
 def test_bad_arguments_rejected():
     with pytest.raises(ValueError):
         oracle.gsvd(np.ones((3, 4)), np.ones((5, 4)))      # m_F < n
+
+
+# ---------------------------------------------------------------- variant 4
+# Section 2.5: criterion C2 calls a transformation small when the unscaled
+# cosines cos(phi) and cos(psi) are 1; C1 when the scaled ones (the diagonal
+# of Zhat' = (1/t)[[cos phi, sin phi], [-sin psi, cos psi]]) are 1.
+
+def test_2x2_cosines_are_those_of_the_printed_form():
+    """The cosines the oracle reports are t times the diagonal of Zhat', and
+    with t times the off-diagonal entries they form unit vectors (cos, sin):
+    the relations of the printed form of Zhat' (real Section 2.1.2, complex
+    Section 2.1.1)."""
+    rng = np.random.default_rng(77)
+    for _ in range(300):
+        a = rng.standard_normal((2, 2))
+        A = a @ a.T
+        x = rng.uniform(-0.95, 0.95)
+        Z, exc, cc = oracle.real_2x2(A[0, 0], A[1, 1], A[0, 1], x, cosines=True)
+        assert not exc
+        t = np.sqrt(1.0 - x * x)
+        assert np.allclose(cc, t * np.diag(Z), rtol=1e-14, atol=0)
+        assert abs(cc[0] ** 2 + (t * Z[0, 1]) ** 2 - 1.0) < 1e-14
+        assert abs(cc[1] ** 2 + (t * Z[1, 0]) ** 2 - 1.0) < 1e-14
+        b = complex(rng.uniform(-0.6, 0.6), rng.uniform(-0.6, 0.6))
+        ac = complex(rng.standard_normal(), rng.standard_normal())
+        aii, ajj = abs(ac) + rng.uniform(0.5, 2), abs(ac) + rng.uniform(0.5, 2)
+        Zc, exc, ccc = oracle.cplx_2x2(aii, ajj, ac, b, cosines=True)
+        tc = np.sqrt(1.0 - abs(b) ** 2)
+        assert not exc
+        assert np.allclose(ccc, tc * np.real(np.diag(Zc)), rtol=1e-14, atol=0)
+        assert abs(ccc[0] ** 2 + abs(tc * Zc[0, 1]) ** 2 - 1.0) < 1e-13
+        assert abs(ccc[1] ** 2 + abs(tc * Zc[1, 0]) ** 2 - 1.0) < 1e-13
+
+
+def test_c1_and_c2_differ_when_t_is_below_one():
+    """x = 2e-8 and a_ij = (a_ii + a_jj) x / 2 make D = 0 exactly, so tan(theta)
+    = 0 and cos(phi) = cos(psi) = 1 - xi*eta rounds to 1 (C2: small), while t =
+    sqrt(1 - x^2) rounds below 1, so the scaled cosines exceed 1 (C1: big)."""
+    x = 2e-8
+    aii, ajj = 2.0, 1.0
+    aij = (aii + ajj) * x / 2.0
+    Z, exc, cc = oracle.real_2x2(aii, ajj, aij, x, cosines=True)
+    assert not exc
+    assert cc[0] == 1.0 and cc[1] == 1.0
+    assert Z[0, 0] != 1.0 and Z[1, 1] != 1.0
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_variant4_constructed_pairs(cplx):
+    """Variant 4 (criterion C2) reaches the prescribed generalized singular
+    values and the output contract, like variant 0."""
+    F, G, s_true = gi.custom_pair(90, 70, 40, kappa=1e2, is_complex=cplx, seed=404)
+    r4 = oracle.gsvd(F, G, variant=4)
+    r0 = oracle.gsvd(F, G, variant=0)
+    assert r4["converged"] and r4["status"] == 0
+    assert rel_err(r4["sigma"], s_true) < 1e-12
+    assert rel_err(r4["sigma"], r0["sigma"]) < 1e-13
+    check_contract(F, G, r4)
+
+
+def test_variant4_equals_variant0_for_orthonormal_g():
+    """With G^T G = I every pivot B' is the identity up to rounding, t = 1
+    exactly, the scaled and unscaled cosines coincide and both criteria give
+    the same run, bit for bit."""
+    rng = np.random.default_rng(405)
+    F = rng.standard_normal((60, 24))
+    G, _ = np.linalg.qr(rng.standard_normal((50, 24)))
+    r0 = oracle.gsvd(F, G, variant=0)
+    r4 = oracle.gsvd(F, G, variant=4)
+    assert r0["sweeps"] == r4["sweeps"] and r0["rot_big"] == r4["rot_big"]
+    for k in ("sigma", "U", "V", "Z"):
+        assert np.array_equal(r0[k], r4[k])
+
+
+def test_variant4_changes_the_classification():
+    """On this seeded pair the two criteria classify some transformations
+    differently (the counts of big transformations differ), so the variant
+    argument reaches the classification."""
+    F, G, _ = gi.custom_pair(120, 100, 48, kappa=1e2, seed=406)
+    r0 = oracle.gsvd(F, G, variant=0, ordering=oracle.ORD_MM, threads=2)
+    r4 = oracle.gsvd(F, G, variant=4, ordering=oracle.ORD_MM, threads=2)
+    assert (r0["rot_big"], r0["sweeps"]) != (r4["rot_big"], r4["sweeps"])
+
+
+def test_bad_variant_rejected():
+    F, G, _ = gi.custom_pair(10, 10, 4, seed=407)
+    with pytest.raises(ValueError):
+        oracle.gsvd(F, G, variant=2)
