@@ -79,7 +79,9 @@ extern "C" {
 #define HZ_SCHED_DATAFLOW 2
 
 typedef struct hz_params {
-    int variant;          /* 0 only: criterion C1, prescaled, ordinary dots (Table 1) */
+    int variant;          /* Table 1, prescaled, ordinary dot products: 0 = small
+                             transformations by criterion C1 (scaled cosines equal 1),
+                             4 = by criterion C2 (unscaled cosines equal 1), Section 2.5 */
     int ordering;         /* outer block ordering, HZ_ORD_MM (default) or HZ_ORD_RR */
     int inner_ordering;   /* pointwise ordering inside a block pair (default HZ_ORD_RR) */
     int w;                /* block-column width: 0 = default, else 8, 16 or 32 */
@@ -127,7 +129,7 @@ size_t hz_dgsvd_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t 
 size_t hz_zgsvd_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n);
 size_t hz_dgsvd_mixed_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n);
 
-/* Real FP64 GSVD (variant 0, Sections 2-3).  Arguments in order:
+/* Real FP64 GSVD (variants 0 and 4, Sections 2-3).  Arguments in order:
  *  1 p (host, may be NULL = defaults), 2 m_f, 3 m_g, 4 n,
  *  5 F (device, m_f x n, overwritten by U), 6 ldf (>= m_f),
  *  7 G (device, m_g x n, overwritten by V), 8 ldg (>= m_g),

@@ -68,7 +68,7 @@ static int build_ordering(int kind, int N, std::vector<T> &tab)
 
 static int params_ok(const hz_params &p)
 {
-    if (p.variant != 0) return 0;
+    if (p.variant != 0 && p.variant != 4) return 0;
     if (p.schedule != 0 && p.schedule != HZ_SCHED_STEPS && p.schedule != HZ_SCHED_DATAFLOW) return 0;
     if (p.ordering != HZ_ORD_MM && p.ordering != HZ_ORD_RR) return 0;
     if (p.inner_ordering != HZ_ORD_MM && p.inner_ordering != HZ_ORD_RR) return 0;
@@ -672,6 +672,7 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
             dfa.isteps = P.isteps;
             dfa.inner_max = prm.inner_max_sweeps;
             dfa.sort = prm.sort;
+            dfa.variant = prm.variant;
             dfa.tol = tol;
             dfa.cnt = W.cnt;
             dfa.status = W.status;

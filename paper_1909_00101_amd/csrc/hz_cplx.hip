@@ -174,7 +174,7 @@ __global__ __launch_bounds__(256) void k_gram_sum_z(const d2 *__restrict__ part,
 template <int W2, int LP>
 __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
     const d2 *__restrict__ gram, int npairs, int step, const int16_t *__restrict__ itab,
-    int isteps, int inner_max, double tol, int sort, d2 *__restrict__ Zt,
+    int isteps, int inner_max, double tol, int sort, int variant, d2 *__restrict__ Zt,
     unsigned long long *__restrict__ cnt, int *__restrict__ status)
 {
     constexpr int W = W2 / 2;
@@ -319,9 +319,12 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
             if (orth) {
                 swap = sort && (aii < ajj);
             } else {
-                hz_cplx_2x2_fast(aii, ajj, ar, ai, br, bi, z11, z21r, z21i, z12r, z12i, z22);
+                bool c2small;
+                hz_cplx_2x2_fast(aii, ajj, ar, ai, br, bi, z11, z21r, z21i, z12r, z12i, z22,
+                                 c2small);
                 sw_all += 1;
-                if (!(z11 == 1.0 && z22 == 1.0)) sw_big += 1;
+                // small: criterion C1 (variant 0) or C2 (variant 4), Section 2.5
+                if (variant == 4 ? !c2small : !(z11 == 1.0 && z22 == 1.0)) sw_big += 1;
                 swap = false;
                 if (sort) {
                     // diagonal of Z^H A Z
@@ -567,7 +570,9 @@ __global__ __launch_bounds__(256) void k_eval_2x2_z(int64_t count, const double 
     if (i >= count) return;
     const double *a = in + 6 * i;
     double *o = out + 6 * i;
-    hz_cplx_2x2_fast(a[0], a[1], a[2], a[3], a[4], a[5], o[0], o[1], o[2], o[3], o[4], o[5]);
+    bool c2small;
+    hz_cplx_2x2_fast(a[0], a[1], a[2], a[3], a[4], a[5], o[0], o[1], o[2], o[3], o[4], o[5],
+                     c2small);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -598,15 +603,18 @@ static void step_impl_z(const Plan &P, const Ptrs &W, int step, const hz_params 
         if (P.inner_lp == 16)
             hipLaunchKernelGGL((k_inner_z<W2, 16>), dim3(P.npairs), dim3((W2 / 2) * 16), 0, s,
                                (const d2 *)W.gram, P.npairs, step, W.itab, P.isteps,
-                               prm.inner_max_sweeps, tol, prm.sort, (d2 *)W.Zt, W.cnt, W.status);
+                               prm.inner_max_sweeps, tol, prm.sort, prm.variant, (d2 *)W.Zt, W.cnt,
+                               W.status);
         else
             hipLaunchKernelGGL((k_inner_z<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s,
                                (const d2 *)W.gram, P.npairs, step, W.itab, P.isteps,
-                               prm.inner_max_sweeps, tol, prm.sort, (d2 *)W.Zt, W.cnt, W.status);
+                               prm.inner_max_sweeps, tol, prm.sort, prm.variant, (d2 *)W.Zt, W.cnt,
+                               W.status);
     } else {
         hipLaunchKernelGGL((k_inner_z<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s,
                            (const d2 *)W.gram, P.npairs, step, W.itab, P.isteps,
-                           prm.inner_max_sweeps, tol, prm.sort, (d2 *)W.Zt, W.cnt, W.status);
+                           prm.inner_max_sweeps, tol, prm.sort, prm.variant, (d2 *)W.Zt, W.cnt,
+                               W.status);
     }
     prof_mark(K_INNER, false, s);
     const int64_t rpt = 4 * (int64_t)P.upd_rows;

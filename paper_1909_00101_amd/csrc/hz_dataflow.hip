@@ -130,7 +130,8 @@ __global__ __launch_bounds__(DF_NT) void k_sweep_df(DFArgs A)
         } else if (kind == DF_INNER) {
             const double *pa = A.part + kl * 2 * S * W2SQ;
             inner_solve<W2, DF_LP>(pa, pa + S * W2SQ, S, W2SQ, A.itab, A.isteps, A.inner_max,
-                                   A.tol, A.sort, A.Zt + kl * W2SQ, A.cnt + kl * 4, A.status,
+                                   A.tol, A.sort, A.variant, A.Zt + kl * W2SQ, A.cnt + kl * 4,
+                                   A.status,
                                    k * 65536 + l, nullptr, lds);
             sig = inner_done + kl;
         } else {

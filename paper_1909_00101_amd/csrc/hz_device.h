@@ -175,7 +175,7 @@ __device__ __forceinline__ void hz_real_2x2(double aii, double ajj, double aij, 
 // hz_real_2x2.  Returns z11, z21, z12, z22 of Z' (column-major).
 __device__ __forceinline__ void hz_real_2x2_fast(double aii, double ajj, double aij, double x,
                                                  double &z11, double &z21, double &z12,
-                                                 double &z22)
+                                                 double &z22, bool &c2small)
 {
     const double t2 = fma(-x, x, 1.0);
     const double h = ajj - aii;
@@ -188,6 +188,7 @@ __device__ __forceinline__ void hz_real_2x2_fast(double aii, double ajj, double 
         z21 = s * p;
         z12 = -s * q;
         z22 = q;
+        c2small = false;
         return;
     }
     const double rt = rsqrt_nr(t2);                       // 1/t
@@ -218,6 +219,7 @@ __device__ __forceinline__ void hz_real_2x2_fast(double aii, double ajj, double 
     z21 = -spsi * rt;
     z12 = sphi * rt;
     z22 = cpsi * rt;
+    c2small = (cphi == 1.0 && cpsi == 1.0);     // criterion C2 (Section 2.5)
 }
 
 // The complex 2x2 transformation of Section 2.1.1 without infinities, for
@@ -239,7 +241,7 @@ __device__ __forceinline__ void hz_real_2x2_fast(double aii, double ajj, double 
 __device__ __forceinline__ void hz_cplx_2x2_fast(double aii, double ajj, double ar, double ai,
                                                  double br, double bi, double &z11,
                                                  double &z21r, double &z21i, double &z12r,
-                                                 double &z12i, double &z22)
+                                                 double &z12i, double &z22, bool &c2small)
 {
     const double x2 = fma(br, br, bi * bi);
     const bool bz = (x2 == 0.0);
@@ -260,6 +262,7 @@ __device__ __forceinline__ void hz_cplx_2x2_fast(double aii, double ajj, double 
         z12r = -er * q;
         z12i = -ei * q;
         z22 = q;
+        c2small = false;
         return;
     }
     const double tau = (h < 0.0) ? -1.0 : 1.0;
@@ -288,6 +291,7 @@ __device__ __forceinline__ void hz_cplx_2x2_fast(double aii, double ajj, double 
     z21i = -(-er * im - ei * br_) * dphi;
     z11 = cphi * rt;
     z22 = cpsi * rt;
+    c2small = (cphi == 1.0 && cpsi == 1.0);     // criterion C2 (Section 2.5)
 }
 
 }  // namespace hz

@@ -130,7 +130,7 @@ struct DFArgs {
     double *part;                // steps x npairs x 2 x splits x 64 x 64
     double *Zt;                  // steps x npairs x 64 x 64
     const int16_t *itab;
-    int isteps, inner_max, sort;
+    int isteps, inner_max, sort, variant;
     double tol;
     unsigned long long *cnt;     // steps x npairs x 4 (as the per-step kernels)
     int *status;

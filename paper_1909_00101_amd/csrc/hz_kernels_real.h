@@ -113,7 +113,7 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
 template <int W2, int LP>
 __device__ __forceinline__ void inner_solve(
     const double *__restrict__ pa, const double *__restrict__ pb, int nsplit, size_t sstride,
-    const int16_t *__restrict__ itab, int isteps, int inner_max, double tol, int sort,
+    const int16_t *__restrict__ itab, int isteps, int inner_max, double tol, int sort, int variant,
     double *__restrict__ zt, unsigned long long *__restrict__ myc, int *__restrict__ status,
     int failcode, unsigned long long *__restrict__ ph, double *__restrict__ lds)
 {
@@ -280,9 +280,11 @@ __device__ __forceinline__ void inner_solve(
             if (orth) {
                 swap = sort && (aii < ajj);
             } else {
-                hz_real_2x2_fast(aii, ajj, aij, bij, z11, z21, z12, z22);
+                bool c2small;
+                hz_real_2x2_fast(aii, ajj, aij, bij, z11, z21, z12, z22, c2small);
                 sw_all += 1;
-                if (!(z11 == 1.0 && z22 == 1.0)) sw_big += 1;
+                // small: criterion C1 (variant 0) or C2 (variant 4), Section 2.5
+                if (variant == 4 ? !c2small : !(z11 == 1.0 && z22 == 1.0)) sw_big += 1;
                 swap = false;
                 if (sort) {
                     const double a11 = fma(z11 * z11, aii, fma(2.0 * z11 * z21, aij, z21 * z21 * ajj));

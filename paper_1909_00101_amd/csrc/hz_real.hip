@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_gram_sum(const double *__restrict__ par
 template <int W2, int LP>
 __global__ __launch_bounds__((W2 / 2) * LP) void k_inner(
     const double *__restrict__ gram, int nsplit, int npairs, int step,
-    const int16_t *__restrict__ itab, int isteps, int inner_max, double tol, int sort,
+    const int16_t *__restrict__ itab, int isteps, int inner_max, double tol, int sort, int variant,
     double *__restrict__ Zt, unsigned long long *__restrict__ cnt, int *__restrict__ status,
     unsigned long long *__restrict__ phase)
 {
@@ -132,7 +132,7 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner(
     const double *pa = gram + (size_t)(pr * 2) * nsplit * (W2 * W2);
     __shared__ __attribute__((aligned(16))) double lds[inner_lds<W2>()];
     inner_solve<W2, LP>(pa, pa + (size_t)nsplit * (W2 * W2), nsplit, W2 * W2, itab, isteps,
-                        inner_max, tol, sort,
+                        inner_max, tol, sort, variant,
                         Zt + (size_t)pr * (W2 * W2), cnt + ((size_t)step * npairs + pr) * 4,
                         status, step * 65536 + pr,
                         phase ? phase + ((size_t)step * npairs + pr) * 8 : nullptr, lds);
@@ -305,7 +305,9 @@ __global__ __launch_bounds__(256) void k_eval_2x2(int64_t count, const double *_
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= count) return;
     double z11, z21, z12, z22;
-    hz_real_2x2_fast(in[4 * i], in[4 * i + 1], in[4 * i + 2], in[4 * i + 3], z11, z21, z12, z22);
+    bool c2small;
+    hz_real_2x2_fast(in[4 * i], in[4 * i + 1], in[4 * i + 2], in[4 * i + 3], z11, z21, z12, z22,
+                     c2small);
     out[4 * i] = z11;
     out[4 * i + 1] = z21;
     out[4 * i + 2] = z12;
@@ -388,22 +390,22 @@ static void inner_impl(const Plan &P, const Ptrs &W, int step, const hz_params &
     if constexpr (W2 == 16) {
         hipLaunchKernelGGL((k_inner<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s, src, ns,
                            P.npairs, step, W.itab, P.isteps, prm.inner_max_sweeps, tol, prm.sort,
-                           W.Zt, W.cnt, W.status, W.phase);
+                           prm.variant, W.Zt, W.cnt, W.status, W.phase);
     } else {
         if (P.inner_lp == 4)
             hipLaunchKernelGGL((k_inner<W2, 4>), dim3(P.npairs), dim3((W2 / 2) * 4), 0, s,
                                src, ns, P.npairs, step, W.itab, P.isteps,
-                               prm.inner_max_sweeps, tol, prm.sort, W.Zt, W.cnt, W.status,
+                               prm.inner_max_sweeps, tol, prm.sort, prm.variant, W.Zt, W.cnt, W.status,
                                W.phase);
         else if (P.inner_lp == 8)
             hipLaunchKernelGGL((k_inner<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s,
                                src, ns, P.npairs, step, W.itab, P.isteps,
-                               prm.inner_max_sweeps, tol, prm.sort, W.Zt, W.cnt, W.status,
+                               prm.inner_max_sweeps, tol, prm.sort, prm.variant, W.Zt, W.cnt, W.status,
                                W.phase);
         else
             hipLaunchKernelGGL((k_inner<W2, 16>), dim3(P.npairs), dim3((W2 / 2) * 16), 0, s,
                                src, ns, P.npairs, step, W.itab, P.isteps,
-                               prm.inner_max_sweeps, tol, prm.sort, W.Zt, W.cnt, W.status,
+                               prm.inner_max_sweeps, tol, prm.sort, prm.variant, W.Zt, W.cnt, W.status,
                                W.phase);
     }
 }
