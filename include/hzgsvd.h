@@ -278,7 +278,9 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
                   hz_params *best, double *best_ms, void *stream);
 
 /* Autotuner of the batched form: as hz_dgsvd_tune over w, inner_lanes and
- * the inner sweep cap, timing hz_dgsvd_batched without the extraction.
+ * the inner sweep cap, and over the outer ordering (modified modulus or
+ * round robin) when p->ordering is 0, timing hz_dgsvd_batched without the
+ * extraction; best->ordering is the chosen one.
  * Arguments: 1 p, 2 batch (1..65535), 3 m_f, 4 m_g, 5 n (host arrays),
  * 6 F, 7 ldf, 8 G, 9 ldg (host arrays; device matrices left unmodified),
  * 10 cache_path, 11 best, 12 best_ms, 13 stream. */

@@ -314,7 +314,7 @@ def gsvd_batched(pairs, *, overwrite=False, workspace=None, **kw):
     return st, out
 
 
-_TUNED = ("w", "inner_max_sweeps", "inner_lanes", "gram_splits", "update_rows")
+_TUNED = ("w", "inner_max_sweeps", "inner_lanes", "gram_splits", "update_rows", "ordering")
 
 
 def tune(F, G, *, cache=None, **kw):
@@ -342,7 +342,9 @@ def tune(F, G, *, cache=None, **kw):
 
 def tune_batched(pairs, *, cache=None, **kw):
     """Autotune the batched solver on [(F_i, G_i), ...] (not modified) with
-    hz_dgsvd_batched_tune; returns (chosen parameters, milliseconds)."""
+    hz_dgsvd_batched_tune; returns (chosen parameters, milliseconds).  The
+    ordering is tuned too unless given."""
+    kw.setdefault("ordering", 0)
     import torch
     L = lib()
     Fs = [_colmajor(F) for F, _ in pairs]

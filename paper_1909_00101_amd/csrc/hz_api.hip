@@ -1255,7 +1255,8 @@ static uint64_t tune_key(const char *kind, const hz_params &p, int batch, const 
 
 static std::mutex g_tune_mu;
 
-// Cache line: "<key hex> w inner_max_sweeps inner_lanes gram_splits update_rows ms".
+// Cache line: "<key hex> w inner_max_sweeps inner_lanes gram_splits update_rows ms
+// ordering" (a line without the ordering leaves it as given).
 static bool cache_lookup(const char *path, uint64_t key, hz_params &p, double &ms)
 {
     if (!path || !*path) return false;
@@ -1266,15 +1267,17 @@ static bool cache_lookup(const char *path, uint64_t key, hz_params &p, double &m
     bool hit = false;
     while (fgets(line, sizeof(line), f)) {
         unsigned long long k;
-        int w, ims, lp, gs, ur;
+        int w, ims, lp, gs, ur, ord = 0;
         double t;
-        if (sscanf(line, "%llx %d %d %d %d %d %lf", &k, &w, &ims, &lp, &gs, &ur, &t) == 7 &&
-            k == key) {
+        const int got = sscanf(line, "%llx %d %d %d %d %d %lf %d", &k, &w, &ims, &lp, &gs, &ur,
+                               &t, &ord);
+        if (got >= 7 && k == key) {
             p.w = w;
             p.inner_max_sweeps = ims;
             p.inner_lanes = lp;
             p.gram_splits = gs;
             p.update_rows = ur;
+            if (got == 8 && ord) p.ordering = ord;
             ms = t;
             hit = true;     // the last matching line wins
         }
@@ -1289,8 +1292,8 @@ static void cache_store(const char *path, uint64_t key, const hz_params &p, doub
     std::lock_guard<std::mutex> lk(g_tune_mu);
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%016llx %d %d %d %d %d %.6f\n", (unsigned long long)key, p.w, p.inner_max_sweeps,
-            p.inner_lanes, p.gram_splits, p.update_rows, ms);
+    fprintf(f, "%016llx %d %d %d %d %d %.6f %d\n", (unsigned long long)key, p.w,
+            p.inner_max_sweeps, p.inner_lanes, p.gram_splits, p.update_rows, ms, p.ordering);
     fclose(f);
 }
 
@@ -1407,6 +1410,9 @@ int hz_dgsvd_batched_tune(const hz_params *p, int batch, const int64_t *m_f, con
 {
     hz_params base;
     if (p) base = *p; else hz_default_params(&base);
+    // ordering 0 asks the tuner to choose between modified modulus and round robin
+    const bool tune_ord = (base.ordering == 0);
+    if (tune_ord) base.ordering = HZ_ORD_MM;
     if (!params_ok(base)) return -1;
     if (batch < 1 || batch > 65535) return -2;
     if (!m_f) return -3;
@@ -1424,7 +1430,8 @@ int hz_dgsvd_batched_tune(const hz_params *p, int batch, const int64_t *m_f, con
     }
     if (!best) return -11;
     hipStream_t st = (hipStream_t)stream;
-    const uint64_t key = tune_key("dgsvd_batched", base, batch, m_f, m_g, n);
+    const uint64_t key = tune_key(tune_ord ? "dgsvd_batched_ord" : "dgsvd_batched", base, batch,
+                                  m_f, m_g, n);
     hz_params cur = base;
     double ms = 0.0;
     if (cache_lookup(cache_path, key, cur, ms)) {
@@ -1460,6 +1467,7 @@ int hz_dgsvd_batched_tune(const hz_params *p, int batch, const int64_t *m_f, con
     axes.push_back({1, base.inner_max_sweeps});
     fields.push_back(&cur.inner_max_sweeps);
     if (!base.inner_lanes) { axes.push_back({4, 8, 16}); fields.push_back(&cur.inner_lanes); }
+    if (tune_ord) { axes.push_back({HZ_ORD_MM, HZ_ORD_RR}); fields.push_back(&cur.ordering); }
     ms = coordinate_search(cur, axes, fields, solve);
     if (herr) return HZ_EHIP;
     if (ms < 0.0) return HZ_ENOCONV;
