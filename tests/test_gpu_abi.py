@@ -1,0 +1,89 @@
+"""GPU checks of the C ABI itself, called through ctypes without the Python
+convenience layer: leading dimensions larger than the row counts (the
+library must read F, G and write U, V, Z through ldf, ldg, ldz and leave the
+padding rows alone), work = NULL (the library allocates its own
+workspace), and small n bordered up to one block pair of the widest
+width."""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import gsvd_inputs as gi
+from contract import assert_contract, max_rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SIG_TOL = 1e-10
+
+
+def _hz():
+    import paper_1909_00101_amd as hz
+    return hz
+
+
+def _padded(a, ld, fill):
+    """Column-major device buffer with leading dimension ld holding a; the
+    rows beyond a's are set to fill."""
+    m, n = a.shape
+    buf = np.full((ld, n), fill, dtype=a.dtype, order="F")
+    buf[:m, :] = a
+    return torch.from_numpy(buf).cuda()
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_leading_dimensions_and_null_workspace(cplx):
+    import oracle
+    hz = _hz()
+    L = hz.lib()
+    m_f, m_g, n = 150, 120, 40
+    F, G, s_true = gi.custom_pair(m_f, m_g, n, kappa=30.0, is_complex=cplx, seed=501)
+    ldf, ldg, ldz = m_f + 7, m_g + 13, n + 5
+    fill = 12345.0
+    dF, dG = _padded(F, ldf, fill), _padded(G, ldg, fill)
+    dtype = torch.complex128 if cplx else torch.float64
+    dZ = torch.from_numpy(np.full((ldz, n), fill, dtype=F.dtype, order="F")).cuda()
+    # the buffers hold exactly ld * n elements of the solver's type
+    for d, ld in ((dF, ldf), (dG, ldg), (dZ, ldz)):
+        assert d.dtype == dtype and d.numel() == ld * n
+    sig = torch.empty(n, dtype=torch.float64, device="cuda")
+    sf, sg = torch.empty_like(sig), torch.empty_like(sig)
+    p = hz.params(w=8)
+    info = hz.HzInfo()
+    fn = L.hz_zgsvd if cplx else L.hz_dgsvd
+    st = fn(ctypes.byref(p), m_f, m_g, n, ctypes.c_void_p(dF.data_ptr()), ldf,
+            ctypes.c_void_p(dG.data_ptr()), ldg, ctypes.c_void_p(dZ.data_ptr()), ldz,
+            ctypes.c_void_p(sig.data_ptr()), ctypes.c_void_p(sf.data_ptr()),
+            ctypes.c_void_p(sg.data_ptr()), None, 0, ctypes.byref(info), None)
+    torch.cuda.synchronize()
+    assert st == 0 and info.converged
+    Uf, Vf, Zf = dF.cpu().numpy(), dG.cpu().numpy(), dZ.cpu().numpy()
+    # padding rows untouched
+    assert np.all(Uf[m_f:, :] == fill) and np.all(Vf[m_g:, :] == fill)
+    assert np.all(Zf[n:, :] == fill)
+    U, V, Z = Uf[:m_f, :], Vf[:m_g, :], Zf[:n, :]
+    s = sig.cpu().numpy()
+    o = oracle.gsvd(F, G)
+    assert max_rel(s, o["sigma"]) < SIG_TOL
+    assert max_rel(s, s_true) < 1e-11
+    assert_contract(F, G, U, V, Z, sf.cpu().numpy(), sg.cpu().numpy(), s,
+                    tol_res=1e-12, tol_orth=1e-12)
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 33])
+def test_small_n_bordered_to_the_widest_block(n):
+    """n far below 2w = 64: the pair is bordered to 64 columns (one pivot pair,
+    two steps); the bordering columns must not leak into the outputs."""
+    import oracle
+    hz = _hz()
+    F, G, s_true = gi.custom_pair(n + 40, n + 17, n, kappa=10.0, seed=510 + n)
+    r = hz.gsvd(torch.from_numpy(np.asfortranarray(F)).cuda(),
+                torch.from_numpy(np.asfortranarray(G)).cuda(), w=32)
+    torch.cuda.synchronize()
+    res = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in r.items()}
+    assert res["status"] == 0
+    assert max_rel(res["sigma"], oracle.gsvd(F, G)["sigma"]) < SIG_TOL
+    assert_contract(F, G, res["U"], res["V"], res["Z"], res["sigma_f"], res["sigma_g"],
+                    res["sigma"], tol_res=1e-12, tol_orth=1e-12)
