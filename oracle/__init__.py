@@ -5,7 +5,8 @@ check and the benchmark's CPU-baseline leg, never by the GPU library.  It
 wraps ``hz_oracle.c`` (plain C, double / double complex, unblocked) through
 ctypes.  The C file shares no code with the GPU path; see its header for the
 algorithm, the paper passages it follows and the readings taken where the
-paper is ambiguous.
+paper is ambiguous.  :func:`gsvd_qr` adds the QR shortening of tall pairs
+(Section 2) around it, with scipy's column-pivoted QR as a library step.
 """
 
 from __future__ import annotations
@@ -99,6 +100,28 @@ def gsvd(F, G, *, ordering=ORD_ROWCYCLIC, tol=0.0, max_sweeps=30, sort=True, thr
         raise ValueError("oracle rejected the arguments")
     return dict(U=U, V=V, Z=Z, sigma=s, sigma_f=sf, sigma_g=sg, sweeps=int(info[0]),
                 rot_all=int(info[1]), rot_big=int(info[2]), converged=bool(info[3]), status=st)
+
+
+def gsvd_qr(F, G, **kw):
+    """GSVD of (F, G) through the shortened pair of Section 2 (the paragraph
+    before the prescaling): F P1 = Q_F R_F and (G P1) P2 = Q_G R_G by
+    column-pivoted Householder QR (LAPACK geqp3, through scipy), the square
+    pair F'' = R_F P2, G'' = R_G of order n is solved by :func:`gsvd` (same
+    keyword arguments), and the factors of (F, G) are recovered as
+    Z = P1 P2 Z'', U = Q_F U'', V = Q_G V''; sigma, sigma_f, sigma_g are those
+    of the shortened pair.  The dict of :func:`gsvd` is returned with U, V, Z
+    replaced and the permutations added as ``p1`` (F[:, p1] = Q_F R_F) and
+    ``q`` (the combined column order, G[:, q] = Q_G R_G)."""
+    import scipy.linalg
+    Q_f, R_f, p1 = scipy.linalg.qr(np.asarray(F), mode="economic", pivoting=True)
+    Q_g, R_g, p2 = scipy.linalg.qr(np.asarray(G)[:, p1], mode="economic", pivoting=True)
+    r = gsvd(R_f[:, p2], R_g, **kw)
+    q = p1[p2]
+    Z = np.empty_like(r["Z"])
+    Z[q, :] = r["Z"]
+    r.update(U=np.asfortranarray(Q_f @ r["U"]), V=np.asfortranarray(Q_g @ r["V"]),
+             Z=np.asfortranarray(Z), p1=p1, q=q)
+    return r
 
 
 def real_2x2(aii, ajj, aij, x, cosines=False):

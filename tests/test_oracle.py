@@ -16,6 +16,7 @@ import pytest
 import scipy.linalg as sl
 
 import gsvd_inputs as gi
+from contract import assert_contract
 import oracle
 
 EPS = np.finfo(np.float64).eps
@@ -417,3 +418,49 @@ def test_bad_variant_rejected():
     F, G, _ = gi.custom_pair(10, 10, 4, seed=407)
     with pytest.raises(ValueError):
         oracle.gsvd(F, G, variant=2)
+
+
+# ---------------------------------------------------------------- QR shortening
+# The shortened pair (R_F P2, R_G) has the Grams P^T F^T F P and P^T G^T G P
+# (P = P1 P2), so its GSVD has the same sigma and, mapped back, the same
+# normalised Z (unique up to column signs, or unit phases in the complex
+# case, for distinct sigma); U = Q_F U''
+# and V = Q_G V'' must satisfy the output contract on the original pair.
+
+def _align_signs(Z, Zref):
+    """Z with each column multiplied by the sign (real) or unit phase
+    (complex) that brings it closest to the same column of Zref."""
+    c = np.sum(Z.conj() * Zref, axis=0)
+    return Z * (c / np.abs(c))
+
+
+@pytest.mark.parametrize("shape", [(300, 200, 60), (64, 48, 32), (40, 40, 40), (90, 150, 17)])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_qr_shortening_same_gsvd(shape, cplx):
+    m_f, m_g, n = shape
+    F, G, s_true = gi.custom_pair(m_f, m_g, n, kappa=50.0, is_complex=cplx, seed=600 + n)
+    a = oracle.gsvd_qr(F, G, ordering=oracle.ORD_MM)
+    b = oracle.gsvd(F, G, ordering=oracle.ORD_MM)
+    assert a["status"] == 0 and a["converged"]
+    assert np.max(np.abs(a["sigma"] - s_true) / s_true) < 1e-12
+    assert np.max(np.abs(a["sigma"] - b["sigma"]) / b["sigma"]) < 1e-12
+    assert_contract(F, G, a["U"], a["V"], a["Z"], a["sigma_f"], a["sigma_g"], a["sigma"])
+    Zb = b["Z"]
+    err = np.max(np.abs(_align_signs(a["Z"], Zb) - Zb)) / np.max(np.abs(Zb))
+    assert err < 1e-10
+
+
+def test_qr_shortening_pivot_order():
+    """Column pivoting takes the column of largest norm first (for F, and for
+    G P1, whose column norms are those of G); with columns of F scaled by
+    distinct powers of 4 the whole first permutation is the norm order."""
+    rng = np.random.default_rng(611)
+    n = 8
+    F = rng.standard_normal((30, n)) * 1e-6 + np.eye(30, n)
+    F = F * (4.0 ** rng.permutation(n))
+    G = rng.standard_normal((20, n)) * np.array([1, 9, 2, 3, 4, 5, 6, 7.0])
+    r = oracle.gsvd_qr(F, G)
+    assert list(r["p1"]) == list(np.argsort(-np.linalg.norm(F, axis=0)))
+    assert r["q"][0] == np.argmax(np.linalg.norm(G, axis=0))
+    assert sorted(r["q"]) == list(range(n))
+    assert_contract(F, G, r["U"], r["V"], r["Z"], r["sigma_f"], r["sigma_g"], r["sigma"])
