@@ -77,6 +77,7 @@ static int params_ok(const hz_params &p)
     if (p.inner_lanes != 0 && p.inner_lanes != 4 && p.inner_lanes != 8 && p.inner_lanes != 16)
         return 0;
     if (p.gram_splits < 0 || p.gram_splits > 16 || p.update_rows < 0 || (p.update_rows % 16) != 0) return 0;
+    if (p.qr_shorten != 0 && p.qr_shorten != 1) return 0;
     return 1;
 }
 
@@ -361,6 +362,12 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
                      const void *G, int64_t ldg, void *U, void *V, void *Z, int64_t ldz,
                      double *sigma, double *sigma_f, double *sigma_g, bool finish = true);
 
+// The QR-shortened real solve (qr_shorten = 1).
+static int run_shortened(const hz_params &prm, const Plan &P, const SPlan &S, void *work,
+                         hz_info *info, hipStream_t st, double *F, int64_t ldf, double *G,
+                         int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
+                         double *sigma_g);
+
 }  // namespace hz
 
 using namespace hz;
@@ -422,7 +429,7 @@ int hz_dataflow_tasks(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, i
     hz_params prm;
     if (p) prm = *p; else hz_default_params(&prm);
     prm.schedule = HZ_SCHED_DATAFLOW;
-    if (!params_ok(prm) || m_f < n || m_g < n || n < 2) return -1;
+    if (!params_ok(prm) || prm.qr_shorten || m_f < n || m_g < n || n < 2) return -1;
     Plan P;
     if (!make_plan(prm, m_f, m_g, n, 0, P) || !P.dataflow) return -1;
     if (info) {
@@ -492,6 +499,7 @@ static int solve_entry(int kind, const hz_params *p, int64_t m_f, int64_t m_g, i
     if (p) prm = *p; else hz_default_params(&prm);
     if (!params_ok(prm) || !w_ok_for(prm, is_complex)) return -1;
     if (kind == KIND_MIXED && (prm.max_fp32_sweeps < 0 || !(prm.mixed_switch >= 0.0))) return -1;
+    if (prm.qr_shorten && (kind != KIND_REAL || (n > 1 && !shorten_cpt(n)))) return -1;
     const int a = check_args(m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g);
     if (a) return a;
     if (is_complex && (((uintptr_t)F | (uintptr_t)G | (uintptr_t)Z) & 15))
@@ -519,6 +527,14 @@ static int solve_entry(int kind, const hz_params *p, int64_t m_f, int64_t m_g, i
         return rc;
     }
     Plan P;
+    if (prm.qr_shorten) {
+        if (!make_plan(prm, n, n, n, 0, P)) return -4;
+        SPlan S;
+        if (!make_splan(m_f, m_g, n, P.total, S)) return -4;
+        if (work && work_bytes < S.total) return -15;
+        return run_shortened(prm, P, S, work, info, st, F, ldf, G, ldg, Z, ldz, sigma, sigma_f,
+                             sigma_g);
+    }
     if (!make_plan(prm, m_f, m_g, n, is_complex, P, kind == KIND_MIXED)) return -4;
     if (work && work_bytes < P.total) return -15;
     return run_solve(prm, P, work, work_bytes, info, st, kind, F, ldf, G, ldg, F, G, Z, ldz,
@@ -532,8 +548,14 @@ static size_t work_size_entry(int kind, const hz_params *p, int64_t m_f, int64_t
     hz_params prm;
     if (p) prm = *p; else hz_default_params(&prm);
     if (!params_ok(prm) || !w_ok_for(prm, is_complex) || m_f < n || m_g < n || n < 1) return 0;
+    if (prm.qr_shorten && (kind != KIND_REAL || (n > 1 && !shorten_cpt(n)))) return 0;
     if (n == 1) return 256;
     Plan P;
+    if (prm.qr_shorten) {
+        SPlan S;
+        if (!make_plan(prm, n, n, n, 0, P) || !make_splan(m_f, m_g, n, P.total, S)) return 0;
+        return S.total;
+    }
     if (!make_plan(prm, m_f, m_g, n, is_complex, P, kind == KIND_MIXED)) return 0;
     return P.total;
 }
@@ -857,6 +879,58 @@ done:
     return rc;
 }
 
+// Shortening (hz_shorten.hip), a host sync to read its status, the square
+// solve in the tail of the workspace (its final extraction writes U'', V''
+// over F'', G'', and Z''), then U = Q_F U'', V = Q_G V'', Z = P1 P2 Z''.
+// A failed factorization returns before the sweeps with info->failed_pair
+// = -1.
+static int run_shortened(const hz_params &prm, const Plan &P, const SPlan &S, void *work,
+                         hz_info *info, hipStream_t st, double *F, int64_t ldf, double *G,
+                         int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
+                         double *sigma_g)
+{
+    bool own = false;
+    if (!work) {
+        if (hipMalloc(&work, S.total) != hipSuccess) return HZ_EHIP;
+        own = true;
+    }
+    char *b = (char *)work;
+    int rc = HZ_OK;
+    int hs[ST_NSLOTS] = {0, 0, 0, 0};
+    if (launch_shorten(S, work, F, ldf, G, ldg, st) != hipSuccess ||
+        hipMemcpyAsync(hs, b + S.o_status, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        rc = HZ_EHIP;
+    else if (hs[ST_FLAGS] & FLAG_NONFINITE)
+        rc = HZ_ENONFINITE;
+    else if (hs[ST_FLAGS] & FLAG_CHOL)
+        rc = HZ_ECHOL;
+    if (rc != HZ_OK) {
+        if (info) {
+            memset(info, 0, sizeof(*info));
+            info->w = P.w;
+            info->failed_pair = -1;
+            info->status = rc;
+        }
+    } else {
+        double *F2 = (double *)(b + S.o_f2), *G2 = (double *)(b + S.o_g2);
+        double *Z2 = (double *)(b + S.o_z2);
+        rc = run_solve(prm, P, b + S.o_solve, S.total - S.o_solve, info, st, KIND_REAL, F2, S.ldn,
+                       G2, S.ldn, F2, G2, Z2, S.ldn, sigma, sigma_f, sigma_g, true);
+        if (rc == HZ_OK || rc == HZ_ENOCONV) {
+            if (launch_unshorten(S, work, F, ldf, G, ldg, Z, ldz, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                rc = HZ_EHIP;
+            if (info) info->status = rc;
+        }
+    }
+    if (own) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(work);
+    }
+    return rc;
+}
+
 }  // namespace hz
 
 // ------------------------------------------------------------ batched form
@@ -1176,7 +1250,7 @@ size_t hz_dgsvd_batched_work_size(const hz_params *p, int batch, const int64_t *
 {
     hz_params prm;
     if (p) prm = *p; else hz_default_params(&prm);
-    if (!params_ok(prm) || batch < 0 || batch > 65535) return 0;
+    if (!params_ok(prm) || prm.qr_shorten || batch < 0 || batch > 65535) return 0;
     if (batch == 0) return 256;
     if (!m_f || !m_g || !n) return 0;
     for (int i = 0; i < batch; ++i)
@@ -1195,7 +1269,7 @@ int hz_dgsvd_batched(const hz_params *p, int batch, const int64_t *m_f, const in
 {
     hz_params prm;
     if (p) prm = *p; else hz_default_params(&prm);
-    if (!params_ok(prm)) return -1;
+    if (!params_ok(prm) || prm.qr_shorten) return -1;
     const int a = check_batched(batch, m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f,
                                 sigma_g);
     if (a) return a;
@@ -1346,7 +1420,7 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
 {
     hz_params base;
     if (p) base = *p; else hz_default_params(&base);
-    if (!params_ok(base)) return -1;
+    if (!params_ok(base) || base.qr_shorten) return -1;
     const double dummy = 0.0;
     const int a = check_args(m_f, m_g, n, F, ldf, G, ldg, &dummy, n, &dummy, &dummy, &dummy);
     if (a) return a;
@@ -1413,7 +1487,7 @@ int hz_dgsvd_batched_tune(const hz_params *p, int batch, const int64_t *m_f, con
     // ordering 0 asks the tuner to choose between modified modulus and round robin
     const bool tune_ord = (base.ordering == 0);
     if (tune_ord) base.ordering = HZ_ORD_MM;
-    if (!params_ok(base)) return -1;
+    if (!params_ok(base) || base.qr_shorten) return -1;
     if (batch < 1 || batch > 65535) return -2;
     if (!m_f) return -3;
     if (!m_g) return -4;

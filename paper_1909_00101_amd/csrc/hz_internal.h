@@ -174,4 +174,25 @@ void launch_eval_2x2_cplx(int64_t count, const double *in, double *out, hipStrea
 void launch_n1_real(int64_t mf, int64_t mg, double *F, double *G, double *Z, double *sigma,
                     double *sigma_f, double *sigma_g, int *status, hipStream_t s);
 
+// QR shortening of a tall real pair (hz_shorten.hip).  Workspace offsets
+// (bytes) of Q_F, Q_G (ld ldqf, ldqg), the n x n buffers (ld ldn): Gram /
+// Schur complement S, R transposed Rt, R_F, R_G, the refinement factor R2,
+// the square pair F'', G'' (overwritten by U'', V'') and Z''; a column-block
+// temporary T, the inverted diagonal blocks Xd, the pivoting state and the
+// permutations p1 (F), q (G, = P1 P2), inv1, p2; then the square solve's
+// own workspace.
+struct SPlan {
+    int64_t mf, mg, n, ldqf, ldqg, ldn;
+    int cpt, nb, nblk;
+    size_t o_qf, o_qg, o_s, o_rt, o_r1f, o_r1g, o_r2, o_f2, o_g2, o_z2, o_t, o_xd, o_d, o_done;
+    size_t o_p1, o_q, o_inv1, o_p2, o_id, o_status, o_solve;
+    size_t total;
+};
+int shorten_cpt(int64_t n);   // 0 if n is beyond the shortening's limit (8192)
+bool make_splan(int64_t mf, int64_t mg, int64_t n, size_t solve_bytes, SPlan &S);
+hipError_t launch_shorten(const SPlan &P, void *work, const double *F, int64_t ldf,
+                          const double *G, int64_t ldg, hipStream_t s);
+hipError_t launch_unshorten(const SPlan &P, void *work, double *U, int64_t ldu, double *V,
+                            int64_t ldv, double *Z, int64_t ldz, hipStream_t s);
+
 }  // namespace hz
