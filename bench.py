@@ -194,6 +194,41 @@ def batched_vs_plain(tune_cache=None, reps=3):
                 max_rel_sigma_err_batched=eb, max_rel_sigma_err_loop=el)
 
 
+def qr_shortened_vs_plain(F0, G0, s_true, tol, plain_kw, tune_cache=None, reps=3):
+    """The QR-shortened solve (hz_dgsvd with qr_shorten = 1: pivoted QR of F
+    and G, sweeps on the square pair (R_F P2, R_G), then U = Q_F U'',
+    V = Q_G V'', Z = P1 P2 Z'') against the plain solve of the headline pair,
+    both timed here the same way (restore from device copies plus solve,
+    fastest of ``reps``).  The plain solve uses the headline's parameters;
+    the shortened one the autotuner's choice for the square pair (block
+    width free), or w = 16 with one inner sweep without the tuner."""
+    import torch
+    import paper_1909_00101_amd as hz
+    Fw, Gw = F0.clone(), G0.clone()
+    skw = dict(w=16, inner_max_sweeps=1)
+    if tune_cache is not None:
+        skw, _ = hz.tune(F0, G0, cache=tune_cache, ordering=hz.HZ_ORD_MM, tol=tol, qr_shorten=1)
+    skw = dict(skw, ordering=hz.HZ_ORD_MM, tol=tol, qr_shorten=1)
+    res = {}
+    for name, kw in (("plain", plain_kw), ("shortened", skw)):
+        def run():
+            Fw.copy_(F0)
+            Gw.copy_(G0)
+            return hz.gsvd(Fw, Gw, overwrite=True, **kw)
+        run()
+        dt, r = _timed(run, reps)
+        err = float(np.max(np.abs(r["sigma"].cpu().numpy() - s_true) / s_true))
+        res[name] = dict(ms=round(dt * 1e3, 2), sweeps=r["sweeps"], max_rel_sigma_err=err,
+                         status=r["status"],
+                         params={k: kw[k] for k in ("w", "inner_max_sweeps", "inner_lanes",
+                                                    "gram_splits", "update_rows") if k in kw})
+    del Fw, Gw
+    torch.cuda.empty_cache()
+    return dict(workload="the headline pair (seeded 4096x1024, kappa(X)=1e2), MM ordering, "
+                         "tol=1024*eps", speedup=round(res["plain"]["ms"] / res["shortened"]["ms"], 3),
+                **res)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,7 +238,7 @@ def main():
     ap.add_argument("--inner-max-sweeps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the mixed-precision and batched comparisons")
+                    help="skip the QR-shortened, mixed-precision and batched comparisons")
     ap.add_argument("--no-tune", action="store_true",
                     help="use --w/--inner-max-sweeps and library defaults, no autotuner")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1909_00101_amd",
@@ -348,7 +383,9 @@ def main():
                fp64_mfma_util_solve=round(mfma_util, 4),
                kernel_time_split=split, kernels=per_kernel, roofline=roof)
     if not args.no_forms:
-        out["forms"] = dict(mixed=mixed_vs_plain(), batched=batched_vs_plain(tune_cache))
+        out["forms"] = dict(
+            qr_shortened=qr_shortened_vs_plain(F0, G0, s_true, tol, kw, tune_cache),
+            mixed=mixed_vs_plain(), batched=batched_vs_plain(tune_cache))
     if not args.no_cpu_baseline:
         golden = os.path.join(ROOT, "tests", "golden", "oracle_config2.json")
         gs = None

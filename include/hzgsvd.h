@@ -265,14 +265,17 @@ size_t hz_dgsvd_batched_work_size(const hz_params *p, int batch, const int64_t *
                                   const int64_t *m_g, const int64_t *n);
 
 /* Autotuner (the launch-parameter search the batched and single-pair
- * forms use).  Starting from p (NULL = defaults), every tunable field that
- * p leaves at 0 -- w, gram_splits, update_rows, inner_lanes -- and the
- * choice between one inner sweep and p->inner_max_sweeps (block-oriented
- * or full-block inner level, Section 3.5) is varied in turn with the
- * others held at the best so far; each candidate is timed as a complete
+ * forms use).  Starting from p (NULL = defaults), the choice between one
+ * inner sweep and p->inner_max_sweeps (block-oriented or full-block inner
+ * level, Section 3.5) and every tunable field that p leaves at 0 -- w,
+ * gram_splits, update_rows, inner_lanes -- are varied in turn, in that
+ * order, with the others held at the best so far, in passes until one
+ * changes nothing (at most two); each candidate is timed as a complete
  * solve up to, not including, the final extraction, which reads F and G
  * (device, caller-owned, left unmodified) and writes only a scratch
- * workspace the tuner allocates.  Only candidates that converge count.
+ * workspace the tuner allocates; with p->qr_shorten = 1 the pair is
+ * shortened once, untimed, and the candidates are timed on the square pair
+ * the shortened solve iterates on.  Only candidates that converge count.
  * The fastest is written to *best (host) and its time in milliseconds to
  * *best_ms (host, may be NULL), and appended to the text file cache_path
  * (may be NULL) under a key of the sizes, the fixed parameters, the device

@@ -1313,6 +1313,7 @@ static uint64_t tune_key(const char *kind, const hz_params &p, int batch, const 
                          p.inner_lanes, p.gram_splits, p.update_rows};
     h = fnv(h, fixed, sizeof(fixed));
     h = fnv(h, &p.tol, sizeof(p.tol));
+    if (p.qr_shorten) h = fnv(h, "qr_shorten", 10);   // keys without it are unchanged
     h = fnv(h, &batch, sizeof(batch));
     h = fnv(h, mf, sizeof(int64_t) * batch);
     h = fnv(h, mg, sizeof(int64_t) * batch);
@@ -1390,22 +1391,29 @@ static double coordinate_search(hz_params &best, const std::vector<std::vector<i
         const double t = solve(best);
         if (t >= 0.0) best_ms = t;
     }
-    for (size_t a = 0; a < axes.size(); ++a) {
-        const int keep = *fields[a];
-        int arg = keep;
-        for (int v : axes[a]) {
-            if (v == keep) continue;
-            hz_params c = best;
-            // the field pointers address `best`; write into the copy instead
-            *(int *)((char *)&c + ((char *)fields[a] - (char *)&best)) = v;
-            if (!params_ok(c)) continue;
-            const double t = solve(c);
-            if (t >= 0.0 && (best_ms < 0.0 || t < best_ms)) {
-                best_ms = t;
-                arg = v;
+    // passes over the axes until one changes nothing (at most two): the best
+    // value on an axis can depend on the ones chosen after it
+    for (int pass = 0; pass < 2; ++pass) {
+        bool changed = false;
+        for (size_t a = 0; a < axes.size(); ++a) {
+            const int keep = *fields[a];
+            int arg = keep;
+            for (int v : axes[a]) {
+                if (v == keep) continue;
+                hz_params c = best;
+                // the field pointers address `best`; write into the copy instead
+                *(int *)((char *)&c + ((char *)fields[a] - (char *)&best)) = v;
+                if (!params_ok(c)) continue;
+                const double t = solve(c);
+                if (t >= 0.0 && (best_ms < 0.0 || t < best_ms)) {
+                    best_ms = t;
+                    arg = v;
+                }
             }
+            if (arg != keep) changed = true;
+            *fields[a] = arg;
         }
-        *fields[a] = arg;
+        if (!changed) break;
     }
     return best_ms;
 }
@@ -1420,7 +1428,7 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
 {
     hz_params base;
     if (p) base = *p; else hz_default_params(&base);
-    if (!params_ok(base) || base.qr_shorten) return -1;
+    if (!params_ok(base) || (base.qr_shorten && n > 1 && !shorten_cpt(n))) return -1;
     const double dummy = 0.0;
     const int a = check_args(m_f, m_g, n, F, ldf, G, ldg, &dummy, n, &dummy, &dummy, &dummy);
     if (a) return a;
@@ -1440,16 +1448,42 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
         return HZ_OK;
     }
     int herr = 0;
+    // With qr_shorten the pair is shortened once, untimed, and the candidates
+    // are timed on the square pair (F'', G'') the sweeps then run on.
+    const double *Ft = F, *Gt = G;
+    int64_t mft = m_f, mgt = m_g, ldft = ldf, ldgt = ldg;
+    void *swork = nullptr;
+    if (base.qr_shorten) {
+        SPlan S;
+        int hs[ST_NSLOTS] = {0, 0, 0, 0};
+        if (!make_splan(m_f, m_g, n, 0, S)) return -4;
+        if (hipMalloc(&swork, S.total) != hipSuccess) return HZ_EHIP;
+        if (launch_shorten(S, swork, F, ldf, G, ldg, st) != hipSuccess ||
+            hipMemcpyAsync(hs, (char *)swork + S.o_status, sizeof(hs), hipMemcpyDeviceToHost,
+                           st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            (void)hipFree(swork);
+            return HZ_EHIP;
+        }
+        if (hs[ST_FLAGS] & (FLAG_NONFINITE | FLAG_CHOL)) {
+            (void)hipFree(swork);
+            return (hs[ST_FLAGS] & FLAG_NONFINITE) ? HZ_ENONFINITE : HZ_ECHOL;
+        }
+        Ft = (const double *)((char *)swork + S.o_f2);
+        Gt = (const double *)((char *)swork + S.o_g2);
+        mft = mgt = n;
+        ldft = ldgt = S.ldn;
+    }
     auto solve = [&](const hz_params &c) -> double {
         Plan P;
-        if (!make_plan(c, m_f, m_g, n, 0, P)) return -1.0;
+        if (!make_plan(c, mft, mgt, n, 0, P)) return -1.0;
         void *work = nullptr;
         if (hipMalloc(&work, P.total) != hipSuccess) { herr = 1; return -1.0; }
         hz_info info;
         memset(&info, 0, sizeof(info));
         (void)hipStreamSynchronize(st);
         const double t0 = now_ms();
-        const int rc = run_solve(c, P, work, P.total, &info, st, KIND_REAL, F, ldf, G, ldg,
+        const int rc = run_solve(c, P, work, P.total, &info, st, KIND_REAL, Ft, ldft, Gt, ldgt,
                                  nullptr, nullptr, nullptr, n, nullptr, nullptr, nullptr, false);
         const double t = now_ms() - t0;
         (void)hipFree(work);
@@ -1462,13 +1496,14 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
     if (!base.inner_lanes) cur.inner_lanes = 0;
     std::vector<std::vector<int>> axes;
     std::vector<int *> fields;
-    if (!base.w) { axes.push_back({8, 16, 32}); fields.push_back(&cur.w); }
     axes.push_back({1, base.inner_max_sweeps});
     fields.push_back(&cur.inner_max_sweeps);
+    if (!base.w) { axes.push_back({8, 16, 32}); fields.push_back(&cur.w); }
     if (!base.gram_splits) { axes.push_back({4, 8, 16}); fields.push_back(&cur.gram_splits); }
     if (!base.update_rows) { axes.push_back({32, 64, 128}); fields.push_back(&cur.update_rows); }
     if (!base.inner_lanes) { axes.push_back({4, 8, 16}); fields.push_back(&cur.inner_lanes); }
     ms = coordinate_search(cur, axes, fields, solve);
+    if (swork) (void)hipFree(swork);
     if (herr) return HZ_EHIP;
     if (ms < 0.0) return HZ_ENOCONV;
     *best = cur;
@@ -1537,9 +1572,9 @@ int hz_dgsvd_batched_tune(const hz_params *p, int batch, const int64_t *m_f, con
     if (!base.w) cur.w = nmax <= 32 ? 8 : 16;
     std::vector<std::vector<int>> axes;
     std::vector<int *> fields;
-    if (!base.w) { axes.push_back({8, 16, 32}); fields.push_back(&cur.w); }
     axes.push_back({1, base.inner_max_sweeps});
     fields.push_back(&cur.inner_max_sweeps);
+    if (!base.w) { axes.push_back({8, 16, 32}); fields.push_back(&cur.w); }
     if (!base.inner_lanes) { axes.push_back({4, 8, 16}); fields.push_back(&cur.inner_lanes); }
     if (tune_ord) { axes.push_back({HZ_ORD_MM, HZ_ORD_RR}); fields.push_back(&cur.ordering); }
     ms = coordinate_search(cur, axes, fields, solve);

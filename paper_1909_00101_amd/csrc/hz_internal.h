@@ -175,17 +175,18 @@ void launch_n1_real(int64_t mf, int64_t mg, double *F, double *G, double *Z, dou
                     double *sigma_f, double *sigma_g, int *status, hipStream_t s);
 
 // QR shortening of a tall real pair (hz_shorten.hip).  Workspace offsets
-// (bytes) of Q_F, Q_G (ld ldqf, ldqg), the n x n buffers (ld ldn): Gram /
-// Schur complement S, R transposed Rt, R_F, R_G, the refinement factor R2,
-// the square pair F'', G'' (overwritten by U'', V'') and Z''; a column-block
-// temporary T, the inverted diagonal blocks Xd, the pivoting state and the
-// permutations p1 (F), q (G, = P1 P2), inv1, p2; then the square solve's
-// own workspace.
+// (bytes) of Q_F, Q_G (ld ldqf, ldqg), the n x n buffers (ld ldn) R1 of F
+// and G, the square pair F'', G'' (overwritten by U'', V'') and Z''; per
+// factored matrix the Gram / Schur complement S (later R), R transposed Rt,
+// the refinement factor R2, a column-block temporary T, the inverted
+// diagonal blocks Xd and the pivoting state; the permutations p1 (F), q (G,
+// = P1 P2), inv1, p2; then the square solve's own workspace.
 struct SPlan {
     int64_t mf, mg, n, ldqf, ldqg, ldn;
     int cpt, nb, nblk;
-    size_t o_qf, o_qg, o_s, o_rt, o_r1f, o_r1g, o_r2, o_f2, o_g2, o_z2, o_t, o_xd, o_d, o_done;
-    size_t o_p1, o_q, o_inv1, o_p2, o_id, o_status, o_solve;
+    size_t o_qf, o_qg, o_r1f, o_r1g, o_f2, o_g2, o_z2;
+    size_t o_s[2], o_rt[2], o_r2[2], o_t[2], o_xd[2], o_d[2], o_done[2], o_id[2];  // per F, G
+    size_t o_p1, o_q, o_inv1, o_p2, o_status, o_solve;
     size_t total;
 };
 int shorten_cpt(int64_t n);   // 0 if n is beyond the shortening's limit (8192)

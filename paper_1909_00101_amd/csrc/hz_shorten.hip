@@ -29,27 +29,42 @@
 
 namespace hz {
 
+
+// F and G are factored side by side: every kernel below takes the two
+// problems in one launch (blockIdx.z, or blockIdx.x for the single-
+// workgroup Cholesky panel), since each step is latency bound and the two
+// factorizations are independent until the permutations are combined.
+
 // ------------------------------------------------------------------ GEMM
-// C (M x N) = alpha * op(A) * B + beta * C0, column-major.  op(A) = A
-// (M x K, ld lda) or, with TA, A^T for A of K x M.  C0 may alias C (each
-// workgroup reads its C0 tile only after its whole K loop, and writes the
-// same tile); with beta == 0 C0 is not read.  A 64 x 64 tile of C per
-// workgroup of four waves, each wave 32 x 32 (2 x 2 MFMA 16x16x4 blocks);
-// K runs in chunks of 32 staged in LDS, the next chunk prefetched into
-// registers while the current one is multiplied.
+// C (M x N) = alpha * op(A) * B + beta * C0, column-major, per problem z.
+// op(A) = A (M x K, ld lda) or, with TA, A^T for A of K x M.  C0 may alias
+// C (each workgroup reads its C0 tile only after its whole K loop, and
+// writes the same tile); with beta == 0 C0 is not read.  A 64 x 64 tile of
+// C per workgroup of four waves, each wave 32 x 32 (2 x 2 MFMA 16x16x4
+// blocks); K runs in chunks of 32 staged in LDS, the next chunk prefetched
+// into registers while the current one is multiplied.
+struct GemmArgs {
+    const double *A[2], *B[2], *C0[2];
+    double *C[2];
+    int64_t M[2], N[2], K[2], lda[2], ldb[2], ldc0[2], ldc[2];
+    double alpha, beta;
+};
+
 static constexpr int GK = 32, GLD = 66;
 
 template <bool TA>
-__global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, double alpha,
-                                              const double *__restrict__ A, int64_t lda,
-                                              const double *__restrict__ B, int64_t ldb,
-                                              double beta, const double *C0, int64_t ldc0,
-                                              double *C, int64_t ldc)
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
 {
     __shared__ __attribute__((aligned(16))) double sA[GK * GLD];   // [k][i]
     __shared__ __attribute__((aligned(16))) double sB[GK * GLD];   // [k][j]
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int z = blockIdx.z;
+    const int64_t M = g.M[z], N = g.N[z], K = g.K[z];
     const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
+    if (r0 >= M || c0 >= N) return;   // the grid covers the larger problem
+    const double *__restrict__ A = g.A[z];
+    const double *__restrict__ B = g.B[z];
+    const int64_t lda = g.lda[z], ldb = g.ldb[z];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = 32 * (wave & 1), wc = 32 * (wave >> 1);
     const int i16 = lane & 15, k4 = lane >> 4;
     d4 acc[2][2];
@@ -58,7 +73,7 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, d
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-    // per-thread load coordinates: 8 elements of the A chunk, 8 of the B chunk
+    // each thread moves 8 elements of the A chunk and 8 of the B chunk
     double ra[8], rb[8];
     auto load = [&](int64_t k0) {
 #pragma unroll
@@ -103,6 +118,9 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, d
                 for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(fb[b], fa[a], acc[a][b]);
         }
     }
+    const double *C0 = g.C0[z];
+    double *C = g.C[z];
+    const int64_t ldc0 = g.ldc0[z], ldc = g.ldc[z];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -112,61 +130,86 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t N, int64_t K, d
                 const int64_t gi = r0 + wr + 16 * a + i16;
                 const int64_t gj = c0 + wc + 16 * b + 4 * r + k4;
                 if (gi < M && gj < N) {
-                    double v = alpha * acc[a][b][r];
-                    if (beta != 0.0) v += beta * C0[gj * ldc0 + gi];
+                    double v = g.alpha * acc[a][b][r];
+                    if (g.beta != 0.0) v += g.beta * C0[gj * ldc0 + gi];
                     C[gj * ldc + gi] = v;
                 }
             }
 }
 
-static void gemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const double *A,
-                 int64_t lda, const double *B, int64_t ldb, double beta, const double *C0,
-                 int64_t ldc0, double *C, int64_t ldc, hipStream_t s)
+static void gemm(bool ta, int nz, const GemmArgs &g, hipStream_t s)
 {
-    if (M <= 0 || N <= 0) return;
-    const dim3 grid((unsigned)((M + 63) / 64), (unsigned)((N + 63) / 64));
-    if (ta)
-        hipLaunchKernelGGL(k_gemm<true>, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
-                           beta, C0, ldc0, C, ldc);
-    else
-        hipLaunchKernelGGL(k_gemm<false>, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
-                           beta, C0, ldc0, C, ldc);
+    int64_t mx = 0, nx = 0;
+    for (int z = 0; z < nz; ++z) {
+        mx = g.M[z] > mx ? g.M[z] : mx;
+        nx = g.N[z] > nx ? g.N[z] : nx;
+    }
+    if (mx <= 0 || nx <= 0) return;
+    const dim3 grid((unsigned)((mx + 63) / 64), (unsigned)((nx + 63) / 64), (unsigned)nz);
+    if (ta) hipLaunchKernelGGL(k_gemm<true>, grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(k_gemm<false>, grid, dim3(256), 0, s, g);
 }
 
 // ------------------------------------------------------ pivoted Cholesky
-// S (n x n, ld lds, both triangles) is the current Schur complement; Rt
-// (n x n, ld ldr) receives R transposed and in the original column order:
-// column j of Rt is row j of R, entry c of it belongs to original column c
-// (zero once c has been pivoted at an earlier step).  d[c] is the current
-// diagonal of S, done[c] marks pivoted columns, piv[j] the original column
-// taken at step j.  One workgroup of PT threads runs the nb steps of the
-// panel [j0, j0 + nb); thread t owns the columns t, t + PT, ... (CPT of
-// them) and keeps their panel rows of R in registers.
+// S (n x n, ld, both triangles) is the current Schur complement; Rt (n x n,
+// ld) receives R transposed and in the original column order: column j of
+// Rt is row j of R, entry c of it belongs to original column c (zero once c
+// has been pivoted at an earlier step).  d[c] is the current diagonal of S,
+// done[c] marks pivoted columns, piv[j] the original column taken at step
+// j (piv[j] = j without pivoting).
+struct PcholArgs {
+    const double *S[2];
+    double *Rt[2], *d[2];
+    int *done[2], *piv[2];
+};
+
 static constexpr int PT = 1024;
 
-template <int CPT, int NB>
-__global__ __launch_bounds__(PT) void k_pchol_panel(int n, const double *__restrict__ S,
-                                                    int64_t lds, double *__restrict__ Rt,
-                                                    int64_t ldr, double *__restrict__ dg,
-                                                    int *__restrict__ doneg, int *__restrict__ piv,
-                                                    int j0, int nb, int pivoting,
+// Workgroup barrier that orders LDS only: global stores of R and loads of
+// S stay in flight across it (nothing in the panel kernel reads global
+// memory written in the same launch).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// One workgroup of PT threads per problem runs the steps [j0, j0 + NB) of
+// a panel.  Thread t owns the columns t, t + PT, ... (CPT of them): their
+// diagonal entries and panel rows of R stay in its registers, and the
+// panel rows are also kept in LDS (row stride CPT * PT), where the pivot
+// column's entries are read by all.  With pivoting (PIV) a step is one
+// barrier: the waves' (largest diagonal, column) candidates meet in LDS and
+// every wave reduces them itself, so the pivot and its diagonal entry are
+// known to all threads without a broadcast; the row of S at the pivot is
+// then read from memory.  Without pivoting the panel's NB rows of S are
+// read at its start and the diagonal entry of the next column is handed
+// over in LDS.
+template <int CPT, int NB, bool PIV>
+__global__ __launch_bounds__(PT) void k_pchol_panel(int n, int64_t ld, PcholArgs a, int j0,
                                                     int *__restrict__ status)
 {
-    __shared__ double s_bv[PT / 64];
-    __shared__ int s_bi[PT / 64];
-    __shared__ double s_rp[NB + 1];
-    __shared__ int s_p;
+    constexpr int RS = CPT * PT;
+    __shared__ double Rp[NB * RS];
+    __shared__ double s_bv[2][PT / 64];
+    __shared__ int s_bi[2][PT / 64];
+    __shared__ double s_dn[2];
+    const int z = blockIdx.x;
+    const double *__restrict__ S = a.S[z];
+    double *__restrict__ Rt = a.Rt[z];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int jn = (j0 + nb < n) ? j0 + nb : n;
+    const int jn = (j0 + NB < n) ? j0 + NB : n;
     double dl[CPT];
     int dn[CPT];
     double rr[NB][CPT];
+    double srows[PIV ? 1 : NB][CPT];
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
         const int c = tid + PT * u;
         if (c < n) {
-            dl[u] = (j0 == 0) ? S[(int64_t)c * lds + c] : dg[c];
-            dn[u] = (j0 == 0) ? 0 : doneg[c];
+            dl[u] = (j0 == 0) ? S[(int64_t)c * ld + c] : a.d[z][c];
+            dn[u] = (j0 == 0) ? 0 : a.done[z][c];
         } else {
             dl[u] = 0.0;
             dn[u] = 1;
@@ -174,10 +217,22 @@ __global__ __launch_bounds__(PT) void k_pchol_panel(int n, const double *__restr
 #pragma unroll
         for (int i = 0; i < NB; ++i) rr[i][u] = 0.0;
     }
+    if (!PIV) {
+#pragma unroll
+        for (int u = 0; u < CPT; ++u) {
+            const int c = tid + PT * u;
+            if (c == j0) s_dn[0] = dl[u];
+#pragma unroll
+            for (int i = 0; i < (PIV ? 1 : NB); ++i)
+                srows[i][u] = (j0 + i < n && c < n) ? S[(int64_t)(j0 + i) * ld + c] : 0.0;
+        }
+    }
     for (int j = j0; j < jn; ++j) {
-        const int t = j - j0;
-        int p = j;
-        if (pivoting) {
+        const int t = j - j0, par = t & 1;
+        int p;
+        double dp;
+        double sv[CPT];
+        if (PIV) {
             // largest remaining diagonal (a NaN counts as +inf, so that it is
             // taken and reported); ties go to the smaller column index
             double bv = -INFINITY;
@@ -201,53 +256,61 @@ __global__ __launch_bounds__(PT) void k_pchol_panel(int n, const double *__restr
                 }
             }
             if (lane == 0) {
-                s_bv[wv] = bv;
-                s_bi[wv] = bi;
+                s_bv[par][wv] = bv;
+                s_bi[par][wv] = bi;
             }
-            __syncthreads();
-            if (tid == 0) {
-                double b = s_bv[0];
-                int ib = s_bi[0];
-                for (int w = 1; w < PT / 64; ++w)
-                    if (s_bv[w] > b || (s_bv[w] == b && s_bi[w] < ib)) {
-                        b = s_bv[w];
-                        ib = s_bi[w];
-                    }
-                s_p = ib;
-            }
-            __syncthreads();
-            p = s_p;
-        }
-        // the owner of column p publishes its panel rows of R and d[p]
-        if (tid == p % PT) {
-            const int up = p / PT;
+            lds_barrier();
+            bv = (lane < PT / 64) ? s_bv[par][lane] : -INFINITY;
+            bi = (lane < PT / 64) ? s_bi[par][lane] : INT_MAX;
 #pragma unroll
-            for (int u = 0; u < CPT; ++u)
-                if (u == up) {
-#pragma unroll
-                    for (int i = 0; i < NB; ++i)
-                        if (i < t) s_rp[i] = rr[i][u];
-                    s_rp[NB] = dl[u];
-                    dn[u] = 1;
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double ov = __shfl_xor(bv, off);
+                const int oi = __shfl_xor(bi, off);
+                if (ov > bv || (ov == bv && oi < bi)) {
+                    bv = ov;
+                    bi = oi;
                 }
+            }
+            p = __builtin_amdgcn_readfirstlane(bi);
+            dp = bv;
+            const double *srow = S + (int64_t)p * ld;   // column p = row p (symmetric)
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                const int c = tid + PT * u;
+                sv[u] = (c < n && !dn[u] && c != p) ? srow[c] : 0.0;
+            }
+        } else {
+            lds_barrier();
+            p = j;
+            dp = s_dn[par];
+#pragma unroll
+            for (int u = 0; u < CPT; ++u) {
+                sv[u] = 0.0;
+#pragma unroll
+                for (int i = 0; i < (PIV ? 1 : NB); ++i)
+                    if (i == t) sv[u] = srows[i][u];
+            }
         }
-        __syncthreads();
-        const double dp = s_rp[NB];
+#pragma unroll
+        for (int u = 0; u < CPT; ++u)
+            if (tid + PT * u == p) dn[u] = 1;
         const bool nonfinite = !(fabs(dp) <= DBL_MAX);
         const bool bad = nonfinite || !(dp > 0.0);
         const double r = bad ? 1.0 : sqrt(dp);
         if (bad && tid == 0) atomicOr(&status[ST_FLAGS], nonfinite ? FLAG_NONFINITE : FLAG_CHOL);
-        const double *srow = S + (int64_t)p * lds;   // column p = row p (symmetric)
+        double rp[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) rp[i] = (i < t) ? Rp[i * RS + p] : 0.0;
 #pragma unroll
         for (int u = 0; u < CPT; ++u) {
             const int c = tid + PT * u;
             double v = 0.0;
             if (c < n && !dn[u]) {
-                double sv = srow[c];
+                double x = sv[u];
 #pragma unroll
                 for (int i = 0; i < NB; ++i)
-                    if (i < t) sv -= s_rp[i] * rr[i][u];
-                v = sv / r;
+                    if (i < t) x -= rp[i] * rr[i][u];
+                v = x / r;
                 dl[u] -= v * v;
             } else if (c == p) {
                 v = r;
@@ -255,35 +318,40 @@ __global__ __launch_bounds__(PT) void k_pchol_panel(int n, const double *__restr
 #pragma unroll
             for (int i = 0; i < NB; ++i)
                 if (i == t) rr[i][u] = v;
-            if (c < n) Rt[(int64_t)j * ldr + c] = v;
+            if (c < n) {
+                Rp[t * RS + c] = v;
+                Rt[(int64_t)j * ld + c] = v;
+            }
+            if (!PIV && c == j + 1) s_dn[par ^ 1] = dl[u];
         }
-        if (tid == 0) piv[j] = p;
-        __syncthreads();
+        if (tid == 0) a.piv[z][j] = p;
     }
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
         const int c = tid + PT * u;
         if (c < n) {
-            dg[c] = dl[u];
-            doneg[c] = dn[u];
+            a.d[z][c] = dl[u];
+            a.done[z][c] = dn[u];
         }
     }
 }
 
 // Trailing update after a panel: S -= Rt(:, j0:j0+nb) Rt(:, j0:j0+nb)^T over
-// all of S (entries of pivoted columns are never read again).
-__global__ __launch_bounds__(256) void k_pchol_update(int n, double *__restrict__ S, int64_t lds,
-                                                      const double *__restrict__ Rt, int64_t ldr,
-                                                      int j0, int nb)
+// all of S (entries of pivoted columns are never read again); nb <= 16.
+__global__ __launch_bounds__(256) void k_pchol_update(int n, int64_t ld, PcholArgs g, int j0,
+                                                      int nb)
 {
     __shared__ double a[16][64], b[16][64];
+    const int z = blockIdx.z;
+    double *__restrict__ S = (double *)g.S[z];
+    const double *__restrict__ Rt = g.Rt[z];
     const int tid = threadIdx.x;
     const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
     for (int e = tid; e < 16 * 64; e += 256) {
         const int i = e / 64, x = e % 64;
         const bool ok = i < nb;
-        a[i][x] = (ok && r0 + x < n) ? Rt[(int64_t)(j0 + i) * ldr + r0 + x] : 0.0;
-        b[i][x] = (ok && c0 + x < n) ? Rt[(int64_t)(j0 + i) * ldr + c0 + x] : 0.0;
+        a[i][x] = (ok && r0 + x < n) ? Rt[(int64_t)(j0 + i) * ld + r0 + x] : 0.0;
+        b[i][x] = (ok && c0 + x < n) ? Rt[(int64_t)(j0 + i) * ld + c0 + x] : 0.0;
     }
     __syncthreads();
     const int r = tid & 63;
@@ -293,35 +361,40 @@ __global__ __launch_bounds__(256) void k_pchol_update(int n, double *__restrict_
         double acc = 0.0;
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc += a[i][r] * b[i][q];
-        S[(int64_t)(c0 + q) * lds + r0 + r] -= acc;
+        S[(int64_t)(c0 + q) * ld + r0 + r] -= acc;
     }
 }
 
 // ------------------------------------------------- triangular pieces
-// Inverses of the 64 x 64 diagonal blocks of the upper triangular R (n x n,
-// ld ldr): block J is written to X + 4096 J (column-major 64 x 64), the
-// trailing partial block padded with the identity.  Each wave solves
-// R_JJ x = e_j for its columns by column-oriented back substitution, one
-// row per lane.
-__global__ __launch_bounds__(256) void k_trinv_diag(int n, const double *__restrict__ R,
-                                                    int64_t ldr, double *__restrict__ X)
+// Inverses of the 64 x 64 diagonal blocks of the upper triangular R[z]
+// (n x n, ld): block J goes to X[z] + 4096 J (column-major 64 x 64), the
+// trailing partial block padded with the identity.  Each of the 16 waves
+// solves R_JJ x = e_j for 4 columns j by column-oriented back substitution,
+// one row per lane, with the diagonal's reciprocals formed once.
+__global__ __launch_bounds__(1024) void k_trinv_diag(int n, int64_t ld, const double *R0,
+                                                     const double *R1, double *X0, double *X1)
 {
     __shared__ double sR[64 * 65];
+    __shared__ double sI[64];
+    const double *__restrict__ R = blockIdx.y ? R1 : R0;
+    double *__restrict__ X = blockIdx.y ? X1 : X0;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int b0 = blockIdx.x * 64;
     const int bs = (n - b0 < 64) ? n - b0 : 64;
-    for (int e = tid; e < 64 * 64; e += 256) {
+    for (int e = tid; e < 64 * 64; e += 1024) {
         const int r = e % 64, c = e / 64;
         double v = (r == c) ? 1.0 : 0.0;
-        if (r < bs && c < bs && r <= c) v = R[(int64_t)(b0 + c) * ldr + b0 + r];
+        if (r < bs && c < bs && r <= c) v = R[(int64_t)(b0 + c) * ld + b0 + r];
         sR[c * 65 + r] = v;
     }
     __syncthreads();
-    for (int jj = 0; jj < 16; ++jj) {
-        const int j = wave + 4 * jj;
+    if (tid < 64) sI[tid] = 1.0 / sR[tid * 65 + tid];
+    __syncthreads();
+    for (int jj = 0; jj < 4; ++jj) {
+        const int j = wave + 16 * jj;
         double x = (lane == j) ? 1.0 : 0.0;
         for (int k = j; k >= 0; --k) {
-            const double xk = __shfl(x, k) / sR[k * 65 + k];
+            const double xk = __shfl(x, k) * sI[k];
             if (lane == k) x = xk;
             else if (lane < k) x -= xk * sR[k * 65 + lane];
         }
@@ -329,38 +402,46 @@ __global__ __launch_bounds__(256) void k_trinv_diag(int n, const double *__restr
     }
 }
 
-// dst(0:m, j) = src(0:m, idx[j]) for j < ncol
-__global__ __launch_bounds__(256) void k_gather_cols(int64_t m, int ncol, const int *__restrict__ idx,
-                                                     const double *__restrict__ src, int64_t lds,
-                                                     double *__restrict__ dst, int64_t ldd)
+// dst[z](0:m[z], j) = src[z](0:m[z], idx[z][j]) for j < ncol
+struct GatherArgs {
+    const int *idx[2];
+    const double *src[2];
+    double *dst[2];
+    int64_t m[2], lds[2], ldd[2];
+};
+
+__global__ __launch_bounds__(256) void k_gather_cols(GatherArgs g)
 {
-    const int j = blockIdx.y;
-    const double *s = src + (int64_t)idx[j] * lds;
-    double *d = dst + (int64_t)j * ldd;
+    const int z = blockIdx.z, j = blockIdx.y;
+    const int64_t m = g.m[z];
+    const double *s = g.src[z] + (int64_t)g.idx[z][j] * g.lds[z];
+    double *d = g.dst[z] + (int64_t)j * g.ldd[z];
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
         d[i] = s[i];
 }
 
-// R(i, k) = Rt(idx[k], i) for i, k < n: the upper triangular factor in the
-// pivoted column order (idx = piv), or the plain transpose (idx = null).
-__global__ __launch_bounds__(256) void k_gather_rt(int n, const int *__restrict__ idx,
-                                                   const double *__restrict__ Rt, int64_t ldr,
-                                                   double *__restrict__ R, int64_t ldo)
+// R[z](i, k) = Rt[z](idx[z][k], i) for i, k < n: the upper triangular factor
+// in the pivoted column order (idx = piv), or the plain transpose (idx[z]
+// null); 32 x 32 tiles through LDS.
+__global__ __launch_bounds__(256) void k_gather_rt(int n, int64_t ld, GatherArgs g)
 {
     __shared__ double tile[32][33];
+    const int z = blockIdx.z;
+    const int *idx = g.idx[z];
+    const double *__restrict__ Rt = g.src[z];
+    double *__restrict__ R = g.dst[z];
     const int i0 = blockIdx.x * 32, k0 = blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
-    // read Rt(idx[k], i): for fixed i (a column of Rt) the rows idx[k]
     for (int y = ty; y < 32; y += 8) {
         const int i = i0 + y, k = k0 + tx;
         double v = 0.0;
-        if (i < n && k < n) v = Rt[(int64_t)i * ldr + (idx ? idx[k] : k)];
+        if (i < n && k < n) v = Rt[(int64_t)i * ld + (idx ? idx[k] : k)];
         tile[y][tx] = v;
     }
     __syncthreads();
     for (int y = ty; y < 32; y += 8) {
         const int k = k0 + y, i = i0 + tx;
-        if (i < n && k < n) R[(int64_t)k * ldo + i] = tile[tx][y];
+        if (i < n && k < n) R[(int64_t)k * ld + i] = tile[tx][y];
     }
 }
 
@@ -376,8 +457,7 @@ __global__ __launch_bounds__(256) void k_scatter_rows(int n, const int *__restri
     Z[(int64_t)c * ldz + q[j]] = Z2[(int64_t)c * ld2 + j];
 }
 
-// inv[p[j]] = j, and q2[j] = inv1[q[j]] when inv1 is given (the slot of
-// q[j] in the order p of the first factorization).
+// p2[j] = slot of q[j] in the order p1 (inv1 = p1^-1 formed first).
 __global__ __launch_bounds__(256) void k_perm_inverse(int n, const int *__restrict__ p,
                                                       int *__restrict__ inv)
 {
@@ -395,7 +475,9 @@ __global__ __launch_bounds__(256) void k_perm_compose(int n, const int *__restri
 
 // ------------------------------------------------------------------ host
 
-static int panel_width(int cpt) { return cpt <= 2 ? 16 : (cpt == 4 ? 8 : 4); }
+// Panel widths: the LDS copy of the panel rows is NB * CPT * 1024 doubles
+// (128 KiB) for every n range.
+static int panel_width(int cpt) { return 16 / cpt; }
 
 int shorten_cpt(int64_t n)
 {
@@ -419,104 +501,121 @@ bool make_splan(int64_t mf, int64_t mg, int64_t n, size_t solve_bytes, SPlan &S)
     S.ldqg = (mg + 7) / 8 * 8;
     S.ldn = (n + 7) / 8 * 8;
     S.nblk = (int)((n + 63) / 64);
-    const int64_t mt = S.ldqf > S.ldqg ? S.ldqf : S.ldqg;
     const size_t nn = 8 * (size_t)S.ldn * n;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t o = 0;
     S.o_qf = o; o = al(o + 8 * (size_t)S.ldqf * n);
     S.o_qg = o; o = al(o + 8 * (size_t)S.ldqg * n);
-    S.o_s = o; o = al(o + nn);
-    S.o_rt = o; o = al(o + nn);
     S.o_r1f = o; o = al(o + nn);
     S.o_r1g = o; o = al(o + nn);
-    S.o_r2 = o; o = al(o + nn);
     S.o_f2 = o; o = al(o + nn);
     S.o_g2 = o; o = al(o + nn);
     S.o_z2 = o; o = al(o + nn);
-    S.o_t = o; o = al(o + 8 * (size_t)mt * 64);
-    S.o_xd = o; o = al(o + 8 * (size_t)S.nblk * 4096);
-    S.o_d = o; o = al(o + 8 * (size_t)n);
-    S.o_done = o; o = al(o + 4 * (size_t)n);
+    for (int z = 0; z < 2; ++z) {
+        const int64_t m = z ? S.ldqg : S.ldqf;
+        S.o_s[z] = o; o = al(o + nn);
+        S.o_rt[z] = o; o = al(o + nn);
+        S.o_r2[z] = o; o = al(o + nn);
+        S.o_t[z] = o; o = al(o + 8 * (size_t)m * 64);
+        S.o_xd[z] = o; o = al(o + 8 * (size_t)S.nblk * 4096);
+        S.o_d[z] = o; o = al(o + 8 * (size_t)n);
+        S.o_done[z] = o; o = al(o + 4 * (size_t)n);
+        S.o_id[z] = o; o = al(o + 4 * (size_t)n);
+    }
     S.o_p1 = o; o = al(o + 4 * (size_t)n);
     S.o_q = o; o = al(o + 4 * (size_t)n);
     S.o_inv1 = o; o = al(o + 4 * (size_t)n);
     S.o_p2 = o; o = al(o + 4 * (size_t)n);
-    S.o_id = o; o = al(o + 4 * (size_t)n);
     S.o_status = o; o = al(o + 4 * ST_NSLOTS);
     S.o_solve = o; o = al(o + solve_bytes);
     S.total = o;
     return true;
 }
 
-// Cholesky of S (ld S.ldn) into Rt, with diagonal pivoting or without.
-static void pchol(const SPlan &P, double *S, double *Rt, double *d, int *done, int *piv,
-                  bool pivoting, int *status, hipStream_t s)
+template <typename T> static T *at(char *b, size_t o) { return (T *)(b + o); }
+
+// Cholesky of S[z] (ld ldn) into Rt[z] for both problems, with diagonal
+// pivoting (piv[z] = pivot order) or without (piv[z] = identity).
+static void pchol(const SPlan &P, char *b, int *const piv[2], bool pivoting, int *status,
+                  hipStream_t s)
 {
     const int n = (int)P.n, nb = P.nb;
+    PcholArgs a;
+    for (int z = 0; z < 2; ++z) {
+        a.S[z] = at<double>(b, P.o_s[z]);
+        a.Rt[z] = at<double>(b, P.o_rt[z]);
+        a.d[z] = at<double>(b, P.o_d[z]);
+        a.done[z] = at<int>(b, P.o_done[z]);
+        a.piv[z] = piv[z];
+    }
     const unsigned gt = (unsigned)((n + 63) / 64);
     for (int j0 = 0; j0 < n; j0 += nb) {
-        switch (P.cpt) {
-        case 1:
-            hipLaunchKernelGGL((k_pchol_panel<1, 16>), dim3(1), dim3(PT), 0, s, n, S, P.ldn, Rt,
-                               P.ldn, d, done, piv, j0, nb, pivoting ? 1 : 0, status);
-            break;
-        case 2:
-            hipLaunchKernelGGL((k_pchol_panel<2, 16>), dim3(1), dim3(PT), 0, s, n, S, P.ldn, Rt,
-                               P.ldn, d, done, piv, j0, nb, pivoting ? 1 : 0, status);
-            break;
-        case 4:
-            hipLaunchKernelGGL((k_pchol_panel<4, 8>), dim3(1), dim3(PT), 0, s, n, S, P.ldn, Rt,
-                               P.ldn, d, done, piv, j0, nb, pivoting ? 1 : 0, status);
-            break;
-        default:
-            hipLaunchKernelGGL((k_pchol_panel<8, 4>), dim3(1), dim3(PT), 0, s, n, S, P.ldn, Rt,
-                               P.ldn, d, done, piv, j0, nb, pivoting ? 1 : 0, status);
-            break;
+        const dim3 g2(2), bt(PT);
+        switch (P.cpt * 2 + (pivoting ? 1 : 0)) {
+        case 3: hipLaunchKernelGGL((k_pchol_panel<1, 16, true>), g2, bt, 0, s, n, P.ldn, a, j0, status); break;
+        case 2: hipLaunchKernelGGL((k_pchol_panel<1, 16, false>), g2, bt, 0, s, n, P.ldn, a, j0, status); break;
+        case 5: hipLaunchKernelGGL((k_pchol_panel<2, 8, true>), g2, bt, 0, s, n, P.ldn, a, j0, status); break;
+        case 4: hipLaunchKernelGGL((k_pchol_panel<2, 8, false>), g2, bt, 0, s, n, P.ldn, a, j0, status); break;
+        case 9: hipLaunchKernelGGL((k_pchol_panel<4, 4, true>), g2, bt, 0, s, n, P.ldn, a, j0, status); break;
+        case 8: hipLaunchKernelGGL((k_pchol_panel<4, 4, false>), g2, bt, 0, s, n, P.ldn, a, j0, status); break;
+        case 17: hipLaunchKernelGGL((k_pchol_panel<8, 2, true>), g2, bt, 0, s, n, P.ldn, a, j0, status); break;
+        default: hipLaunchKernelGGL((k_pchol_panel<8, 2, false>), g2, bt, 0, s, n, P.ldn, a, j0, status); break;
         }
         if (j0 + nb < n)
-            hipLaunchKernelGGL(k_pchol_update, dim3(gt, gt), dim3(256), 0, s, n, S, P.ldn, Rt,
-                               P.ldn, j0, nb);
+            hipLaunchKernelGGL(k_pchol_update, dim3(gt, gt, 2), dim3(256), 0, s, n, P.ldn, a, j0,
+                               nb);
     }
 }
 
-// In place Y (m x n, ld ldy) <- Y R^-1 for the upper triangular R (ld ldn),
-// by 64-column blocks: T = Y_J - Y_{<J} R_{<J,J}, then Y_J = T inv(R_JJ).
-static void trsm_right(const SPlan &P, int64_t m, double *Y, int64_t ldy, const double *R,
-                       double *T, double *Xd, hipStream_t s)
+// In place Y[z] (m[z] x n, ld ldy[z]) <- Y[z] R[z]^-1 for upper triangular
+// R[z] (ld ldn), by 64-column blocks: T = Y_J - Y_{<J} R_{<J,J}, then
+// Y_J = T inv(R_JJ).
+static void trsm_right(const SPlan &P, char *b, double *const Y[2], const int64_t ldy[2],
+                       const double *const R[2], hipStream_t s)
 {
     const int n = (int)P.n;
-    hipLaunchKernelGGL(k_trinv_diag, dim3((unsigned)P.nblk), dim3(256), 0, s, n, R, P.ldn, Xd);
+    const int64_t m[2] = {P.mf, P.mg};
+    double *T[2] = {at<double>(b, P.o_t[0]), at<double>(b, P.o_t[1])};
+    double *X[2] = {at<double>(b, P.o_xd[0]), at<double>(b, P.o_xd[1])};
+    hipLaunchKernelGGL(k_trinv_diag, dim3((unsigned)P.nblk, 2), dim3(1024), 0, s, n, P.ldn, R[0],
+                       R[1], X[0], X[1]);
     for (int J = 0; J < P.nblk; ++J) {
         const int64_t j0 = 64 * (int64_t)J, bs = (n - j0 < 64) ? n - j0 : 64;
-        gemm(false, m, bs, j0, -1.0, Y, ldy, R + j0 * P.ldn, P.ldn, 1.0, Y + j0 * ldy, ldy, T,
-             m, s);
-        gemm(false, m, bs, bs, 1.0, T, m, Xd + 4096 * (int64_t)J, 64, 0.0, nullptr, 0,
-             Y + j0 * ldy, ldy, s);
+        GemmArgs g1, g2;
+        for (int z = 0; z < 2; ++z) {
+            g1.A[z] = Y[z]; g1.lda[z] = ldy[z];
+            g1.B[z] = R[z] + j0 * P.ldn; g1.ldb[z] = P.ldn;
+            g1.C0[z] = Y[z] + j0 * ldy[z]; g1.ldc0[z] = ldy[z];
+            g1.C[z] = T[z]; g1.ldc[z] = m[z];
+            g1.M[z] = m[z]; g1.N[z] = bs; g1.K[z] = j0;
+            g2.A[z] = T[z]; g2.lda[z] = m[z];
+            g2.B[z] = X[z] + 4096 * (int64_t)J; g2.ldb[z] = 64;
+            g2.C0[z] = nullptr; g2.ldc0[z] = 0;
+            g2.C[z] = Y[z] + j0 * ldy[z]; g2.ldc[z] = ldy[z];
+            g2.M[z] = m[z]; g2.N[z] = bs; g2.K[z] = bs;
+        }
+        g1.alpha = -1.0; g1.beta = 1.0;
+        g2.alpha = 1.0; g2.beta = 0.0;
+        gemm(false, 2, g1, s);
+        gemm(false, 2, g2, s);
     }
 }
 
-// Given Q = Y P (m x n, ld ldq: Y's columns already in the pivot order) and
-// R = R1 with R1^T R1 = P^T Y^T Y P (ld ldn), forms the orthonormal factor
-// in place (Q <- Y P R1^-1, then one Cholesky-QR refinement) and R <- R2 R1,
-// so that Y P = Q R.
-static void cholqr2(const SPlan &P, int64_t m, double *Q, int64_t ldq, double *R, char *b,
-                    hipStream_t s)
+// S[z] = Y[z]^T Y[z] (n x n, ld ldn) for Y[z] of m[z] rows.
+static void gram2(const SPlan &P, char *b, const double *const Y[2], const int64_t ldy[2],
+                  hipStream_t s)
 {
-    const int n = (int)P.n;
-    double *S = (double *)(b + P.o_s), *Rt = (double *)(b + P.o_rt);
-    double *R2 = (double *)(b + P.o_r2), *T = (double *)(b + P.o_t), *Xd = (double *)(b + P.o_xd);
-    double *d = (double *)(b + P.o_d);
-    int *done = (int *)(b + P.o_done), *id = (int *)(b + P.o_id);
-    int *status = (int *)(b + P.o_status);
-    trsm_right(P, m, Q, ldq, R, T, Xd, s);
-    gemm(true, n, n, m, 1.0, Q, ldq, Q, ldq, 0.0, nullptr, 0, S, P.ldn, s);
-    pchol(P, S, Rt, d, done, id, false, status, s);
-    hipLaunchKernelGGL(k_gather_rt, dim3((unsigned)((n + 31) / 32), (unsigned)((n + 31) / 32)),
-                       dim3(256), 0, s, n, (const int *)nullptr, Rt, P.ldn, R2, P.ldn);
-    trsm_right(P, m, Q, ldq, R2, T, Xd, s);
-    // R <- R2 R (both upper triangular); S is free again and takes the product
-    gemm(false, n, n, n, 1.0, R2, P.ldn, R, P.ldn, 0.0, nullptr, 0, S, P.ldn, s);
-    (void)hipMemcpyAsync(R, S, 8 * (size_t)P.ldn * n, hipMemcpyDeviceToDevice, s);
+    GemmArgs g;
+    const int64_t m[2] = {P.mf, P.mg};
+    for (int z = 0; z < 2; ++z) {
+        g.A[z] = Y[z]; g.lda[z] = ldy[z];
+        g.B[z] = Y[z]; g.ldb[z] = ldy[z];
+        g.C0[z] = nullptr; g.ldc0[z] = 0;
+        g.C[z] = at<double>(b, P.o_s[z]); g.ldc[z] = P.ldn;
+        g.M[z] = P.n; g.N[z] = P.n; g.K[z] = m[z];
+    }
+    g.alpha = 1.0; g.beta = 0.0;
+    gemm(true, 2, g, s);
 }
 
 hipError_t launch_shorten(const SPlan &P, void *work, const double *F, int64_t ldf,
@@ -524,43 +623,80 @@ hipError_t launch_shorten(const SPlan &P, void *work, const double *F, int64_t l
 {
     char *b = (char *)work;
     const int n = (int)P.n;
-    double *Qf = (double *)(b + P.o_qf), *Qg = (double *)(b + P.o_qg);
-    double *S = (double *)(b + P.o_s), *Rt = (double *)(b + P.o_rt);
-    double *R1f = (double *)(b + P.o_r1f), *R1g = (double *)(b + P.o_r1g);
-    double *F2 = (double *)(b + P.o_f2), *G2 = (double *)(b + P.o_g2);
-    double *d = (double *)(b + P.o_d);
-    int *done = (int *)(b + P.o_done), *p1 = (int *)(b + P.o_p1), *q = (int *)(b + P.o_q);
-    int *inv1 = (int *)(b + P.o_inv1), *p2 = (int *)(b + P.o_p2);
-    int *status = (int *)(b + P.o_status);
+    int *p1 = at<int>(b, P.o_p1), *q = at<int>(b, P.o_q);
+    int *inv1 = at<int>(b, P.o_inv1), *p2 = at<int>(b, P.o_p2);
+    int *status = at<int>(b, P.o_status);
+    double *Q[2] = {at<double>(b, P.o_qf), at<double>(b, P.o_qg)};
+    const int64_t ldq[2] = {P.ldqf, P.ldqg};
+    double *R1[2] = {at<double>(b, P.o_r1f), at<double>(b, P.o_r1g)};
     const unsigned g1 = (unsigned)((n + 255) / 256);
-    const dim3 gtr((unsigned)((n + 31) / 32), (unsigned)((n + 31) / 32));
+    const unsigned gn = (unsigned)((n + 31) / 32);
     hipError_t e = hipMemsetAsync(status, 0, 4 * ST_NSLOTS, s);
     if (e != hipSuccess) return e;
-    // F P1 = Q_F R_F: pivots from the Gram of F
-    gemm(true, n, n, P.mf, 1.0, F, ldf, F, ldf, 0.0, nullptr, 0, S, P.ldn, s);
-    pchol(P, S, Rt, d, done, p1, true, status, s);
-    hipLaunchKernelGGL(k_gather_rt, gtr, dim3(256), 0, s, n, (const int *)p1, Rt, P.ldn, R1f,
-                       P.ldn);
-    hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((P.mf + 255) / 256), (unsigned)n),
-                       dim3(256), 0, s, P.mf, n, (const int *)p1, F, ldf, Qf, P.ldqf);
-    cholqr2(P, P.mf, Qf, P.ldqf, R1f, b, s);
-    // (G P1) P2 = Q_G R_G: the pivoted Cholesky of G^T G yields the combined
-    // order q = P1 P2 directly; P2 is its position in the order P1
-    gemm(true, n, n, P.mg, 1.0, G, ldg, G, ldg, 0.0, nullptr, 0, S, P.ldn, s);
-    pchol(P, S, Rt, d, done, q, true, status, s);
-    hipLaunchKernelGGL(k_gather_rt, gtr, dim3(256), 0, s, n, (const int *)q, Rt, P.ldn, R1g,
-                       P.ldn);
-    hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((P.mg + 255) / 256), (unsigned)n),
-                       dim3(256), 0, s, P.mg, n, (const int *)q, G, ldg, Qg, P.ldqg);
-    cholqr2(P, P.mg, Qg, P.ldqg, R1g, b, s);
+    // 1. pivots and R1 from the Grams: F P1 = Q_F R_F, and (G P1) P2 = Q_G R_G
+    //    through the pivoted Cholesky of G^T G, whose order is q = P1 P2 (the
+    //    position of q in the order P1 is P2)
+    const double *Y0[2] = {F, G};
+    const int64_t ldy0[2] = {ldf, ldg};
+    gram2(P, b, Y0, ldy0, s);
+    int *const piv1[2] = {p1, q};
+    pchol(P, b, piv1, true, status, s);
+    GatherArgs gr;
+    for (int z = 0; z < 2; ++z) {
+        gr.idx[z] = piv1[z];
+        gr.src[z] = at<double>(b, P.o_rt[z]);
+        gr.dst[z] = R1[z];
+        gr.m[z] = n; gr.lds[z] = P.ldn; gr.ldd[z] = P.ldn;
+    }
+    hipLaunchKernelGGL(k_gather_rt, dim3(gn, gn, 2), dim3(256), 0, s, n, P.ldn, gr);
+    // 2. Q = Y P, in place Q <- Q R1^-1
+    GatherArgs gc;
+    for (int z = 0; z < 2; ++z) {
+        gc.idx[z] = piv1[z];
+        gc.src[z] = Y0[z]; gc.lds[z] = ldy0[z];
+        gc.dst[z] = Q[z]; gc.ldd[z] = ldq[z];
+    }
+    gc.m[0] = P.mf;
+    gc.m[1] = P.mg;
+    const int64_t mmax = P.mf > P.mg ? P.mf : P.mg;
+    hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((mmax + 255) / 256), (unsigned)n, 2),
+                       dim3(256), 0, s, gc);
+    const double *R1c[2] = {R1[0], R1[1]};
+    trsm_right(P, b, Q, ldq, R1c, s);
+    // 3. refinement: R2^T R2 = Q^T Q, Q <- Q R2^-1, R = R2 R1
+    const double *Qc[2] = {Q[0], Q[1]};
+    gram2(P, b, Qc, ldq, s);
+    int *const pid[2] = {at<int>(b, P.o_id[0]), at<int>(b, P.o_id[1])};
+    pchol(P, b, pid, false, status, s);
+    double *R2[2] = {at<double>(b, P.o_r2[0]), at<double>(b, P.o_r2[1])};
+    for (int z = 0; z < 2; ++z) {
+        gr.idx[z] = nullptr;
+        gr.dst[z] = R2[z];
+    }
+    hipLaunchKernelGGL(k_gather_rt, dim3(gn, gn, 2), dim3(256), 0, s, n, P.ldn, gr);
+    const double *R2c[2] = {R2[0], R2[1]};
+    trsm_right(P, b, Q, ldq, R2c, s);
+    GemmArgs g;
+    for (int z = 0; z < 2; ++z) {
+        g.A[z] = R2[z]; g.lda[z] = P.ldn;
+        g.B[z] = R1[z]; g.ldb[z] = P.ldn;
+        g.C0[z] = nullptr; g.ldc0[z] = 0;
+        g.C[z] = at<double>(b, P.o_s[z]); g.ldc[z] = P.ldn;   // S[z] <- R = R2 R1
+        g.M[z] = P.n; g.N[z] = P.n; g.K[z] = P.n;
+    }
+    g.alpha = 1.0; g.beta = 0.0;
+    gemm(false, 2, g, s);
+    // 4. F'' = R_F P2, G'' = R_G
     hipLaunchKernelGGL(k_perm_inverse, dim3(g1), dim3(256), 0, s, n, (const int *)p1, inv1);
     hipLaunchKernelGGL(k_perm_compose, dim3(g1), dim3(256), 0, s, n, (const int *)inv1,
                        (const int *)q, p2);
-    // F'' = R_F P2, G'' = R_G
-    hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((n + 255) / 256), (unsigned)n), dim3(256),
-                       0, s, (int64_t)n, n, (const int *)p2, R1f, P.ldn, F2, P.ldn);
-    e = hipMemcpyAsync(G2, R1g, 8 * (size_t)P.ldn * n, hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) return e;
+    for (int z = 0; z < 2; ++z) {
+        gc.idx[z] = z ? pid[1] : p2;     // G'' keeps its order (pid[1] is the identity)
+        gc.src[z] = at<double>(b, P.o_s[z]); gc.lds[z] = P.ldn;
+        gc.dst[z] = at<double>(b, z ? P.o_g2 : P.o_f2); gc.ldd[z] = P.ldn;
+        gc.m[z] = n;
+    }
+    hipLaunchKernelGGL(k_gather_cols, dim3(g1, (unsigned)n, 2), dim3(256), 0, s, gc);
     return hipGetLastError();
 }
 
@@ -569,15 +705,23 @@ hipError_t launch_unshorten(const SPlan &P, void *work, double *U, int64_t ldu, 
 {
     char *b = (char *)work;
     const int n = (int)P.n;
-    const double *Qf = (const double *)(b + P.o_qf), *Qg = (const double *)(b + P.o_qg);
-    const double *U2 = (const double *)(b + P.o_f2), *V2 = (const double *)(b + P.o_g2);
-    const double *Z2 = (const double *)(b + P.o_z2);
-    const int *q = (const int *)(b + P.o_q);
-    gemm(false, P.mf, n, n, 1.0, Qf, P.ldqf, U2, P.ldn, 0.0, nullptr, 0, U, ldu, s);
-    gemm(false, P.mg, n, n, 1.0, Qg, P.ldqg, V2, P.ldn, 0.0, nullptr, 0, V, ldv, s);
+    GemmArgs g;
+    g.A[0] = at<double>(b, P.o_qf); g.lda[0] = P.ldqf;
+    g.A[1] = at<double>(b, P.o_qg); g.lda[1] = P.ldqg;
+    g.B[0] = at<double>(b, P.o_f2); g.B[1] = at<double>(b, P.o_g2);
+    g.ldb[0] = g.ldb[1] = P.ldn;
+    g.C0[0] = g.C0[1] = nullptr;
+    g.ldc0[0] = g.ldc0[1] = 0;
+    g.C[0] = U; g.ldc[0] = ldu;
+    g.C[1] = V; g.ldc[1] = ldv;
+    g.M[0] = P.mf; g.M[1] = P.mg;
+    g.N[0] = g.N[1] = n;
+    g.K[0] = g.K[1] = n;
+    g.alpha = 1.0; g.beta = 0.0;
+    gemm(false, 2, g, s);
     const int64_t nn = (int64_t)n * n;
-    hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, n, q,
-                       Z2, P.ldn, Z, ldz);
+    hipLaunchKernelGGL(k_scatter_rows, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, n,
+                       at<int>(b, P.o_q), at<double>(b, P.o_z2), P.ldn, Z, ldz);
     return hipGetLastError();
 }
 

@@ -262,8 +262,8 @@ def test_dataflow_task_list_is_a_dependency_order(hz, shape):
 
 def test_qr_shorten_sizes_and_rejections(hz):
     """The shortened solve needs Q_F, Q_G and the square solve's workspace;
-    the complex, mixed, batched and tuner entry points and n beyond the
-    pivoted Cholesky's limit reject it, all on the host."""
+    the complex, mixed and batched entry points, and n beyond the pivoted
+    Cholesky's limit (also in the tuner), reject it, all on the host."""
     L = hz.lib()
     p = hz.params(w=32, qr_shorten=1)
     plain = L.hz_dgsvd_work_size(ctypes.byref(hz.params(w=32)), 1024, 1024, 1024)
@@ -283,5 +283,5 @@ def test_qr_shorten_sizes_and_rejections(hz):
     assert L.hz_dgsvd_batched_work_size(ctypes.byref(p), 1, i64([64]), i64([64]),
                                         i64([32])) == 0
     best = hz.HzParams()
-    assert L.hz_dgsvd_tune(ctypes.byref(p), 64, 64, 32, v, 64, v, 64, None, ctypes.byref(best),
-                           None, None) == -1
+    assert L.hz_dgsvd_tune(ctypes.byref(hz.params(qr_shorten=1)), 9000, 9000, 8193, v, 9000, v,
+                           9000, None, ctypes.byref(best), None, None) == -1
