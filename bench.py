@@ -239,6 +239,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the QR-shortened, mixed-precision and batched comparisons")
+    ap.add_argument("--only-form", choices=("qr_shortened", "mixed", "batched"),
+                    help="run only this comparison and print its JSON (for profiling)")
     ap.add_argument("--no-tune", action="store_true",
                     help="use --w/--inner-max-sweeps and library defaults, no autotuner")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1909_00101_amd",
@@ -270,6 +272,15 @@ def main():
         # picks the inner sweep cap, Gram splits, update rows and inner lanes
         best, _ = hz.tune(F0, G0, cache=tune_cache, w=args.w, ordering=hz.HZ_ORD_MM, tol=tol)
         kw.update(best)
+    if args.only_form:
+        if args.only_form == "qr_shortened":
+            res = qr_shortened_vs_plain(F0, G0, s_true, tol, kw, tune_cache)
+        elif args.only_form == "mixed":
+            res = mixed_vs_plain()
+        else:
+            res = batched_vs_plain(tune_cache)
+        print(json.dumps(dict(form=args.only_form, **res)))
+        return
     p = hz.params(**kw)
     nbytes = hz.lib().hz_dgsvd_work_size(ctypes.byref(p), spec.m_f, spec.m_g, spec.n)
     work = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
