@@ -49,15 +49,16 @@ def algorithmic(m_f, m_g, n, w):
     return gram, upd
 
 
-def inner_flops(w, launches, inner_sweeps, rotations, npairs):
+def inner_flops(w, launches, inner_sweeps, rotations, npairs, isteps):
     """Algorithmic FP64 work of the inner solver per launch (one step of
     n/(2w) pivot pairs): two Cholesky factorizations of order 2w,
-    (2w)^3/3 multiply-adds each; per inner sweep (2w-1) steps of w column
-    pairs, each forming 4 dot products of length 2w (16w flops); per applied
-    transformation 6 columns of length 2w updated (36w flops)."""
+    (2w)^3/3 multiply-adds each; per inner sweep ``isteps`` steps (2w - 1
+    for round robin, 2w for modified modulus) of w column pairs, each forming
+    4 dot products of length 2w (16w flops); per applied transformation 6
+    columns of length 2w updated (36w flops)."""
     W2 = 2 * w
     chol = npairs * launches * 2.0 * (2.0 * W2 ** 3 / 3.0)
-    dots = inner_sweeps * (W2 - 1) * w * 16.0 * w
+    dots = inner_sweeps * isteps * w * 16.0 * w
     apply = rotations * 36.0 * w
     return (chol + dots + apply) / max(1, launches)
 
@@ -207,7 +208,8 @@ def qr_shortened_vs_plain(F0, G0, s_true, tol, plain_kw, tune_cache=None, reps=3
     Fw, Gw = F0.clone(), G0.clone()
     skw = dict(w=16, inner_max_sweeps=1)
     if tune_cache is not None:
-        skw, _ = hz.tune(F0, G0, cache=tune_cache, ordering=hz.HZ_ORD_MM, tol=tol, qr_shorten=1)
+        skw, _ = hz.tune(F0, G0, cache=tune_cache, ordering=hz.HZ_ORD_MM, tol=tol, qr_shorten=1,
+                         inner_ordering=0)
     skw = dict(skw, ordering=hz.HZ_ORD_MM, tol=tol, qr_shorten=1)
     res = {}
     for name, kw in (("plain", plain_kw), ("shortened", skw)):
@@ -220,8 +222,9 @@ def qr_shortened_vs_plain(F0, G0, s_true, tol, plain_kw, tune_cache=None, reps=3
         err = float(np.max(np.abs(r["sigma"].cpu().numpy() - s_true) / s_true))
         res[name] = dict(ms=round(dt * 1e3, 2), sweeps=r["sweeps"], max_rel_sigma_err=err,
                          status=r["status"],
-                         params={k: kw[k] for k in ("w", "inner_max_sweeps", "inner_lanes",
-                                                    "gram_splits", "update_rows") if k in kw})
+                         params={k: kw[k] for k in ("w", "inner_ordering", "inner_max_sweeps",
+                                                    "inner_lanes", "gram_splits", "update_rows")
+                                 if k in kw})
     del Fw, Gw
     torch.cuda.empty_cache()
     return dict(workload="the headline pair (seeded 4096x1024, kappa(X)=1e2), MM ordering, "
@@ -268,9 +271,11 @@ def main():
     kw = dict(w=args.w, ordering=hz.HZ_ORD_MM, tol=tol, inner_max_sweeps=args.inner_max_sweeps)
     tune_cache = None if args.no_tune else args.tune_cache
     if tune_cache is not None:
-        # block width, ordering and tolerance are the workload's; the tuner
-        # picks the inner sweep cap, Gram splits, update rows and inner lanes
-        best, _ = hz.tune(F0, G0, cache=tune_cache, w=args.w, ordering=hz.HZ_ORD_MM, tol=tol)
+        # block width, outer ordering and tolerance are the workload's; the
+        # tuner picks the ordering inside a block pair, the inner sweep cap,
+        # Gram splits, update rows and inner lanes
+        best, _ = hz.tune(F0, G0, cache=tune_cache, w=args.w, ordering=hz.HZ_ORD_MM, tol=tol,
+                          inner_ordering=0)
         kw.update(best)
     if args.only_form:
         if args.only_form == "qr_shortened":
@@ -326,7 +331,9 @@ def main():
     gram, upd = algorithmic(spec.m_f, spec.m_g, spec.n, args.w)
     npairs = spec.n // (2 * args.w)
     launches_timed = sum(sweeps) * (spec.n // args.w)     # inner launches in the timed solves
-    inner = dict(flops=inner_flops(args.w, launches_timed, isw, rots, npairs), bytes=None)
+    isteps = 2 * args.w if kw.get("inner_ordering") == hz.HZ_ORD_MM else 2 * args.w - 1
+    inner = dict(flops=inner_flops(args.w, launches_timed, isw, rots, npairs, isteps),
+                 bytes=None)
     kinds = {"gram": (*split_ms["gram"], gram), "inner": (*split_ms["inner"], inner),
              "update": (*split_ms["update"], upd)}
     split = {k: round(v[0] / max(1e-9, sum(x[0] for x in split_pass.values())), 4)
@@ -388,8 +395,9 @@ def main():
                                     "(kappa(X)=1e2, sigma log-uniform in [1e-3,1e3])",
                            m_f=spec.m_f, m_g=spec.m_g, n=spec.n, w=args.w, ordering="MM",
                            tol="1024*eps", parallelism="single GPU",
-                           launch={k: kw[k] for k in ("inner_max_sweeps", "inner_lanes",
-                                                      "gram_splits", "update_rows") if k in kw}),
+                           launch={k: kw[k] for k in ("inner_ordering", "inner_max_sweeps",
+                                                      "inner_lanes", "gram_splits",
+                                                      "update_rows") if k in kw}),
                sweeps=sweeps, max_rel_sigma_err_vs_prescribed=err,
                fp64_mfma_util_solve=round(mfma_util, 4),
                kernel_time_split=split, kernels=per_kernel, roofline=roof)

@@ -265,11 +265,12 @@ size_t hz_dgsvd_batched_work_size(const hz_params *p, int batch, const int64_t *
                                   const int64_t *m_g, const int64_t *n);
 
 /* Autotuner (the launch-parameter search the batched and single-pair
- * forms use).  Starting from p (NULL = defaults), the choice between one
- * inner sweep and p->inner_max_sweeps (block-oriented or full-block inner
- * level, Section 3.5) and every tunable field that p leaves at 0 -- w,
- * gram_splits, update_rows, inner_lanes -- are varied in turn, in that
- * order, with the others held at the best so far, in passes until one
+ * forms use).  Starting from p (NULL = defaults), the ordering inside a
+ * block pair when p->inner_ordering is 0 (round robin or modified modulus),
+ * the choice between one inner sweep and p->inner_max_sweeps (block-oriented
+ * or full-block inner level, Section 3.5) and every tunable field that p
+ * leaves at 0 -- w, gram_splits, update_rows, inner_lanes -- are varied in
+ * turn, in that order, with the others held at the best so far, in passes until one
  * changes nothing (at most two); each candidate is timed as a complete
  * solve up to, not including, the final extraction, which reads F and G
  * (device, caller-owned, left unmodified) and writes only a scratch

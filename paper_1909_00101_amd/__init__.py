@@ -315,7 +315,8 @@ def gsvd_batched(pairs, *, overwrite=False, workspace=None, **kw):
     return st, out
 
 
-_TUNED = ("w", "inner_max_sweeps", "inner_lanes", "gram_splits", "update_rows", "ordering")
+_TUNED = ("w", "inner_max_sweeps", "inner_lanes", "gram_splits", "update_rows", "ordering",
+          "inner_ordering")
 
 
 def tune(F, G, *, cache=None, **kw):

@@ -1331,7 +1331,7 @@ static uint64_t tune_key(const char *kind, const hz_params &p, int batch, const 
 static std::mutex g_tune_mu;
 
 // Cache line: "<key hex> w inner_max_sweeps inner_lanes gram_splits update_rows ms
-// ordering" (a line without the ordering leaves it as given).
+// ordering inner_ordering" (a line without the orderings leaves them as given).
 static bool cache_lookup(const char *path, uint64_t key, hz_params &p, double &ms)
 {
     if (!path || !*path) return false;
@@ -1342,17 +1342,18 @@ static bool cache_lookup(const char *path, uint64_t key, hz_params &p, double &m
     bool hit = false;
     while (fgets(line, sizeof(line), f)) {
         unsigned long long k;
-        int w, ims, lp, gs, ur, ord = 0;
+        int w, ims, lp, gs, ur, ord = 0, iord = 0;
         double t;
-        const int got = sscanf(line, "%llx %d %d %d %d %d %lf %d", &k, &w, &ims, &lp, &gs, &ur,
-                               &t, &ord);
+        const int got = sscanf(line, "%llx %d %d %d %d %d %lf %d %d", &k, &w, &ims, &lp, &gs,
+                               &ur, &t, &ord, &iord);
         if (got >= 7 && k == key) {
             p.w = w;
             p.inner_max_sweeps = ims;
             p.inner_lanes = lp;
             p.gram_splits = gs;
             p.update_rows = ur;
-            if (got == 8 && ord) p.ordering = ord;
+            if (got >= 8 && ord) p.ordering = ord;
+            if (got >= 9 && iord) p.inner_ordering = iord;
             ms = t;
             hit = true;     // the last matching line wins
         }
@@ -1367,8 +1368,9 @@ static void cache_store(const char *path, uint64_t key, const hz_params &p, doub
     std::lock_guard<std::mutex> lk(g_tune_mu);
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%016llx %d %d %d %d %d %.6f %d\n", (unsigned long long)key, p.w,
-            p.inner_max_sweeps, p.inner_lanes, p.gram_splits, p.update_rows, ms, p.ordering);
+    fprintf(f, "%016llx %d %d %d %d %d %.6f %d %d\n", (unsigned long long)key, p.w,
+            p.inner_max_sweeps, p.inner_lanes, p.gram_splits, p.update_rows, ms, p.ordering,
+            p.inner_ordering);
     fclose(f);
 }
 
@@ -1428,13 +1430,16 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
 {
     hz_params base;
     if (p) base = *p; else hz_default_params(&base);
+    // inner_ordering 0 asks the tuner to choose the ordering inside a block pair
+    const bool tune_iord = (base.inner_ordering == 0);
+    if (tune_iord) base.inner_ordering = HZ_ORD_RR;
     if (!params_ok(base) || (base.qr_shorten && n > 1 && !shorten_cpt(n))) return -1;
     const double dummy = 0.0;
     const int a = check_args(m_f, m_g, n, F, ldf, G, ldg, &dummy, n, &dummy, &dummy, &dummy);
     if (a) return a;
     if (!best) return -10;
     hipStream_t st = (hipStream_t)stream;
-    const uint64_t key = tune_key("dgsvd", base, 1, &m_f, &m_g, &n);
+    const uint64_t key = tune_key(tune_iord ? "dgsvd_iord" : "dgsvd", base, 1, &m_f, &m_g, &n);
     hz_params cur = base;
     double ms = 0.0;
     if (cache_lookup(cache_path, key, cur, ms)) {
@@ -1496,6 +1501,7 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
     if (!base.inner_lanes) cur.inner_lanes = 0;
     std::vector<std::vector<int>> axes;
     std::vector<int *> fields;
+    if (tune_iord) { axes.push_back({HZ_ORD_RR, HZ_ORD_MM}); fields.push_back(&cur.inner_ordering); }
     axes.push_back({1, base.inner_max_sweeps});
     fields.push_back(&cur.inner_max_sweeps);
     if (!base.w) { axes.push_back({8, 16, 32}); fields.push_back(&cur.w); }

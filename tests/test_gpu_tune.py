@@ -61,3 +61,32 @@ def test_tune_batched(tmp_path):
     assert st == 0
     for (F, G, _), o in zip(pairs[:6], outs[:6]):
         assert max_rel(o["sigma"].cpu().numpy(), oracle.gsvd(F, G)["sigma"]) < SIG_TOL
+
+
+def test_tune_inner_ordering_and_shortened(tmp_path):
+    """inner_ordering = 0 lets the tuner choose the ordering inside a block
+    pair (stored in the cache line and returned again on a hit, under a key
+    of its own); with qr_shorten = 1 the candidates are timed on the
+    shortened pair, and the chosen parameters solve the tall pair to oracle
+    parity."""
+    import oracle
+    hz = _hz()
+    F, G, s_true = gi.custom_pair(900, 700, 128, kappa=1e2, seed=62)
+    dF, dG = _dev(F), _dev(G)
+    cache = str(tmp_path / "tune.txt")
+    best, ms = hz.tune(dF, dG, cache=cache, w=16, inner_ordering=0)
+    assert best["inner_ordering"] in (hz.HZ_ORD_MM, hz.HZ_ORD_RR) and ms > 0
+    fields = open(cache).read().split()
+    assert len(fields) == 9 and int(fields[8]) == best["inner_ordering"]
+    again, _ = hz.tune(dF, dG, cache=cache, w=16, inner_ordering=0)
+    assert again == best
+    fixed, _ = hz.tune(dF, dG, cache=cache, w=16)          # inner ordering given: own key
+    assert fixed["inner_ordering"] == hz.HZ_ORD_RR
+    assert len(open(cache).read().splitlines()) == 2
+    sbest, sms = hz.tune(dF, dG, cache=cache, qr_shorten=1, inner_ordering=0)
+    assert sms > 0 and len(open(cache).read().splitlines()) == 3
+    assert np.array_equal(dF.cpu().numpy(), F) and np.array_equal(dG.cpu().numpy(), G)
+    r = hz.gsvd(dF, dG, qr_shorten=1, **sbest)
+    assert r["status"] == 0
+    assert max_rel(r["sigma"].cpu().numpy(), oracle.gsvd(F, G, threads=4)["sigma"]) < SIG_TOL
+    assert max_rel(r["sigma"].cpu().numpy(), s_true) < SIG_TOL
