@@ -57,6 +57,10 @@ def _load():
         lib.hzo_cplx_2x2_v.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp, dp,
                                        ctypes.POINTER(ctypes.c_int), dp]
         lib.hzo_cplx_2x2_v.restype = None
+        lib.hzo_edot.argtypes = [ctypes.c_int64, dp, dp]
+        lib.hzo_edot.restype = ctypes.c_double
+        lib.hzo_mul_rd.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
+        lib.hzo_mul_rd.restype = None
         lib.hzo_ordering.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         lib.hzo_ordering.restype = ctypes.c_int
         _lib = lib
@@ -74,7 +78,9 @@ def gsvd(F, G, *, ordering=ORD_ROWCYCLIC, tol=0.0, max_sweeps=30, sort=True, thr
     Returns a dict with U, V, Z (Fortran-ordered), sigma, sigma_f, sigma_g
     (descending in sigma), sweeps, rot_all, rot_big, converged, status.
     tol <= 0 selects sqrt(n)*eps.  variant 0 classifies small transformations
-    by criterion C1, variant 4 by criterion C2 (Section 2.5, Table 1).
+    by criterion C1, variant 4 by criterion C2 (Section 2.5, Table 1); for
+    real pairs variants 1 and 5 are 0 and 4 with the enhanced dot products of
+    Appendix A.
     F and G are copied, not modified.
     """
     lib = _load()
@@ -122,6 +128,21 @@ def gsvd_qr(F, G, **kw):
     r.update(U=np.asfortranarray(Q_f @ r["U"]), V=np.asfortranarray(Q_g @ r["V"]),
              Z=np.asfortranarray(Z), p1=p1, q=q)
     return r
+
+
+def edot(x, y):
+    """The enhanced dot product of Appendix A of two real vectors."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    return float(_load().hzo_edot(len(x), _dptr(x), _dptr(y)))
+
+
+def mul_rd(a, b):
+    """(c, d): a*b rounded toward -infinity and d = fma(a, b, -c)."""
+    c = ctypes.c_double()
+    d = ctypes.c_double()
+    _load().hzo_mul_rd(float(a), float(b), ctypes.byref(c), ctypes.byref(d))
+    return c.value, d.value
 
 
 def real_2x2(aii, ajj, aij, x, cosines=False):

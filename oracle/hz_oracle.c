@@ -25,8 +25,11 @@
  *                 Sigma, Z.
  *   Section 2.5 : big/small classification (criteria C1 and C2) and the stop rule
  *                 "no big transformation in a sweep".
- *   Table 1     : variant 0 (C1, prescaled, ordinary dot products) and
- *                 variant 4 (the same with criterion C2).
+ *   Table 1     : variant 0 (C1, prescaled, ordinary dot products),
+ *                 variant 4 (the same with criterion C2), and for real
+ *                 pairs variants 1 and 5 (0 and 4 with the enhanced dot
+ *                 products of Appendix A for the pivot entries a_ii, a_jj,
+ *                 a_ij, b_ij).
  *
  * Readings of passages that are silent, garbled or inconsistent (each one is
  * also listed in the design notes of the repository):
@@ -74,6 +77,41 @@ static double dot_rr(const double *x, const double *y, int64_t m)
     for (int64_t r = 0; r < m; ++r)
         s += x[r] * y[r];
     return s;
+}
+
+/* The product a*b rounded toward -infinity, from the round-to-nearest
+ * product p and its exact error e = a*b - p (one FMA): the exact product
+ * is p + e, so it rounds down to p when e >= 0 and otherwise to the next
+ * double below p (the one the exact value lies above).  Normal range. */
+static double mul_rd(double a, double b)
+{
+    const double p = a * b;
+    const double e = fma(a, b, -p);
+    return (e < 0.0) ? nextafter(p, -INFINITY) : p;
+}
+
+/* Enhanced dot product (Appendix A): for each pair of entries the product
+ * rounded down, c, and its rounding error d = fma(a, b, -c) >= 0, summed
+ * separately; the result is (sum of c) + (sum of d). */
+static double dot_rr_enh(const double *x, const double *y, int64_t m)
+{
+    double sc = 0.0, sd = 0.0;
+    for (int64_t r = 0; r < m; ++r) {
+        const double c = mul_rd(x[r], y[r]);
+        sc += c;
+        sd += fma(x[r], y[r], -c);
+    }
+    return sc + sd;
+}
+
+/* Exported for the tests: the enhanced dot product of x and y (n entries),
+ * and the rounded-down product with its error term. */
+double hzo_edot(int64_t n, const double *x, const double *y) { return dot_rr_enh(x, y, n); }
+
+void hzo_mul_rd(double a, double b, double *c, double *d)
+{
+    *c = mul_rd(a, b);
+    *d = fma(a, b, -*c);
 }
 
 /* x^* y for complex columns. */
@@ -384,13 +422,13 @@ static void rot_cols_r(double *Y, int64_t ld, int64_t m, int64_t i, int64_t j, c
  */
 static int is_big(int variant, double z11, double z22, const double cc[2])
 {
-    if (variant == 4) return !(cc[0] == 1.0 && cc[1] == 1.0);
+    if (variant == 4 || variant == 5) return !(cc[0] == 1.0 && cc[1] == 1.0);
     return !(z11 == 1.0 && z22 == 1.0);
 }
 
 /*
  * One pointwise step on the pivot pair (i, j), i < j (Section 2.1, variant
- * 0 or 4).  Adds to *all and *big and returns nothing else.
+ * 0, 1, 4 or 5).  Adds to *all and *big and returns nothing else.
  */
 static void step_real(int64_t m_f, int64_t m_g, int64_t n, double *F, int64_t ldf,
                       double *G, int64_t ldg, double *Z, int64_t ldz,
@@ -398,10 +436,12 @@ static void step_real(int64_t m_f, int64_t m_g, int64_t n, double *F, int64_t ld
                       int64_t *all, int64_t *big)
 {
     const double *fi = F + i * ldf, *fj = F + j * ldf;
-    const double aii = dot_rr(fi, fi, m_f);
-    const double ajj = dot_rr(fj, fj, m_f);
-    const double aij = dot_rr(fi, fj, m_f);
-    const double bij = dot_rr(G + i * ldg, G + j * ldg, m_g);
+    double (*dot)(const double *, const double *, int64_t) =
+        (variant == 1 || variant == 5) ? dot_rr_enh : dot_rr;
+    const double aii = dot(fi, fi, m_f);
+    const double ajj = dot(fj, fj, m_f);
+    const double aij = dot(fi, fj, m_f);
+    const double bij = dot(G + i * ldg, G + j * ldg, m_g);
     if (fabs(aij) < sqrt(aii) * sqrt(ajj) * tol && fabs(bij) < tol) {
         if (sort && aii < ajj) {
             swap_cols_r(F, ldf, m_f, i, j);
@@ -445,7 +485,7 @@ int hzo_dgsvd(int64_t m_f, int64_t m_g, int64_t n,
               int64_t *info)
 {
     if (n < 1 || m_f < n || m_g < n || ldf < m_f || ldg < m_g || ldz < n ||
-        (variant != 0 && variant != 4))
+        (variant != 0 && variant != 1 && variant != 4 && variant != 5))
         return -1;
     info[0] = info[1] = info[2] = 0;
     info[3] = 1;

@@ -464,3 +464,71 @@ def test_qr_shortening_pivot_order():
     assert r["q"][0] == np.argmax(np.linalg.norm(G, axis=0))
     assert sorted(r["q"]) == list(range(n))
     assert_contract(F, G, r["U"], r["V"], r["Z"], r["sigma_f"], r["sigma_g"], r["sigma"])
+
+
+# ------------------------------------------------ enhanced dot products (App. A)
+
+def _rd_pairs():
+    rng = np.random.default_rng(812)
+    a = rng.standard_normal(3000) * 2.0 ** rng.integers(-40, 40, 3000)
+    b = rng.standard_normal(3000) * 2.0 ** rng.integers(-40, 40, 3000)
+    # products whose round-to-nearest value lies above the exact one
+    extra_a = [1.0 + 2.0 ** -30, 3.0, -(1.0 + 2.0 ** -29), 0.1, 1e300]
+    extra_b = [1.0 + 2.0 ** -30 - 2.0 ** -52, 0.1, 1.0 + 2.0 ** -31, -0.7, 1e-300]
+    return list(zip(np.r_[a, extra_a], np.r_[b, extra_b]))
+
+
+def test_mul_rd_is_the_rounded_down_product():
+    """c is the largest double not above a*b and c + d == a*b exactly, so
+    d >= 0 (exact rational arithmetic; round toward -infinity by definition)."""
+    from fractions import Fraction
+    for a, b in _rd_pairs():
+        c, d = oracle.mul_rd(a, b)
+        exact = Fraction(float(a)) * Fraction(float(b))
+        assert Fraction(c) <= exact < Fraction(np.nextafter(c, np.inf))
+        assert Fraction(c) + Fraction(d) == exact
+        assert d >= 0.0
+
+
+def test_edot_recovers_what_the_products_lose():
+    """x = (1 + 2^-30, 1), y = (1 + 2^-30, -(1 + 2^-29)): x.y = 2^-60 exactly;
+    every rounded product loses it and the ordinary dot product gives 0,
+    the enhanced one adds the (non-negative) errors back and gets it."""
+    x = np.array([1.0 + 2.0 ** -30, 1.0])
+    y = np.array([1.0 + 2.0 ** -30, -(1.0 + 2.0 ** -29)])
+    assert x[0] * y[0] + x[1] * y[1] == 0.0
+    assert oracle.edot(x, y) == 2.0 ** -60
+
+
+def test_edot_exact_on_integers_and_close_to_exact():
+    from fractions import Fraction
+    rng = np.random.default_rng(813)
+    xi = rng.integers(-1000, 1000, 500).astype(float)
+    yi = rng.integers(-1000, 1000, 500).astype(float)
+    assert oracle.edot(xi, yi) == float(np.dot(xi.astype(np.int64), yi.astype(np.int64)))
+    x = rng.standard_normal(400)
+    y = rng.standard_normal(400)
+    exact = sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(x, y))
+    bound = 400 * np.finfo(float).eps * float(np.sum(np.abs(x * y)))
+    assert abs(Fraction(oracle.edot(x, y)) - exact) <= Fraction(bound)
+
+
+@pytest.mark.parametrize("v_enh,v_plain", [(1, 0), (5, 4)])
+def test_enhanced_variants_same_gsvd(v_enh, v_plain):
+    """Variants 1 and 5 differ from 0 and 4 only in how the pivot entries are
+    summed: the same GSVD to rounding, the contract, but not the same bits."""
+    F, G, s_true = gi.custom_pair(150, 120, 40, kappa=1e2, seed=814)
+    e = oracle.gsvd(F, G, variant=v_enh, ordering=oracle.ORD_MM, threads=2)
+    p = oracle.gsvd(F, G, variant=v_plain, ordering=oracle.ORD_MM, threads=2)
+    assert e["status"] == 0 and e["converged"]
+    assert np.max(np.abs(e["sigma"] - p["sigma"]) / p["sigma"]) < 1e-12
+    assert np.max(np.abs(e["sigma"] - s_true) / s_true) < 1e-12
+    assert_contract(F, G, e["U"], e["V"], e["Z"], e["sigma_f"], e["sigma_g"], e["sigma"])
+    assert not np.array_equal(e["Z"], p["Z"])
+
+
+def test_enhanced_variants_real_only():
+    F, G, _ = gi.custom_pair(20, 20, 6, is_complex=True, seed=815)
+    for v in (1, 5):
+        with pytest.raises(ValueError):
+            oracle.gsvd(F, G, variant=v)
