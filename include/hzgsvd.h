@@ -79,9 +79,14 @@ extern "C" {
 #define HZ_SCHED_DATAFLOW 2
 
 typedef struct hz_params {
-    int variant;          /* Table 1, prescaled, ordinary dot products: 0 = small
-                             transformations by criterion C1 (scaled cosines equal 1),
-                             4 = by criterion C2 (unscaled cosines equal 1), Section 2.5 */
+    int variant;          /* Table 1, prescaled: 0 = small transformations by criterion
+                             C1 (scaled cosines equal 1), 4 = by criterion C2 (unscaled
+                             cosines equal 1), Section 2.5, both with ordinary dot
+                             products; 1 and 5 = 0 and 4 with the enhanced dot products
+                             of Appendix A for the pointwise pivot entries a_ii, a_jj,
+                             a_ij, b_ij of the inner solver (products rounded toward
+                             -infinity and their non-negative errors summed apart; real
+                             solvers only) */
     int ordering;         /* outer block ordering, HZ_ORD_MM (default) or HZ_ORD_RR */
     int inner_ordering;   /* pointwise ordering inside a block pair (default HZ_ORD_RR) */
     int w;                /* block-column width: 0 = default, else 8, 16 or 32 */
@@ -175,6 +180,15 @@ int hz_dataflow_tasks(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, i
  * 2x2 A positive semidefinite), out (device, 4*count doubles: Z11, Z21, Z12,
  * Z22 of Z' per pair).  Returns 0 or HZ_EHIP. */
 int hz_eval_2x2(int64_t count, const double *in, double *out, void *stream);
+
+/* Diagnostic: the device's product rounded toward -infinity and its error
+ * term, as the enhanced dot products of variants 1 and 5 form them
+ * (Appendix A): for each of `count` pairs, c[i] = a[i]*b[i] rounded down and
+ * d[i] = a[i]*b[i] - c[i] >= 0 (exact in the normal range).  a, b, c, d are
+ * device arrays of count doubles.  Returns 0, -1 (bad arguments) or
+ * HZ_EHIP. */
+int hz_eval_mul_rd(int64_t count, const double *a, const double *b, double *c, double *d,
+                   void *stream);
 
 /* Diagnostic: the device's complex 2x2 transformation (Section 2.1.1) on
  * `count` pivot pairs.  in (device, 6*count doubles per pair: a_ii, a_jj,

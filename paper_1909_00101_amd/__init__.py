@@ -108,6 +108,8 @@ def lib():
         L.hz_strerror.restype = ctypes.c_char_p
         L.hz_eval_2x2.argtypes = [i64, vp, vp, vp]
         L.hz_eval_2x2.restype = ctypes.c_int
+        L.hz_eval_mul_rd.argtypes = [i64, vp, vp, vp, vp, vp]
+        L.hz_eval_mul_rd.restype = ctypes.c_int
         L.hz_ordering.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.hz_ordering.restype = ctypes.c_int
         L.hz_profile_enable.argtypes = [ctypes.c_int]
@@ -148,6 +150,24 @@ def params(**kw) -> HzParams:
             raise TypeError(f"unknown parameter {k}")
         setattr(p, k, v)
     return p
+
+
+def eval_mul_rd(a, b):
+    """The device's rounded-down products of two float64 CUDA tensors of the
+    same length and their error terms (hz_eval_mul_rd): (c, d)."""
+    import torch
+    L = lib()
+    a = a.contiguous()
+    b = b.contiguous()
+    if a.dtype != torch.float64 or b.dtype != torch.float64 or a.shape != b.shape:
+        raise TypeError("a and b must be float64 tensors of one shape")
+    c = torch.empty_like(a)
+    d = torch.empty_like(a)
+    st = L.hz_eval_mul_rd(a.numel(), _ptr(a), _ptr(b), _ptr(c), _ptr(d),
+                          ctypes.c_void_p(torch.cuda.current_stream(a.device).cuda_stream))
+    if st != 0:
+        raise RuntimeError(f"hz_eval_mul_rd returned {st}")
+    return c, d
 
 
 def eval_2x2(inp):

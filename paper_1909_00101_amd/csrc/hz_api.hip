@@ -68,7 +68,7 @@ static int build_ordering(int kind, int N, std::vector<T> &tab)
 
 static int params_ok(const hz_params &p)
 {
-    if (p.variant != 0 && p.variant != 4) return 0;
+    if (p.variant != 0 && p.variant != 1 && p.variant != 4 && p.variant != 5) return 0;
     if (p.schedule != 0 && p.schedule != HZ_SCHED_STEPS && p.schedule != HZ_SCHED_DATAFLOW) return 0;
     if (p.ordering != HZ_ORD_MM && p.ordering != HZ_ORD_RR) return 0;
     if (p.inner_ordering != HZ_ORD_MM && p.inner_ordering != HZ_ORD_RR) return 0;
@@ -414,6 +414,17 @@ int hz_eval_2x2(int64_t count, const double *in, double *out, void *stream)
     return 0;
 }
 
+int hz_eval_mul_rd(int64_t count, const double *a, const double *b, double *c, double *d,
+                   void *stream)
+{
+    if (count < 0 || (count > 0 && (!a || !b || !c || !d))) return -1;
+    if (count == 0) return 0;
+    launch_eval_mul_rd(count, a, b, c, d, (hipStream_t)stream);
+    if (hipGetLastError() != hipSuccess) return HZ_EHIP;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return HZ_EHIP;
+    return 0;
+}
+
 int hz_ordering(int kind, int N, int *table)
 {
     if ((kind != HZ_ORD_MM && kind != HZ_ORD_RR) || N < 2 || (N & 1) || N > (1 << 15)) return -1;
@@ -500,6 +511,7 @@ static int solve_entry(int kind, const hz_params *p, int64_t m_f, int64_t m_g, i
     if (!params_ok(prm) || !w_ok_for(prm, is_complex)) return -1;
     if (kind == KIND_MIXED && (prm.max_fp32_sweeps < 0 || !(prm.mixed_switch >= 0.0))) return -1;
     if (prm.qr_shorten && (kind != KIND_REAL || (n > 1 && !shorten_cpt(n)))) return -1;
+    if (is_complex && (prm.variant & 1)) return -1;   // enhanced dot products: real only
     const int a = check_args(m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g);
     if (a) return a;
     if (is_complex && (((uintptr_t)F | (uintptr_t)G | (uintptr_t)Z) & 15))
@@ -549,6 +561,7 @@ static size_t work_size_entry(int kind, const hz_params *p, int64_t m_f, int64_t
     if (p) prm = *p; else hz_default_params(&prm);
     if (!params_ok(prm) || !w_ok_for(prm, is_complex) || m_f < n || m_g < n || n < 1) return 0;
     if (prm.qr_shorten && (kind != KIND_REAL || (n > 1 && !shorten_cpt(n)))) return 0;
+    if (is_complex && (prm.variant & 1)) return 0;
     if (n == 1) return 256;
     Plan P;
     if (prm.qr_shorten) {

@@ -294,4 +294,32 @@ __device__ __forceinline__ void hz_cplx_2x2_fast(double aii, double ajj, double 
     c2small = (cphi == 1.0 && cpsi == 1.0);     // criterion C2 (Section 2.5)
 }
 
+// Appendix A (enhanced dot products): a*b rounded toward -infinity, from the
+// round-to-nearest product p and its exact error e = a*b - p (one FMA): the
+// exact product rounds down to p when e >= 0, else to the double just below
+// p.  The rounding mode register is left alone; contraction is off here so
+// that the product and the sums stay separately rounded operations.
+__device__ __forceinline__ double mul_rd(double a, double b)
+{
+#pragma clang fp contract(off)
+    const double p = a * b;
+    const double e = fma(a, b, -p);
+    if (!(e < 0.0)) return p;
+    long long bits = __double_as_longlong(p);
+    if (p > 0.0) bits -= 1;
+    else if (p < 0.0) bits += 1;
+    else bits = (long long)0x8000000000000001ull;   // below +-0: -denorm_min
+    return __longlong_as_double(bits);
+}
+
+// Accumulate a*b into the pair (sum of rounded-down products, sum of their
+// non-negative rounding errors).
+__device__ __forceinline__ void edot_acc(double a, double b, double &sc, double &sd)
+{
+#pragma clang fp contract(off)
+    const double c = mul_rd(a, b);
+    sc = sc + c;
+    sd = sd + fma(a, b, -c);
+}
+
 }  // namespace hz

@@ -106,6 +106,8 @@ void launch_finish_real(const Plan &P, const Ptrs &W, double *F, int64_t ldf, do
                         int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
                         double *sigma_g, hipStream_t s);
 void launch_eval_2x2(int64_t count, const double *in, double *out, hipStream_t s);
+void launch_eval_mul_rd(int64_t count, const double *a, const double *b, double *c, double *d,
+                        hipStream_t s);
 void launch_rank(const Plan &P, const Ptrs &W, hipStream_t s);
 void launch_gram_sum(const Plan &P, const Ptrs &W, hipStream_t s);
 void launch_inner_real(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,

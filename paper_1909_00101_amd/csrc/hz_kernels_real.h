@@ -263,17 +263,34 @@ __device__ __forceinline__ void inner_solve(
                 zj[r] = c1[0]; zj[r + 1] = c1[1];
             }
             double aii = 0.0, ajj = 0.0, aij = 0.0, bij = 0.0;
+            if (variant & 1) {
+                // enhanced dot products (variants 1 and 5, Appendix A): the
+                // rounded-down products and their errors are summed apart
+                double ei = 0.0, ej = 0.0, eij = 0.0, eb = 0.0;
 #pragma unroll
-            for (int r = 0; r < RPL; ++r) {
-                aii = fma(fi[r], fi[r], aii);
-                ajj = fma(fj[r], fj[r], ajj);
-                aij = fma(fi[r], fj[r], aij);
-                bij = fma(gi[r], gj[r], bij);
+                for (int r = 0; r < RPL; ++r) {
+                    edot_acc(fi[r], fi[r], aii, ei);
+                    edot_acc(fj[r], fj[r], ajj, ej);
+                    edot_acc(fi[r], fj[r], aij, eij);
+                    edot_acc(gi[r], gj[r], bij, eb);
+                }
+                aii = dpp_group_sum<LP>(aii) + dpp_group_sum<LP>(ei);
+                ajj = dpp_group_sum<LP>(ajj) + dpp_group_sum<LP>(ej);
+                aij = dpp_group_sum<LP>(aij) + dpp_group_sum<LP>(eij);
+                bij = dpp_group_sum<LP>(bij) + dpp_group_sum<LP>(eb);
+            } else {
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) {
+                    aii = fma(fi[r], fi[r], aii);
+                    ajj = fma(fj[r], fj[r], ajj);
+                    aij = fma(fi[r], fj[r], aij);
+                    bij = fma(gi[r], gj[r], bij);
+                }
+                aii = dpp_group_sum<LP>(aii);
+                ajj = dpp_group_sum<LP>(ajj);
+                aij = dpp_group_sum<LP>(aij);
+                bij = dpp_group_sum<LP>(bij);
             }
-            aii = dpp_group_sum<LP>(aii);
-            ajj = dpp_group_sum<LP>(ajj);
-            aij = dpp_group_sum<LP>(aij);
-            bij = dpp_group_sum<LP>(bij);
             double z11 = 1.0, z21 = 0.0, z12 = 0.0, z22 = 1.0;
             bool swap;
             const bool orth = (aij * aij < aii * ajj * tol2) && (fabs(bij) < tol);
@@ -283,8 +300,8 @@ __device__ __forceinline__ void inner_solve(
                 bool c2small;
                 hz_real_2x2_fast(aii, ajj, aij, bij, z11, z21, z12, z22, c2small);
                 sw_all += 1;
-                // small: criterion C1 (variant 0) or C2 (variant 4), Section 2.5
-                if (variant == 4 ? !c2small : !(z11 == 1.0 && z22 == 1.0)) sw_big += 1;
+                // small: criterion C1 (variants 0, 1) or C2 (variants 4, 5), Section 2.5
+                if ((variant & 4) ? !c2small : !(z11 == 1.0 && z22 == 1.0)) sw_big += 1;
                 swap = false;
                 if (sort) {
                     const double a11 = fma(z11 * z11, aii, fma(2.0 * z11 * z21, aij, z21 * z21 * ajj));

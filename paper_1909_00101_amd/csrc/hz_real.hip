@@ -314,6 +314,27 @@ __global__ __launch_bounds__(256) void k_eval_2x2(int64_t count, const double *_
     out[4 * i + 3] = z22;
 }
 
+// Diagnostic: the device's rounded-down product and its error term
+// (Appendix A) on `count` operand pairs.
+__global__ __launch_bounds__(256) void k_eval_mul_rd(int64_t count, const double *__restrict__ a,
+                                                     const double *__restrict__ b,
+                                                     double *__restrict__ c, double *__restrict__ d)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= count) return;
+    const double x = a[e], y = b[e];
+    const double cd = mul_rd(x, y);
+    c[e] = cd;
+    d[e] = fma(x, y, -cd);
+}
+
+void launch_eval_mul_rd(int64_t count, const double *a, const double *b, double *c, double *d,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_eval_mul_rd, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                       count, a, b, c, d);
+}
+
 void launch_eval_2x2(int64_t count, const double *in, double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_eval_2x2, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, count,

@@ -83,7 +83,8 @@ def test_argument_validation_before_device_work(hz, case, expect):
 
 
 def test_bad_params_rejected(hz):
-    for kw in (dict(variant=1), dict(w=12), dict(ordering=7), dict(inner_max_sweeps=0),
+    for kw in (dict(variant=2), dict(variant=3), dict(w=12), dict(ordering=7),
+               dict(inner_max_sweeps=0),
                dict(max_sweeps=0), dict(inner_ordering=0)):
         assert _call(hz, hz.params(**kw), 64, 64, 32) == -1
 
@@ -285,3 +286,17 @@ def test_qr_shorten_sizes_and_rejections(hz):
     best = hz.HzParams()
     assert L.hz_dgsvd_tune(ctypes.byref(hz.params(qr_shorten=1)), 9000, 9000, 8193, v, 9000, v,
                            9000, None, ctypes.byref(best), None, None) == -1
+
+
+def test_enhanced_variants_real_only(hz):
+    """Variants 1 and 5 (enhanced dot products) are accepted by the real
+    solvers and rejected, on the host, by the complex one."""
+    L = hz.lib()
+    v = ctypes.c_void_p(256)
+    for variant in (1, 5):
+        p = hz.params(variant=variant)
+        assert L.hz_dgsvd_work_size(ctypes.byref(p), 64, 64, 32) > 0
+        assert L.hz_dgsvd_mixed_work_size(ctypes.byref(p), 64, 64, 32) > 0
+        assert L.hz_zgsvd_work_size(ctypes.byref(p), 64, 64, 32) == 0
+        assert L.hz_zgsvd(ctypes.byref(p), 64, 64, 32, v, 64, v, 64, v, 32, v, v, v, None, 0,
+                          None, None) == -1
