@@ -119,6 +119,12 @@ typedef struct hz_params {
                              Cholesky-QR refinement, so F and G must each have full column
                              rank with kappa^2 * eps well below 1, else HZ_ECHOL; n <= 8192.
                              0 (default) = no shortening */
+    int pivot_qr;         /* hz_dgsvd only, per-step schedule: 1 = the pivot factors of every
+                             block pair come from QR factorizations of the block-column
+                             pairs [F_p F_q], [G_p G_q] (Section 2.3, Appendix E; a tree of
+                             Householder factorizations of row tiles) instead of Cholesky
+                             factorizations of their Grams, for pairs whose block columns are
+                             too ill-conditioned for the Grams; 0 (default) = Grams */
 } hz_params;
 
 typedef struct hz_info {

@@ -22,7 +22,7 @@ _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libhzgsvd.so")
 CSRC = os.path.join(_HERE, "csrc")
 SOURCES = ["hz_api.hip", "hz_real.hip", "hz_cplx.hip", "hz_mixed.hip", "hz_batched.hip",
-           "hz_dataflow.hip", "hz_shorten.hip"]
+           "hz_dataflow.hip", "hz_shorten.hip", "hz_pivqr.hip"]
 
 HZ_OK, HZ_ENOCONV, HZ_ECHOL, HZ_ENONFINITE, HZ_EHIP = 0, 1, 2, 3, 4
 HZ_ORD_MM, HZ_ORD_RR = 1, 2
@@ -65,7 +65,7 @@ class HzParams(ctypes.Structure):
                 ("mixed_switch", ctypes.c_double), ("max_fp32_sweeps", ctypes.c_int),
                 ("inner_lanes", ctypes.c_int), ("gram_splits", ctypes.c_int),
                 ("update_rows", ctypes.c_int), ("schedule", ctypes.c_int),
-                ("qr_shorten", ctypes.c_int)]
+                ("qr_shorten", ctypes.c_int), ("pivot_qr", ctypes.c_int)]
 
 
 class HzInfo(ctypes.Structure):

@@ -78,6 +78,8 @@ static int params_ok(const hz_params &p)
         return 0;
     if (p.gram_splits < 0 || p.gram_splits > 16 || p.update_rows < 0 || (p.update_rows % 16) != 0) return 0;
     if (p.qr_shorten != 0 && p.qr_shorten != 1) return 0;
+    if (p.pivot_qr != 0 && p.pivot_qr != 1) return 0;
+    if (p.pivot_qr && p.schedule == HZ_SCHED_DATAFLOW) return 0;
     return 1;
 }
 
@@ -160,6 +162,11 @@ static bool make_plan(const hz_params &prm, int64_t mf, int64_t mg, int64_t n, i
         P.o_ddep = o; o = align256(o + 4 * (3 * kl + 4));
         P.o_dwg = o; o = align256(o + 4 * ((size_t)DF_MAX_WG + 1 + P.df_ntasks));
     }
+    if (prm.pivot_qr && !is_complex && !mixed) {
+        const size_t tri = 8 * (size_t)P.npairs * 2 * pivot_qr_tiles(P) * P.W2 * P.W2;
+        P.o_qr[0] = o; o = align256(o + tri);
+        P.o_qr[1] = o; o = align256(o + tri);
+    }
     P.mixed = mixed;
     if (mixed) {
         P.o_fs = o; o = align256(o + sizeof(float) * (size_t)P.mfw * P.nw);
@@ -198,6 +205,8 @@ static Ptrs make_ptrs(const Plan &P, void *work)
     W.Gs = P.mixed ? (float *)(b + P.o_gs) : nullptr;
     W.Zs = P.mixed ? (float *)(b + P.o_zs) : nullptr;
     W.offd = P.mixed ? (double *)(b + P.o_offd) : nullptr;
+    W.qr[0] = P.o_qr[0] ? (double *)(b + P.o_qr[0]) : nullptr;
+    W.qr[1] = P.o_qr[1] ? (double *)(b + P.o_qr[1]) : nullptr;
     return W;
 }
 
@@ -512,6 +521,7 @@ static int solve_entry(int kind, const hz_params *p, int64_t m_f, int64_t m_g, i
     if (kind == KIND_MIXED && (prm.max_fp32_sweeps < 0 || !(prm.mixed_switch >= 0.0))) return -1;
     if (prm.qr_shorten && (kind != KIND_REAL || (n > 1 && !shorten_cpt(n)))) return -1;
     if (is_complex && (prm.variant & 1)) return -1;   // enhanced dot products: real only
+    if (prm.pivot_qr && kind != KIND_REAL) return -1;
     const int a = check_args(m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g);
     if (a) return a;
     if (is_complex && (((uintptr_t)F | (uintptr_t)G | (uintptr_t)Z) & 15))
@@ -562,6 +572,7 @@ static size_t work_size_entry(int kind, const hz_params *p, int64_t m_f, int64_t
     if (!params_ok(prm) || !w_ok_for(prm, is_complex) || m_f < n || m_g < n || n < 1) return 0;
     if (prm.qr_shorten && (kind != KIND_REAL || (n > 1 && !shorten_cpt(n)))) return 0;
     if (is_complex && (prm.variant & 1)) return 0;
+    if (prm.pivot_qr && kind != KIND_REAL) return 0;
     if (n == 1) return 256;
     Plan P;
     if (prm.qr_shorten) {
@@ -1263,7 +1274,7 @@ size_t hz_dgsvd_batched_work_size(const hz_params *p, int batch, const int64_t *
 {
     hz_params prm;
     if (p) prm = *p; else hz_default_params(&prm);
-    if (!params_ok(prm) || prm.qr_shorten || batch < 0 || batch > 65535) return 0;
+    if (!params_ok(prm) || prm.qr_shorten || prm.pivot_qr || batch < 0 || batch > 65535) return 0;
     if (batch == 0) return 256;
     if (!m_f || !m_g || !n) return 0;
     for (int i = 0; i < batch; ++i)
@@ -1282,7 +1293,7 @@ int hz_dgsvd_batched(const hz_params *p, int batch, const int64_t *m_f, const in
 {
     hz_params prm;
     if (p) prm = *p; else hz_default_params(&prm);
-    if (!params_ok(prm) || prm.qr_shorten) return -1;
+    if (!params_ok(prm) || prm.qr_shorten || prm.pivot_qr) return -1;
     const int a = check_batched(batch, m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f,
                                 sigma_g);
     if (a) return a;
@@ -1327,6 +1338,7 @@ static uint64_t tune_key(const char *kind, const hz_params &p, int batch, const 
     h = fnv(h, fixed, sizeof(fixed));
     h = fnv(h, &p.tol, sizeof(p.tol));
     if (p.qr_shorten) h = fnv(h, "qr_shorten", 10);   // keys without it are unchanged
+    if (p.pivot_qr) h = fnv(h, "pivot_qr", 8);
     h = fnv(h, &batch, sizeof(batch));
     h = fnv(h, mf, sizeof(int64_t) * batch);
     h = fnv(h, mg, sizeof(int64_t) * batch);
@@ -1541,7 +1553,7 @@ int hz_dgsvd_batched_tune(const hz_params *p, int batch, const int64_t *m_f, con
     // ordering 0 asks the tuner to choose between modified modulus and round robin
     const bool tune_ord = (base.ordering == 0);
     if (tune_ord) base.ordering = HZ_ORD_MM;
-    if (!params_ok(base) || base.qr_shorten) return -1;
+    if (!params_ok(base) || base.qr_shorten || base.pivot_qr) return -1;
     if (batch < 1 || batch > 65535) return -2;
     if (!m_f) return -3;
     if (!m_g) return -4;

@@ -32,6 +32,7 @@ struct Plan {
     size_t o_fw, o_gw, o_zw, o_part, o_gram, o_arrive, o_zt, o_otab, o_itab, o_cnt, o_status, o_tot;
     size_t o_sf, o_sg, o_sig, o_rank, o_border;
     size_t o_fs, o_gs, o_zs, o_offd;   // mixed form only (FP32 copies, off-diagonal measure)
+    size_t o_qr[2];                    // pivot_qr only: triangles of the QR tree, two levels
     int dataflow;                      // one persistent launch per sweep (hz_dataflow.hip)
     int df_tiles_f, df_tiles_g, df_tiles_z, df_ntasks;
     int64_t df_tile_rows;
@@ -54,6 +55,7 @@ struct Ptrs {
     int *rank, *border;
     float *Fs, *Gs, *Zs;         // mixed form: FP32 working copies
     double *offd;                // mixed form: per (step, pair, matrix) off-diagonal measure
+    double *qr[2];               // pivot_qr: QR tree levels (ping-pong)
     unsigned long long *tot;   // per-sweep summary (SWEEP_TOT_N words)
 };
 
@@ -110,6 +112,11 @@ void launch_eval_mul_rd(int64_t count, const double *a, const double *b, double 
                         hipStream_t s);
 void launch_rank(const Plan &P, const Ptrs &W, hipStream_t s);
 void launch_gram_sum(const Plan &P, const Ptrs &W, hipStream_t s);
+
+// QR factors of the block-column pairs as pivot factors (hz_pivqr.hip): the
+// tree levels of one step, ending in W.gram (per pair R_F, R_G, W2 x W2 upper).
+void launch_pivot_qr(const Plan &P, const Ptrs &W, int step, hipStream_t s);
+int pivot_qr_tiles(const Plan &P);   // leaf tiles of the taller matrix
 void launch_inner_real(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
                        bool partials, hipStream_t s);
 

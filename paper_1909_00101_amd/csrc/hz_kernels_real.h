@@ -135,10 +135,12 @@ __device__ __forceinline__ void inner_solve(
     if (ph && tid == 0) ph[0] = wall_clock64();
     // 1. load the Gram blocks (lower triangles) into LDS; with nsplit > 1 the
     // blocks arrive as nsplit row-split partials (stride sstride), added in
-    // split order.
+    // split order; with nsplit 0 they are the upper triangular factors
+    // themselves (QR of the block-column pairs).
     {
         for (int e = 2 * tid; e < W2 * W2; e += 2 * NT) {
-            if ((e / W2) / 16 > (e % W2) / 16) continue;      // upper tiles are never read
+            // upper tiles of a Gram are never read; a factor (nsplit 0) is upper
+            if (nsplit > 0 && (e / W2) / 16 > (e % W2) / 16) continue;
             d2 a = *(const d2 *)(pa + e), b = *(const d2 *)(pb + e);
             for (int sp = 1; sp < nsplit; ++sp) {
                 a += *(const d2 *)(pa + sp * sstride + e);
@@ -154,8 +156,16 @@ __device__ __forceinline__ void inner_solve(
     __syncthreads();
     if (ph && tid == 0) ph[1] = wall_clock64();
 
-    // 2. Cholesky factorizations, lane = row, one wave per matrix.
-    {
+    // 2. Cholesky factorizations, lane = row, one wave per matrix.  With
+    // nsplit 0 the factors came in (QR of the block-column pairs): only their
+    // diagonals are checked for zeros and non-finite values.
+    if (nsplit == 0) {
+        if (tid < W2) {
+            const double df = sF[tid * LDI + tid], dg = sG[tid * LDI + tid];
+            if (!(fabs(df) > 0.0 && fabs(df) < INFINITY && fabs(dg) > 0.0 && fabs(dg) < INFINITY))
+                s_fail = 1;
+        }
+    } else {
         constexpr bool two = (W2 == 64);
         const int mat = two ? wave : (lane >> 5);
         const int i = two ? lane : (lane & 31);

@@ -129,9 +129,10 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner(
     unsigned long long *__restrict__ phase)
 {
     const int pr = blockIdx.x;
-    const double *pa = gram + (size_t)(pr * 2) * nsplit * (W2 * W2);
+    const int ns = nsplit > 0 ? nsplit : 1;   // nsplit 0: one triangular factor per matrix
+    const double *pa = gram + (size_t)(pr * 2) * ns * (W2 * W2);
     __shared__ __attribute__((aligned(16))) double lds[inner_lds<W2>()];
-    inner_solve<W2, LP>(pa, pa + (size_t)nsplit * (W2 * W2), nsplit, W2 * W2, itab, isteps,
+    inner_solve<W2, LP>(pa, pa + (size_t)ns * (W2 * W2), nsplit, W2 * W2, itab, isteps,
                         inner_max, tol, sort, variant,
                         Zt + (size_t)pr * (W2 * W2), cnt + ((size_t)step * npairs + pr) * 4,
                         status, step * 65536 + pr,
@@ -407,7 +408,7 @@ static void inner_impl(const Plan &P, const Ptrs &W, int step, const hz_params &
                        bool partials, hipStream_t s)
 {
     const double *src = partials ? W.part : W.gram;
-    const int ns = partials ? P.splits : 1;
+    const int ns = partials ? P.splits : (prm.pivot_qr ? 0 : 1);
     if constexpr (W2 == 16) {
         hipLaunchKernelGGL((k_inner<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s, src, ns,
                            P.npairs, step, W.itab, P.isteps, prm.inner_max_sweeps, tol, prm.sort,
@@ -466,9 +467,13 @@ static void step_impl(const Plan &P, const Ptrs &W, int step, const hz_params &p
 {
     const int *pairs = W.otab + (size_t)step * P.npairs * 2;
     prof_mark(K_GRAM, true, s);
-    hipLaunchKernelGGL(k_gram<W2>, dim3(P.splits, P.npairs, 2), dim3(256), 0, s, W.Fw, W.Gw,
-                       P.mfw, P.mgw, pairs, P.splits, W.part);
-    launch_gram_sum(P, W, s);
+    if (prm.pivot_qr) {
+        launch_pivot_qr(P, W, step, s);
+    } else {
+        hipLaunchKernelGGL(k_gram<W2>, dim3(P.splits, P.npairs, 2), dim3(256), 0, s, W.Fw, W.Gw,
+                           P.mfw, P.mgw, pairs, P.splits, W.part);
+        launch_gram_sum(P, W, s);
+    }
     prof_mark(K_GRAM, false, s);
     prof_mark(K_INNER, true, s);
     inner_impl<W2>(P, W, step, prm, tol, false, s);
