@@ -7,10 +7,11 @@
 // is never formed.
 //
 // Tall-skinny QR as a reduction tree: every workgroup factors one tile of
-// 2 * W2 rows and W2 columns with Householder reflections in LDS and writes
-// its W2 x W2 triangle; the leaves are consecutive row chunks of [Y_p Y_q],
-// each further level factors two stacked triangles of the level below,
-// until one triangle per block pair and matrix is left.  All pivot pairs of
+// 2 * W2 rows and W2 columns with Householder reflections (the tile in
+// registers, the reflectors through LDS) and writes its W2 x W2 triangle;
+// the leaves are consecutive row chunks of [Y_p Y_q], each further level
+// factors two stacked triangles of the level below, until one triangle per
+// block pair and matrix is left.  All pivot pairs of
 // a step, F and G, go in one launch per level.  The factor is not squared,
 // so a block pair whose columns are independent to working accuracy gets a
 // usable factor where its Gram would lose half the digits.
@@ -38,97 +39,104 @@ struct QRLevel {
     int level;
 };
 
+// Thread t owns column t / Q of the tile, rows t % Q, t % Q + Q, ... (RPQ
+// of them) in registers.  Step k: the Q owners of column k form the
+// reflector H = I - tau v v^T (v_k = 1) that maps the column to
+// (beta, 0, ..., 0) and publish v and tau in LDS (two buffers, so one
+// barrier per step); the owners of the columns right of k apply H to their
+// rows.  Sums over a column use a fixed reduction order.
 template <int W2>
 __global__ __launch_bounds__(256) void k_qr_tile(QRLevel a)
 {
     constexpr int CH = 2 * W2;          // tile rows
-    constexpr int LDA = CH + 1;
-    constexpr int NT = 256, NW = NT / 64;
-    constexpr int Q = NT / W2;          // threads per column in the update
-    constexpr int RPQ = CH / Q;         // rows per thread in the update
-    static_assert(CH <= NT && Q >= 1 && (64 % Q) == 0, "bad QR tile geometry");
-    __shared__ double A[W2 * LDA];      // column j at A + j * LDA
-    __shared__ double s_v[CH];
-    __shared__ double s_part[NW];
+    constexpr int NT = 256;
+    constexpr int Q = NT / W2;          // threads per column
+    constexpr int RPQ = CH / Q;         // rows per thread
+    static_assert(Q >= 1 && (64 % Q) == 0 && RPQ % 2 == 0, "bad QR tile geometry");
+    __shared__ double s_v[2][CH];
+    __shared__ double s_tau[2];
     const int mt = blockIdx.z, l = blockIdx.y, c = blockIdx.x;
     if (c >= (mt ? a.nodes_g : a.nodes_f)) return;   // uniform: the grid covers the larger
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
+    const int tid = threadIdx.x;
+    const int jc = tid / Q, q = tid % Q;
+    double x[RPQ];
     if (a.level == 0) {
         const double *__restrict__ Y = mt ? a.Gw : a.Fw;
         const int64_t m = mt ? a.mgw : a.mfw;
         const int W = W2 / 2;
-        const int p = a.pairs[2 * l], q = a.pairs[2 * l + 1];
-        for (int e = tid; e < W2 * CH; e += NT) {
-            const int j = e / CH, r = e % CH;
-            const int64_t gc = (j < W) ? (int64_t)p * W + j : (int64_t)q * W + (j - W);
-            const int64_t gr = (int64_t)c * CH + r;
-            A[j * LDA + r] = (gr < m) ? Y[gc * m + gr] : 0.0;
+        const int p = a.pairs[2 * l], qq = a.pairs[2 * l + 1];
+        const int64_t gc = (jc < W) ? (int64_t)p * W + jc : (int64_t)qq * W + (jc - W);
+        const double *col = Y + gc * m;
+#pragma unroll
+        for (int i = 0; i < RPQ; ++i) {
+            const int64_t gr = (int64_t)c * CH + q + Q * i;
+            x[i] = (gr < m) ? col[gr] : 0.0;
         }
     } else {
         const int prev = mt ? a.prev_g : a.prev_f;
         const double *__restrict__ ra =
             a.in + (((size_t)l * 2 + mt) * a.in_stride + 2 * (size_t)c) * (W2 * W2);
         const bool second = 2 * c + 1 < prev;
-        for (int e = tid; e < W2 * CH; e += NT) {
-            const int j = e / CH, r = e % CH;
+#pragma unroll
+        for (int i = 0; i < RPQ; ++i) {
+            const int r = q + Q * i;
             double v = 0.0;
-            if (r < W2) v = ra[j * W2 + r];
-            else if (second) v = ra[W2 * W2 + j * W2 + (r - W2)];
-            A[j * LDA + r] = v;
+            if (r < W2) v = ra[jc * W2 + r];
+            else if (second) v = ra[W2 * W2 + jc * W2 + (r - W2)];
+            x[i] = v;
         }
     }
-    __syncthreads();
-
-    const int jc = tid / Q, r0 = (tid % Q) * RPQ;   // update: column jc, rows r0 .. r0+RPQ-1
     for (int k = 0; k < W2; ++k) {
-        // sum of squares below the diagonal of column k, in a fixed order
-        double sq = 0.0;
-        if (tid < CH && tid > k) {
-            const double x = A[k * LDA + tid];
-            sq = x * x;
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) sq += __shfl_xor(sq, off);
-        if (lane == 0) s_part[wave] = sq;
-        __syncthreads();
-        double sigma = 0.0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) sigma += s_part[w];
-        const double alpha = A[k * LDA + k];
-        // Householder reflector H = I - tau v v^T with v_k = 1 mapping
-        // column k to (beta, 0, ..., 0); none when nothing is below the diagonal
-        double beta = alpha, tau = 0.0, scale = 0.0;
-        if (sigma > 0.0) {
-            beta = -copysign(sqrt(fma(alpha, alpha, sigma)), alpha);
-            tau = (beta - alpha) / beta;
-            scale = 1.0 / (alpha - beta);
-        }
-        if (tid < CH) s_v[tid] = (tid == k) ? 1.0 : ((tid > k) ? A[k * LDA + tid] * scale : 0.0);
-        __syncthreads();
-        if (tid == 0) A[k * LDA + k] = beta;
-        if (tau != 0.0 && jc > k) {
-            double w = 0.0;
+        const int par = k & 1;
+        if (jc == k) {
+            double sq = 0.0, al = 0.0;
 #pragma unroll
             for (int i = 0; i < RPQ; ++i) {
-                const int r = r0 + i;
-                if (r >= k) w = fma(s_v[r], A[jc * LDA + r], w);
+                const int r = q + Q * i;
+                if (r > k) sq = fma(x[i], x[i], sq);
+                if (r == k) al = x[i];
             }
+#pragma unroll
+            for (int off = Q / 2; off >= 1; off >>= 1) {
+                sq += __shfl_xor(sq, off);
+                al += __shfl_xor(al, off);       // one nonzero term: exact
+            }
+            double beta = al, tau = 0.0, scale = 0.0;
+            if (sq > 0.0) {
+                beta = -copysign(sqrt(fma(al, al, sq)), al);
+                tau = (beta - al) / beta;
+                scale = 1.0 / (al - beta);
+            }
+#pragma unroll
+            for (int i = 0; i < RPQ; ++i) {
+                const int r = q + Q * i;
+                s_v[par][r] = (r == k) ? 1.0 : ((r > k) ? x[i] * scale : 0.0);
+                if (r == k) x[i] = beta;
+            }
+            if (q == 0) s_tau[par] = tau;
+        }
+        __syncthreads();
+        const double tau = s_tau[par];
+        if (tau != 0.0 && jc > k) {
+            double w0 = 0.0, w1 = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPQ; i += 2) {
+                w0 = fma(s_v[par][q + Q * i], x[i], w0);
+                w1 = fma(s_v[par][q + Q * (i + 1)], x[i + 1], w1);
+            }
+            double w = w0 + w1;
 #pragma unroll
             for (int off = Q / 2; off >= 1; off >>= 1) w += __shfl_xor(w, off);
             const double tw = tau * w;
 #pragma unroll
-            for (int i = 0; i < RPQ; ++i) {
-                const int r = r0 + i;
-                if (r >= k) A[jc * LDA + r] = fma(-tw, s_v[r], A[jc * LDA + r]);
-            }
+            for (int i = 0; i < RPQ; ++i) x[i] = fma(-tw, s_v[par][q + Q * i], x[i]);
         }
-        __syncthreads();
     }
     double *__restrict__ R = a.out + (((size_t)l * 2 + mt) * a.out_stride + c) * (W2 * W2);
-    for (int e = tid; e < W2 * W2; e += NT) {
-        const int j = e / W2, r = e % W2;
-        R[j * W2 + r] = (r <= j) ? A[j * LDA + r] : 0.0;
+#pragma unroll
+    for (int i = 0; i < RPQ; ++i) {
+        const int r = q + Q * i;
+        if (r < W2) R[jc * W2 + r] = (r <= jc) ? x[i] : 0.0;
     }
 }
 
