@@ -122,8 +122,9 @@ def _timed(fn, reps):
 def mixed_vs_plain(reps=2):
     """hz_dgsvd_mixed against hz_dgsvd on the seeded 8192 x 2048 pair (w = 32,
     one inner sweep, tol = n eps, the same launch parameters for both, the
-    switch to FP64 at the default off-diagonal measure 1e-5); both restore
-    the pair from device copies inside the timed call (two 128 MiB copies)."""
+    switch to FP64 at the default off-diagonal measure 1e-5), and both again
+    on the QR-shortened pair (qr_shorten = 1); all restore the pair from
+    device copies inside the timed call (two 128 MiB copies)."""
     import torch
     import gsvd_inputs as gi
     import paper_1909_00101_amd as hz
@@ -135,11 +136,12 @@ def mixed_vs_plain(reps=2):
     kw = dict(w=32, inner_max_sweeps=1, tol=spec.n * np.finfo(np.float64).eps, gram_splits=8,
               update_rows=64)
     res = {}
-    for name, mixed in (("plain", False), ("mixed", True)):
+    for name, mixed, short in (("plain", False, 0), ("mixed", True, 0),
+                               ("plain_shortened", False, 1), ("mixed_shortened", True, 1)):
         def run():
             Fw.copy_(F0)
             Gw.copy_(G0)
-            return hz.gsvd(Fw, Gw, overwrite=True, mixed=mixed, **kw)
+            return hz.gsvd(Fw, Gw, overwrite=True, mixed=mixed, qr_shorten=short, **kw)
         run()
         dt, r = _timed(run, reps)
         err = float(np.max(np.abs(r["sigma"].cpu().numpy() - s_true) / s_true))
@@ -149,7 +151,10 @@ def mixed_vs_plain(reps=2):
     torch.cuda.empty_cache()
     return dict(workload=f"seeded {spec.m_f}x{spec.n} real pair, kappa(X)=1e2, w=32, "
                          f"one inner sweep, tol=n*eps, 8 Gram splits, 64 update rows per wave",
-                speedup=round(res["plain"]["ms"] / res["mixed"]["ms"], 3), **res)
+                speedup=round(res["plain"]["ms"] / res["mixed"]["ms"], 3),
+                speedup_shortened=round(res["plain"]["ms"] / res["plain_shortened"]["ms"], 3),
+                speedup_mixed_shortened=round(res["plain"]["ms"] / res["mixed_shortened"]["ms"], 3),
+                **res)
 
 
 def batched_vs_plain(tune_cache=None, reps=3):

@@ -110,7 +110,7 @@ typedef struct hz_params {
                              phase and block step, HZ_SCHED_DATAFLOW = one persistent
                              launch per sweep whose workgroups take Gram, inner-solve and
                              update tasks from a dependency-ordered queue (w = 32 only) */
-    int qr_shorten;       /* hz_dgsvd only: 1 = shorten the pair first (Section 2, before the
+    int qr_shorten;       /* hz_dgsvd, hz_dgsvd_mixed: 1 = shorten the pair first (Section 2, before the
                              prescaling): F P1 = Q_F R_F and (G P1) P2 = Q_G R_G with column
                              pivoting, the sweeps run on the n x n pair (R_F P2, R_G), and
                              Z = P1 P2 Z'', U = Q_F U'', V = Q_G V''.  The factorizations are

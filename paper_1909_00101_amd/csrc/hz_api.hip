@@ -373,9 +373,9 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
 
 // The QR-shortened real solve (qr_shorten = 1).
 static int run_shortened(const hz_params &prm, const Plan &P, const SPlan &S, void *work,
-                         hz_info *info, hipStream_t st, double *F, int64_t ldf, double *G,
-                         int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
-                         double *sigma_g);
+                         hz_info *info, hipStream_t st, int kind, double *F, int64_t ldf,
+                         double *G, int64_t ldg, double *Z, int64_t ldz, double *sigma,
+                         double *sigma_f, double *sigma_g);
 
 }  // namespace hz
 
@@ -519,7 +519,7 @@ static int solve_entry(int kind, const hz_params *p, int64_t m_f, int64_t m_g, i
     if (p) prm = *p; else hz_default_params(&prm);
     if (!params_ok(prm) || !w_ok_for(prm, is_complex)) return -1;
     if (kind == KIND_MIXED && (prm.max_fp32_sweeps < 0 || !(prm.mixed_switch >= 0.0))) return -1;
-    if (prm.qr_shorten && (kind != KIND_REAL || (n > 1 && !shorten_cpt(n)))) return -1;
+    if (prm.qr_shorten && (kind == KIND_COMPLEX || (n > 1 && !shorten_cpt(n)))) return -1;
     if (is_complex && (prm.variant & 1)) return -1;   // enhanced dot products: real only
     if (prm.pivot_qr && kind != KIND_REAL) return -1;
     const int a = check_args(m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g);
@@ -550,12 +550,12 @@ static int solve_entry(int kind, const hz_params *p, int64_t m_f, int64_t m_g, i
     }
     Plan P;
     if (prm.qr_shorten) {
-        if (!make_plan(prm, n, n, n, 0, P)) return -4;
+        if (!make_plan(prm, n, n, n, 0, P, kind == KIND_MIXED)) return -4;
         SPlan S;
         if (!make_splan(m_f, m_g, n, P.total, S)) return -4;
         if (work && work_bytes < S.total) return -15;
-        return run_shortened(prm, P, S, work, info, st, F, ldf, G, ldg, Z, ldz, sigma, sigma_f,
-                             sigma_g);
+        return run_shortened(prm, P, S, work, info, st, kind, F, ldf, G, ldg, Z, ldz, sigma,
+                             sigma_f, sigma_g);
     }
     if (!make_plan(prm, m_f, m_g, n, is_complex, P, kind == KIND_MIXED)) return -4;
     if (work && work_bytes < P.total) return -15;
@@ -570,14 +570,16 @@ static size_t work_size_entry(int kind, const hz_params *p, int64_t m_f, int64_t
     hz_params prm;
     if (p) prm = *p; else hz_default_params(&prm);
     if (!params_ok(prm) || !w_ok_for(prm, is_complex) || m_f < n || m_g < n || n < 1) return 0;
-    if (prm.qr_shorten && (kind != KIND_REAL || (n > 1 && !shorten_cpt(n)))) return 0;
+    if (prm.qr_shorten && (kind == KIND_COMPLEX || (n > 1 && !shorten_cpt(n)))) return 0;
     if (is_complex && (prm.variant & 1)) return 0;
     if (prm.pivot_qr && kind != KIND_REAL) return 0;
     if (n == 1) return 256;
     Plan P;
     if (prm.qr_shorten) {
         SPlan S;
-        if (!make_plan(prm, n, n, n, 0, P) || !make_splan(m_f, m_g, n, P.total, S)) return 0;
+        if (!make_plan(prm, n, n, n, 0, P, kind == KIND_MIXED) ||
+            !make_splan(m_f, m_g, n, P.total, S))
+            return 0;
         return S.total;
     }
     if (!make_plan(prm, m_f, m_g, n, is_complex, P, kind == KIND_MIXED)) return 0;
@@ -909,9 +911,9 @@ done:
 // A failed factorization returns before the sweeps with info->failed_pair
 // = -1.
 static int run_shortened(const hz_params &prm, const Plan &P, const SPlan &S, void *work,
-                         hz_info *info, hipStream_t st, double *F, int64_t ldf, double *G,
-                         int64_t ldg, double *Z, int64_t ldz, double *sigma, double *sigma_f,
-                         double *sigma_g)
+                         hz_info *info, hipStream_t st, int kind, double *F, int64_t ldf,
+                         double *G, int64_t ldg, double *Z, int64_t ldz, double *sigma,
+                         double *sigma_f, double *sigma_g)
 {
     bool own = false;
     if (!work) {
@@ -939,7 +941,9 @@ static int run_shortened(const hz_params &prm, const Plan &P, const SPlan &S, vo
     } else {
         double *F2 = (double *)(b + S.o_f2), *G2 = (double *)(b + S.o_g2);
         double *Z2 = (double *)(b + S.o_z2);
-        rc = run_solve(prm, P, b + S.o_solve, S.total - S.o_solve, info, st, KIND_REAL, F2, S.ldn,
+        // the mixed form reads F'', G'' again for its FP64 restart; its final
+        // extraction, the only writer of U'', V'' over them, comes after
+        rc = run_solve(prm, P, b + S.o_solve, S.total - S.o_solve, info, st, kind, F2, S.ldn,
                        G2, S.ldn, F2, G2, Z2, S.ldn, sigma, sigma_f, sigma_g, true);
         if (rc == HZ_OK || rc == HZ_ENOCONV) {
             if (launch_unshorten(S, work, F, ldf, G, ldg, Z, ldz, st) != hipSuccess ||

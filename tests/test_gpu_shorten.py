@@ -129,3 +129,20 @@ def test_shortened_rank_deficient_f():
         _run(F, G, w=8)
     assert ei.value.status == hz.HZ_ECHOL
     assert ei.value.info.failed_pair == -1 and ei.value.info.sweeps == 0
+
+
+def test_shortened_mixed():
+    """The mixed-precision solver on the shortened pair: FP32 sweeps and the
+    FP64 restart run on (R_F P2, R_G); sigma against the oracle's, the
+    contract on the original pair."""
+    import oracle
+    F, G, s_true = gi.custom_pair(1500, 1200, 256, kappa=1e2, seed=740)
+    print("shortened mixed 1500x256", flush=True)
+    r = _run(F, G, w=32, inner_max_sweeps=1, mixed=True)
+    assert r["status"] == 0 and r["converged"]
+    print(f"  sweeps fp32={r['sweeps_fp32']} fp64={r['sweeps']}")
+    assert r["sweeps_fp32"] > 0
+    assert max_rel(r["sigma"], oracle.gsvd(F, G, threads=4)["sigma"]) < SIG_TOL
+    assert max_rel(r["sigma"], s_true) < SIG_TOL
+    assert_contract(F, G, r["U"], r["V"], r["Z"], r["sigma_f"], r["sigma_g"], r["sigma"],
+                    tol_res=1e-12, tol_orth=1e-12)
