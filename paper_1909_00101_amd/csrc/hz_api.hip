@@ -519,7 +519,7 @@ static int solve_entry(int kind, const hz_params *p, int64_t m_f, int64_t m_g, i
     if (p) prm = *p; else hz_default_params(&prm);
     if (!params_ok(prm) || !w_ok_for(prm, is_complex)) return -1;
     if (kind == KIND_MIXED && (prm.max_fp32_sweeps < 0 || !(prm.mixed_switch >= 0.0))) return -1;
-    if (prm.qr_shorten && (kind == KIND_COMPLEX || (n > 1 && !shorten_cpt(n)))) return -1;
+    if (prm.qr_shorten && n > 1 && !shorten_cpt(n)) return -1;
     if (is_complex && (prm.variant & 1)) return -1;   // enhanced dot products: real only
     if (prm.pivot_qr && kind != KIND_REAL) return -1;
     const int a = check_args(m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g);
@@ -550,9 +550,9 @@ static int solve_entry(int kind, const hz_params *p, int64_t m_f, int64_t m_g, i
     }
     Plan P;
     if (prm.qr_shorten) {
-        if (!make_plan(prm, n, n, n, 0, P, kind == KIND_MIXED)) return -4;
+        if (!make_plan(prm, n, n, n, is_complex, P, kind == KIND_MIXED)) return -4;
         SPlan S;
-        if (!make_splan(m_f, m_g, n, P.total, S)) return -4;
+        if (!make_splan(m_f, m_g, n, P.total, S, is_complex)) return -4;
         if (work && work_bytes < S.total) return -15;
         return run_shortened(prm, P, S, work, info, st, kind, F, ldf, G, ldg, Z, ldz, sigma,
                              sigma_f, sigma_g);
@@ -570,15 +570,15 @@ static size_t work_size_entry(int kind, const hz_params *p, int64_t m_f, int64_t
     hz_params prm;
     if (p) prm = *p; else hz_default_params(&prm);
     if (!params_ok(prm) || !w_ok_for(prm, is_complex) || m_f < n || m_g < n || n < 1) return 0;
-    if (prm.qr_shorten && (kind == KIND_COMPLEX || (n > 1 && !shorten_cpt(n)))) return 0;
+    if (prm.qr_shorten && n > 1 && !shorten_cpt(n)) return 0;
     if (is_complex && (prm.variant & 1)) return 0;
     if (prm.pivot_qr && kind != KIND_REAL) return 0;
     if (n == 1) return 256;
     Plan P;
     if (prm.qr_shorten) {
         SPlan S;
-        if (!make_plan(prm, n, n, n, 0, P, kind == KIND_MIXED) ||
-            !make_splan(m_f, m_g, n, P.total, S))
+        if (!make_plan(prm, n, n, n, is_complex, P, kind == KIND_MIXED) ||
+            !make_splan(m_f, m_g, n, P.total, S, is_complex))
             return 0;
         return S.total;
     }
@@ -1490,7 +1490,7 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
     if (base.qr_shorten) {
         SPlan S;
         int hs[ST_NSLOTS] = {0, 0, 0, 0};
-        if (!make_splan(m_f, m_g, n, 0, S)) return -4;
+        if (!make_splan(m_f, m_g, n, 0, S, 0)) return -4;
         if (hipMalloc(&swork, S.total) != hipSuccess) return HZ_EHIP;
         if (launch_shorten(S, swork, F, ldf, G, ldg, st) != hipSuccess ||
             hipMemcpyAsync(hs, (char *)swork + S.o_status, sizeof(hs), hipMemcpyDeviceToHost,

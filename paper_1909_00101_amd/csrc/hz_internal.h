@@ -183,7 +183,7 @@ void launch_eval_2x2_cplx(int64_t count, const double *in, double *out, hipStrea
 void launch_n1_real(int64_t mf, int64_t mg, double *F, double *G, double *Z, double *sigma,
                     double *sigma_f, double *sigma_g, int *status, hipStream_t s);
 
-// QR shortening of a tall real pair (hz_shorten.hip).  Workspace offsets
+// QR shortening of a tall pair, real or complex (hz_shorten.hip).  Workspace offsets
 // (bytes) of Q_F, Q_G (ld ldqf, ldqg), the n x n buffers (ld ldn) R1 of F
 // and G, the square pair F'', G'' (overwritten by U'', V'') and Z''; per
 // factored matrix the Gram / Schur complement S (later R), R transposed Rt,
@@ -193,13 +193,14 @@ void launch_n1_real(int64_t mf, int64_t mg, double *F, double *G, double *Z, dou
 struct SPlan {
     int64_t mf, mg, n, ldqf, ldqg, ldn;
     int cpt, nb, nblk;
+    int cx;                      // complex (interleaved) elements
     size_t o_qf, o_qg, o_r1f, o_r1g, o_f2, o_g2, o_z2;
     size_t o_s[2], o_rt[2], o_r2[2], o_t[2], o_xd[2], o_d[2], o_done[2], o_id[2];  // per F, G
     size_t o_p1, o_q, o_inv1, o_p2, o_status, o_solve;
     size_t total;
 };
 int shorten_cpt(int64_t n);   // 0 if n is beyond the shortening's limit (8192)
-bool make_splan(int64_t mf, int64_t mg, int64_t n, size_t solve_bytes, SPlan &S);
+bool make_splan(int64_t mf, int64_t mg, int64_t n, size_t solve_bytes, SPlan &S, int cx);
 hipError_t launch_shorten(const SPlan &P, void *work, const double *F, int64_t ldf,
                           const double *G, int64_t ldg, hipStream_t s);
 hipError_t launch_unshorten(const SPlan &P, void *work, double *U, int64_t ldu, double *V,

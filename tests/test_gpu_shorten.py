@@ -146,3 +146,42 @@ def test_shortened_mixed():
     assert max_rel(r["sigma"], s_true) < SIG_TOL
     assert_contract(F, G, r["U"], r["V"], r["Z"], r["sigma_f"], r["sigma_g"], r["sigma"],
                     tol_res=1e-12, tol_orth=1e-12)
+
+
+def _z_err_phase(Z, Zref):
+    c = np.sum(Z.conj() * Zref, axis=0)
+    return float(np.max(np.abs(Z * (c / np.abs(c)) - Zref)) / np.max(np.abs(Zref)))
+
+
+@pytest.mark.parametrize("shape,w", [((150, 120, 40), 8), ((300, 200, 100), 16),
+                                     ((64, 48, 32), 16), ((21, 19, 3), 8)])
+def test_shortened_complex_parity(shape, w):
+    """Complex pairs: Hermitian Grams, the Hermitian pivoted Cholesky and the
+    complex triangular solves; Z is unique up to unit phases of its columns."""
+    import oracle
+    m_f, m_g, n = shape
+    F, G, s_true = gi.custom_pair(m_f, m_g, n, kappa=30.0, is_complex=True, seed=750 + n)
+    print(f"shortened complex {shape} w={w}", flush=True)
+    r = _run(F, G, w=w, ordering=_hz().HZ_ORD_MM)
+    assert r["status"] == 0 and r["converged"]
+    o = oracle.gsvd_qr(F, G, ordering=oracle.ORD_MM)
+    print(f"  sweeps {r['sweeps']} err {max_rel(r['sigma'], o['sigma']):.2e} "
+          f"z {_z_err_phase(r['Z'], o['Z']):.2e}")
+    assert max_rel(r["sigma"], o["sigma"]) < SIG_TOL
+    assert max_rel(r["sigma"], s_true) < SIG_TOL
+    assert _z_err_phase(r["Z"], o["Z"]) < 1e-9
+    assert_contract(F, G, r["U"], r["V"], r["Z"], r["sigma_f"], r["sigma_g"], r["sigma"],
+                    tol_res=1e-12, tol_orth=1e-12)
+
+
+def test_shortened_complex_workload_shape():
+    """The complex 3072x1024 / 2048x1024 pair at w = 16."""
+    F, G, s_true = gi.config_pair(3)
+    print("shortened complex 3072x1024", flush=True)
+    r = _run(F, G, w=16, ordering=_hz().HZ_ORD_MM, inner_max_sweeps=1,
+             tol=1024 * EPS)
+    print(f"  sweeps {r['sweeps']} err_vs_truth {max_rel(r['sigma'], s_true):.2e}")
+    assert r["status"] == 0 and r["converged"]
+    assert max_rel(r["sigma"], s_true) < SIG_TOL
+    assert_contract(F, G, r["U"], r["V"], r["Z"], r["sigma_f"], r["sigma_g"], r["sigma"],
+                    tol_res=1e-12, tol_orth=1e-12)
