@@ -157,6 +157,40 @@ def mixed_vs_plain(reps=2):
                 **res)
 
 
+def complex_shortened_vs_plain(reps=2):
+    """hz_zgsvd on the seeded complex 3072x1024 / 2048x1024 pair (kappa(X) =
+    50, w = 16, modified-modulus outer and inner orderings, one inner sweep,
+    tol = n eps) plain and QR-shortened; both restore the pair from device
+    copies inside the timed call."""
+    import torch
+    import gsvd_inputs as gi
+    import paper_1909_00101_amd as hz
+    spec = gi.CONFIGS[3]
+    F, G, s_true = gi.config_pair(3)
+    dev = torch.device("cuda:0")
+    F0, G0 = torch.from_numpy(F).to(dev), torch.from_numpy(G).to(dev)
+    Fw, Gw = F0.clone(), G0.clone()
+    kw = dict(w=16, ordering=hz.HZ_ORD_MM, inner_ordering=hz.HZ_ORD_MM, inner_max_sweeps=1,
+              tol=spec.n * np.finfo(np.float64).eps)
+    res = {}
+    for name, short in (("plain", 0), ("shortened", 1)):
+        def run():
+            Fw.copy_(F0)
+            Gw.copy_(G0)
+            return hz.gsvd(Fw, Gw, overwrite=True, qr_shorten=short, **kw)
+        run()
+        dt, r = _timed(run, reps)
+        err = float(np.max(np.abs(r["sigma"].cpu().numpy() - s_true) / s_true))
+        res[name] = dict(ms=round(dt * 1e3, 2), sweeps=r["sweeps"], max_rel_sigma_err=err,
+                         status=r["status"])
+    del F0, G0, Fw, Gw
+    torch.cuda.empty_cache()
+    return dict(workload=f"seeded complex {spec.m_f}x{spec.n} / {spec.m_g}x{spec.n} pair, "
+                         "kappa(X)=50, w=16, MM outer and inner orderings, one inner sweep, "
+                         "tol=n*eps",
+                speedup=round(res["plain"]["ms"] / res["shortened"]["ms"], 3), **res)
+
+
 def batched_vs_plain(tune_cache=None, reps=3):
     """hz_dgsvd_batched on the 512-pair ensemble (n ~ U{16..256}, m ~ U{n..2n})
     against hz_dgsvd called on each pair in turn, both with the parameters
@@ -246,8 +280,8 @@ def main():
     ap.add_argument("--inner-max-sweeps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the QR-shortened, mixed-precision and batched comparisons")
-    ap.add_argument("--only-form", choices=("qr_shortened", "mixed", "batched"),
+                    help="skip the QR-shortened, mixed-precision, complex and batched comparisons")
+    ap.add_argument("--only-form", choices=("qr_shortened", "mixed", "complex", "batched"),
                     help="run only this comparison and print its JSON (for profiling)")
     ap.add_argument("--no-tune", action="store_true",
                     help="use --w/--inner-max-sweeps and library defaults, no autotuner")
@@ -287,6 +321,8 @@ def main():
             res = qr_shortened_vs_plain(F0, G0, s_true, tol, kw, tune_cache)
         elif args.only_form == "mixed":
             res = mixed_vs_plain()
+        elif args.only_form == "complex":
+            res = complex_shortened_vs_plain()
         else:
             res = batched_vs_plain(tune_cache)
         print(json.dumps(dict(form=args.only_form, **res)))
@@ -409,7 +445,8 @@ def main():
     if not args.no_forms:
         out["forms"] = dict(
             qr_shortened=qr_shortened_vs_plain(F0, G0, s_true, tol, kw, tune_cache),
-            mixed=mixed_vs_plain(), batched=batched_vs_plain(tune_cache))
+            mixed=mixed_vs_plain(), complex=complex_shortened_vs_plain(),
+            batched=batched_vs_plain(tune_cache))
     if not args.no_cpu_baseline:
         golden = os.path.join(ROOT, "tests", "golden", "oracle_config2.json")
         gs = None
