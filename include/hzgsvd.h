@@ -110,14 +110,15 @@ typedef struct hz_params {
                              phase and block step, HZ_SCHED_DATAFLOW = one persistent
                              launch per sweep whose workgroups take Gram, inner-solve and
                              update tasks from a dependency-ordered queue (w = 32 only) */
-    int qr_shorten;       /* hz_dgsvd, hz_dgsvd_mixed: 1 = shorten the pair first (Section 2, before the
-                             prescaling): F P1 = Q_F R_F and (G P1) P2 = Q_G R_G with column
-                             pivoting, the sweeps run on the n x n pair (R_F P2, R_G), and
-                             Z = P1 P2 Z'', U = Q_F U'', V = Q_G V''.  The factorizations are
-                             formed from the Grams F^T F, G^T G by Cholesky with diagonal
-                             pivoting (the pivot rule of column-pivoted QR) and one
-                             Cholesky-QR refinement, so F and G must each have full column
-                             rank with kappa^2 * eps well below 1, else HZ_ECHOL; n <= 8192.
+    int qr_shorten;       /* hz_dgsvd, hz_zgsvd, hz_dgsvd_mixed: 1 = shorten the pair first
+                             (Section 2, before the prescaling): F P1 = Q_F R_F and
+                             (G P1) P2 = Q_G R_G with column pivoting, the sweeps run on the
+                             n x n pair (R_F P2, R_G), and Z = P1 P2 Z'', U = Q_F U'',
+                             V = Q_G V''.  The factorizations are formed from the Grams F^H F,
+                             G^H G by Cholesky with diagonal pivoting (the pivot rule of
+                             column-pivoted QR) and one Cholesky-QR refinement, so F and G
+                             must each have full column rank with kappa^2 * eps well below 1,
+                             else HZ_ECHOL (failed_pair = -1); n <= 8192.
                              0 (default) = no shortening */
     int pivot_qr;         /* hz_dgsvd only, per-step schedule: 1 = the pivot factors of every
                              block pair come from QR factorizations of the block-column
