@@ -134,7 +134,6 @@ static bool make_plan(const hz_params &prm, int64_t mf, int64_t mg, int64_t n, i
     P.o_zw = o; o = align256(o + es * (size_t)P.nzw * P.nw);
     P.o_part = o; o = align256(o + es * (size_t)P.npairs * 2 * P.splits * P.W2 * P.W2);
     P.o_gram = o; o = align256(o + es * (size_t)P.npairs * 2 * P.W2 * P.W2);
-    P.o_arrive = o; o = align256(o + sizeof(unsigned) * (size_t)P.npairs * 2);
     P.o_zt = o; o = align256(o + es * (size_t)P.npairs * P.W2 * P.W2);
     P.o_otab = o; o = align256(o + sizeof(int) * (size_t)P.steps * P.npairs * 2);
     P.o_itab = o; o = align256(o + sizeof(int16_t) * (size_t)P.isteps * P.w * 2);
@@ -188,7 +187,6 @@ static Ptrs make_ptrs(const Plan &P, void *work)
     W.Zw = (double *)(b + P.o_zw);
     W.part = (double *)(b + P.o_part);
     W.gram = (double *)(b + P.o_gram);
-    W.arrive = (unsigned *)(b + P.o_arrive);
     W.phase = nullptr;
     W.Zt = (double *)(b + P.o_zt);
     W.otab = (int *)(b + P.o_otab);

@@ -29,7 +29,7 @@ struct Plan {
     int is_complex;
     size_t esz;               // bytes per matrix element (8 or 16)
     // workspace offsets (bytes)
-    size_t o_fw, o_gw, o_zw, o_part, o_gram, o_arrive, o_zt, o_otab, o_itab, o_cnt, o_status, o_tot;
+    size_t o_fw, o_gw, o_zw, o_part, o_gram, o_zt, o_otab, o_itab, o_cnt, o_status, o_tot;
     size_t o_sf, o_sg, o_sig, o_rank, o_border;
     size_t o_fs, o_gs, o_zs, o_offd;   // mixed form only (FP32 copies, off-diagonal measure)
     size_t o_qr[2];                    // pivot_qr only: triangles of the QR tree, two levels
@@ -45,7 +45,6 @@ struct Plan {
 struct Ptrs {
     char *base;
     double *Fw, *Gw, *Zw, *part, *gram, *Zt;
-    unsigned *arrive;
     unsigned long long *phase;   // optional per-(step, pair) phase clocks, or null
     int *otab;
     int16_t *itab;
