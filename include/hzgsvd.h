@@ -120,7 +120,7 @@ typedef struct hz_params {
                              must each have full column rank with kappa^2 * eps well below 1,
                              else HZ_ECHOL (failed_pair = -1); n <= 8192.
                              0 (default) = no shortening */
-    int pivot_qr;         /* hz_dgsvd only, per-step schedule: 1 = the pivot factors of every
+    int pivot_qr;         /* hz_dgsvd, hz_zgsvd, per-step schedule: 1 = the pivot factors of every
                              block pair come from QR factorizations of the block-column
                              pairs [F_p F_q], [G_p G_q] (Section 2.3, Appendix E; a tree of
                              Householder factorizations of row tiles) instead of Cholesky

@@ -161,8 +161,8 @@ static bool make_plan(const hz_params &prm, int64_t mf, int64_t mg, int64_t n, i
         P.o_ddep = o; o = align256(o + 4 * (3 * kl + 4));
         P.o_dwg = o; o = align256(o + 4 * ((size_t)DF_MAX_WG + 1 + P.df_ntasks));
     }
-    if (prm.pivot_qr && !is_complex && !mixed) {
-        const size_t tri = 8 * (size_t)P.npairs * 2 * pivot_qr_tiles(P) * P.W2 * P.W2;
+    if (prm.pivot_qr && !mixed) {
+        const size_t tri = P.esz * (size_t)P.npairs * 2 * pivot_qr_tiles(P) * P.W2 * P.W2;
         P.o_qr[0] = o; o = align256(o + tri);
         P.o_qr[1] = o; o = align256(o + tri);
     }
@@ -519,7 +519,7 @@ static int solve_entry(int kind, const hz_params *p, int64_t m_f, int64_t m_g, i
     if (kind == KIND_MIXED && (prm.max_fp32_sweeps < 0 || !(prm.mixed_switch >= 0.0))) return -1;
     if (prm.qr_shorten && n > 1 && !shorten_cpt(n)) return -1;
     if (is_complex && (prm.variant & 1)) return -1;   // enhanced dot products: real only
-    if (prm.pivot_qr && kind != KIND_REAL) return -1;
+    if (prm.pivot_qr && kind == KIND_MIXED) return -1;
     const int a = check_args(m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g);
     if (a) return a;
     if (is_complex && (((uintptr_t)F | (uintptr_t)G | (uintptr_t)Z) & 15))
@@ -570,7 +570,7 @@ static size_t work_size_entry(int kind, const hz_params *p, int64_t m_f, int64_t
     if (!params_ok(prm) || !w_ok_for(prm, is_complex) || m_f < n || m_g < n || n < 1) return 0;
     if (prm.qr_shorten && n > 1 && !shorten_cpt(n)) return 0;
     if (is_complex && (prm.variant & 1)) return 0;
-    if (prm.pivot_qr && kind != KIND_REAL) return 0;
+    if (prm.pivot_qr && kind == KIND_MIXED) return 0;
     if (n == 1) return 256;
     Plan P;
     if (prm.qr_shorten) {

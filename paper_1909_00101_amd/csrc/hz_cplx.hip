@@ -173,9 +173,9 @@ __global__ __launch_bounds__(256) void k_gram_sum_z(const d2 *__restrict__ part,
 // interleaved complex in LDS.
 template <int W2, int LP>
 __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
-    const d2 *__restrict__ gram, int npairs, int step, const int16_t *__restrict__ itab,
-    int isteps, int inner_max, double tol, int sort, int variant, d2 *__restrict__ Zt,
-    unsigned long long *__restrict__ cnt, int *__restrict__ status)
+    const d2 *__restrict__ gram, int factors, int npairs, int step,
+    const int16_t *__restrict__ itab, int isteps, int inner_max, double tol, int sort, int variant,
+    d2 *__restrict__ Zt, unsigned long long *__restrict__ cnt, int *__restrict__ status)
 {
     constexpr int W = W2 / 2;
     constexpr int NT = W * LP;
@@ -206,7 +206,16 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
     __syncthreads();
 
     // Hermitian Cholesky, lane = row, A in lanes 0..31 and B in 32..63 of wave 0.
-    {
+    // With `factors` the blocks are already the upper triangular factors (QR
+    // of the block-column pairs, real diagonal): only the diagonals are
+    // checked for zeros and non-finite values.
+    if (factors) {
+        if (tid < W2) {
+            const double df = sF[tid * LDI + tid][0], dg = sG[tid * LDI + tid][0];
+            if (!(fabs(df) > 0.0 && fabs(df) < INFINITY && fabs(dg) > 0.0 && fabs(dg) < INFINITY))
+                s_fail = 1;
+        }
+    } else {
         const int mat = lane >> 5, i = lane & 31;
         if (wave == 0 && i < W2) {
             d2 *M = mat ? sG : sF;
@@ -592,27 +601,32 @@ static void step_impl_z(const Plan &P, const Ptrs &W, int step, const hz_params 
 {
     const int *pairs = W.otab + (size_t)step * P.npairs * 2;
     prof_mark(K_GRAM, true, s);
-    hipLaunchKernelGGL(k_gram_z<W2>, dim3(P.splits, P.npairs, 2), dim3(256), 0, s,
-                       (const d2 *)W.Fw, (const d2 *)W.Gw, P.mfw, P.mgw, pairs, P.splits,
-                       (d2 *)W.part);
-    hipLaunchKernelGGL(k_gram_sum_z<W2>, dim3((W2 * W2 + 255) / 256, 2 * P.npairs), dim3(256), 0,
-                       s, (const d2 *)W.part, P.splits, (d2 *)W.gram);
+    const int fac = prm.pivot_qr ? 1 : 0;
+    if (fac) {
+        launch_pivot_qr(P, W, step, s);
+    } else {
+        hipLaunchKernelGGL(k_gram_z<W2>, dim3(P.splits, P.npairs, 2), dim3(256), 0, s,
+                           (const d2 *)W.Fw, (const d2 *)W.Gw, P.mfw, P.mgw, pairs, P.splits,
+                           (d2 *)W.part);
+        hipLaunchKernelGGL(k_gram_sum_z<W2>, dim3((W2 * W2 + 255) / 256, 2 * P.npairs),
+                           dim3(256), 0, s, (const d2 *)W.part, P.splits, (d2 *)W.gram);
+    }
     prof_mark(K_GRAM, false, s);
     prof_mark(K_INNER, true, s);
     if constexpr (W2 == 32) {
         if (P.inner_lp == 16)
             hipLaunchKernelGGL((k_inner_z<W2, 16>), dim3(P.npairs), dim3((W2 / 2) * 16), 0, s,
-                               (const d2 *)W.gram, P.npairs, step, W.itab, P.isteps,
+                               (const d2 *)W.gram, fac, P.npairs, step, W.itab, P.isteps,
                                prm.inner_max_sweeps, tol, prm.sort, prm.variant, (d2 *)W.Zt, W.cnt,
                                W.status);
         else
             hipLaunchKernelGGL((k_inner_z<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s,
-                               (const d2 *)W.gram, P.npairs, step, W.itab, P.isteps,
+                               (const d2 *)W.gram, fac, P.npairs, step, W.itab, P.isteps,
                                prm.inner_max_sweeps, tol, prm.sort, prm.variant, (d2 *)W.Zt, W.cnt,
                                W.status);
     } else {
         hipLaunchKernelGGL((k_inner_z<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s,
-                           (const d2 *)W.gram, P.npairs, step, W.itab, P.isteps,
+                           (const d2 *)W.gram, fac, P.npairs, step, W.itab, P.isteps,
                            prm.inner_max_sweeps, tol, prm.sort, prm.variant, (d2 *)W.Zt, W.cnt,
                                W.status);
     }

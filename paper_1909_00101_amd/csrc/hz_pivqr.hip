@@ -41,102 +41,180 @@ struct QRLevel {
 
 // Thread t owns column t / Q of the tile, rows t % Q, t % Q + Q, ... (RPQ
 // of them) in registers.  Step k: the Q owners of column k form the
-// reflector H = I - tau v v^T (v_k = 1) that maps the column to
-// (beta, 0, ..., 0) and publish v and tau in LDS (two buffers, so one
-// barrier per step); the owners of the columns right of k apply H to their
-// rows.  Sums over a column use a fixed reduction order.
-template <int W2>
+// reflector H = I - tau v v^H (v_k = 1) with H^H x = (beta, 0, ..., 0),
+// beta real (for real data the transpose and a real tau), and publish v and
+// tau in LDS (two buffers, so one barrier per step); the owners of the
+// columns right of k apply H^H = I - conj(tau) v v^H to their rows.  Sums
+// over a column use a fixed reduction order.  Complex elements are
+// interleaved (CX).
+template <int W2, bool CX>
 __global__ __launch_bounds__(256) void k_qr_tile(QRLevel a)
 {
     constexpr int CH = 2 * W2;          // tile rows
     constexpr int NT = 256;
     constexpr int Q = NT / W2;          // threads per column
     constexpr int RPQ = CH / Q;         // rows per thread
+    constexpr int NP = CX ? 2 : 1;      // planes (real, imaginary)
     static_assert(Q >= 1 && (64 % Q) == 0 && RPQ % 2 == 0, "bad QR tile geometry");
-    __shared__ double s_v[2][CH];
-    __shared__ double s_tau[2];
+    __shared__ double s_v[2][NP][CH];
+    __shared__ double s_tau[2][NP];
     const int mt = blockIdx.z, l = blockIdx.y, c = blockIdx.x;
     if (c >= (mt ? a.nodes_g : a.nodes_f)) return;   // uniform: the grid covers the larger
     const int tid = threadIdx.x;
     const int jc = tid / Q, q = tid % Q;
-    double x[RPQ];
+    double x[NP][RPQ];
     if (a.level == 0) {
         const double *__restrict__ Y = mt ? a.Gw : a.Fw;
         const int64_t m = mt ? a.mgw : a.mfw;
         const int W = W2 / 2;
         const int p = a.pairs[2 * l], qq = a.pairs[2 * l + 1];
         const int64_t gc = (jc < W) ? (int64_t)p * W + jc : (int64_t)qq * W + (jc - W);
-        const double *col = Y + gc * m;
+        const double *col = Y + NP * gc * m;
 #pragma unroll
         for (int i = 0; i < RPQ; ++i) {
             const int64_t gr = (int64_t)c * CH + q + Q * i;
-            x[i] = (gr < m) ? col[gr] : 0.0;
+#pragma unroll
+            for (int pl = 0; pl < NP; ++pl) x[pl][i] = (gr < m) ? col[NP * gr + pl] : 0.0;
         }
     } else {
         const int prev = mt ? a.prev_g : a.prev_f;
         const double *__restrict__ ra =
-            a.in + (((size_t)l * 2 + mt) * a.in_stride + 2 * (size_t)c) * (W2 * W2);
+            a.in + NP * (((size_t)l * 2 + mt) * a.in_stride + 2 * (size_t)c) * (W2 * W2);
         const bool second = 2 * c + 1 < prev;
 #pragma unroll
         for (int i = 0; i < RPQ; ++i) {
             const int r = q + Q * i;
-            double v = 0.0;
-            if (r < W2) v = ra[jc * W2 + r];
-            else if (second) v = ra[W2 * W2 + jc * W2 + (r - W2)];
-            x[i] = v;
+#pragma unroll
+            for (int pl = 0; pl < NP; ++pl) {
+                double v = 0.0;
+                if (r < W2) v = ra[NP * (jc * W2 + r) + pl];
+                else if (second) v = ra[NP * (W2 * W2 + jc * W2 + (r - W2)) + pl];
+                x[pl][i] = v;
+            }
         }
     }
     for (int k = 0; k < W2; ++k) {
         const int par = k & 1;
         if (jc == k) {
-            double sq = 0.0, al = 0.0;
+            double sq = 0.0, al[NP];
+#pragma unroll
+            for (int pl = 0; pl < NP; ++pl) al[pl] = 0.0;
 #pragma unroll
             for (int i = 0; i < RPQ; ++i) {
                 const int r = q + Q * i;
-                if (r > k) sq = fma(x[i], x[i], sq);
-                if (r == k) al = x[i];
+                if (r > k) {
+#pragma unroll
+                    for (int pl = 0; pl < NP; ++pl) sq = fma(x[pl][i], x[pl][i], sq);
+                }
+                if (r == k) {
+#pragma unroll
+                    for (int pl = 0; pl < NP; ++pl) al[pl] = x[pl][i];
+                }
             }
 #pragma unroll
             for (int off = Q / 2; off >= 1; off >>= 1) {
                 sq += __shfl_xor(sq, off);
-                al += __shfl_xor(al, off);       // one nonzero term: exact
+#pragma unroll
+                for (int pl = 0; pl < NP; ++pl) al[pl] += __shfl_xor(al[pl], off);   // exact
             }
-            double beta = al, tau = 0.0, scale = 0.0;
-            if (sq > 0.0) {
-                beta = -copysign(sqrt(fma(al, al, sq)), al);
-                tau = (beta - al) / beta;
-                scale = 1.0 / (al - beta);
+            const double ali = CX ? al[NP - 1] : 0.0;
+            double beta = al[0], tau[NP], scale[NP];
+#pragma unroll
+            for (int pl = 0; pl < NP; ++pl) tau[pl] = scale[pl] = 0.0;
+            if (sq > 0.0 || ali != 0.0) {
+                beta = -copysign(sqrt(fma(al[0], al[0], fma(ali, ali, sq))), al[0]);
+                tau[0] = (beta - al[0]) / beta;
+                if constexpr (CX) {
+                    tau[NP - 1] = -ali / beta;
+                    // 1 / (alpha - beta)
+                    const double dr = al[0] - beta, di = ali;
+                    const double den = fma(dr, dr, di * di);
+                    scale[0] = dr / den;
+                    scale[NP - 1] = -di / den;
+                } else {
+                    scale[0] = 1.0 / (al[0] - beta);
+                }
             }
 #pragma unroll
             for (int i = 0; i < RPQ; ++i) {
                 const int r = q + Q * i;
-                s_v[par][r] = (r == k) ? 1.0 : ((r > k) ? x[i] * scale : 0.0);
-                if (r == k) x[i] = beta;
+                if constexpr (CX) {
+                    double vr = 0.0, vi = 0.0;
+                    if (r == k) vr = 1.0;
+                    else if (r > k) {
+                        vr = x[0][i] * scale[0] - x[NP - 1][i] * scale[NP - 1];
+                        vi = x[0][i] * scale[NP - 1] + x[NP - 1][i] * scale[0];
+                    }
+                    s_v[par][0][r] = vr;
+                    s_v[par][NP - 1][r] = vi;
+                    if (r == k) {
+                        x[0][i] = beta;
+                        x[NP - 1][i] = 0.0;
+                    }
+                } else {
+                    s_v[par][0][r] = (r == k) ? 1.0 : ((r > k) ? x[0][i] * scale[0] : 0.0);
+                    if (r == k) x[0][i] = beta;
+                }
             }
-            if (q == 0) s_tau[par] = tau;
+            if (q == 0) {
+#pragma unroll
+                for (int pl = 0; pl < NP; ++pl) s_tau[par][pl] = tau[pl];
+            }
         }
         __syncthreads();
-        const double tau = s_tau[par];
-        if (tau != 0.0 && jc > k) {
-            double w0 = 0.0, w1 = 0.0;
+        const double tr = s_tau[par][0], ti = CX ? s_tau[par][NP - 1] : 0.0;
+        if ((tr != 0.0 || ti != 0.0) && jc > k) {
+            if constexpr (CX) {
+                // w = v^H a_j, then a_j -= conj(tau) w v
+                double wr0 = 0.0, wr1 = 0.0, wi0 = 0.0, wi1 = 0.0;
 #pragma unroll
-            for (int i = 0; i < RPQ; i += 2) {
-                w0 = fma(s_v[par][q + Q * i], x[i], w0);
-                w1 = fma(s_v[par][q + Q * (i + 1)], x[i + 1], w1);
+                for (int i = 0; i < RPQ; i += 2) {
+                    const int r = q + Q * i, r1 = q + Q * (i + 1);
+                    const double v0r = s_v[par][0][r], v0i = s_v[par][NP - 1][r];
+                    const double v1r = s_v[par][0][r1], v1i = s_v[par][NP - 1][r1];
+                    wr0 = fma(v0r, x[0][i], fma(v0i, x[NP - 1][i], wr0));
+                    wi0 = fma(v0r, x[NP - 1][i], fma(-v0i, x[0][i], wi0));
+                    wr1 = fma(v1r, x[0][i + 1], fma(v1i, x[NP - 1][i + 1], wr1));
+                    wi1 = fma(v1r, x[NP - 1][i + 1], fma(-v1i, x[0][i + 1], wi1));
+                }
+                double wr = wr0 + wr1, wi = wi0 + wi1;
+#pragma unroll
+                for (int off = Q / 2; off >= 1; off >>= 1) {
+                    wr += __shfl_xor(wr, off);
+                    wi += __shfl_xor(wi, off);
+                }
+                const double cr = tr * wr + ti * wi, ci = tr * wi - ti * wr;   // conj(tau) w
+#pragma unroll
+                for (int i = 0; i < RPQ; ++i) {
+                    const int r = q + Q * i;
+                    const double vr = s_v[par][0][r], vi = s_v[par][NP - 1][r];
+                    x[0][i] -= cr * vr - ci * vi;
+                    x[NP - 1][i] -= cr * vi + ci * vr;
+                }
+            } else {
+                double w0 = 0.0, w1 = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPQ; i += 2) {
+                    w0 = fma(s_v[par][0][q + Q * i], x[0][i], w0);
+                    w1 = fma(s_v[par][0][q + Q * (i + 1)], x[0][i + 1], w1);
+                }
+                double w = w0 + w1;
+#pragma unroll
+                for (int off = Q / 2; off >= 1; off >>= 1) w += __shfl_xor(w, off);
+                const double tw = tr * w;
+#pragma unroll
+                for (int i = 0; i < RPQ; ++i) x[0][i] = fma(-tw, s_v[par][0][q + Q * i], x[0][i]);
             }
-            double w = w0 + w1;
-#pragma unroll
-            for (int off = Q / 2; off >= 1; off >>= 1) w += __shfl_xor(w, off);
-            const double tw = tau * w;
-#pragma unroll
-            for (int i = 0; i < RPQ; ++i) x[i] = fma(-tw, s_v[par][q + Q * i], x[i]);
         }
     }
-    double *__restrict__ R = a.out + (((size_t)l * 2 + mt) * a.out_stride + c) * (W2 * W2);
+    double *__restrict__ R = a.out + NP * (((size_t)l * 2 + mt) * a.out_stride + c) * (W2 * W2);
 #pragma unroll
     for (int i = 0; i < RPQ; ++i) {
         const int r = q + Q * i;
-        if (r < W2) R[jc * W2 + r] = (r <= jc) ? x[i] : 0.0;
+        if (r < W2) {
+#pragma unroll
+            for (int pl = 0; pl < NP; ++pl) R[NP * (jc * W2 + r) + pl] = (r <= jc) ? x[pl][i] : 0.0;
+        }
     }
 }
 
@@ -147,7 +225,7 @@ int pivot_qr_tiles(const Plan &P)
     return (int)((m + ch - 1) / ch);
 }
 
-template <int W2>
+template <int W2, bool CX>
 static void pivot_qr_impl(const Plan &P, const Ptrs &W, int step, hipStream_t s)
 {
     constexpr int64_t CH = 2 * W2;
@@ -172,7 +250,7 @@ static void pivot_qr_impl(const Plan &P, const Ptrs &W, int step, hipStream_t s)
         a.in_stride = L0;
         a.out = last ? W.gram : W.qr[level & 1];
         a.out_stride = last ? 1 : L0;
-        hipLaunchKernelGGL(k_qr_tile<W2>, dim3((unsigned)(nf > ng ? nf : ng), P.npairs, 2),
+        hipLaunchKernelGGL((k_qr_tile<W2, CX>), dim3((unsigned)(nf > ng ? nf : ng), P.npairs, 2),
                            dim3(256), 0, s, a);
         if (last) break;
         in = a.out;
@@ -185,13 +263,19 @@ static void pivot_qr_impl(const Plan &P, const Ptrs &W, int step, hipStream_t s)
 }
 
 // The pivot factors of every block pair of one step into W.gram (per pair:
-// R_F, then R_G, W2 x W2 upper triangular).
+// R_F, then R_G, W2 x W2 upper triangular; interleaved complex for complex
+// pairs, with a real diagonal).
 void launch_pivot_qr(const Plan &P, const Ptrs &W, int step, hipStream_t s)
 {
+    if (P.is_complex) {
+        if (P.W2 == 16) pivot_qr_impl<16, true>(P, W, step, s);
+        else pivot_qr_impl<32, true>(P, W, step, s);
+        return;
+    }
     switch (P.W2) {
-    case 16: pivot_qr_impl<16>(P, W, step, s); break;
-    case 32: pivot_qr_impl<32>(P, W, step, s); break;
-    default: pivot_qr_impl<64>(P, W, step, s); break;
+    case 16: pivot_qr_impl<16, false>(P, W, step, s); break;
+    case 32: pivot_qr_impl<32, false>(P, W, step, s); break;
+    default: pivot_qr_impl<64, false>(P, W, step, s); break;
     }
 }
 

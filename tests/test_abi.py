@@ -302,24 +302,24 @@ def test_enhanced_variants_real_only(hz):
 
 
 def test_pivot_qr_sizes_and_rejections(hz):
-    """QR pivot factors (pivot_qr = 1) belong to the real FP64 solver with the
-    per-step schedule: more workspace there (the QR tree levels); rejected on
-    the host by the complex, mixed and batched solvers and with the dataflow
-    schedule."""
+    """QR pivot factors (pivot_qr = 1) belong to the real and complex solvers
+    with the per-step schedule: more workspace there (the QR tree levels);
+    rejected on the host by the mixed and batched solvers and with the
+    dataflow schedule."""
     L = hz.lib()
     v = ctypes.c_void_p(256)
     p = hz.params(pivot_qr=1, w=32)
     plain = L.hz_dgsvd_work_size(ctypes.byref(hz.params(w=32)), 4096, 4096, 1024)
     assert L.hz_dgsvd_work_size(ctypes.byref(p), 4096, 4096, 1024) > plain
-    assert L.hz_zgsvd_work_size(ctypes.byref(hz.params(pivot_qr=1)), 64, 64, 32) == 0
+    assert L.hz_zgsvd_work_size(ctypes.byref(hz.params(pivot_qr=1)), 64, 64, 32) > \
+        L.hz_zgsvd_work_size(ctypes.byref(hz.params()), 64, 64, 32)
     assert L.hz_dgsvd_mixed_work_size(ctypes.byref(p), 64, 64, 32) == 0
     assert L.hz_dgsvd_work_size(ctypes.byref(hz.params(pivot_qr=1, w=32,
                                                        schedule=hz.HZ_SCHED_DATAFLOW)),
                                 64, 64, 64) == 0
     assert L.hz_dgsvd_work_size(ctypes.byref(hz.params(pivot_qr=2)), 64, 64, 32) == 0
-    for fn in (L.hz_zgsvd, L.hz_dgsvd_mixed):
-        assert fn(ctypes.byref(hz.params(pivot_qr=1)), 64, 64, 32, v, 64, v, 64, v, 32, v, v, v,
-                  None, 0, None, None) == -1
+    assert L.hz_dgsvd_mixed(ctypes.byref(hz.params(pivot_qr=1)), 64, 64, 32, v, 64, v, 64, v,
+                            32, v, v, v, None, 0, None, None) == -1
     i64 = lambda vals: (ctypes.c_int64 * len(vals))(*vals)
     assert L.hz_dgsvd_batched_work_size(ctypes.byref(p), 1, i64([64]), i64([64]),
                                         i64([32])) == 0
