@@ -83,10 +83,11 @@ typedef struct hz_params {
                              C1 (scaled cosines equal 1), 4 = by criterion C2 (unscaled
                              cosines equal 1), Section 2.5, both with ordinary dot
                              products; 1 and 5 = 0 and 4 with the enhanced dot products
-                             of Appendix A for the pointwise pivot entries a_ii, a_jj,
-                             a_ij, b_ij of the inner solver (products rounded toward
-                             -infinity and their non-negative errors summed apart; real
-                             solvers only) */
+                             of Appendix A for the pointwise pivot entries of the inner
+                             solver: real pairs a_ii, a_jj, a_ij, b_ij (products rounded
+                             toward -infinity and their non-negative errors summed apart),
+                             complex pairs the squared norms a_ii, a_jj by the appendix's
+                             simpler procedure (a_ij, b_ij ordinary) */
     int ordering;         /* outer block ordering, HZ_ORD_MM (default) or HZ_ORD_RR */
     int inner_ordering;   /* pointwise ordering inside a block pair (default HZ_ORD_RR) */
     int w;                /* block-column width: 0 = default, else 8, 16 or 32 */

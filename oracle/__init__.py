@@ -61,6 +61,8 @@ def _load():
         lib.hzo_edot.restype = ctypes.c_double
         lib.hzo_mul_rd.argtypes = [ctypes.c_double, ctypes.c_double, dp, dp]
         lib.hzo_mul_rd.restype = None
+        lib.hzo_enh_abs2.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.hzo_enh_abs2.restype = ctypes.c_double
         lib.hzo_ordering.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         lib.hzo_ordering.restype = ctypes.c_int
         _lib = lib
@@ -78,9 +80,9 @@ def gsvd(F, G, *, ordering=ORD_ROWCYCLIC, tol=0.0, max_sweeps=30, sort=True, thr
     Returns a dict with U, V, Z (Fortran-ordered), sigma, sigma_f, sigma_g
     (descending in sigma), sweeps, rot_all, rot_big, converged, status.
     tol <= 0 selects sqrt(n)*eps.  variant 0 classifies small transformations
-    by criterion C1, variant 4 by criterion C2 (Section 2.5, Table 1); for
-    real pairs variants 1 and 5 are 0 and 4 with the enhanced dot products of
-    Appendix A.
+    by criterion C1, variant 4 by criterion C2 (Section 2.5, Table 1);
+    variants 1 and 5 are 0 and 4 with the enhanced dot products of Appendix
+    A (complex pairs: the squared norms only).
     F and G are copied, not modified.
     """
     lib = _load()
@@ -135,6 +137,11 @@ def edot(x, y):
     x = np.ascontiguousarray(x, dtype=np.float64)
     y = np.ascontiguousarray(y, dtype=np.float64)
     return float(_load().hzo_edot(len(x), _dptr(x), _dptr(y)))
+
+
+def enh_abs2(z):
+    """|z|^2 by the simpler complex procedure of Appendix A."""
+    return float(_load().hzo_enh_abs2(float(np.real(z)), float(np.imag(z))))
 
 
 def mul_rd(a, b):

@@ -26,10 +26,13 @@
  *   Section 2.5 : big/small classification (criteria C1 and C2) and the stop rule
  *                 "no big transformation in a sweep".
  *   Table 1     : variant 0 (C1, prescaled, ordinary dot products),
- *                 variant 4 (the same with criterion C2), and for real
- *                 pairs variants 1 and 5 (0 and 4 with the enhanced dot
- *                 products of Appendix A for the pivot entries a_ii, a_jj,
- *                 a_ij, b_ij).
+ *                 variant 4 (the same with criterion C2), and variants 1
+ *                 and 5 (0 and 4 with the enhanced dot products of
+ *                 Appendix A: for real pairs all the pivot entries a_ii,
+ *                 a_jj, a_ij, b_ij; for complex pairs the squared norms
+ *                 a_ii, a_jj by the appendix's simpler procedure, the
+ *                 off-diagonal entries, for which it defines none,
+ *                 ordinary).
  *
  * Readings of passages that are silent, garbled or inconsistent (each one is
  * also listed in the design notes of the repository):
@@ -122,6 +125,29 @@ static zdouble dot_zz(const zdouble *x, const zdouble *y, int64_t m)
         s += conj(x[r]) * y[r];
     return s;
 }
+
+/* Squared norm of a complex column by the simpler procedure of Appendix A:
+ * per entry the rounded-down squares of the real and the imaginary part,
+ * c_r and c_i, and the sum e of their errors, combined as (e + min) + max
+ * of the two squares, and these summed. */
+static double enh_abs2(zdouble a)
+{
+    const double re = creal(a), im = cimag(a);
+    const double cr = mul_rd(re, re), ci = mul_rd(im, im);
+    const double e = fma(re, re, -cr) + fma(im, im, -ci);
+    return (cr <= ci) ? (e + cr) + ci : (e + ci) + cr;
+}
+
+static double nrm2sq_z_enh(const zdouble *x, int64_t m)
+{
+    double s = 0.0;
+    for (int64_t r = 0; r < m; ++r)
+        s += enh_abs2(x[r]);
+    return s;
+}
+
+/* Exported for the tests: enh_abs2 of re + i im. */
+double hzo_enh_abs2(double re, double im) { return enh_abs2(CMPLX(re, im)); }
 
 static double nrm2sq_z(const zdouble *x, int64_t m)
 {
@@ -581,8 +607,10 @@ static void step_cplx(int64_t m_f, int64_t m_g, int64_t n, zdouble *F, int64_t l
                       int64_t *all, int64_t *big)
 {
     zdouble *fi = F + i * ldf, *fj = F + j * ldf;
-    const double aii = nrm2sq_z(fi, m_f);
-    const double ajj = nrm2sq_z(fj, m_f);
+    double (*nrm)(const zdouble *, int64_t) =
+        (variant == 1 || variant == 5) ? nrm2sq_z_enh : nrm2sq_z;
+    const double aii = nrm(fi, m_f);
+    const double ajj = nrm(fj, m_f);
     const zdouble aij = dot_zz(fi, fj, m_f);
     const zdouble bij = dot_zz(G + i * ldg, G + j * ldg, m_g);
     const double abs_a = hypot(creal(aij), cimag(aij));
@@ -623,7 +651,7 @@ int hzo_zgsvd(int64_t m_f, int64_t m_g, int64_t n,
 {
     zdouble *F = (zdouble *)Fd, *G = (zdouble *)Gd, *Z = (zdouble *)Zd;
     if (n < 1 || m_f < n || m_g < n || ldf < m_f || ldg < m_g || ldz < n ||
-        (variant != 0 && variant != 4))
+        (variant != 0 && variant != 1 && variant != 4 && variant != 5))
         return -1;
     info[0] = info[1] = info[2] = 0;
     info[3] = 1;

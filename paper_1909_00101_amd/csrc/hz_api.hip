@@ -518,7 +518,6 @@ static int solve_entry(int kind, const hz_params *p, int64_t m_f, int64_t m_g, i
     if (!params_ok(prm) || !w_ok_for(prm, is_complex)) return -1;
     if (kind == KIND_MIXED && (prm.max_fp32_sweeps < 0 || !(prm.mixed_switch >= 0.0))) return -1;
     if (prm.qr_shorten && n > 1 && !shorten_cpt(n)) return -1;
-    if (is_complex && (prm.variant & 1)) return -1;   // enhanced dot products: real only
     if (prm.pivot_qr && kind == KIND_MIXED) return -1;
     const int a = check_args(m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g);
     if (a) return a;
@@ -569,7 +568,6 @@ static size_t work_size_entry(int kind, const hz_params *p, int64_t m_f, int64_t
     if (p) prm = *p; else hz_default_params(&prm);
     if (!params_ok(prm) || !w_ok_for(prm, is_complex) || m_f < n || m_g < n || n < 1) return 0;
     if (prm.qr_shorten && n > 1 && !shorten_cpt(n)) return 0;
-    if (is_complex && (prm.variant & 1)) return 0;
     if (prm.pivot_qr && kind == KIND_MIXED) return 0;
     if (n == 1) return 256;
     Plan P;

@@ -306,10 +306,23 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
                 zj[r] = sZ[cj * LDI + r0 + r];
             }
             double aii = 0.0, ajj = 0.0, ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+            if (variant & 1) {
+                // variants 1 and 5: squared norms by the enhanced procedure
+                // of Appendix A (the off-diagonal entries stay ordinary)
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) {
+                    aii += enh_abs2(fi[r][0], fi[r][1]);
+                    ajj += enh_abs2(fj[r][0], fj[r][1]);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) {
+                    aii = fma(fi[r][0], fi[r][0], fma(fi[r][1], fi[r][1], aii));
+                    ajj = fma(fj[r][0], fj[r][0], fma(fj[r][1], fj[r][1], ajj));
+                }
+            }
 #pragma unroll
             for (int r = 0; r < RPL; ++r) {
-                aii = fma(fi[r][0], fi[r][0], fma(fi[r][1], fi[r][1], aii));
-                ajj = fma(fj[r][0], fj[r][0], fma(fj[r][1], fj[r][1], ajj));
                 ar = fma(fi[r][0], fj[r][0], fma(fi[r][1], fj[r][1], ar));
                 ai = fma(fi[r][0], fj[r][1], fma(-fi[r][1], fj[r][0], ai));
                 br = fma(gi[r][0], gj[r][0], fma(gi[r][1], gj[r][1], br));
@@ -332,8 +345,8 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
                 hz_cplx_2x2_fast(aii, ajj, ar, ai, br, bi, z11, z21r, z21i, z12r, z12i, z22,
                                  c2small);
                 sw_all += 1;
-                // small: criterion C1 (variant 0) or C2 (variant 4), Section 2.5
-                if (variant == 4 ? !c2small : !(z11 == 1.0 && z22 == 1.0)) sw_big += 1;
+                // small: criterion C1 (variants 0, 1) or C2 (variants 4, 5), Section 2.5
+                if ((variant & 4) ? !c2small : !(z11 == 1.0 && z22 == 1.0)) sw_big += 1;
                 swap = false;
                 if (sort) {
                     // diagonal of Z^H A Z

@@ -312,6 +312,17 @@ __device__ __forceinline__ double mul_rd(double a, double b)
     return __longlong_as_double(bits);
 }
 
+// |re + i im|^2 by the simpler complex procedure of Appendix A: the
+// rounded-down squares c_r, c_i and the sum e of their errors, combined as
+// (e + min(c_r, c_i)) + max(c_r, c_i).
+__device__ __forceinline__ double enh_abs2(double re, double im)
+{
+#pragma clang fp contract(off)
+    const double cr = mul_rd(re, re), ci = mul_rd(im, im);
+    const double e = fma(re, re, -cr) + fma(im, im, -ci);
+    return (cr <= ci) ? (e + cr) + ci : (e + ci) + cr;
+}
+
 // Accumulate a*b into the pair (sum of rounded-down products, sum of their
 // non-negative rounding errors).
 __device__ __forceinline__ void edot_acc(double a, double b, double &sc, double &sd)

@@ -3,7 +3,7 @@ Appendix A): the inner solver forms the pointwise pivot entries from
 products rounded toward -infinity and their non-negative errors, summed
 apart.  Checked: the device's rounded-down product and error term bit for
 bit against the oracle's (both are exact by definition), sigma against the
-oracle's run of the same variant (1e-10 relative, the bar of the plain
+oracle's run of the same variant (real and complex pairs) (1e-10 relative, the bar of the plain
 path) and the output contract, in the single-pair, batched, mixed and
 dataflow forms; and that the variant reaches the kernel (the bits differ
 from those of variants 0 and 4)."""
@@ -109,3 +109,23 @@ def test_enhanced_dataflow_matches_steps():
     assert a["status"] == 0 and b["status"] == 0
     for k in ("sigma", "U", "V", "Z"):
         assert np.array_equal(a[k], b[k])
+
+
+@pytest.mark.parametrize("variant", [1, 5])
+@pytest.mark.parametrize("shape,w", [((120, 90, 32), 8), ((300, 200, 100), 16)])
+def test_enhanced_complex_parity(variant, shape, w):
+    """Complex pairs: the squared norms by the simpler procedure of Appendix
+    A, the off-diagonal entries ordinary."""
+    import oracle
+    m_f, m_g, n = shape
+    F, G, s_true = gi.custom_pair(m_f, m_g, n, kappa=1e2, is_complex=True, seed=870 + n)
+    print(f"enhanced complex variant {variant} {shape} w={w}", flush=True)
+    r = _run(F, G, w=w, variant=variant, ordering=_hz().HZ_ORD_MM)
+    assert r["status"] == 0 and r["converged"]
+    o = oracle.gsvd(F, G, variant=variant, ordering=oracle.ORD_MM, threads=4)
+    assert max_rel(r["sigma"], o["sigma"]) < SIG_TOL
+    assert max_rel(r["sigma"], s_true) < SIG_TOL
+    assert_contract(F, G, r["U"], r["V"], r["Z"], r["sigma_f"], r["sigma_g"], r["sigma"],
+                    tol_res=1e-12, tol_orth=1e-12)
+    p = _run(F, G, w=w, variant=variant & 4, ordering=_hz().HZ_ORD_MM)
+    assert not np.array_equal(p["Z"], r["Z"])

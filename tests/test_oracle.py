@@ -527,8 +527,32 @@ def test_enhanced_variants_same_gsvd(v_enh, v_plain):
     assert not np.array_equal(e["Z"], p["Z"])
 
 
-def test_enhanced_variants_real_only():
-    F, G, _ = gi.custom_pair(20, 20, 6, is_complex=True, seed=815)
-    for v in (1, 5):
-        with pytest.raises(ValueError):
-            oracle.gsvd(F, G, variant=v)
+def test_enh_abs2_complex_norm_procedure():
+    """The simpler complex procedure of Appendix A: exact where the squares
+    are, and within 1 ulp of the exact |z|^2 on random and crafted entries
+    (dropping the error terms of the rounded-down squares costs up to 2
+    ulp on the crafted ones)."""
+    from fractions import Fraction
+    assert oracle.enh_abs2(3 + 4j) == 25.0 and oracle.enh_abs2(-12 + 5j) == 169.0
+    rng = np.random.default_rng(816)
+    n = 4000
+    zs = list(rng.standard_normal(n) * 2.0 ** rng.integers(-30, 30, n)
+              + 1j * rng.standard_normal(n) * 2.0 ** rng.integers(-30, 30, n))
+    zs += [complex(1.0 + k * 2.0 ** -40, 0.0) for k in range(1, 500)]
+    zs += [complex(1.0 + k * 2.0 ** -40, 0.75 + k * 2.0 ** -41) for k in range(1, 500)]
+    for z in zs:
+        exact = Fraction(z.real) ** 2 + Fraction(z.imag) ** 2
+        err = abs(Fraction(oracle.enh_abs2(z)) - exact)
+        assert err <= Fraction(float(np.spacing(float(exact))))
+
+
+@pytest.mark.parametrize("v_enh,v_plain", [(1, 0), (5, 4)])
+def test_enhanced_variants_complex_same_gsvd(v_enh, v_plain):
+    F, G, s_true = gi.custom_pair(120, 90, 32, kappa=1e2, is_complex=True, seed=817)
+    e = oracle.gsvd(F, G, variant=v_enh, ordering=oracle.ORD_MM, threads=2)
+    p = oracle.gsvd(F, G, variant=v_plain, ordering=oracle.ORD_MM, threads=2)
+    assert e["status"] == 0 and e["converged"]
+    assert np.max(np.abs(e["sigma"] - p["sigma"]) / p["sigma"]) < 1e-12
+    assert np.max(np.abs(e["sigma"] - s_true) / s_true) < 1e-12
+    assert_contract(F, G, e["U"], e["V"], e["Z"], e["sigma_f"], e["sigma_g"], e["sigma"])
+    assert not np.array_equal(e["Z"], p["Z"])
