@@ -10,7 +10,10 @@ namespace hz {
 
 // LDS (doubles) each body needs; the caller provides it, so one kernel can
 // run several bodies over a single allocation.
-template <int W2> constexpr int gram_lds() { return W2 * 66; }
+// (gram: 64-row chunks of W2 columns with stride 66, then the waves'
+// partial blocks summed with stride W2 + 2, which puts the 16 lanes of a
+// tile row in distinct banks)
+template <int W2> constexpr int gram_lds() { return W2 * 66 > W2 * (W2 + 2) ? W2 * 66 : W2 * (W2 + 2); }
 template <int W2> constexpr int update_lds() { return W2 * (W2 + 1); }
 template <int W2> constexpr int inner_lds()
 {
@@ -82,7 +85,8 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
             }
         }
     }
-    // Sum the waves' partial tiles in wave order (tile reused, ld W2).
+    // Sum the waves' partial tiles in wave order (tile reused, ld W2 + 2).
+    constexpr int LDSUM = W2 + 2;
     for (int wv = 0; wv < NW; ++wv) {
         __syncthreads();
         if (wave == wv) {
@@ -94,7 +98,7 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int gi = 16 * a + 4 * r + (lane >> 4), gj = 16 * b + (lane & 15);
-                        double *dst = tile + gj * W2 + gi;
+                        double *dst = tile + gj * LDSUM + gi;
                         *dst = (wv == 0) ? acc[t][r] : *dst + acc[t][r];
                     }
         }
@@ -102,7 +106,7 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
     __syncthreads();
     // Only lower-triangle tiles are meaningful; upper ones are not written.
     if (act)
-        for (int e = 2 * tid; e < W2 * W2; e += 2 * NT) *(d2 *)(out + e) = *(const d2 *)(tile + e);
+        for (int e = tid; e < W2 * W2; e += NT) out[e] = tile[(e / W2) * LDSUM + e % W2];
 }
 
 // Device body: the workgroup (NT threads) solves the block pair whose Gram
