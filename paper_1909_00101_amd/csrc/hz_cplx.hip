@@ -59,8 +59,11 @@ __global__ __launch_bounds__(256) void k_gram_z(const d2 *__restrict__ Fw,
                                                 int64_t mgw, const int *__restrict__ pairs,
                                                 int splits, d2 *__restrict__ part)
 {
-    constexpr int W = W2 / 2, NB = W2 / 16, LDT = 66, NLD = W2 / 4;
+    // LDR: row stride of the summed tile (padded so that the 16 lanes of a
+    // tile row fall in distinct LDS banks); it fits in the staging arrays.
+    constexpr int W = W2 / 2, NB = W2 / 16, LDT = 66, NLD = W2 / 4, LDR = W2 + 2;
     constexpr int NT = NB * (NB + 1) / 2;
+    static_assert(LDR <= LDT, "summed tile exceeds the staging arrays");
     __shared__ __attribute__((aligned(16))) double tre[W2 * LDT];
     __shared__ __attribute__((aligned(16))) double tim[W2 * LDT];
     const int split = blockIdx.x, pr = blockIdx.y, mat = blockIdx.z;
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(256) void k_gram_z(const d2 *__restrict__ Fw,
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int gi = 16 * a + 4 * r + (lane >> 4), gj = 16 * b + (lane & 15);
-                        double *dr = tre + gj * W2 + gi, *di = tim + gj * W2 + gi;
+                        double *dr = tre + gj * LDR + gi, *di = tim + gj * LDR + gi;
                         *dr = (wv == 0) ? accr[t][r] : *dr + accr[t][r];
                         *di = (wv == 0) ? acci[t][r] : *di + acci[t][r];
                     }
@@ -143,7 +146,10 @@ __global__ __launch_bounds__(256) void k_gram_z(const d2 *__restrict__ Fw,
     }
     __syncthreads();
     d2 *out = part + ((size_t)(pr * 2 + mat) * splits + split) * (W2 * W2);
-    for (int e = tid; e < W2 * W2; e += 256) out[e] = d2{tre[e], tim[e]};
+    for (int e = tid; e < W2 * W2; e += 256) {
+        const int o = (e / W2) * LDR + e % W2;
+        out[e] = d2{tre[o], tim[o]};
+    }
 }
 
 template <int W2>

@@ -57,7 +57,8 @@ __global__ __launch_bounds__(256) void k_prescale_copy32(
 }
 
 // Pivot Gram blocks from FP32 data with FP32 MFMA and FP32 accumulation;
-// lower tiles; the four waves' tiles are summed in FP64 and the split
+// lower tiles; the four waves' tiles are summed in FP64 (row stride W2 + 2
+// in LDS, so the 16 lanes of a tile row fall in distinct banks) and the split
 // partial is written widened to FP64 (summed in split order by k_gram_sum).
 template <int W2>
 __global__ __launch_bounds__(256) void k_gram32(const float *__restrict__ Fs,
@@ -65,10 +66,10 @@ __global__ __launch_bounds__(256) void k_gram32(const float *__restrict__ Fs,
                                                 int64_t mgw, const int *__restrict__ pairs,
                                                 int splits, double *__restrict__ part)
 {
-    constexpr int W = W2 / 2, NB = W2 / 16, LDT = 68, NLD = W2 / 16;
+    constexpr int W = W2 / 2, NB = W2 / 16, LDT = 68, NLD = W2 / 16, LDR = W2 + 2;
     constexpr int NT = NB * (NB + 1) / 2;
     __shared__ __attribute__((aligned(16))) float tile[W2 * LDT];
-    __shared__ double red[W2 * W2];
+    __shared__ __attribute__((aligned(16))) double red[W2 * LDR];
     const int split = blockIdx.x, pr = blockIdx.y, mat = blockIdx.z;
     const float *Y = mat ? Gs : Fs;
     const int64_t m = mat ? mgw : mfw;
@@ -127,14 +128,15 @@ __global__ __launch_bounds__(256) void k_gram32(const float *__restrict__ Fs,
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int gi = 16 * a + 4 * (lane >> 4) + r, gj = 16 * b + (lane & 15);
-                        double *dst = red + gj * W2 + gi;
+                        double *dst = red + gj * LDR + gi;
                         *dst = (wv == 0) ? (double)acc[t][r] : *dst + (double)acc[t][r];
                     }
         }
     }
     __syncthreads();
     double *out = part + ((size_t)(pr * 2 + mat) * splits + split) * (W2 * W2);
-    for (int e = 2 * tid; e < W2 * W2; e += 512) *(d2 *)(out + e) = *(const d2 *)(red + e);
+    for (int e = 2 * tid; e < W2 * W2; e += 512)
+        *(d2 *)(out + e) = *(const d2 *)(red + (e / W2) * LDR + e % W2);
 }
 
 // Block update of the FP32 copies, [Y_p Y_q] <- [Y_p Y_q] fl32(Z_tilde), FP32
