@@ -2,9 +2,13 @@
 every kernel sums in a fixed order and no result depends on which
 workgroup runs first, so two runs of the same call give the same bits.
 Checked for QR shortening (real, complex, mixed), the QR pivot factors and
-the enhanced-dot-product variants."""
+the enhanced-dot-product variants, and, for the plain real and complex
+solves, across two processes."""
 
 import hashlib
+import os
+import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -39,3 +43,34 @@ def test_reruns_are_bitwise_equal(cplx, kw):
     a = _digest(F, G, **kw)
     b = _digest(F, G, **kw)
     assert a[0] == 0 and a == b
+
+
+_CHILD = """
+import sys
+sys.path[:0] = [{root!r}, {tests!r}]
+import test_gpu_reproducible as t
+import gsvd_inputs as gi
+F, G, _ = gi.custom_pair(700, 520, 192, kappa=1e2, is_complex={cplx}, seed=961)
+st, h = t._digest(F, G, **{kw!r})
+print("DIGEST", st, h, flush=True)
+"""
+
+
+@pytest.mark.parametrize("cplx,kw", [
+    (False, dict(w=32, inner_ordering=1, inner_max_sweeps=1)),
+    (True, dict(w=8)),
+], ids=["real_w32_inner_mm", "complex_w8"])
+def test_results_match_across_processes(cplx, kw):
+    """A second interpreter, with its own HIP context, plan cache and
+    workspace addresses, must produce the same bits."""
+    F, G, _ = gi.custom_pair(700, 520, 192, kappa=1e2, is_complex=cplx, seed=961)
+    print(f"cross-process {kw} complex={cplx}", flush=True)
+    here = _digest(F, G, **kw)
+    tests = os.path.dirname(os.path.abspath(__file__))
+    code = _CHILD.format(root=os.path.dirname(tests), tests=tests, cplx=cplx, kw=kw)
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         timeout=240)
+    assert res.returncode == 0, res.stderr[-2000:]
+    line = [x for x in res.stdout.splitlines() if x.startswith("DIGEST ")][-1].split()
+    assert here[0] == 0
+    assert (int(line[1]), line[2]) == here
