@@ -124,7 +124,10 @@ static bool make_plan(const hz_params &prm, int64_t mf, int64_t mg, int64_t n, i
     if (sp > maxch) sp = maxch;
     if (sp < 1) sp = 1;
     P.splits = (int)sp;
-    P.upd_rows = prm.update_rows ? prm.update_rows : 128;
+    // rows per wave of the update: 48 makes the real FP64 update of a tall
+    // pair about three workgroups per compute unit (its rows of F, G and Z
+    // are cut as one sequence); the complex and FP32 updates tile per matrix
+    P.upd_rows = prm.update_rows ? prm.update_rows : ((!is_complex && !mixed) ? 48 : 128);
     P.inner_lp = prm.inner_lanes ? prm.inner_lanes : ((P.W2 == 64) ? 16 : 8);
     if (P.W2 == 16) P.inner_lp = 8;       // 8 column pairs x 8 lanes: one wave
     const size_t es = P.esz;
@@ -1522,7 +1525,7 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
     };
     if (!base.w) cur.w = default_w(n, 0);
     if (!base.gram_splits) cur.gram_splits = 8;
-    if (!base.update_rows) cur.update_rows = 64;
+    if (!base.update_rows) cur.update_rows = 48;
     if (!base.inner_lanes) cur.inner_lanes = 0;
     std::vector<std::vector<int>> axes;
     std::vector<int *> fields;
@@ -1531,7 +1534,7 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
     fields.push_back(&cur.inner_max_sweeps);
     if (!base.w) { axes.push_back({8, 16, 32}); fields.push_back(&cur.w); }
     if (!base.gram_splits) { axes.push_back({4, 8, 16}); fields.push_back(&cur.gram_splits); }
-    if (!base.update_rows) { axes.push_back({32, 64, 128}); fields.push_back(&cur.update_rows); }
+    if (!base.update_rows) { axes.push_back({16, 32, 48, 64, 80, 128}); fields.push_back(&cur.update_rows); }
     if (!base.inner_lanes) { axes.push_back({4, 8, 16}); fields.push_back(&cur.inner_lanes); }
     ms = coordinate_search(cur, axes, fields, solve);
     if (swork) (void)hipFree(swork);

@@ -394,14 +394,16 @@ __device__ __forceinline__ void inner_solve(
 #undef s_fail
 }
 
-// Device body: one workgroup of NW waves updates rows [rb, re) (a multiple
-// of 16 rows) of the block-column pair (p, q) of Y (ld m) by zt
-// (column-major W2 x W2), staged in LDS (sz, update_lds<W2>() doubles).
-template <int W2, int NW>
-__device__ __forceinline__ void update_rows(double *__restrict__ Y, int64_t m, int p, int q,
-                                            int64_t rb, int64_t re,
-                                            const double *__restrict__ zt,
-                                            double *__restrict__ sz)
+// Device body: one workgroup of NW waves updates the rows [rb, re) (a
+// multiple of 16 rows) of a row sequence by zt (column-major W2 x W2),
+// staged in LDS (sz, update_lds<W2>() doubles).  locate(v, Y, m, r) maps
+// sequence row v (the first of a 16-row tile, which never straddles two
+// matrices) to the matrix Y (ld m) and its row r; in Y the block-column
+// pair (p, q) is updated.
+template <int W2, int NW, class Locate>
+__device__ __forceinline__ void update_row_seq(Locate locate, int p, int q, int64_t rb,
+                                               int64_t re, const double *__restrict__ zt,
+                                               double *__restrict__ sz)
 {
     constexpr int W = W2 / 2, NB = W2 / 16, KS = W2 / 4, LDZ = W2 + 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -411,12 +413,15 @@ __device__ __forceinline__ void update_rows(double *__restrict__ Y, int64_t m, i
     // block column p, W..2W-1 block column q; every k-step's column offset
     // is a uniform multiple of m.
     const int k4 = lane >> 4, i16 = lane & 15;
-    const double *bp = Y + ((int64_t)p * W + k4) * m + i16;
-    const double *bq = Y + ((int64_t)q * W + k4) * m + i16;
-    for (int64_t r0 = rb + 16 * wave; r0 < re; r0 += 16 * NW) {
+    for (int64_t v0 = rb + 16 * wave; v0 < re; v0 += 16 * NW) {
         // keep the Z_tilde fragment reads inside the loop (in LDS, not in
         // 128 registers hoisted out of it)
         __asm__ volatile("" ::: "memory");
+        double *Y;
+        int64_t m, r0;
+        locate(v0, Y, m, r0);
+        const double *bp = Y + ((int64_t)p * W + k4) * m + i16;
+        const double *bq = Y + ((int64_t)q * W + k4) * m + i16;
         double xb[KS];
 #pragma unroll
         for (int s = 0; s < KS; ++s)
@@ -443,6 +448,22 @@ __device__ __forceinline__ void update_rows(double *__restrict__ Y, int64_t m, i
                 *dst = acc[jb][r];
             }
     }
+}
+
+// The same for the rows [rb, re) of one matrix Y (ld m).
+template <int W2, int NW>
+__device__ __forceinline__ void update_rows(double *__restrict__ Y, int64_t m, int p, int q,
+                                            int64_t rb, int64_t re,
+                                            const double *__restrict__ zt,
+                                            double *__restrict__ sz)
+{
+    update_row_seq<W2, NW>(
+        [=](int64_t v, double *&y, int64_t &ld, int64_t &r) {
+            y = Y;
+            ld = m;
+            r = v;
+        },
+        p, q, rb, re, zt, sz);
 }
 
 }  // namespace hz

@@ -149,7 +149,7 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner(
 // bank conflicts) and read as MFMA A-fragments per k-step, which keeps the
 // register count low enough for several waves per SIMD.  A wave reads
 // all W2 columns of its 16 rows before writing them: in place, no races.
-// Grid (row blocks of Fw | Gw | Zw, pairs); each workgroup owns
+// Grid (row ranges of the rows of Fw, Gw and Zw in sequence, pairs); each workgroup owns
 // 4 * rows_per_wave consecutive rows, its waves taking 16-row tiles in turn.
 // ------------------------------------------------------------------------
 template <int W2>
@@ -157,30 +157,38 @@ __global__ __launch_bounds__(256) void k_update(double *__restrict__ Fw, double 
                                                 double *__restrict__ Zw, int64_t mfw,
                                                 int64_t mgw, int64_t nzw,
                                                 const int *__restrict__ pairs,
-                                                const double *__restrict__ Zt, int tiles_f,
-                                                int tiles_g, int rows_per_wave)
+                                                const double *__restrict__ Zt, int rows_per_wave)
 {
+    // The rows of F, G and Z (each padded to a multiple of 64) are taken as
+    // one sequence and cut into equal ranges of 4 * rows_per_wave; a range
+    // that reaches the end of one matrix continues in the next (a 16-row
+    // tile never straddles two), so the launch is one rounding of the
+    // total, not three.
     const int pr = blockIdx.y;
-    int64_t t = blockIdx.x;
-    double *Y;
-    int64_t m;
-    if (t < tiles_f) {
-        Y = Fw;
-        m = mfw;
-    } else if (t < tiles_f + tiles_g) {
-        Y = Gw;
-        m = mgw;
-        t -= tiles_f;
-    } else {
-        Y = Zw;
-        m = nzw;
-        t -= tiles_f + tiles_g;
-    }
-    const int64_t rb = t * 4 * (int64_t)rows_per_wave;
-    const int64_t re = (rb + 4 * (int64_t)rows_per_wave < m) ? rb + 4 * (int64_t)rows_per_wave : m;
+    const int p = pairs[2 * pr], q = pairs[2 * pr + 1];
+    const double *zt = Zt + (size_t)pr * (W2 * W2);
+    const int64_t span = 4 * (int64_t)rows_per_wave;
+    const int64_t vb = (int64_t)blockIdx.x * span;
+    const int64_t total = mfw + mgw + nzw;
+    const int64_t ve = (vb + span < total) ? vb + span : total;
     __shared__ double sz[update_lds<W2>()];
-    update_rows<W2, 4>(Y, m, pairs[2 * pr], pairs[2 * pr + 1], rb, re, Zt + (size_t)pr * (W2 * W2),
-                       sz);
+    update_row_seq<W2, 4>(
+        [=](int64_t v, double *&y, int64_t &ld, int64_t &r) {
+            if (v < mfw) {
+                y = Fw;
+                ld = mfw;
+                r = v;
+            } else if (v < mfw + mgw) {
+                y = Gw;
+                ld = mgw;
+                r = v - mfw;
+            } else {
+                y = Zw;
+                ld = nzw;
+                r = v - mfw - mgw;
+            }
+        },
+        p, q, vb, ve, zt, sz);
 }
 
 // ------------------------------------------------------------------------
@@ -479,11 +487,10 @@ static void step_impl(const Plan &P, const Ptrs &W, int step, const hz_params &p
     inner_impl<W2>(P, W, step, prm, tol, false, s);
     prof_mark(K_INNER, false, s);
     const int64_t rpt = 4 * (int64_t)P.upd_rows;
-    const int tf = (int)((P.mfw + rpt - 1) / rpt), tg = (int)((P.mgw + rpt - 1) / rpt),
-              tz = (int)((P.nzw + rpt - 1) / rpt);
+    const int nt = (int)((P.mfw + P.mgw + P.nzw + rpt - 1) / rpt);
     prof_mark(K_UPDATE, true, s);
-    hipLaunchKernelGGL(k_update<W2>, dim3(tf + tg + tz, P.npairs), dim3(256), 0, s, W.Fw, W.Gw,
-                       W.Zw, P.mfw, P.mgw, P.nzw, pairs, W.Zt, tf, tg, P.upd_rows);
+    hipLaunchKernelGGL(k_update<W2>, dim3(nt, P.npairs), dim3(256), 0, s, W.Fw, W.Gw, W.Zw,
+                       P.mfw, P.mgw, P.nzw, pairs, W.Zt, P.upd_rows);
     prof_mark(K_UPDATE, false, s);
 }
 
