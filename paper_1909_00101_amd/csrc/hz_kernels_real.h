@@ -13,7 +13,10 @@ namespace hz {
 // (gram: 64-row chunks of W2 columns with stride 66, then the waves'
 // partial blocks summed with stride W2 + 2, which puts the 16 lanes of a
 // tile row in distinct banks)
-template <int W2> constexpr int gram_lds() { return W2 * 66 > W2 * (W2 + 2) ? W2 * 66 : W2 * (W2 + 2); }
+template <int W2, bool DB = false> constexpr int gram_lds()
+{
+    return (DB ? 2 : 1) * W2 * 66 > W2 * (W2 + 2) ? (DB ? 2 : 1) * W2 * 66 : W2 * (W2 + 2);
+}
 template <int W2> constexpr int update_lds() { return W2 * (W2 + 1); }
 template <int W2> constexpr int inner_lds()
 {
@@ -23,12 +26,13 @@ template <int W2> constexpr int inner_lds()
 // Device body: NW waves form the Gram block of the block-column pair (p, q)
 // of Y (m rows, ld m) over the 64-row chunks [c0, c1) and write it to out
 // (column-major W2 x W2, lower tiles).  Each chunk is staged in LDS (tile,
-// gram_lds<W2>() doubles) with the next one prefetched into registers; wave
+// gram_lds<W2, DB>() doubles; with DB two tiles taken in turn) with the
+// next two prefetched into registers; wave
 // w takes the k-steps w, w + NW, ... of every chunk, and the waves' partial
 // tiles are summed in wave order.  Further waves of a larger workgroup only
 // take part in the barriers, so the sums do not depend on the workgroup
 // size.
-template <int W2, int NW>
+template <int W2, int NW, bool DB = false>
 __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t m, int p, int q,
                                            int64_t c0, int64_t c1, double *__restrict__ out,
                                            double *__restrict__ tile)
@@ -53,37 +57,47 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
         const int gc = (cc < W) ? p * W + cc : q * W + (cc - W);
         colp[t] = Y + (int64_t)gc * m + lrow;
     }
-    d2 buf[NLD];
-    if (act && c0 < c1) {
+    // Two chunks in flight: while chunk c is staged and multiplied, the loads
+    // of chunk c + 1 are outstanding, and chunk c + 2's go out as soon as
+    // c's registers are free.  The chunks are still accumulated in order.
+    d2 bufa[NLD], bufb[NLD];
+    auto load = [&](d2 (&b)[NLD], int64_t c) {
 #pragma unroll
-        for (int t = 0; t < NLD; ++t) buf[t] = *(const d2 *)(colp[t] + c0 * 64);
-    }
-    for (int64_t c = c0; c < c1; ++c) {
-        __syncthreads();
+        for (int t = 0; t < NLD; ++t) b[t] = *(const d2 *)(colp[t] + c * 64);
+    };
+    // With DB the chunks alternate between two LDS tiles: the tile chunk c
+    // writes was last read for chunk c - 2, before chunk c - 1's barrier,
+    // so one barrier per chunk suffices.
+    auto chunk = [&](d2 (&b)[NLD], int64_t c, int slot) {
+        double *const tl = tile + (DB ? slot * W2 * LDT : 0);
+        if (!DB) __syncthreads();
         if (act) {
 #pragma unroll
-            for (int t = 0; t < NLD; ++t) *(d2 *)(tile + (lcol + CPP * t) * LDT + lrow) = buf[t];
+            for (int t = 0; t < NLD; ++t) *(d2 *)(tl + (lcol + CPP * t) * LDT + lrow) = b[t];
         }
         __syncthreads();
         if (act) {
-            if (c + 1 < c1) {
-#pragma unroll
-                for (int t = 0; t < NLD; ++t) buf[t] = *(const d2 *)(colp[t] + (c + 1) * 64);
-            }
+            if (c + 2 < c1) load(b, c + 2);
 #pragma unroll
             for (int s = 0; s < 16 / NW; ++s) {
                 const int ks = wave + NW * s;
                 double fr[NB];
 #pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    fr[b] = tile[(16 * b + (lane & 15)) * LDT + 4 * ks + (lane >> 4)];
+                for (int b2 = 0; b2 < NB; ++b2)
+                    fr[b2] = tl[(16 * b2 + (lane & 15)) * LDT + 4 * ks + (lane >> 4)];
                 int t = 0;
 #pragma unroll
                 for (int a = 0; a < NB; ++a)
 #pragma unroll
-                    for (int b = 0; b <= a; ++b, ++t) acc[t] = mfma16(fr[a], fr[b], acc[t]);
+                    for (int b2 = 0; b2 <= a; ++b2, ++t) acc[t] = mfma16(fr[a], fr[b2], acc[t]);
             }
         }
+    };
+    if (act && c0 < c1) load(bufa, c0);
+    if (act && c0 + 1 < c1) load(bufb, c0 + 1);
+    for (int64_t c = c0; c < c1; c += 2) {
+        chunk(bufa, c, 0);
+        if (c + 1 < c1) chunk(bufb, c + 1, 1);
     }
     // Sum the waves' partial tiles in wave order (tile reused, ld W2 + 2).
     constexpr int LDSUM = W2 + 2;
