@@ -118,9 +118,10 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
         }
     }
     __syncthreads();
-    // Only lower-triangle tiles are meaningful; upper ones are not written.
+    // Only lower-triangle tiles are meaningful and written.
     if (act)
-        for (int e = tid; e < W2 * W2; e += NT) out[e] = tile[(e / W2) * LDSUM + e % W2];
+        for (int e = tid; e < W2 * W2; e += NT)
+            if ((e % W2) / 16 >= (e / W2) / 16) out[e] = tile[(e / W2) * LDSUM + e % W2];
 }
 
 // Device body: the workgroup (NT threads) solves the block pair whose Gram

@@ -90,6 +90,7 @@ __global__ __launch_bounds__(256) void k_gram_sum(const double *__restrict__ par
     const int pm = blockIdx.y;
     const int e = 2 * (blockIdx.x * 256 + threadIdx.x);
     if (e >= W2 * W2) return;
+    if ((e % W2) / 16 < (e / W2) / 16) return;   // upper tiles: never read
     const double *src = part + (size_t)pm * splits * (W2 * W2) + e;
     d2 v[MAXS];
 #pragma unroll
