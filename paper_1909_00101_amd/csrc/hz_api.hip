@@ -124,10 +124,10 @@ static bool make_plan(const hz_params &prm, int64_t mf, int64_t mg, int64_t n, i
     if (sp > maxch) sp = maxch;
     if (sp < 1) sp = 1;
     P.splits = (int)sp;
-    // rows per wave of the update: 48 makes the real FP64 update of a tall
-    // pair about three workgroups per compute unit (its rows of F, G and Z
-    // are cut as one sequence); the complex and FP32 updates tile per matrix
-    P.upd_rows = prm.update_rows ? prm.update_rows : ((!is_complex && !mixed) ? 48 : 128);
+    // rows per wave of the update (the rows of F, G and Z are cut as one
+    // sequence): 48 gives the real FP64 update of the 4096x1024 pair three
+    // workgroups per compute unit
+    P.upd_rows = prm.update_rows ? prm.update_rows : 48;
     P.inner_lp = prm.inner_lanes ? prm.inner_lanes : ((P.W2 == 64) ? 16 : 8);
     if (P.W2 == 16) P.inner_lp = 8;       // 8 column pairs x 8 lanes: one wave
     const size_t es = P.esz;

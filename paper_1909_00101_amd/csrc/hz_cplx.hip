@@ -434,12 +434,14 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
 // Complex block update [Y_p Y_q] <- [Y_p Y_q] Z_tilde in place
 // (Section 2.3, Section 3.5.4): D' = Z_tilde^T X^T with
 // Re = Zr^T Xr^T - Zi^T Xi^T, Im = Zi^T Xr^T + Zr^T Xi^T on FP64 MFMA.
+// The rows of F, G and Z (each padded to a multiple of 64) are taken as one
+// sequence cut into equal workgroup ranges of 4 * rows_per_wave; a 16-row
+// tile never straddles two matrices, and its matrix is chosen per tile.
 template <int W2>
 __global__ __launch_bounds__(256) void k_update_z(d2 *__restrict__ Fw, d2 *__restrict__ Gw,
                                                   d2 *__restrict__ Zw, int64_t mfw, int64_t mgw,
                                                   int64_t nzw, const int *__restrict__ pairs,
-                                                  const d2 *__restrict__ Zt, int tiles_f,
-                                                  int tiles_g, int rows_per_wave)
+                                                  const d2 *__restrict__ Zt, int rows_per_wave)
 {
     constexpr int W = W2 / 2, NB = W2 / 16, KS = W2 / 4, LDZ = W2 + 1;
     __shared__ d2 sz[W2 * LDZ];
@@ -448,29 +450,30 @@ __global__ __launch_bounds__(256) void k_update_z(d2 *__restrict__ Fw, d2 *__res
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const d2 *zt = Zt + (size_t)pr * (W2 * W2);
     for (int e = tid; e < W2 * W2; e += 256) sz[(e / W2) * LDZ + (e % W2)] = zt[e];
-    int64_t t = blockIdx.x;
-    d2 *Y;
-    int64_t m;
-    if (t < tiles_f) {
-        Y = Fw;
-        m = mfw;
-    } else if (t < tiles_f + tiles_g) {
-        Y = Gw;
-        m = mgw;
-        t -= tiles_f;
-    } else {
-        Y = Zw;
-        m = nzw;
-        t -= tiles_f + tiles_g;
-    }
-    const int64_t rb = t * 4 * (int64_t)rows_per_wave;
-    const int64_t re = (rb + 4 * (int64_t)rows_per_wave < m) ? rb + 4 * (int64_t)rows_per_wave : m;
+    const int64_t span = 4 * (int64_t)rows_per_wave;
+    const int64_t vb = (int64_t)blockIdx.x * span, total = mfw + mgw + nzw;
+    const int64_t ve = (vb + span < total) ? vb + span : total;
     __syncthreads();
     const int k4 = lane >> 4, i16 = lane & 15;
-    d2 *bp = Y + ((int64_t)p * W + k4) * m + i16;
-    d2 *bq = Y + ((int64_t)q * W + k4) * m + i16;
-    for (int64_t r0 = rb + 16 * wave; r0 < re; r0 += 64) {
+    for (int64_t v0 = vb + 16 * wave; v0 < ve; v0 += 64) {
         __asm__ volatile("" ::: "memory");
+        d2 *Y;
+        int64_t m, r0;
+        if (v0 < mfw) {
+            Y = Fw;
+            m = mfw;
+            r0 = v0;
+        } else if (v0 < mfw + mgw) {
+            Y = Gw;
+            m = mgw;
+            r0 = v0 - mfw;
+        } else {
+            Y = Zw;
+            m = nzw;
+            r0 = v0 - mfw - mgw;
+        }
+        d2 *bp = Y + ((int64_t)p * W + k4) * m + i16;
+        d2 *bq = Y + ((int64_t)q * W + k4) * m + i16;
         d2 xb[KS];
 #pragma unroll
         for (int s = 0; s < KS; ++s)
@@ -651,12 +654,11 @@ static void step_impl_z(const Plan &P, const Ptrs &W, int step, const hz_params 
     }
     prof_mark(K_INNER, false, s);
     const int64_t rpt = 4 * (int64_t)P.upd_rows;
-    const int tf = (int)((P.mfw + rpt - 1) / rpt), tg = (int)((P.mgw + rpt - 1) / rpt),
-              tz = (int)((P.nzw + rpt - 1) / rpt);
+    const int nt = (int)((P.mfw + P.mgw + P.nzw + rpt - 1) / rpt);
     prof_mark(K_UPDATE, true, s);
-    hipLaunchKernelGGL(k_update_z<W2>, dim3(tf + tg + tz, P.npairs), dim3(256), 0, s,
-                       (d2 *)W.Fw, (d2 *)W.Gw, (d2 *)W.Zw, P.mfw, P.mgw, P.nzw, pairs,
-                       (const d2 *)W.Zt, tf, tg, P.upd_rows);
+    hipLaunchKernelGGL(k_update_z<W2>, dim3(nt, P.npairs), dim3(256), 0, s, (d2 *)W.Fw,
+                       (d2 *)W.Gw, (d2 *)W.Zw, P.mfw, P.mgw, P.nzw, pairs, (const d2 *)W.Zt,
+                       P.upd_rows);
     prof_mark(K_UPDATE, false, s);
 }
 

@@ -150,8 +150,8 @@ __global__ __launch_bounds__(256) void k_update32(float *__restrict__ Fs, float 
                                                   float *__restrict__ Zs, int64_t mfw,
                                                   int64_t mgw, int64_t nzw,
                                                   const int *__restrict__ pairs,
-                                                  const double *__restrict__ Zt, int tiles_f,
-                                                  int tiles_g, int rows_per_wave)
+                                                  const double *__restrict__ Zt,
+                                                  int rows_per_wave)
 {
     constexpr int W = W2 / 2, NB = W2 / 16, KS = W2 / 4, LDZ = W2 + 1;
     __shared__ float sz[W2 * LDZ];
@@ -160,30 +160,34 @@ __global__ __launch_bounds__(256) void k_update32(float *__restrict__ Fs, float 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double *zt = Zt + (size_t)pr * (W2 * W2);
     for (int e = tid; e < W2 * W2; e += 256) sz[(e / W2) * LDZ + (e % W2)] = (float)zt[e];
-    int64_t t = blockIdx.x;
-    float *Y;
-    int64_t m;
-    if (t < tiles_f) {
-        Y = Fs;
-        m = mfw;
-    } else if (t < tiles_f + tiles_g) {
-        Y = Gs;
-        m = mgw;
-        t -= tiles_f;
-    } else {
-        Y = Zs;
-        m = nzw;
-        t -= tiles_f + tiles_g;
-    }
-    // tiles are 4 * rows_per_wave rows (a multiple of 64), m a multiple of 64
-    const int64_t rb = t * 4 * (int64_t)rows_per_wave;
-    const int64_t re = (rb + 4 * (int64_t)rows_per_wave < m) ? rb + 4 * (int64_t)rows_per_wave : m;
+    // The rows of F, G and Z (each a multiple of 64) are taken as one
+    // sequence cut into workgroup ranges of 4 * rows_per_wave rows (a
+    // multiple of 64); a 32-row tile never straddles two matrices, and its
+    // matrix is chosen per tile.
+    const int64_t span = 4 * (int64_t)rows_per_wave;
+    const int64_t vb = (int64_t)blockIdx.x * span, total = mfw + mgw + nzw;
+    const int64_t ve = (vb + span < total) ? vb + span : total;
     __syncthreads();
     const int k4 = lane >> 4, i16 = lane & 15;
-    float *bp = Y + ((int64_t)p * W + k4) * m + 2 * i16;
-    float *bq = Y + ((int64_t)q * W + k4) * m + 2 * i16;
-    for (int64_t r0 = rb + 32 * wave; r0 < re; r0 += 128) {
+    for (int64_t v0 = vb + 32 * wave; v0 < ve; v0 += 128) {
         __asm__ volatile("" ::: "memory");
+        float *Y;
+        int64_t m, r0;
+        if (v0 < mfw) {
+            Y = Fs;
+            m = mfw;
+            r0 = v0;
+        } else if (v0 < mfw + mgw) {
+            Y = Gs;
+            m = mgw;
+            r0 = v0 - mfw;
+        } else {
+            Y = Zs;
+            m = nzw;
+            r0 = v0 - mfw - mgw;
+        }
+        float *bp = Y + ((int64_t)p * W + k4) * m + 2 * i16;
+        float *bq = Y + ((int64_t)q * W + k4) * m + 2 * i16;
         f2 xb[KS];
 #pragma unroll
         for (int s = 0; s < KS; ++s)
@@ -350,11 +354,10 @@ static void step32_impl(const Plan &P, const Ptrs &W, int step, const hz_params 
     launch_inner_real(P, W, step, prm, tol, false, s);
     prof_mark(K_INNER, false, s);
     const int64_t rpt = 4 * (int64_t)P.upd_rows;
-    const int tf = (int)((P.mfw + rpt - 1) / rpt), tg = (int)((P.mgw + rpt - 1) / rpt),
-              tz = (int)((P.nzw + rpt - 1) / rpt);
+    const int nt = (int)((P.mfw + P.mgw + P.nzw + rpt - 1) / rpt);
     prof_mark(K_UPDATE, true, s);
-    hipLaunchKernelGGL(k_update32<W2>, dim3(tf + tg + tz, P.npairs), dim3(256), 0, s, W.Fs, W.Gs,
-                       W.Zs, P.mfw, P.mgw, P.nzw, pairs, W.Zt, tf, tg, P.upd_rows);
+    hipLaunchKernelGGL(k_update32<W2>, dim3(nt, P.npairs), dim3(256), 0, s, W.Fs, W.Gs, W.Zs,
+                       P.mfw, P.mgw, P.nzw, pairs, W.Zt, P.upd_rows);
     prof_mark(K_UPDATE, false, s);
 }
 
