@@ -429,9 +429,12 @@ def main():
     if dom == "inner":
         # latency-bound FP64 VALU work on one workgroup per pivot pair
         achieved = work_d["flops"] / t_launch / 1e12
+        # the solver uses one workgroup (one compute unit) per pivot pair:
+        # frac_of_used_cus prices it against the FP64 vector peak of those
+        cu_peak = FP64_MFMA_PEAK_TFS * npairs / 256
         roof = dict(bound="alu", achieved=round(achieved, 4), peak=FP64_MFMA_PEAK_TFS,
                     unit="TFLOP/s", frac=round(achieved / FP64_MFMA_PEAK_TFS, 5), traffic=None,
-                    cus_used=npairs)
+                    cus_used=npairs, frac_of_used_cus=round(achieved / cu_peak, 4))
         intensity = None
     else:
         intensity = work_d["flops"] / work_d["bytes"]
