@@ -184,6 +184,68 @@ __device__ __forceinline__ void inner_solve(
             if (!(fabs(df) > 0.0 && fabs(df) < INFINITY && fabs(dg) > 0.0 && fabs(dg) < INFINITY))
                 s_fail = 1;
         }
+    } else if constexpr (W2 == 64) {
+        // Blocked right-looking Cholesky, one wave per matrix, panels of 16
+        // columns.  A panel (its rows c0.. of columns c0..c0+15, lane = row)
+        // is factored in registers, the entries of a column reaching the
+        // later panel columns by readlane; the panel goes back to LDS and the
+        // trailing lower tiles take the update A22 -= L21 L21^T as FP64 MFMA
+        // products (tile (ti, tj): A operand L rows of ti, B operand L rows
+        // of tj, four k-steps of 4 panel columns).
+        if (wave < 2) {
+            double *M = wave ? sG : sF;
+            bool ok = true;
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                const int c0 = 16 * kb, row = c0 + lane;
+                const bool live = row < 64;
+                double pv[16];
+#pragma unroll
+                for (int t = 0; t < 16; ++t) pv[t] = live ? M[(c0 + t) * LDI + row] : 0.0;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const double piv = readlane_d(pv[j], j);
+                    ok = ok && (piv > 0.0) && (piv < INFINITY);
+                    const double inv = rsqrt_nr(piv);
+                    const double l = (lane >= j) ? pv[j] * inv : 0.0;
+                    pv[j] = l;
+#pragma unroll
+                    for (int t = j + 1; t < 16; ++t) pv[t] = fma(-l, readlane_d(l, t), pv[t]);
+                }
+                if (live) {
+#pragma unroll
+                    for (int t = 0; t < 16; ++t) M[(c0 + t) * LDI + row] = pv[t];
+                }
+                wave_fence();
+                const int i16 = lane & 15, k4 = lane >> 4;
+#pragma unroll
+                for (int ti = kb + 1; ti < 4; ++ti)
+#pragma unroll
+                    for (int tj = kb + 1; tj <= ti; ++tj) {
+                        // element r of lane l: row 16 ti + 4 r + l/16, column 16 tj + l%16
+                        double *const ct = M + (16 * tj + i16) * LDI + 16 * ti + k4;
+                        d4 acc = d4{ct[0], ct[4], ct[8], ct[12]};
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            const double *const lc = M + (c0 + 4 * s + k4) * LDI;
+                            acc = mfma16(-lc[16 * ti + i16], lc[16 * tj + i16], acc);
+                        }
+                        ct[0] = acc[0];
+                        ct[4] = acc[1];
+                        ct[8] = acc[2];
+                        ct[12] = acc[3];
+                    }
+                wave_fence();
+            }
+            // F_hat = L^T: column i of F_hat is row i of L.
+            double a[64];
+#pragma unroll
+            for (int k = 0; k < 64; ++k) a[k] = M[k * LDI + lane];
+            wave_fence();
+#pragma unroll
+            for (int k = 0; k < 64; ++k) M[lane * LDI + k] = (k <= lane) ? a[k] : 0.0;
+            if (!ok) s_fail = 1;
+        }
     } else {
         constexpr bool two = (W2 == 64);
         const int mat = two ? wave : (lane >> 5);
