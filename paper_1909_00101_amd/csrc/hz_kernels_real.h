@@ -184,21 +184,22 @@ __device__ __forceinline__ void inner_solve(
             if (!(fabs(df) > 0.0 && fabs(df) < INFINITY && fabs(dg) > 0.0 && fabs(dg) < INFINITY))
                 s_fail = 1;
         }
-    } else if constexpr (W2 == 64) {
+    } else if constexpr (W2 >= 32 && NT >= 128) {
         // Blocked right-looking Cholesky, one wave per matrix, panels of 16
-        // columns.  A panel (its rows c0.. of columns c0..c0+15, lane = row)
+        // columns (2w = 32 or 64; lanes past the block's rows idle).  A panel (its rows c0.. of columns c0..c0+15, lane = row)
         // is factored in registers, the entries of a column reaching the
         // later panel columns by readlane; the panel goes back to LDS and the
         // trailing lower tiles take the update A22 -= L21 L21^T as FP64 MFMA
         // products (tile (ti, tj): A operand L rows of ti, B operand L rows
         // of tj, four k-steps of 4 panel columns).
+        constexpr int NBK = W2 / 16;
         if (wave < 2) {
             double *M = wave ? sG : sF;
             bool ok = true;
 #pragma unroll
-            for (int kb = 0; kb < 4; ++kb) {
+            for (int kb = 0; kb < NBK; ++kb) {
                 const int c0 = 16 * kb, row = c0 + lane;
-                const bool live = row < 64;
+                const bool live = row < W2;
                 double pv[16];
 #pragma unroll
                 for (int t = 0; t < 16; ++t) pv[t] = live ? M[(c0 + t) * LDI + row] : 0.0;
@@ -219,7 +220,7 @@ __device__ __forceinline__ void inner_solve(
                 wave_fence();
                 const int i16 = lane & 15, k4 = lane >> 4;
 #pragma unroll
-                for (int ti = kb + 1; ti < 4; ++ti)
+                for (int ti = kb + 1; ti < NBK; ++ti)
 #pragma unroll
                     for (int tj = kb + 1; tj <= ti; ++tj) {
                         // element r of lane l: row 16 ti + 4 r + l/16, column 16 tj + l%16
@@ -238,12 +239,16 @@ __device__ __forceinline__ void inner_solve(
                 wave_fence();
             }
             // F_hat = L^T: column i of F_hat is row i of L.
-            double a[64];
+            double a[W2];
+            if (lane < W2) {
 #pragma unroll
-            for (int k = 0; k < 64; ++k) a[k] = M[k * LDI + lane];
+                for (int k = 0; k < W2; ++k) a[k] = M[k * LDI + lane];
+            }
             wave_fence();
+            if (lane < W2) {
 #pragma unroll
-            for (int k = 0; k < 64; ++k) M[lane * LDI + k] = (k <= lane) ? a[k] : 0.0;
+                for (int k = 0; k < W2; ++k) M[lane * LDI + k] = (k <= lane) ? a[k] : 0.0;
+            }
             if (!ok) s_fail = 1;
         }
     } else {
