@@ -74,3 +74,20 @@ def test_results_match_across_processes(cplx, kw):
     line = [x for x in res.stdout.splitlines() if x.startswith("DIGEST ")][-1].split()
     assert here[0] == 0
     assert (int(line[1]), line[2]) == here
+
+
+@pytest.mark.parametrize("cplx,mixed,w", [(False, False, 16), (False, False, 32), (True, False, 8),
+                                          (False, True, 16)],
+                         ids=["real_w16", "real_w32", "complex_w8", "mixed_w16"])
+def test_update_row_partition_does_not_change_bits(cplx, mixed, w):
+    """The block update cuts the rows of F, G and Z as one sequence into
+    workgroup ranges; every 16-row tile is computed the same way whatever
+    the cut, so rows-per-wave settings whose ranges cross the F/G and G/Z
+    boundaries at different places (512: one range holds all three) must
+    give the same bits, and a valid solve."""
+    F, G, _ = gi.custom_pair(700, 520, 192, kappa=1e2, is_complex=cplx, seed=962)
+    print(f"update partition w={w} complex={cplx} mixed={mixed}", flush=True)
+    got = {ur: _digest(F, G, w=w, mixed=mixed, update_rows=ur, inner_max_sweeps=1)
+           for ur in (16, 48, 80, 512)}
+    assert all(st == 0 for st, _ in got.values()), got
+    assert len({h for _, h in got.values()}) == 1, got
