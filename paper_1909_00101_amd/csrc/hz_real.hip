@@ -111,10 +111,12 @@ __global__ __launch_bounds__(256) void k_gram_sum(const double *__restrict__ par
 // column pair of an inner step, RPL = W2/LP rows per lane.  Steps:
 //  1. A_hat, B_hat = sum of the Gram partials (split order) into LDS.
 //  2. Cholesky A_hat = F_hat^T F_hat, B_hat = G_hat^T G_hat (F_hat, G_hat
-//     upper triangular) inside one wave per matrix (both matrices in one
-//     wave when 2w <= 32): lane i keeps row i in registers, the pivot comes
-//     by readlane, the new column of L is broadcast through LDS; a
-//     non-positive pivot flags HZ_ECHOL.
+//     upper triangular), one wave per matrix: for 2w = 64 (and 2w = 32 with
+//     two or more waves) in panels of 16 columns factored in registers
+//     (lane = row, entries by readlane) with the trailing lower tiles
+//     updated by FP64 MFMA; otherwise column by column, lane i keeping row
+//     i, the new column of L broadcast through LDS (both matrices in one
+//     wave); a non-positive pivot flags HZ_ECHOL.
 //  3. Z_hat = diag(1/||g_hat_j||), F_hat, G_hat scaled by it.
 //  4. Inner sweeps (<= inner_max, stop after a sweep without
 //     transformations): per step, the LP lanes of a column pair form a_ii,
