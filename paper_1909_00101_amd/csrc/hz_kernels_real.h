@@ -186,12 +186,13 @@ __device__ __forceinline__ void inner_solve(
         }
     } else if constexpr (W2 >= 32 && NT >= 128) {
         // Blocked right-looking Cholesky, one wave per matrix, panels of 16
-        // columns (2w = 32 or 64; lanes past the block's rows idle).  A panel (its rows c0.. of columns c0..c0+15, lane = row)
-        // is factored in registers, the entries of a column reaching the
-        // later panel columns by readlane; the panel goes back to LDS and the
-        // trailing lower tiles take the update A22 -= L21 L21^T as FP64 MFMA
-        // products (tile (ti, tj): A operand L rows of ti, B operand L rows
-        // of tj, four k-steps of 4 panel columns).
+        // columns (2w = 32 or 64; lanes past the block's rows idle).  A
+        // panel (its rows c0.. of columns c0..c0+15, lane = row) is factored
+        // in registers, the entries of a column reaching the later panel
+        // columns by readlane; the panel goes back to LDS and the trailing
+        // lower tiles take the update A22 -= L21 L21^T as FP64 MFMA products
+        // (tile (ti, tj): A operand L rows of ti, B operand L rows of tj,
+        // four k-steps of 4 panel columns).
         constexpr int NBK = W2 / 16;
         if (wave < 2) {
             double *M = wave ? sG : sF;
