@@ -154,10 +154,16 @@ def test_sweep_cap():
     assert r["status"] == 1 and not r["converged"] and r["sweeps"] == 1
 
 
-def test_config2_full_size_vs_oracle_golden():
-    """The 4096x1024 workload in the benchmark's launch configuration
-    (w = 32, modified modulus, tol = 1024 eps) against the oracle's sigma for
-    the same seeded pair (tests/golden/oracle_config2.json, written by
+@pytest.mark.parametrize("launch", [
+    {},
+    dict(inner_ordering=1, inner_max_sweeps=1, gram_splits=8, update_rows=48, inner_lanes=16),
+], ids=["defaults", "bench_tuned"])
+def test_config2_full_size_vs_oracle_golden(launch):
+    """The 4096x1024 workload (w = 32, modified modulus, tol = 1024 eps), with
+    the library's default launch and with the launch the benchmark times
+    (modified modulus inside the blocks, one inner sweep, 8 Gram splits, 48
+    update rows per wave, 16 inner lanes), against the oracle's sigma for the
+    same seeded pair (tests/golden/oracle_config2.json, written by
     tests/golden/make_golden.py from the oracle alone), plus the contract
     residuals of the GPU outputs computed on the GPU."""
     import json
@@ -168,7 +174,8 @@ def test_config2_full_size_vs_oracle_golden():
     hz = _hz()
     dF = torch.from_numpy(F).cuda()
     dG = torch.from_numpy(G).cuda()
-    r = hz.gsvd(dF, dG, w=32, ordering=hz.HZ_ORD_MM, tol=1024 * EPS)
+    print(f"config2 launch={launch}", flush=True)
+    r = hz.gsvd(dF, dG, w=32, ordering=hz.HZ_ORD_MM, tol=1024 * EPS, **launch)
     torch.cuda.synchronize()
     s = r["sigma"].cpu().numpy()
     err = max_rel(s, np.array(gold["sigma"]))
