@@ -70,6 +70,8 @@ SHAPES = [
     (256, 200, 96, 16, 1e2),
     (300, 300, 160, 16, 1e2),     # 10 block columns, several row chunks
     (700, 520, 256, 32, 1e2),     # 2w = 64 pivot blocks
+    (400, 300, 100, 32, 1e2),     # 2w = 64, ragged n: bordered to 128 columns
+    (260, 240, 70, 32, 10.0),     # 2w = 64, bordering columns in both blocks
     (64, 64, 2, 8, 3.0),          # smallest blocked case (bordered to 16)
     (333, 65, 65, 16, 50.0),      # square G, ragged everywhere
 ]
