@@ -322,3 +322,18 @@ def test_pivot_qr_sizes_and_rejections(hz):
     i64 = lambda vals: (ctypes.c_int64 * len(vals))(*vals)
     assert L.hz_dgsvd_batched_work_size(ctypes.byref(p), 1, i64([64]), i64([64]),
                                         i64([32])) == 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus N > 1 (or a WORLD_SIZE above 1)
+    exits with a message before touching a device."""
+    import subprocess
+    import sys
+    bench = os.path.join(ROOT, "bench.py")
+    for args, env in (([bench, "--gpus", "2"], {}), ([bench], {"WORLD_SIZE": "2"})):
+        e = dict(os.environ)
+        e.update(env)
+        r = subprocess.run([sys.executable, *args], capture_output=True, text=True, env=e,
+                           timeout=120)
+        assert r.returncode == 2, (r.returncode, r.stderr[-500:])
+        assert "one GPU" in r.stderr
