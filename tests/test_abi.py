@@ -337,3 +337,34 @@ def test_bench_refuses_more_than_one_gpu():
                            timeout=120)
         assert r.returncode == 2, (r.returncode, r.stderr[-500:])
         assert "one GPU" in r.stderr
+
+
+def test_product_path_fails_loudly_without_library():
+    """With the HIP library absent, the binding raises instead of computing
+    anything on the CPU (there is no fallback path)."""
+    import subprocess
+    import sys
+    code = f"""
+import sys
+sys.path.insert(0, {ROOT!r})
+import torch
+import paper_1909_00101_amd as hz
+hz.LIB_PATH = '/nonexistent/libhzgsvd.so'
+hz._lib = None
+try:
+    hz.lib()
+    print('LOADED')
+except RuntimeError as e:
+    print('lib raised')
+F = torch.randn(8, 4, dtype=torch.float64)
+G = torch.randn(8, 4, dtype=torch.float64)
+try:
+    hz.gsvd(F, G)
+    print('RESULT')
+except Exception as e:
+    print('gsvd raised', type(e).__name__)
+"""
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-800:]
+    assert "lib raised" in r.stdout and "gsvd raised" in r.stdout, r.stdout
+    assert "LOADED" not in r.stdout and "RESULT" not in r.stdout, r.stdout
