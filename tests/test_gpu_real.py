@@ -141,6 +141,22 @@ def test_rank_deficient_reports_cholesky_failure():
     assert e.value.info.failed_pair >= 0
 
 
+def test_exact_zero_pivot_in_blocked_cholesky():
+    """2w = 64 (the blocked Cholesky): columns 0 and 1 of G both equal e_0,
+    so their prescale factor is 1, their Gram entries exactly 1 and the
+    second pivot exactly 0: the per-step solver reports HZ_ECHOL."""
+    hz = _hz()
+    F, G, _ = gi.custom_pair(300, 300, 128, seed=93)
+    G[:, 0] = 0.0
+    G[0, 0] = 1.0
+    G[:, 1] = G[:, 0]
+    print("exact zero pivot, w=32 per-step", flush=True)
+    with pytest.raises(hz.GsvdError) as e:
+        _run(F, G, w=32)
+    assert e.value.status == hz.HZ_ECHOL
+    assert e.value.info.failed_pair >= 0
+
+
 def test_nonfinite_input():
     hz = _hz()
     F, G, _ = gi.custom_pair(80, 80, 32, seed=9)
