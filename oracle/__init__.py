@@ -65,6 +65,13 @@ def _load():
         lib.hzo_enh_abs2.restype = ctypes.c_double
         lib.hzo_ordering.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         lib.hzo_ordering.restype = ctypes.c_int
+        lib.hzo_real_sort_keys.argtypes = [ctypes.c_double] * 3 + [dp, dp, dp]
+        lib.hzo_real_sort_keys.restype = None
+        for name in ("hzo_step_real", "hzo_step_cplx"):
+            f = getattr(lib, name)
+            f.argtypes = [i64, i64, i64, dp, i64, dp, i64, dp, i64, i64, i64, ctypes.c_double,
+                          ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64)]
+            f.restype = None
         _lib = lib
     return _lib
 
@@ -193,3 +200,35 @@ def ordering(kind: int, n: int) -> np.ndarray:
     got = lib.hzo_ordering(kind, n, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
     assert got == steps
     return t.reshape(steps, pp, 2)
+
+
+def real_sort_keys(aii, ajj, aij, Z):
+    """The oracle's sort keys of a real transformed pivot pair (Section
+    3.5.3): (a''_11, a''_22) from the pivot entries and the 2x2 Z."""
+    z = np.asfortranarray(np.asarray(Z, dtype=np.float64)).ravel(order="F")
+    a11 = ctypes.c_double()
+    a22 = ctypes.c_double()
+    _load().hzo_real_sort_keys(float(aii), float(ajj), float(aij), _dptr(z),
+                               ctypes.byref(a11), ctypes.byref(a22))
+    return a11.value, a22.value
+
+
+def step(F, G, Z, i, j, *, tol=0.0, sort=True, variant=0):
+    """One pointwise step of the oracle (Section 2.1) on the pivot pair
+    (i, j), i < j, of copies of F, G, Z; returns (F, G, Z, transformations,
+    big transformations) after the step.  tol <= 0 selects sqrt(n)*eps."""
+    lib = _load()
+    is_c = np.iscomplexobj(F) or np.iscomplexobj(G) or np.iscomplexobj(Z)
+    dt = np.complex128 if is_c else np.float64
+    F = np.array(F, dtype=dt, order="F", copy=True)
+    G = np.array(G, dtype=dt, order="F", copy=True)
+    Z = np.array(Z, dtype=dt, order="F", copy=True)
+    m_f, n = F.shape
+    m_g = G.shape[0]
+    if tol <= 0.0:
+        tol = np.sqrt(n) * np.finfo(np.float64).eps
+    c = np.zeros(2, dtype=np.int64)
+    fn = lib.hzo_step_cplx if is_c else lib.hzo_step_real
+    fn(m_f, m_g, n, _dptr(F), m_f, _dptr(G), m_g, _dptr(Z), n, int(i), int(j), float(tol),
+       1 if sort else 0, int(variant), c.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return F, G, Z, int(c[0]), int(c[1])

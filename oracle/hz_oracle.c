@@ -453,6 +453,22 @@ static int is_big(int variant, double z11, double z22, const double cc[2])
 }
 
 /*
+ * Section 3.5.3, real case: the sort decision of a transformed pivot pair
+ * compares the diagonal of Zhat'^T A' Zhat', i.e. the squared norms the two
+ * columns of F will have after the transformation, computed from the pivot
+ * entries without touching the columns:
+ *   a''_11 = Z11^2 a_ii + 2 Z11 Z21 a_ij + Z21^2 a_jj,
+ *   a''_22 = Z12^2 a_ii + 2 Z12 Z22 a_ij + Z22^2 a_jj
+ * (Zh column-major: Z11, Z21, Z12, Z22).  Exported for the tests.
+ */
+void hzo_real_sort_keys(double aii, double ajj, double aij, const double Zh[4], double *a11,
+                        double *a22)
+{
+    *a11 = Zh[0] * Zh[0] * aii + 2.0 * Zh[0] * Zh[1] * aij + Zh[1] * Zh[1] * ajj;
+    *a22 = Zh[2] * Zh[2] * aii + 2.0 * Zh[2] * Zh[3] * aij + Zh[3] * Zh[3] * ajj;
+}
+
+/*
  * One pointwise step on the pivot pair (i, j), i < j (Section 2.1, variant
  * 0, 1, 4 or 5).  Adds to *all and *big and returns nothing else.
  */
@@ -483,8 +499,8 @@ static void step_real(int64_t m_f, int64_t m_g, int64_t n, double *F, int64_t ld
     if (is_big(variant, Zh[0], Zh[3], cc))
         *big += 1;
     if (sort) {
-        const double a11 = Zh[0] * Zh[0] * aii + 2.0 * Zh[0] * Zh[1] * aij + Zh[1] * Zh[1] * ajj;
-        const double a22 = Zh[2] * Zh[2] * aii + 2.0 * Zh[3] * Zh[2] * aij + Zh[3] * Zh[3] * ajj;
+        double a11, a22;
+        hzo_real_sort_keys(aii, ajj, aij, Zh, &a11, &a22);
         if (a11 < a22) {
             double t;
             t = Zh[0]; Zh[0] = Zh[2]; Zh[2] = t;
@@ -640,6 +656,31 @@ static void step_cplx(int64_t m_f, int64_t m_g, int64_t n, zdouble *F, int64_t l
         swap_cols_z(G, ldg, m_g, i, j);
         swap_cols_z(Z, ldz, n, i, j);
     }
+}
+
+/*
+ * Exported for the tests: one pointwise step (Section 2.1) on the pivot pair
+ * (i, j), i < j, of the real or the interleaved complex pair (F, G, Z), exactly
+ * as a sweep takes it (skip test, transformation, counters, sorting).
+ * counts[0] and counts[1] receive the transformation and the big
+ * transformation the step applied (0 or 1 each).
+ */
+void hzo_step_real(int64_t m_f, int64_t m_g, int64_t n, double *F, int64_t ldf, double *G,
+                   int64_t ldg, double *Z, int64_t ldz, int64_t i, int64_t j, double tol,
+                   int sort, int variant, int64_t counts[2])
+{
+    counts[0] = counts[1] = 0;
+    step_real(m_f, m_g, n, F, ldf, G, ldg, Z, ldz, i, j, tol, sort, variant, &counts[0],
+              &counts[1]);
+}
+
+void hzo_step_cplx(int64_t m_f, int64_t m_g, int64_t n, double *F, int64_t ldf, double *G,
+                   int64_t ldg, double *Z, int64_t ldz, int64_t i, int64_t j, double tol,
+                   int sort, int variant, int64_t counts[2])
+{
+    counts[0] = counts[1] = 0;
+    step_cplx(m_f, m_g, n, (zdouble *)F, ldf, (zdouble *)G, ldg, (zdouble *)Z, ldz, i, j, tol,
+              sort, variant, &counts[0], &counts[1]);
 }
 
 /* Complex GSVD; arguments as hzo_dgsvd, with interleaved complex F, G, Z. */

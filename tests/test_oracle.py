@@ -556,3 +556,89 @@ def test_enhanced_variants_complex_same_gsvd(v_enh, v_plain):
     assert np.max(np.abs(e["sigma"] - s_true) / s_true) < 1e-12
     assert_contract(F, G, e["U"], e["V"], e["Z"], e["sigma_f"], e["sigma_g"], e["sigma"])
     assert not np.array_equal(e["Z"], p["Z"])
+
+
+# ------------------------------------------- per-step sorting (Section 3.5.3)
+
+def test_real_sort_keys_are_the_transformed_diagonal():
+    """The real sort keys a''_11, a''_22 must be the diagonal of Z'^T A' Z'
+    (the squared norms the two columns of F get from the transformation),
+    for random pencils, both signs of x, and the exception's matrix."""
+    rng = np.random.default_rng(31)
+    cases = []
+    for _ in range(3000):
+        A = _spd(rng)
+        cases.append((A, rng.uniform(-0.99, 0.99)))
+    for x in (0.6, -0.6, 0.0, -0.95):
+        cases.append((2.5 * np.array([[1.0, x], [x, 1.0]]), x))   # the exception
+    for A, x in cases:
+        Z, _ = oracle.real_2x2(A[0, 0], A[1, 1], A[0, 1], x)
+        k11, k22 = oracle.real_sort_keys(A[0, 0], A[1, 1], A[0, 1], Z)
+        D = Z.T @ A @ Z
+        scale = np.linalg.norm(A) * np.linalg.norm(Z) ** 2
+        assert abs(k11 - D[0, 0]) < 16 * EPS * scale, (k11, D[0, 0])
+        assert abs(k22 - D[1, 1]) < 16 * EPS * scale, (k22, D[1, 1])
+
+
+def _random_step_pair(rng, m, n, cplx):
+    F = rng.standard_normal((m, n))
+    G = rng.standard_normal((m, n))
+    if cplx:
+        F = F + 1j * rng.standard_normal((m, n))
+        G = G + 1j * rng.standard_normal((m, n))
+    # prescaled as the sweeps see it: unit columns of G (Section 2)
+    d = 1.0 / np.linalg.norm(G, axis=0)
+    F, G = F * d, G * d
+    # spread the column norms of F so the sort decision is clear-cut
+    F = F * np.geomspace(1.0, 50.0, n)[rng.permutation(n)]
+    Z = np.diag(d).astype(F.dtype)
+    return F, G, Z
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_sorted_step_puts_the_larger_norm_first(cplx):
+    """After a step with sorting, column i of F has the larger norm (Section
+    3.5.3), and the step is the congruence [f_i f_j] Z' (up to the swap) of
+    the columns it was given: checked against the transformed pair's own
+    norms, in many random pairs where the transformation alone would leave
+    the larger norm second about half of the time."""
+    rng = np.random.default_rng(32 if cplx else 33)
+    swapped = kept = 0
+    for _ in range(400):
+        F, G, Z = _random_step_pair(rng, 9, 4, cplx)
+        i, j = sorted(rng.choice(4, 2, replace=False))
+        F1, G1, Z1, nall, _ = oracle.step(F, G, Z, i, j, sort=True)
+        assert nall == 1
+        ni, nj = np.linalg.norm(F1[:, i]), np.linalg.norm(F1[:, j])
+        assert ni >= nj * (1 - 1e-13), (ni, nj)
+        # unsorted step: the same transformation without the swap
+        F0, G0, Z0, _, _ = oracle.step(F, G, Z, i, j, sort=False)
+        same = np.allclose(F1[:, [i, j]], F0[:, [i, j]], rtol=0, atol=0)
+        flip = np.array_equal(F1[:, [i, j]], F0[:, [j, i]])
+        assert same or flip
+        swapped += flip and not same
+        kept += same
+        # untouched columns stay put; G and Z follow F's swap
+        others = [c for c in range(4) if c not in (i, j)]
+        assert np.array_equal(F1[:, others], F[:, others])
+        order = [j, i] if (flip and not same) else [i, j]
+        assert np.array_equal(G1[:, [i, j]], G0[:, order])
+        assert np.array_equal(Z1[:, [i, j]], Z0[:, order])
+    assert swapped > 50 and kept > 50, (swapped, kept)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_sorted_skip_step_swaps_by_norm(cplx):
+    """An orthogonal pair is not transformed, only sorted: column i gets the
+    larger norm (Section 2.1, the skip test, with the sorting swap)."""
+    rng = np.random.default_rng(34)
+    Q, _ = np.linalg.qr(rng.standard_normal((8, 8)) + (1j * rng.standard_normal((8, 8)) if cplx else 0))
+    F = Q[:, :2] * np.array([1.0, 3.0])          # orthogonal, ||f_0|| < ||f_1||
+    G = Q[:, 2:4]                                  # orthonormal: b_ij = 0
+    Z = np.eye(2, dtype=F.dtype)
+    F1, G1, Z1, nall, _ = oracle.step(F, G, Z, 0, 1, sort=True, tol=1e-8)
+    assert nall == 0
+    assert np.array_equal(F1, F[:, [1, 0]]) and np.array_equal(G1, G[:, [1, 0]])
+    assert np.array_equal(Z1, Z[:, [1, 0]])
+    F2, _, _, _, _ = oracle.step(F, G, Z, 0, 1, sort=False, tol=1e-8)
+    assert np.array_equal(F2, F)
