@@ -200,6 +200,30 @@ def _ld(t):
     return t.stride(1) if t.shape[1] > 1 else max(1, t.shape[0])
 
 
+def aligned_span(ptr: int, size: int):
+    """The 256-byte aligned start inside a buffer of ``size`` bytes at
+    ``ptr`` and the bytes that remain from there (0 if none)."""
+    start = (ptr + 255) & ~255
+    return start, max(0, ptr + size - start)
+
+
+def _workspace(workspace, nbytes, dev):
+    """(aligned pointer, usable bytes, tensor kept alive) for a solve that
+    needs ``nbytes``: the caller's buffer when at least ``nbytes`` remain
+    after aligning its start to 256 bytes, else a fresh allocation.  The
+    usable byte count, not ``nbytes``, is what the library is told, so its
+    own size check sees the real extent of the buffer."""
+    import torch
+    if workspace is not None:
+        wptr, avail = aligned_span(workspace.data_ptr(),
+                                   workspace.numel() * workspace.element_size())
+        if avail >= nbytes:
+            return wptr, avail, workspace
+    workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+    wptr, avail = aligned_span(workspace.data_ptr(), workspace.numel())
+    return wptr, avail, workspace
+
+
 class GsvdError(RuntimeError):
     def __init__(self, status, info):
         msg = lib().hz_strerror(status).decode()
@@ -246,15 +270,13 @@ def gsvd(F, G, *, overwrite=False, raise_on_noconv=False, workspace=None, mixed=
     nbytes = wsz(ctypes.byref(p), m_f, m_g, n)
     if nbytes == 0:
         raise ValueError("invalid shape or parameters")
-    if workspace is None or workspace.numel() < nbytes:
-        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
-    wptr = (workspace.data_ptr() + 255) & ~255
+    wptr, wbytes, workspace = _workspace(workspace, nbytes, dev)
     info = HzInfo()
     stream = torch.cuda.current_stream(dev).cuda_stream
     fn = L.hz_zgsvd if cplx else (L.hz_dgsvd_mixed if mixed else L.hz_dgsvd)
     st = fn(ctypes.byref(p), m_f, m_g, n, _ptr(U), _ld(U), _ptr(V), _ld(V),
                     _ptr(Z), _ld(Z), _ptr(sig), _ptr(sf), _ptr(sg), ctypes.c_void_p(wptr),
-                    nbytes, ctypes.byref(info), ctypes.c_void_p(stream))
+                    wbytes, ctypes.byref(info), ctypes.c_void_p(stream))
     if st < 0:
         raise ValueError(f"{'hz_zgsvd' if cplx else 'hz_dgsvd'} rejected argument {-st}")
     if st in (HZ_ECHOL, HZ_ENONFINITE, HZ_EHIP) or (raise_on_noconv and st == HZ_ENOCONV):
@@ -310,16 +332,14 @@ def gsvd_batched(pairs, *, overwrite=False, workspace=None, **kw):
     nbytes = L.hz_dgsvd_batched_work_size(ctypes.byref(p), batch, mf, mg, nn)
     if nbytes == 0:
         raise ValueError("invalid shapes or parameters")
-    if workspace is None or workspace.numel() < nbytes + 256:
-        workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
-    wptr = (workspace.data_ptr() + 255) & ~255
+    wptr, wbytes, workspace = _workspace(workspace, nbytes, dev)
     infos = (HzInfo * batch)()
     stream = torch.cuda.current_stream(dev).cuda_stream
     st = L.hz_dgsvd_batched(ctypes.byref(p), batch, mf, mg, nn,
                             _ptrs(Us), _i64s([_ld(u) for u in Us]),
                             _ptrs(Vs), _i64s([_ld(v) for v in Vs]),
                             _ptrs(Zs), _i64s([_ld(z) for z in Zs]),
-                            _ptrs(sg_), _ptrs(sfs), _ptrs(sgs), ctypes.c_void_p(wptr), nbytes,
+                            _ptrs(sg_), _ptrs(sfs), _ptrs(sgs), ctypes.c_void_p(wptr), wbytes,
                             infos, ctypes.c_void_p(stream))
     if st < 0:
         raise ValueError(f"hz_dgsvd_batched rejected argument {-st}")

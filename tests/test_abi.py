@@ -368,3 +368,28 @@ except Exception as e:
     assert r.returncode == 0, r.stderr[-800:]
     assert "lib raised" in r.stdout and "gsvd raised" in r.stdout, r.stdout
     assert "LOADED" not in r.stdout and "RESULT" not in r.stdout, r.stdout
+
+
+def test_caller_workspace_is_used_only_when_aligned_space_suffices():
+    """A caller workspace whose start is not 256-byte aligned loses up to 255
+    bytes to the alignment: the binding must not hand the library a buffer
+    shorter than the solve needs, and must tell it the usable size."""
+    import torch
+    import paper_1909_00101_amd as hz
+    assert hz.aligned_span(256, 1000) == (256, 1000)
+    assert hz.aligned_span(264, 1000) == (512, 752)
+    assert hz.aligned_span(264, 100) == (512, 0)
+    need = 4096
+    base = torch.empty(need + 1024, dtype=torch.uint8)
+    off = (-base.data_ptr()) % 256          # first 256-byte boundary inside base
+    aligned = base[off:off + need]
+    wptr, avail, keep = hz._workspace(aligned, need, "cpu")
+    assert keep is aligned and wptr == aligned.data_ptr() and avail == need
+    misaligned = base[off + 8:off + 8 + need]   # exactly `need` bytes, 8 past a boundary
+    wptr, avail, keep = hz._workspace(misaligned, need, "cpu")
+    assert keep is not misaligned and wptr % 256 == 0 and avail >= need
+    assert wptr >= keep.data_ptr() and wptr + need <= keep.data_ptr() + keep.numel()
+    roomy = base[off + 8:]                  # room to spare after aligning
+    wptr, avail, keep = hz._workspace(roomy, need, "cpu")
+    assert keep is roomy and wptr % 256 == 0
+    assert wptr + avail == roomy.data_ptr() + roomy.numel() and avail >= need

@@ -87,3 +87,25 @@ def test_small_n_bordered_to_the_widest_block(n):
     assert max_rel(res["sigma"], oracle.gsvd(F, G)["sigma"]) < SIG_TOL
     assert_contract(F, G, res["U"], res["V"], res["Z"], res["sigma_f"], res["sigma_g"],
                     res["sigma"], tol_res=1e-12, tol_orth=1e-12)
+
+
+def test_misaligned_exact_workspace_is_not_overrun():
+    """A caller workspace 8 bytes past a 256-byte boundary holding exactly
+    the bytes the solve needs: the binding may not place the aligned
+    workspace past its end.  Bytes after the view must stay untouched, and
+    the solve must be bitwise the one with a fresh workspace."""
+    hz = _hz()
+    F, G, _ = gi.custom_pair(90, 70, 24, kappa=10.0, seed=520)
+    dF = torch.from_numpy(np.asfortranarray(F)).cuda()
+    dG = torch.from_numpy(np.asfortranarray(G)).cuda()
+    p = hz.params(w=8)
+    need = hz.lib().hz_dgsvd_work_size(ctypes.byref(p), 90, 70, 24)
+    base = torch.full((need + 2048,), 0xA5, dtype=torch.uint8, device="cuda")
+    off = (-base.data_ptr()) % 256 + 8
+    view = base[off:off + need]
+    ref = hz.gsvd(dF, dG, w=8)
+    got = hz.gsvd(dF, dG, w=8, workspace=view)
+    torch.cuda.synchronize()
+    assert torch.all(base[off + need:] == 0xA5).item()
+    for k in ("U", "V", "Z", "sigma", "sigma_f", "sigma_g"):
+        assert torch.equal(ref[k], got[k]), k
