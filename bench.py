@@ -9,14 +9,20 @@ steps to convergence, extraction and sort), inputs resident in HBM; before
 each solve the pair is restored from pristine device copies (two 32 MiB
 device-to-device copies, inside the timed region, <0.1% of a solve).
 
-Prints one JSON line: solves/s, the measured per-kernel split, the roofline
-entry of the dominant kernel (algorithmic bytes or flops per launch over its
-average launch time, measured with HIP events on the solve's stream) and the
-CPU oracle timed on a bounded sample on the host.  Unless --no-forms is
-given, the line also carries the mixed-precision form against plain FP64 on
-the 8192 x 2048 pair and the batched form against a loop of single-pair
-solves on the 512-pair ensemble (wall time of each, same parameters, with
-the accuracy each reaches).
+The headline region times exactly what ships: the library's default path
+(sweeps replayed from a cached hipGraph), no events.  Afterwards, outside
+that region: one solve with per-call timing (hz_params.timing) gives the
+per-kernel split, and a second timed region of the same solves brackets
+only the dominant kernel's launches with HIP events on the solve's stream,
+which gives that kernel's average launch time for the roofline entry
+(algorithmic bytes or flops per launch over it).
+
+Prints one JSON line: solves/s, the split, the roofline entry, the CPU
+oracle timed on one complete solve of the same pair on the host cores, and
+(unless --no-forms) the QR-shortened, mixed-precision, complex and batched
+forms, each with absolute times, its fraction of the FP64 MFMA and HBM
+rooflines from the algorithmic work of the sweeps it executed, and its
+error against the oracle's sigma for the same seeded pair.
 """
 
 import argparse
@@ -33,20 +39,28 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFS = 78.6
+FP32_MFMA_PEAK_TFS = 157.3
 METRIC = "GSVD solves/s + FP64 MFMA util, 4096x1024 pair; mixed/batched vs plain"
+GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_config%d.json")
 
 
-def algorithmic(m_f, m_g, n, w):
+def algorithmic(m_f, m_g, n, w, esz=8, cmul=1):
     """Algorithmic work per launch of each block-step kernel (one step =
-    n/(2w) pivot pairs).  Gram: reads all of F and G once, 8 n (m_F+m_G)
+    n/(2w) pivot pairs).  Gram: reads all of F and G once, esz n (m_F+m_G)
     bytes; 2w(2w+1)(m_F+m_G) flops per pair using symmetry.  Update: reads
-    and writes all of F, G, Z, 16 n (m_F+m_G+n) bytes; 2 (2w)^2 (m_F+m_G+n)
-    flops per pair."""
+    and writes all of F, G, Z, 2 esz n (m_F+m_G+n) bytes; 2 (2w)^2
+    (m_F+m_G+n) flops per pair.  esz is the element size (8 FP64, 4 FP32,
+    16 complex128); cmul = 4 counts a complex multiply-add as 8 flops."""
     pairs = n // (2 * w)
-    gram = dict(bytes=8.0 * n * (m_f + m_g), flops=pairs * 2.0 * w * (2 * w + 1) * (m_f + m_g))
-    upd = dict(bytes=16.0 * n * (m_f + m_g + n),
-               flops=pairs * 2.0 * (2 * w) ** 2 * (m_f + m_g + n))
+    gram = dict(bytes=float(esz) * n * (m_f + m_g),
+                flops=cmul * pairs * 2.0 * w * (2 * w + 1) * (m_f + m_g))
+    upd = dict(bytes=2.0 * esz * n * (m_f + m_g + n),
+               flops=cmul * pairs * 2.0 * (2 * w) ** 2 * (m_f + m_g + n))
     return gram, upd
+
+
+def nw_of(n, w):
+    return (n + 2 * w - 1) // (2 * w) * (2 * w)
 
 
 def inner_flops(w, launches, inner_sweeps, rotations, npairs, isteps):
@@ -63,20 +77,87 @@ def inner_flops(w, launches, inner_sweeps, rotations, npairs, isteps):
     return (chol + dots + apply) / max(1, launches)
 
 
-def cpu_baseline(F, G, tol, golden_sweeps):
-    """Time one sweep of the CPU oracle (modified-modulus ordering, OpenMP over
-    the disjoint pairs of each step, all host threads) on the same pair, and
-    scale by the oracle's sweep count for this pair to solves/s."""
+def solve_work(m_f, m_g, n, w, sweeps, esz=8, cmul=1, skipped=0):
+    """Algorithmic flops and HBM bytes of `sweeps` complete outer sweeps
+    (every step forms its Gram blocks and, unless skipped, updates), with
+    the bordered column count; `skipped` block updates are not counted."""
+    nw = nw_of(n, w)
+    steps = nw // w
+    gram, upd = algorithmic(m_f, m_g, nw, w, esz, cmul)
+    pairs = nw // (2 * w)
+    upd_pair_f, upd_pair_b = upd["flops"] / pairs, upd["bytes"] / pairs
+    flops = sweeps * steps * (gram["flops"] + upd["flops"]) - skipped * upd_pair_f
+    byts = sweeps * steps * (gram["bytes"] + upd["bytes"]) - skipped * upd_pair_b
+    return flops, byts
+
+
+def roof_of(flops, byts, seconds, peak_tfs=FP64_MFMA_PEAK_TFS):
+    """Whole-solve throughput from algorithmic work: TFLOP/s against the
+    MFMA peak and GB/s against the HBM peak."""
+    if seconds <= 0:
+        return None
+    tf = flops / seconds / 1e12
+    gb = byts / seconds / 1e9
+    return dict(tflops=round(tf, 3), frac_mfma=round(tf / peak_tfs, 4), mfma_peak=peak_tfs,
+                hbm_GBs=round(gb, 1), frac_hbm=round(gb / HBM_PEAK_GBS, 4))
+
+
+def kernel_roofs(times_ms, launches, gram, upd, peak_tfs=FP64_MFMA_PEAK_TFS):
+    """Per-kind average launch time and the Gram and update kernels'
+    algorithmic GB/s and TFLOP/s (with fractions of the peaks) from one
+    call's per-kind times and launch count."""
+    out = {}
+    for k in ("gram", "inner", "update"):
+        t = times_ms[k] / max(1, launches) * 1e-3
+        e = dict(avg_us=round(t * 1e6, 2), total_ms=round(times_ms[k], 3))
+        wd = gram if k == "gram" else upd if k == "update" else None
+        if wd is not None and t > 0:
+            e["GB_s"] = round(wd["bytes"] / t / 1e9, 1)
+            e["frac_hbm"] = round(wd["bytes"] / t / 1e9 / HBM_PEAK_GBS, 4)
+            e["TFLOP_s"] = round(wd["flops"] / t / 1e12, 2)
+            e["frac_mfma"] = round(wd["flops"] / t / 1e12 / peak_tfs, 4)
+        out[k] = e
+    return out
+
+
+def golden_sigma(k):
+    p = GOLDEN % k
+    if not os.path.exists(p):
+        return None, None
+    with open(p) as fh:
+        g = json.load(fh)
+    return np.array(g["sigma"]), g
+
+
+def max_rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b)) / np.abs(np.asarray(b))))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(F, G, tol):
+    """One complete solve of the same pair by the CPU oracle (unblocked,
+    modified-modulus ordering, OpenMP over the disjoint pairs of each step,
+    all host threads), timed on the host."""
     import oracle
     threads = len(os.sched_getaffinity(0))
     t0 = time.perf_counter()
-    r = oracle.gsvd(F, G, ordering=oracle.ORD_MM, tol=tol, max_sweeps=1, threads=threads)
+    r = oracle.gsvd(F, G, ordering=oracle.ORD_MM, tol=tol, max_sweeps=30, threads=threads)
     dt = time.perf_counter() - t0
-    sweeps = golden_sweeps
-    return dict(value=1.0 / (dt * sweeps), unit="solves/s", cores=threads, kind="oracle",
-                sample=f"one full sweep ({r['rot_all']} pointwise steps) of the unblocked "
-                       f"oracle on the 4096x1024 pair took {dt:.2f} s on {threads} threads; "
-                       f"scaled by the {sweeps} sweeps the oracle needs on this pair")
+    return dict(value=1.0 / dt, unit="solves/s", cores=threads, kind="oracle",
+                sample=f"one complete solve of the 4096x1024 pair by the unblocked oracle "
+                       f"({r['sweeps']} sweeps, {r['rot_all']} pointwise transformations) "
+                       f"took {dt:.1f} s on {threads} threads",
+                cpu_model=cpu_model(), seconds=round(dt, 2), sweeps=r["sweeps"]), r
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gsvd_real_4096x1024_w32_bo_traffic.txt")
@@ -84,16 +165,19 @@ KERNEL_SOURCES = ["paper_1909_00101_amd/csrc/hz_real.hip", "paper_1909_00101_amd
                   "paper_1909_00101_amd/csrc/hz_device.h"]
 
 
+def source_sha():
+    import hashlib
+    return hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read()
+                                   for f in KERNEL_SOURCES)).hexdigest()[:16]
+
+
 def measured_traffic():
     """HBM bytes per dispatch of each kernel of the 4096x1024 workload, from
     the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (each counter
     scaled by its reading for a 32 MiB device copy).  Empty when the kernel
     sources have changed since the counters were taken."""
-    import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return {}
-    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read()
-                                for f in KERNEL_SOURCES)).hexdigest()[:16]
     out, sha = {}, None
     for line in open(TRAFFIC_FILE):
         if line.startswith("#") or not line.strip():
@@ -103,7 +187,7 @@ def measured_traffic():
             sha = t[1]
         elif len(t) == 7:
             out[t[0]] = (float(t[5]) + float(t[6])) * 2.0 ** 20
-    return out if sha == h else {}
+    return out if sha == source_sha() else {}
 
 
 def _timed(fn, reps):
@@ -119,35 +203,70 @@ def _timed(fn, reps):
     return best, out
 
 
+def _form_entry(name, r, dt, spec_mnw, err_ref, s_true, esz=8, cmul=1, timing=None,
+                extra_flops=0.0, extra_bytes=0.0, fp32=None):
+    """Absolute time, algorithmic throughput of the executed sweeps as
+    fractions of the FP64 MFMA and HBM peaks, errors, and (from a timed
+    call) the per-kind split of one form."""
+    m_f, m_g, n, w = spec_mnw
+    f, b = solve_work(m_f, m_g, n, w, r["sweeps"], esz, cmul, r.get("updates_skipped", 0))
+    if fp32 is not None:     # the mixed form's FP32 sweeps move half the bytes
+        f32, b32 = solve_work(m_f, m_g, n, w, r["sweeps_fp32"], 4, 1)
+        f, b = f + f32, b + b32
+    f, b = f + extra_flops, b + extra_bytes
+    e = dict(ms=round(dt * 1e3, 2), status=r["status"], sweeps=r["sweeps"],
+             roofline=roof_of(f, b, dt))
+    if fp32 is not None:
+        e["sweeps_fp32"] = r["sweeps_fp32"]
+        e["fp32_offdiag"] = [float("%.3g" % x) for x in r.get("fp32_offdiag", [])]
+    if err_ref is not None:
+        e["max_rel_sigma_err_vs_oracle"] = max_rel(r["sigma"], err_ref)
+    e["max_rel_sigma_err_vs_prescribed"] = max_rel(r["sigma"], s_true)
+    if timing is not None:
+        e["split_ms"] = {k: round(v, 2) for k, v in timing.items()}
+    return e
+
+
 def mixed_vs_plain(reps=2):
     """hz_dgsvd_mixed against hz_dgsvd on the seeded 8192 x 2048 pair (w = 32,
     one inner sweep, tol = n eps, the same launch parameters for both, the
     switch to FP64 at the default off-diagonal measure 1e-5), and both again
     on the QR-shortened pair (qr_shorten = 1); all restore the pair from
-    device copies inside the timed call (two 128 MiB copies)."""
+    device copies inside the timed call (two 128 MiB copies).  Errors are
+    against the oracle's sigma for the same pair (golden file)."""
     import torch
     import gsvd_inputs as gi
     import paper_1909_00101_amd as hz
     spec = gi.CONFIGS[4]
     F, G, s_true = gi.config_pair(4)
+    gold, _ = golden_sigma(4)
     dev = torch.device("cuda:0")
     F0, G0 = torch.from_numpy(F).to(dev), torch.from_numpy(G).to(dev)
     Fw, Gw = F0.clone(), G0.clone()
     kw = dict(w=32, inner_max_sweeps=1, tol=spec.n * np.finfo(np.float64).eps, gram_splits=8,
               update_rows=64)
+    work = torch.empty(4 << 30, dtype=torch.uint8, device=dev)
     res = {}
+    mnw = (spec.m_f, spec.m_g, spec.n, 32)
     for name, mixed, short in (("plain", False, 0), ("mixed", True, 0),
                                ("plain_shortened", False, 1), ("mixed_shortened", True, 1)):
-        def run():
+        def run(**extra):
             Fw.copy_(F0)
             Gw.copy_(G0)
-            return hz.gsvd(Fw, Gw, overwrite=True, mixed=mixed, qr_shorten=short, **kw)
+            return hz.gsvd(Fw, Gw, overwrite=True, mixed=mixed, qr_shorten=short, workspace=work,
+                           **kw, **extra)
         run()
         dt, r = _timed(run, reps)
-        err = float(np.max(np.abs(r["sigma"].cpu().numpy() - s_true) / s_true))
-        res[name] = dict(ms=round(dt * 1e3, 2), sweeps_fp64=r["sweeps"],
-                         sweeps_fp32=r["sweeps_fp32"], max_rel_sigma_err=err, status=r["status"])
-    del F0, G0, Fw, Gw
+        r = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in r.items()}
+        tr = run(timing=1)["times_ms"]
+        # the FP64 restart F Z32, G Z32: 2 (m_F + m_G) n^2 flops, reads F, G, Z32 and
+        # writes the FP64 iterates
+        ef = 2.0 * (spec.m_f + spec.m_g) * spec.n ** 2 if mixed else 0.0
+        eb = (16.0 * (spec.m_f + spec.m_g) * spec.n + 4.0 * spec.n ** 2) if mixed else 0.0
+        m_eff = (spec.n, spec.n) if short else (spec.m_f, spec.m_g)
+        res[name] = _form_entry(name, r, dt, (*m_eff, spec.n, 32), gold, s_true, timing=tr,
+                                extra_flops=ef, extra_bytes=eb, fp32=True if mixed else None)
+    del F0, G0, Fw, Gw, work
     torch.cuda.empty_cache()
     return dict(workload=f"seeded {spec.m_f}x{spec.n} real pair, kappa(X)=1e2, w=32, "
                          f"one inner sweep, tol=n*eps, 8 Gram splits, 64 update rows per wave",
@@ -161,29 +280,35 @@ def complex_shortened_vs_plain(reps=2):
     """hz_zgsvd on the seeded complex 3072x1024 / 2048x1024 pair (kappa(X) =
     50, w = 16, modified-modulus outer and inner orderings, one inner sweep,
     tol = n eps) plain and QR-shortened; both restore the pair from device
-    copies inside the timed call."""
+    copies inside the timed call.  Complex work counts a complex
+    multiply-add as 8 real flops and 16 bytes per element."""
     import torch
     import gsvd_inputs as gi
     import paper_1909_00101_amd as hz
     spec = gi.CONFIGS[3]
     F, G, s_true = gi.config_pair(3)
+    gold, _ = golden_sigma(3)
     dev = torch.device("cuda:0")
     F0, G0 = torch.from_numpy(F).to(dev), torch.from_numpy(G).to(dev)
     Fw, Gw = F0.clone(), G0.clone()
     kw = dict(w=16, ordering=hz.HZ_ORD_MM, inner_ordering=hz.HZ_ORD_MM, inner_max_sweeps=1,
               tol=spec.n * np.finfo(np.float64).eps)
+    work = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
     res = {}
     for name, short in (("plain", 0), ("shortened", 1)):
-        def run():
+        def run(**extra):
             Fw.copy_(F0)
             Gw.copy_(G0)
-            return hz.gsvd(Fw, Gw, overwrite=True, qr_shorten=short, **kw)
+            return hz.gsvd(Fw, Gw, overwrite=True, qr_shorten=short, workspace=work, **kw,
+                           **extra)
         run()
         dt, r = _timed(run, reps)
-        err = float(np.max(np.abs(r["sigma"].cpu().numpy() - s_true) / s_true))
-        res[name] = dict(ms=round(dt * 1e3, 2), sweeps=r["sweeps"], max_rel_sigma_err=err,
-                         status=r["status"])
-    del F0, G0, Fw, Gw
+        r = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in r.items()}
+        tr = run(timing=1)["times_ms"]
+        m_eff = (spec.n, spec.n) if short else (spec.m_f, spec.m_g)
+        res[name] = _form_entry(name, r, dt, (*m_eff, spec.n, 16), gold, s_true, esz=16,
+                                cmul=4, timing=tr)
+    del F0, G0, Fw, Gw, work
     torch.cuda.empty_cache()
     return dict(workload=f"seeded complex {spec.m_f}x{spec.n} / {spec.m_g}x{spec.n} pair, "
                          "kappa(X)=50, w=16, MM outer and inner orderings, one inner sweep, "
@@ -191,13 +316,18 @@ def complex_shortened_vs_plain(reps=2):
                 speedup=round(res["plain"]["ms"] / res["shortened"]["ms"], 3), **res)
 
 
-def batched_vs_plain(tune_cache=None, reps=3):
+def batched_vs_plain(tune_cache=None, reps=3, oracle_sample=16):
     """hz_dgsvd_batched on the 512-pair ensemble (n ~ U{16..256}, m ~ U{n..2n})
     against hz_dgsvd called on each pair in turn, both with the parameters
-    the batched autotuner picks (or its defaults with one inner sweep); the
-    pairs are restored from device copies in both."""
+    the batched autotuner picks (or its defaults with one inner sweep).
+    Every pair of the loop keeps its own workspace, so from the second pass
+    on each call replays its cached sweep graph; the loop is timed after one
+    untimed pass.  The pairs are restored from device copies in both.  The
+    error of a sample of pairs (the largest first) is taken against the
+    oracle, every pair's against its prescribed sigma."""
     import torch
     import gsvd_inputs as gi
+    import oracle
     import paper_1909_00101_amd as hz
     pairs = gi.make_batch()
     dev = torch.device("cuda:0")
@@ -207,6 +337,11 @@ def batched_vs_plain(tune_cache=None, reps=3):
     kw = dict(inner_max_sweeps=1)
     if tune_cache is not None:
         kw, _ = hz.tune_batched(D, cache=tune_cache)
+    works = []
+    for f, g in W:
+        p = hz.params(**kw)
+        nb = hz.lib().hz_dgsvd_work_size(ctypes.byref(p), f.shape[0], g.shape[0], f.shape[1])
+        works.append(torch.empty(nb + 256, dtype=torch.uint8, device=dev))
 
     def restore():
         for (f0, g0), (f, g) in zip(D, W):
@@ -219,19 +354,37 @@ def batched_vs_plain(tune_cache=None, reps=3):
 
     def loop():
         restore()
-        return [hz.gsvd(f, g, overwrite=True, **kw) for f, g in W]
+        return [hz.gsvd(f, g, overwrite=True, workspace=wk, **kw) for (f, g), wk in zip(W, works)]
 
     batched()
     tb, (st, outs) = _timed(batched, reps)
-    eb = max(float(np.max(np.abs(o["sigma"].cpu().numpy() - s) / s)) for o, s in zip(outs, S))
+    sig_b = [o["sigma"].cpu().numpy() for o in outs]
+    eb = max(max_rel(s, t) for s, t in zip(sig_b, S))
+    loop()
     tl, louts = _timed(loop, 1)
-    el = max(float(np.max(np.abs(o["sigma"].cpu().numpy() - s) / s)) for o, s in zip(louts, S))
+    el = max(max_rel(o["sigma"].cpu().numpy(), t) for o, t in zip(louts, S))
+    order = sorted(range(len(pairs)), key=lambda i: -pairs[i][0].shape[1] * pairs[i][0].shape[0])
+    eo = 0.0
+    for i in order[:oracle_sample]:
+        F, G, _ = pairs[i]
+        ref = oracle.gsvd(F, G, ordering=oracle.ORD_MM, tol=0.0,
+                          threads=len(os.sched_getaffinity(0)))
+        eo = max(eo, max_rel(sig_b[i], ref["sigma"]))
+    w = kw.get("w") or 16
+    fl = by = 0.0
+    for (F, G, _), o in zip(pairs, outs):
+        f, b = solve_work(F.shape[0], G.shape[0], F.shape[1], w, o["sweeps"])
+        fl, by = fl + f, by + b
     return dict(workload="512 seeded real pairs, n~U{16..256}, m_F,m_G~U{n..2n}, "
                          "kappa log-uniform in [1,1e2]", params=kw,
                 batched_ms=round(tb * 1e3, 2), loop_ms=round(tl * 1e3, 2),
                 speedup=round(tl / tb, 2), pairs_per_s=round(len(pairs) / tb, 1),
                 status=st, max_sweeps=max(o["sweeps"] for o in outs),
-                max_rel_sigma_err_batched=eb, max_rel_sigma_err_loop=el)
+                roofline=roof_of(fl, by, tb),
+                max_rel_sigma_err_batched_vs_prescribed=eb,
+                max_rel_sigma_err_loop_vs_prescribed=el,
+                max_rel_sigma_err_batched_vs_oracle=eo,
+                oracle_sample=f"the {oracle_sample} largest pairs")
 
 
 def qr_shortened_vs_plain(F0, G0, s_true, tol, plain_kw, tune_cache=None, reps=3):
@@ -244,27 +397,33 @@ def qr_shortened_vs_plain(F0, G0, s_true, tol, plain_kw, tune_cache=None, reps=3
     width free), or w = 16 with one inner sweep without the tuner."""
     import torch
     import paper_1909_00101_amd as hz
+    gold, _ = golden_sigma(2)
     Fw, Gw = F0.clone(), G0.clone()
     skw = dict(w=16, inner_max_sweeps=1)
     if tune_cache is not None:
         skw, _ = hz.tune(F0, G0, cache=tune_cache, ordering=hz.HZ_ORD_MM, tol=tol, qr_shorten=1,
                          inner_ordering=0)
     skw = dict(skw, ordering=hz.HZ_ORD_MM, tol=tol, qr_shorten=1)
+    work = torch.empty(1 << 30, dtype=torch.uint8, device=F0.device)
+    m_f, n = F0.shape
+    m_g = G0.shape[0]
     res = {}
     for name, kw in (("plain", plain_kw), ("shortened", skw)):
-        def run():
+        def run(**extra):
             Fw.copy_(F0)
             Gw.copy_(G0)
-            return hz.gsvd(Fw, Gw, overwrite=True, **kw)
+            return hz.gsvd(Fw, Gw, overwrite=True, workspace=work, **kw, **extra)
         run()
         dt, r = _timed(run, reps)
-        err = float(np.max(np.abs(r["sigma"].cpu().numpy() - s_true) / s_true))
-        res[name] = dict(ms=round(dt * 1e3, 2), sweeps=r["sweeps"], max_rel_sigma_err=err,
-                         status=r["status"],
-                         params={k: kw[k] for k in ("w", "inner_ordering", "inner_max_sweeps",
-                                                    "inner_lanes", "gram_splits", "update_rows")
-                                 if k in kw})
-    del Fw, Gw
+        r = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in r.items()}
+        tr = run(timing=1)["times_ms"]
+        w = kw["w"]
+        m_eff = (n, n) if name == "shortened" else (m_f, m_g)
+        res[name] = _form_entry(name, r, dt, (*m_eff, n, w), gold, s_true, timing=tr)
+        res[name]["params"] = {k: kw[k] for k in ("w", "inner_ordering", "inner_max_sweeps",
+                                                  "inner_lanes", "gram_splits", "update_rows")
+                               if k in kw}
+    del Fw, Gw, work
     torch.cuda.empty_cache()
     return dict(workload="the headline pair (seeded 4096x1024, kappa(X)=1e2), MM ordering, "
                          "tol=1024*eps", speedup=round(res["plain"]["ms"] / res["shortened"]["ms"], 3),
@@ -322,6 +481,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--w", type=int, default=32)
     ap.add_argument("--inner-max-sweeps", type=int, default=1)
+    ap.add_argument("--kernel-reps", type=int, default=3,
+                    help="solves in the region that times the dominant kernel's launches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the QR-shortened, mixed-precision, complex and batched comparisons")
@@ -375,56 +536,57 @@ def main():
     nbytes = hz.lib().hz_dgsvd_work_size(ctypes.byref(p), spec.m_f, spec.m_g, spec.n)
     work = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
 
-    def solve():
+    def solve(**extra):
         Fw.copy_(F0)
         Gw.copy_(G0)
-        return hz.gsvd(Fw, Gw, overwrite=True, workspace=work, **kw)
+        return hz.gsvd(Fw, Gw, overwrite=True, workspace=work, **kw, **extra)
 
     for _ in range(args.warmup):
         r = solve()
-    torch.cuda.synchronize()
     L = hz.lib()
-    # untimed pass with events around every launch: the per-kernel split
-    L.hz_profile_enable(1)
-    solve()
-    torch.cuda.synchronize()
-    ms = (ctypes.c_double * 4)()
-    cnt = (ctypes.c_int64 * 4)()
-    L.hz_profile_read(ms, cnt, 4)
-    kind_index = {"gram": 0, "inner": 1, "update": 2}
-    dom = max(kind_index, key=lambda k: ms[kind_index[k]])
-    split_ms = {k: (ms[i], cnt[i]) for k, i in kind_index.items()}
-    split_pass = dict(split_ms)
-    # timed region: events only around the dominant kernel's launches (events
-    # around every launch would stretch the solve by about 10 %)
-    L.hz_profile_enable(4 + kind_index[dom])
+    L.hz_profile_enable(0)
+    # ---- headline: the shipped path, nothing instrumented
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sweeps, isw, rots = [], 0, 0
+    sweeps, isw, rots, skipped = [], 0, 0, 0
     for _ in range(args.steps):
         r = solve()
         sweeps.append(r["sweeps"])
         isw += r["inner_sweeps"]
         rots += r["rot_total"]
+        skipped += r["updates_skipped"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    err = max_rel(r["sigma"].cpu().numpy(), s_true)
+    gold, _ = golden_sigma(2)
+    err_o = max_rel(r["sigma"].cpu().numpy(), gold) if gold is not None else None
+
+    # ---- per-kernel split: one solve with per-call timing (not timed above)
+    rt = solve(timing=1)
+    split_ms = rt["times_ms"]
+    kind_index = {"gram": 0, "inner": 1, "update": 2}
+    dom = max(kind_index, key=lambda k: split_ms[k])
+    # ---- dominant kernel: events around its launches only, in a region of
+    # its own; average launch time = accumulated event time / launches
+    L.hz_profile_enable(4 + kind_index[dom])
+    torch.cuda.synchronize()
+    for _ in range(args.kernel_reps):
+        solve()
+    torch.cuda.synchronize()
+    ms = (ctypes.c_double * 4)()
+    cnt = (ctypes.c_int64 * 4)()
     L.hz_profile_read(ms, cnt, 4)
     L.hz_profile_enable(0)
-    split_ms[dom] = (ms[kind_index[dom]], cnt[kind_index[dom]])
-    err = float(np.max(np.abs(r["sigma"].cpu().numpy() - s_true) / s_true))
+    t_launch = ms[kind_index[dom]] / max(1, cnt[kind_index[dom]]) * 1e-3
 
-    gram, upd = algorithmic(spec.m_f, spec.m_g, spec.n, args.w)
-    npairs = spec.n // (2 * args.w)
-    launches_timed = sum(sweeps) * (spec.n // args.w)     # inner launches in the timed solves
-    isteps = 2 * args.w if kw.get("inner_ordering") == hz.HZ_ORD_MM else 2 * args.w - 1
-    inner = dict(flops=inner_flops(args.w, launches_timed, isw, rots, npairs, isteps),
-                 bytes=None)
-    kinds = {"gram": (*split_ms["gram"], gram), "inner": (*split_ms["inner"], inner),
-             "update": (*split_ms["update"], upd)}
-    split = {k: round(v[0] / max(1e-9, sum(x[0] for x in split_pass.values())), 4)
-             for k, v in split_pass.items()}
-    t_launch = kinds[dom][0] / max(1, kinds[dom][1]) * 1e-3
-    work_d = kinds[dom][2]
+    w = args.w
+    gram, upd = algorithmic(spec.m_f, spec.m_g, spec.n, w)
+    npairs = spec.n // (2 * w)
+    steps_per_sweep = spec.n // w
+    launches_timed = sum(sweeps) * steps_per_sweep
+    isteps = 2 * w if kw.get("inner_ordering") == hz.HZ_ORD_MM else 2 * w - 1
+    inner = dict(flops=inner_flops(w, launches_timed, isw, rots, npairs, isteps), bytes=None)
+    work_d = {"gram": gram, "inner": inner, "update": upd}[dom]
     ridge = FP64_MFMA_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
     if dom == "inner":
         # latency-bound FP64 VALU work on one workgroup per pivot pair
@@ -447,33 +609,30 @@ def main():
             roof = dict(bound="mfma", achieved=round(achieved, 2), peak=FP64_MFMA_PEAK_TFS,
                         unit="TFLOP/s", frac=round(achieved / FP64_MFMA_PEAK_TFS, 4),
                         traffic=None)
-    lp = kw.get("inner_lanes") or (16 if args.w == 32 else 8)
-    names = {"gram": [f"hz::k_gram<{2 * args.w}>", f"hz::k_gram_sum<{2 * args.w}>"],
-             "inner": [f"hz::k_inner<{2 * args.w},{lp}>"],
-             "update": [f"hz::k_update<{2 * args.w}>"]}
+    lp = kw.get("inner_lanes") or (16 if w == 32 else 8)
+    names = {"gram": [f"hz::k_gram<{2 * w}>", f"hz::k_gram_sum<{2 * w}>"],
+             "inner": [f"hz::k_inner<{2 * w},{lp}>"],
+             "update": [f"hz::k_update<{2 * w}>"]}
     traffic = measured_traffic()
     tr = {k: (sum(traffic[n] for n in v) if all(n in traffic for n in v) else None)
           for k, v in names.items()}
     roof["traffic"] = tr[dom]
     roof["kernel"] = "+".join(names[dom])
     roof["avg_launch_us"] = round(t_launch * 1e6, 2)
+    roof["launches_timed"] = int(cnt[kind_index[dom]])
     if intensity is not None:
         roof["intensity_flop_per_byte"] = round(intensity, 2)
-    per_kernel = {k: dict(avg_us=round(v[0] / max(1, v[1]) * 1e3, 2), launches=int(v[1]))
-                  for k, v in kinds.items()}
-    for k in kinds:
+    tot = sum(split_ms[k] for k in kind_index)
+    split = {k: round(split_ms[k] / max(1e-9, tot), 4) for k in kind_index}
+    per_kernel = kernel_roofs(split_ms, rt["sweeps"] * steps_per_sweep, gram, upd)
+    for k in per_kernel:
         per_kernel[k]["traffic_bytes"] = tr[k]
-    for k in ("gram", "update"):
-        wd = kinds[k][2]
-        t = kinds[k][0] / max(1, kinds[k][1]) * 1e-3
-        per_kernel[k]["GB_s"] = round(wd["bytes"] / t / 1e9, 1) if t > 0 else None
-        per_kernel[k]["TFLOP_s"] = round(wd["flops"] / t / 1e12, 2) if t > 0 else None
-    # whole-solve FP64 MFMA utilisation from algorithmic flops of the executed steps
-    steps_per_sweep = spec.n // args.w
+    # whole-solve algorithmic work of the executed steps (skipped updates excluded)
     mean_sweeps = float(np.mean(sweeps))
-    solve_flops = mean_sweeps * steps_per_sweep * (gram["flops"] + upd["flops"])
+    sflops, sbytes = solve_work(spec.m_f, spec.m_g, spec.n, w, mean_sweeps,
+                                skipped=skipped / max(1, args.steps))
     solves_per_s = args.steps / dt
-    mfma_util = solve_flops * solves_per_s / (FP64_MFMA_PEAK_TFS * 1e12)
+    mfma_util = sflops * solves_per_s / (FP64_MFMA_PEAK_TFS * 1e12)
 
     out = dict(metric=METRIC, value=round(solves_per_s, 3), unit="solves/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=round(dt / args.steps * 1e3, 3),
@@ -481,14 +640,17 @@ def main():
                data="synthetic",
                config=dict(workload="blocked real FP64 GSVD of a seeded 4096x1024 pair "
                                     "(kappa(X)=1e2, sigma log-uniform in [1e-3,1e3])",
-                           m_f=spec.m_f, m_g=spec.m_g, n=spec.n, w=args.w, ordering="MM",
+                           m_f=spec.m_f, m_g=spec.m_g, n=spec.n, w=w, ordering="MM",
                            tol="1024*eps", parallelism="single GPU",
                            launch={k: kw[k] for k in ("inner_ordering", "inner_max_sweeps",
                                                       "inner_lanes", "gram_splits",
                                                       "update_rows") if k in kw}),
-               sweeps=sweeps, max_rel_sigma_err_vs_prescribed=err,
+               sweeps=sweeps, updates_skipped_per_solve=skipped / max(1, args.steps),
+               max_rel_sigma_err_vs_prescribed=err, max_rel_sigma_err_vs_oracle=err_o,
                fp64_mfma_util_solve=round(mfma_util, 4),
-               kernel_time_split=split, kernels=per_kernel, roofline=roof)
+               hbm_frac_solve=round(sbytes * solves_per_s / (HBM_PEAK_GBS * 1e9), 4),
+               kernel_time_split=split, split_ms={k: round(v, 2) for k, v in split_ms.items()},
+               kernels=per_kernel, roofline=roof)
     if not args.no_forms:
         out["transfer_inclusive"] = transfer_inclusive(F, G, Fw, Gw, work, kw)
         out["forms"] = dict(
@@ -496,12 +658,10 @@ def main():
             mixed=mixed_vs_plain(), complex=complex_shortened_vs_plain(),
             batched=batched_vs_plain(tune_cache))
     if not args.no_cpu_baseline:
-        golden = os.path.join(ROOT, "tests", "golden", "oracle_config2.json")
-        gs = None
-        if os.path.exists(golden):
-            with open(golden) as fh:
-                gs = json.load(fh)["sweeps"]
-        out["cpu_baseline"] = cpu_baseline(F, G, tol, gs if gs else int(round(mean_sweeps)))
+        cb, ro = cpu_baseline(F, G, tol)
+        if gold is not None:
+            cb["oracle_matches_golden"] = bool(np.array_equal(ro["sigma"], gold))
+        out["cpu_baseline"] = cb
     print(json.dumps(out))
 
 

@@ -127,6 +127,10 @@ typedef struct hz_params {
                              Householder factorizations of row tiles) instead of Cholesky
                              factorizations of their Grams, for pairs whose block columns are
                              too ill-conditioned for the Grams; 0 (default) = Grams */
+    int timing;           /* 1 = fill hz_info.t_gram, t_inner, t_update, t_other for this call:
+                             HIP events bracket every Gram, inner-solve and update launch and
+                             the sweeps are launched directly instead of replayed from a
+                             captured graph (a few per cent slower); 0 (default) = no timing */
 } hz_params;
 
 typedef struct hz_info {
@@ -140,6 +144,18 @@ typedef struct hz_info {
     double last_offdiag;  /* mixed form: off-diagonal measure of the last FP32 sweep */
     uint64_t inner_sweeps;/* inner sweeps run, summed over all block steps */
     int status;           /* this solve's status code (per pair in the batched form) */
+    int n_offdiag;        /* mixed form: FP32 sweeps recorded in fp32_offdiag */
+    double fp32_offdiag[32]; /* mixed form: the off-diagonal measure (largest scaled
+                             off-diagonal pivot Gram entry) of each FP32 sweep, first 32 */
+    double t_gram, t_inner, t_update, t_other; /* with hz_params.timing = 1: milliseconds
+                             spent in the Gram (with their split sums or QR pivot factors),
+                             inner-solve and update launches of this call, and the rest of
+                             the call's wall time (prescale, extraction, host syncs) */
+    uint64_t updates_skipped; /* block updates skipped because the inner solve applied no
+                             transformation and no swap, so Z_tilde = I (Section 2.5) */
+    int fp32_chol_restarts; /* mixed form: 1 if an FP32 pivot Gram was not numerically
+                             positive definite and the FP32 phase ended early; the FP64
+                             restart and sweeps then ran as usual */
 } hz_info;
 
 /* Fill *p with the defaults listed above. */

@@ -65,7 +65,8 @@ class HzParams(ctypes.Structure):
                 ("mixed_switch", ctypes.c_double), ("max_fp32_sweeps", ctypes.c_int),
                 ("inner_lanes", ctypes.c_int), ("gram_splits", ctypes.c_int),
                 ("update_rows", ctypes.c_int), ("schedule", ctypes.c_int),
-                ("qr_shorten", ctypes.c_int), ("pivot_qr", ctypes.c_int)]
+                ("qr_shorten", ctypes.c_int), ("pivot_qr", ctypes.c_int),
+                ("timing", ctypes.c_int)]
 
 
 class HzInfo(ctypes.Structure):
@@ -73,7 +74,11 @@ class HzInfo(ctypes.Structure):
                 ("converged", ctypes.c_int), ("w", ctypes.c_int),
                 ("failed_pair", ctypes.c_int64), ("rot_total", ctypes.c_uint64),
                 ("rot_big", ctypes.c_uint64), ("last_offdiag", ctypes.c_double),
-                ("inner_sweeps", ctypes.c_uint64), ("status", ctypes.c_int)]
+                ("inner_sweeps", ctypes.c_uint64), ("status", ctypes.c_int),
+                ("n_offdiag", ctypes.c_int), ("fp32_offdiag", ctypes.c_double * 32),
+                ("t_gram", ctypes.c_double), ("t_inner", ctypes.c_double),
+                ("t_update", ctypes.c_double), ("t_other", ctypes.c_double),
+                ("updates_skipped", ctypes.c_uint64), ("fp32_chol_restarts", ctypes.c_int)]
 
 
 _lib = None
@@ -285,7 +290,12 @@ def gsvd(F, G, *, overwrite=False, raise_on_noconv=False, workspace=None, mixed=
                 sweeps=info.sweeps, converged=bool(info.converged), w=info.w,
                 rot_total=info.rot_total, rot_big=info.rot_big,
                 inner_sweeps=info.inner_sweeps, sweeps_fp32=info.sweeps_fp32,
-                last_offdiag=info.last_offdiag)
+                last_offdiag=info.last_offdiag,
+                fp32_offdiag=[info.fp32_offdiag[i] for i in range(info.n_offdiag)],
+                times_ms=dict(gram=info.t_gram, inner=info.t_inner, update=info.t_update,
+                              other=info.t_other),
+                updates_skipped=info.updates_skipped,
+                fp32_chol_restarts=info.fp32_chol_restarts, info=info)
 
 
 def _i64s(vals):

@@ -10,7 +10,9 @@
 
 #include <algorithm>
 #include <chrono>
+#include <list>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "hz_internal.h"
@@ -240,50 +242,144 @@ static int check_args(int64_t mf, int64_t mg, int64_t n, const void *F, int64_t 
 }
 
 // ------------------------------------------------------------ profiler
-// When enabled, every timed launch is bracketed by two HIP events on its
+// Event timer: every timed launch is bracketed by two HIP events on its
 // stream; the pending pairs are resolved at the host syncs the sweep loop
-// already makes (prof_flush), so the profiler adds no synchronisation.
-struct Prof {
-    std::mutex mu;
-    bool on = false;
+// already makes (flush), so timing adds no synchronisation.  One instance
+// serves the process-wide profiler (hz_profile_*), another a single call
+// with hz_params.timing = 1 (thread-local while that call runs).
+struct EvTimer {
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     std::vector<int> kind;
+    int only = -1;                 // >= 0: events around launches of this kind only
     double ms[K_NKINDS] = {0, 0, 0, 0};
     int64_t launches[K_NKINDS] = {0, 0, 0, 0};
+    void mark(int k, bool begin, hipStream_t s)
+    {
+        if (only >= 0 && k != only) return;
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return;
+            pool.push_back(e);
+        }
+        if (begin) kind.push_back(k);
+        (void)hipEventRecord(pool[used++], s);
+    }
+    // Resolve recorded pairs; the caller has synchronised the stream.
+    void flush()
+    {
+        for (size_t i = 0; i + 1 < used; i += 2) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, pool[i], pool[i + 1]) == hipSuccess) {
+                const int k = kind[i / 2];
+                ms[k] += t;
+                launches[k] += 1;
+            }
+        }
+        used = 0;
+        kind.clear();
+    }
+    void clear()
+    {
+        used = 0;
+        kind.clear();
+        for (int k = 0; k < K_NKINDS; ++k) {
+            ms[k] = 0.0;
+            launches[k] = 0;
+        }
+    }
+    ~EvTimer()
+    {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+struct Prof {
+    std::mutex mu;
+    bool on = false;
+    EvTimer t;
     bool phases = false;           // also time the inner solver's phases
-    int only = -1;                 // >= 0: events around launches of this kind only
     double phase_us[5] = {0, 0, 0, 0, 0};
     int64_t phase_n = 0;
 };
 static Prof g_prof;
+static thread_local EvTimer *tl_timer = nullptr;   // the running call's own timer
 
 void prof_mark(int kind, bool begin, hipStream_t s)
 {
-    if (!g_prof.on || (g_prof.only >= 0 && kind != g_prof.only)) return;
-    if (g_prof.used == g_prof.pool.size()) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return;
-        g_prof.pool.push_back(e);
-    }
-    if (begin) g_prof.kind.push_back(kind);
-    (void)hipEventRecord(g_prof.pool[g_prof.used++], s);
+    if (g_prof.on) g_prof.t.mark(kind, begin, s);
+    if (tl_timer) tl_timer->mark(kind, begin, s);
 }
 
-// Resolve recorded pairs; the caller has synchronised the stream.
 static void prof_flush()
 {
-    if (!g_prof.on) return;
-    for (size_t i = 0; i + 1 < g_prof.used; i += 2) {
-        float t = 0.f;
-        if (hipEventElapsedTime(&t, g_prof.pool[i], g_prof.pool[i + 1]) == hipSuccess) {
-            const int k = g_prof.kind[i / 2];
-            g_prof.ms[k] += t;
-            g_prof.launches[k] += 1;
+    if (g_prof.on) g_prof.t.flush();
+    if (tl_timer) tl_timer->flush();
+}
+
+// Pinned host words the sweep loop reads the per-sweep summary into: one
+// buffer per thread, allocated on first use and kept (so a solve does not
+// pay for a pinned allocation).
+static unsigned long long *sweep_readback()
+{
+    static thread_local unsigned long long *buf = nullptr;
+    if (!buf && hipHostMalloc((void **)&buf, 64 * sizeof(unsigned long long), 0) != hipSuccess)
+        buf = nullptr;
+    return buf;
+}
+
+// Captured sweep graphs, kept across calls.  A graph holds the workspace
+// addresses, the plan and the kernel arguments of one sweep, so it is keyed
+// by all of them (the ordering tables are data in the workspace, rewritten
+// by every call before the graph runs); the least recently used entry is
+// destroyed beyond GRAPH_CACHE_MAX.  Calls that share a workspace must not
+// overlap (they would race on it anyway).
+static constexpr size_t GRAPH_CACHE_MAX = 1024;
+struct GraphEntry {
+    std::string key;
+    hipGraph_t g;
+    hipGraphExec_t e;
+};
+static std::mutex g_graph_mu;
+static std::list<GraphEntry> g_graphs;
+
+template <class Enqueue>
+static hipError_t cached_graph(const std::string &key, Enqueue enqueue, hipStream_t cs,
+                               hipGraphExec_t &exec)
+{
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
+        if (it->key == key) {
+            g_graphs.splice(g_graphs.begin(), g_graphs, it);
+            exec = it->e;
+            return hipSuccess;
         }
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (err != hipSuccess) return err;
+    enqueue(cs);
+    err = hipStreamEndCapture(cs, &g);
+    if (err != hipSuccess) return err;
+    err = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    if (err != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return err;
     }
-    g_prof.used = 0;
-    g_prof.kind.clear();
+    g_graphs.push_front(GraphEntry{key, g, e});
+    while (g_graphs.size() > GRAPH_CACHE_MAX) {
+        (void)hipGraphExecDestroy(g_graphs.back().e);
+        (void)hipGraphDestroy(g_graphs.back().g);
+        g_graphs.pop_back();
+    }
+    exec = e;
+    return hipSuccess;
+}
+
+template <class T>
+static void key_add(std::string &k, const T &v)
+{
+    k.append((const char *)&v, sizeof(v));
 }
 
 // One private non-blocking stream per device to capture the sweep graphs on
@@ -476,15 +572,10 @@ void hz_profile_enable(int enable)
     std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.on = enable != 0;
     g_prof.phases = enable == 2;
-    g_prof.only = (enable >= 4 && enable < 4 + K_NKINDS) ? enable - 4 : -1;
+    g_prof.t.only = (enable >= 4 && enable < 4 + K_NKINDS) ? enable - 4 : -1;
     for (int k = 0; k < 5; ++k) g_prof.phase_us[k] = 0.0;
     g_prof.phase_n = 0;
-    g_prof.used = 0;
-    g_prof.kind.clear();
-    for (int k = 0; k < K_NKINDS; ++k) {
-        g_prof.ms[k] = 0.0;
-        g_prof.launches[k] = 0;
-    }
+    g_prof.t.clear();
 }
 
 int hz_profile_read_phases(double *us, int nphases)
@@ -501,8 +592,8 @@ int hz_profile_read(double *ms, int64_t *launches, int nkinds)
     std::lock_guard<std::mutex> lk(g_prof.mu);
     const int n = nkinds < K_NKINDS ? nkinds : K_NKINDS;
     for (int k = 0; k < n; ++k) {
-        if (ms) ms[k] = g_prof.ms[k];
-        if (launches) launches[k] = g_prof.launches[k];
+        if (ms) ms[k] = g_prof.t.ms[k];
+        if (launches) launches[k] = g_prof.t.launches[k];
     }
     return n;
 }
@@ -645,14 +736,23 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
                      double *sigma, double *sigma_f, double *sigma_g, bool finish)
 {
     (void)work_bytes;
+    const auto t_start = std::chrono::steady_clock::now();
     int rc = HZ_OK;
     bool own = false;
-    hipGraph_t graphs[2] = {nullptr, nullptr};
+    hipGraph_t own_graph[2] = {nullptr, nullptr};      // uncached (library-owned workspace)
+    hipGraphExec_t own_exec[2] = {nullptr, nullptr};
     hipGraphExec_t execs[2] = {nullptr, nullptr};
-    unsigned long long *hpin = nullptr;
+    unsigned long long *hpin = sweep_readback();
     unsigned long long *dphase = nullptr;
+    if (!hpin) return HZ_EHIP;
+    EvTimer call_timer;
+    EvTimer *const prev_timer = tl_timer;
+    if (prm.timing) tl_timer = &call_timer;
     if (!work) {
-        if (hipMalloc(&work, P.total) != hipSuccess) return HZ_EHIP;
+        if (hipMallocAsync(&work, P.total, st) != hipSuccess) {
+            tl_timer = prev_timer;
+            return HZ_EHIP;
+        }
         own = true;
     }
     {
@@ -675,15 +775,18 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
         std::vector<int16_t> itab;
         build_ordering<int>(prm.ordering, P.nblk, otab);
         build_ordering<int16_t>(prm.inner_ordering, P.W2, itab);
+        const int hs0[ST_NSLOTS] = {0, INT_MAX, 0, 0};
         int hs[ST_NSLOTS] = {0, INT_MAX, 0, 0};
-        uint64_t tot_all = 0, tot_big = 0, tot_isw = 0;
-        int sweeps = 0, sweeps32 = 0, converged = 0;
+        uint64_t tot_all = 0, tot_big = 0, tot_isw = 0, tot_skip = 0;
+        int sweeps = 0, sweeps32 = 0, converged = 0, chol32 = 0;
+        int n_off = 0;
+        double offs[32];
         double last_off = 0.0;
         HZ_CHECK(hipMemcpyAsync(W.otab, otab.data(), otab.size() * sizeof(int),
                                 hipMemcpyHostToDevice, st));
         HZ_CHECK(hipMemcpyAsync(W.itab, itab.data(), itab.size() * sizeof(int16_t),
                                 hipMemcpyHostToDevice, st));
-        HZ_CHECK(hipMemcpyAsync(W.status, hs, sizeof(hs), hipMemcpyHostToDevice, st));
+        HZ_CHECK(hipMemcpyAsync(W.status, hs0, sizeof(hs0), hipMemcpyHostToDevice, st));
         DFArgs dfa;
         int df_wg = 0;
         std::vector<int4> dtasks;
@@ -769,11 +872,11 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
         HZ_CHECK(hipGetLastError());
 
         // One outer sweep: all block steps and the end-of-sweep summary,
-        // then SWEEP_TOT_N words read back once (Algorithm 1).  Without the
-        // profiler the sweep is captured once as a hipGraph (per precision)
-        // and replayed.
-        // the dataflow sweep is a cooperative launch, which is not captured
-        const bool use_graph = !g_prof.on && !P.dataflow;
+        // then SWEEP_TOT_N words read back once (Algorithm 1).  Without
+        // timing the sweep is replayed from a captured hipGraph (per
+        // precision), cached across calls that reuse the workspace; the
+        // dataflow sweep is a cooperative launch, which is not captured.
+        const bool use_graph = !g_prof.on && !prm.timing && !P.dataflow;
         auto enqueue = [&](bool fp32, hipStream_t s) {
             if (P.dataflow && !fp32) {
                 df_err = launch_sweep_df(dfa, df_wg, s);
@@ -787,22 +890,48 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
             }
             launch_sweep_totals(P, W, s);
         };
+        auto get_graph = [&](bool fp32) -> hipError_t {
+            const int g = fp32 ? 1 : 0;
+            if (execs[g]) return hipSuccess;
+            hipStream_t cs = capture_stream();
+            if (!cs) return hipErrorInvalidValue;
+            auto enq = [&](hipStream_t s) { enqueue(fp32, s); };
+            if (own) {
+                // a workspace of this call only: capture, use once, destroy
+                hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) return e;
+                enq(cs);
+                e = hipStreamEndCapture(cs, &own_graph[g]);
+                if (e != hipSuccess) return e;
+                e = hipGraphInstantiate(&own_exec[g], own_graph[g], nullptr, nullptr, 0);
+                execs[g] = own_exec[g];
+                return e;
+            }
+            int dev = 0;
+            (void)hipGetDevice(&dev);
+            std::string key;
+            key_add(key, dev);
+            key_add(key, kind);
+            key_add(key, g);
+            key_add(key, work);
+            key_add(key, tol);
+            key_add(key, P);
+            key_add(key, prm.variant);
+            key_add(key, prm.inner_max_sweeps);
+            key_add(key, prm.sort);
+            key_add(key, prm.pivot_qr);
+            return cached_graph(key, enq, cs, execs[g]);
+        };
         auto sweep = [&](bool fp32, uint64_t &s_all, uint64_t &s_big) -> hipError_t {
             hipError_t e = hipSuccess;
             const int g = fp32 ? 1 : 0;
-            if (use_graph && !execs[g]) {
-                hipStream_t cs = capture_stream();
-                if (!cs) return hipErrorInvalidValue;
-                e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (use_graph) {
+                e = get_graph(fp32);
                 if (e != hipSuccess) return e;
-                enqueue(fp32, cs);
-                e = hipStreamEndCapture(cs, &graphs[g]);
-                if (e != hipSuccess) return e;
-                e = hipGraphInstantiate(&execs[g], graphs[g], nullptr, nullptr, 0);
-                if (e != hipSuccess) return e;
+                e = hipGraphLaunch(execs[g], st);
+            } else {
+                enqueue(fp32, st);
             }
-            if (use_graph) e = hipGraphLaunch(execs[g], st);
-            else enqueue(fp32, st);
             if (e != hipSuccess) return e;
             if (df_err != hipSuccess) return df_err;
             e = hipGetLastError();
@@ -827,14 +956,17 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
             s_all = hpin[TOT_ALL];
             s_big = hpin[TOT_BIG];
             tot_isw += hpin[TOT_ISW];
+            tot_skip += hpin[TOT_SKIP];
             hs[ST_FLAGS] = (int)hpin[TOT_FLAGS];
             hs[ST_FAILPAIR] = (int)hpin[TOT_FAILPAIR];
-            if (fp32) last_off = __builtin_bit_cast(double, hpin[TOT_OFFD]);
+            if (fp32) {
+                last_off = __builtin_bit_cast(double, hpin[TOT_OFFD]);
+                if (n_off < 32) offs[n_off++] = last_off;
+            }
             tot_all += s_all;
             tot_big += s_big;
             return hipSuccess;
         };
-        HZ_CHECK(hipHostMalloc((void **)&hpin, SWEEP_TOT_N * sizeof(unsigned long long), 0));
 
         if (kind == KIND_MIXED) {
             // FP32 sweeps until the largest scaled off-diagonal Gram entry of a
@@ -847,21 +979,37 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
                 if (hs[ST_FLAGS]) break;
                 if (s_big == 0 || last_off < prm.mixed_switch) break;
             }
-            if (!hs[ST_FLAGS]) {
+            if (hs[ST_FLAGS]) {
+                // An FP32 pivot Gram that is not numerically positive
+                // definite ends the FP32 phase early: the failing block kept
+                // Z_tilde = I and every other block's transformation was
+                // applied, so Z32 is still a product of congruences and the
+                // FP64 restart from F Z32, G Z32 is valid.  A non-finite
+                // value in the FP32 iterates (e.g. an input beyond FP32
+                // range) leaves nothing to restart from: the FP64 phase then
+                // starts from the prescaled input, as the plain solver does
+                // (and flags an input that is non-finite itself again).
+                const bool nonfinite = (hs[ST_FLAGS] & FLAG_NONFINITE) != 0;
+                chol32 = (hs[ST_FLAGS] & FLAG_CHOL) ? 1 : 0;
+                memcpy(hs, hs0, sizeof(hs));
+                HZ_CHECK(hipMemcpyAsync(W.status, hs0, sizeof(hs0), hipMemcpyHostToDevice, st));
+                if (nonfinite)
+                    launch_prescale_real(P, W, (const double *)F, ldf, (const double *)G, ldg, st);
+                else
+                    launch_restart_mixed(P, W, (const double *)F, ldf, (const double *)G, ldg, st);
+            } else {
                 launch_restart_mixed(P, W, (const double *)F, ldf, (const double *)G, ldg, st);
-                HZ_CHECK(hipGetLastError());
             }
+            HZ_CHECK(hipGetLastError());
         }
-        if (!hs[ST_FLAGS]) {
-            for (int sw = 0; sw < prm.max_sweeps; ++sw) {
-                uint64_t s_all, s_big;
-                HZ_CHECK(sweep(false, s_all, s_big));
-                ++sweeps;
-                if (hs[ST_FLAGS]) break;
-                if (s_big == 0) {
-                    converged = 1;
-                    break;
-                }
+        for (int sw = 0; sw < prm.max_sweeps; ++sw) {
+            uint64_t s_all, s_big;
+            HZ_CHECK(sweep(false, s_all, s_big));
+            ++sweeps;
+            if (hs[ST_FLAGS]) break;
+            if (s_big == 0) {
+                converged = 1;
+                break;
             }
         }
         if (finish && !(hs[ST_FLAGS] & FLAG_CHOL)) {
@@ -889,18 +1037,36 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
             info->rot_big = tot_big;
             info->inner_sweeps = tot_isw;
             info->last_offdiag = last_off;
+            info->n_offdiag = n_off;
+            for (int i = 0; i < n_off; ++i) info->fp32_offdiag[i] = offs[i];
+            info->updates_skipped = tot_skip;
+            info->fp32_chol_restarts = chol32;
             info->status = rc;
         }
     }
 done:
     (void)hipStreamSynchronize(st);
     for (int g = 0; g < 2; ++g) {
-        if (execs[g]) (void)hipGraphExecDestroy(execs[g]);
-        if (graphs[g]) (void)hipGraphDestroy(graphs[g]);
+        if (own_exec[g]) (void)hipGraphExecDestroy(own_exec[g]);
+        if (own_graph[g]) (void)hipGraphDestroy(own_graph[g]);
     }
-    if (hpin) (void)hipHostFree(hpin);
     if (dphase) (void)hipFree(dphase);
-    if (own) (void)hipFree(work);
+    if (own) {
+        (void)hipFreeAsync(work, st);
+        (void)hipStreamSynchronize(st);
+    }
+    tl_timer = prev_timer;
+    if (prm.timing && info) {
+        call_timer.flush();
+        const double wall =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+                .count();
+        info->t_gram = call_timer.ms[K_GRAM];
+        info->t_inner = call_timer.ms[K_INNER];
+        info->t_update = call_timer.ms[K_UPDATE];
+        const double other = wall - info->t_gram - info->t_inner - info->t_update;
+        info->t_other = other > 0.0 ? other : 0.0;
+    }
     return rc;
 }
 

@@ -266,6 +266,7 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
             myc[0] = 0;
             myc[1] = 0;
             myc[2] = 0;
+            myc[3] = 0;
             atomicOr(status + ST_FLAGS, FLAG_CHOL);
             atomicMin(status + ST_FAILPAIR, step * 65536 + pr);
         }
@@ -294,7 +295,7 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
     __syncthreads();
 
     const double tol2 = tol * tol;
-    unsigned my_all = 0, my_big = 0;
+    unsigned my_all = 0, my_big = 0, my_chg = 0;
     int nsw = 0;
     for (int sw = 0; sw < inner_max; ++sw) {
         unsigned sw_all = 0, sw_big = 0;
@@ -366,6 +367,7 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
                 }
             }
             if (!orth || swap) {
+                my_chg = 1;
                 // [y_i y_j] <- [y_i y_j] Z (z11, z22 real), then the sorting swap
                 auto rot = [&](const d2 yi, const d2 yj, d2 &oi, d2 &oj) {
                     d2 a, b;
@@ -398,10 +400,19 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
         if (any == 0) break;
     }
 
+    // Z_tilde = Z_hat Theta, or exactly I when nothing was transformed or
+    // swapped (the block update is then skipped, Section 2.5)
     d2 *zt = Zt + (size_t)pr * (W2 * W2);
+    const int nchg = __syncthreads_count(gl == 0 && my_chg != 0);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int c = 2 * grp + h;
+        if (nchg == 0) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r)
+                zt[c * W2 + r0 + r] = d2{(r0 + r == c) ? 1.0 : 0.0, 0.0};
+            continue;
+        }
         double s = 0.0;
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
@@ -428,6 +439,7 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
         myc[0] = ta;
         myc[1] = tb;
         myc[2] = (unsigned long long)nsw;
+        myc[3] = (nchg == 0) ? 1ull : 0ull;
     }
 }
 
@@ -441,11 +453,13 @@ template <int W2>
 __global__ __launch_bounds__(256) void k_update_z(d2 *__restrict__ Fw, d2 *__restrict__ Gw,
                                                   d2 *__restrict__ Zw, int64_t mfw, int64_t mgw,
                                                   int64_t nzw, const int *__restrict__ pairs,
-                                                  const d2 *__restrict__ Zt, int rows_per_wave)
+                                                  const d2 *__restrict__ Zt, int rows_per_wave,
+                                                  const unsigned long long *__restrict__ scnt)
 {
     constexpr int W = W2 / 2, NB = W2 / 16, KS = W2 / 4, LDZ = W2 + 1;
     __shared__ d2 sz[W2 * LDZ];
     const int pr = blockIdx.y;
+    if (scnt[(size_t)pr * 4 + 3]) return;   // Z_tilde = I: nothing to update
     const int p = pairs[2 * pr], q = pairs[2 * pr + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const d2 *zt = Zt + (size_t)pr * (W2 * W2);
@@ -658,7 +672,7 @@ static void step_impl_z(const Plan &P, const Ptrs &W, int step, const hz_params 
     prof_mark(K_UPDATE, true, s);
     hipLaunchKernelGGL(k_update_z<W2>, dim3(nt, P.npairs), dim3(256), 0, s, (d2 *)W.Fw,
                        (d2 *)W.Gw, (d2 *)W.Zw, P.mfw, P.mgw, P.nzw, pairs, (const d2 *)W.Zt,
-                       P.upd_rows);
+                       P.upd_rows, W.cnt + (size_t)step * P.npairs * 4);
     prof_mark(K_UPDATE, false, s);
 }
 

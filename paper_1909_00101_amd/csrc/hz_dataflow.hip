@@ -152,7 +152,9 @@ __global__ __launch_bounds__(DF_NT) void k_sweep_df(DFArgs A)
             }
             const int64_t rb = tt * A.tile_rows;
             const int64_t re = (rb + A.tile_rows < m) ? rb + A.tile_rows : m;
-            update_rows<W2, 8>(Y, m, pr[0], pr[1], rb, re, A.Zt + kl * W2SQ, lds);
+            // Z_tilde = I (counter word 3 of the inner task): nothing to update
+            if (__builtin_amdgcn_readfirstlane((int)A.cnt[kl * 4 + 3]) == 0)
+                update_rows<W2, 8>(Y, m, pr[0], pr[1], rb, re, A.Zt + kl * W2SQ, lds);
             sig = upd_done + kl;
         }
         // publish: every thread's stores reach the agent scope, then one

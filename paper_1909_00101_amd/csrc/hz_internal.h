@@ -121,9 +121,9 @@ void launch_inner_real(const Plan &P, const Ptrs &W, int step, const hz_params &
 
 // Per-sweep summary written by k_sweep_totals: sums of the per-(step, pair)
 // counters, the largest off-diagonal measure (mixed form, as bits of a
-// double) and the status words.
+// double), the status words and the number of block updates skipped.
 enum { TOT_ALL = 0, TOT_BIG = 1, TOT_ISW = 2, TOT_OFFD = 3, TOT_FLAGS = 4, TOT_FAILPAIR = 5,
-       SWEEP_TOT_N = 8 };
+       TOT_SKIP = 6, SWEEP_TOT_N = 8 };
 void launch_sweep_totals(const Plan &P, const Ptrs &W, hipStream_t s);
 
 // Persistent dataflow sweep (hz_dataflow.hip), real FP64, pivot blocks of 64.

@@ -127,8 +127,13 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
 // Device body: the workgroup (NT threads) solves the block pair whose Gram
 // blocks are pa (F) and pb (G) (column-major W2 x W2, lower triangles),
 // writes Z_tilde to zt, the counters (transformations, big ones, inner
-// sweeps) to myc[0..2], and on a non-positive pivot sets FLAG_CHOL in
-// status[ST_FLAGS] and failcode into status[ST_FAILPAIR] (minimum kept).
+// sweeps) to myc[0..2] and to myc[3] whether Z_tilde is the identity, and
+// on a non-positive pivot sets FLAG_CHOL in status[ST_FLAGS] and failcode
+// into status[ST_FAILPAIR] (minimum kept).  When no pair of the block was
+// transformed or swapped, Z_tilde is the diagonal Theta-scaled prescale,
+// which only renormalizes columns that already have ||f_j||^2 + ||g_j||^2 =
+// 1 up to rounding; it is then set to I exactly and myc[3] = 1, so the
+// block update may be skipped (Section 2.5).
 template <int W2, int LP>
 __device__ __forceinline__ void inner_solve(
     const double *__restrict__ pa, const double *__restrict__ pb, int nsplit, size_t sstride,
@@ -305,6 +310,7 @@ __device__ __forceinline__ void inner_solve(
             myc[0] = 0;
             myc[1] = 0;
             myc[2] = 0;
+            myc[3] = 0;
             atomicOr(status + ST_FLAGS, FLAG_CHOL);
             atomicMin(status + ST_FAILPAIR, failcode);
         }
@@ -336,7 +342,7 @@ __device__ __forceinline__ void inner_solve(
 
     // 4. inner sweeps
     const double tol2 = tol * tol;
-    unsigned my_all = 0, my_big = 0;
+    unsigned my_all = 0, my_big = 0, my_chg = 0;
     int nsw = 0;
     for (int sw = 0; sw < inner_max; ++sw) {
         unsigned sw_all = 0, sw_big = 0;
@@ -412,6 +418,7 @@ __device__ __forceinline__ void inner_solve(
                 t = z21; z21 = z22; z22 = t;
             }
             if (!orth || swap) {
+                my_chg = 1;
 #pragma unroll
                 for (int r = 0; r < RPL; r += 2) {
                     d2 nfi, nfj, ngi, ngj, nzi, nzj;
@@ -441,10 +448,18 @@ __device__ __forceinline__ void inner_solve(
     }
 
     if (ph && tid == 0) ph[4] = wall_clock64();
-    // 5. Theta rescale and write Z_tilde (column-major W2 x W2).
+    // 5. Theta rescale and write Z_tilde (column-major W2 x W2); the
+    // identity when nothing was transformed or swapped.
+    const int nchg =
+        __builtin_amdgcn_readfirstlane(__syncthreads_count(gl == 0 && my_chg != 0));
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int c = 2 * grp + h;
+        if (nchg == 0) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) zt[c * W2 + r0 + r] = (r0 + r == c) ? 1.0 : 0.0;
+            continue;
+        }
         double s = 0.0;
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
@@ -472,6 +487,7 @@ __device__ __forceinline__ void inner_solve(
         myc[0] = ta;
         myc[1] = tb;
         myc[2] = (unsigned long long)nsw;
+        myc[3] = (nchg == 0) ? 1ull : 0ull;
         if (ph) ph[5] = wall_clock64();
     }
 #undef s_fail

@@ -151,11 +151,13 @@ __global__ __launch_bounds__(256) void k_update32(float *__restrict__ Fs, float 
                                                   int64_t mgw, int64_t nzw,
                                                   const int *__restrict__ pairs,
                                                   const double *__restrict__ Zt,
-                                                  int rows_per_wave)
+                                                  int rows_per_wave,
+                                                  const unsigned long long *__restrict__ scnt)
 {
     constexpr int W = W2 / 2, NB = W2 / 16, KS = W2 / 4, LDZ = W2 + 1;
     __shared__ float sz[W2 * LDZ];
     const int pr = blockIdx.y;
+    if (scnt[(size_t)pr * 4 + 3]) return;   // Z_tilde = I: nothing to update
     const int p = pairs[2 * pr], q = pairs[2 * pr + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double *zt = Zt + (size_t)pr * (W2 * W2);
@@ -357,7 +359,8 @@ static void step32_impl(const Plan &P, const Ptrs &W, int step, const hz_params 
     const int nt = (int)((P.mfw + P.mgw + P.nzw + rpt - 1) / rpt);
     prof_mark(K_UPDATE, true, s);
     hipLaunchKernelGGL(k_update32<W2>, dim3(nt, P.npairs), dim3(256), 0, s, W.Fs, W.Gs, W.Zs,
-                       P.mfw, P.mgw, P.nzw, pairs, W.Zt, P.upd_rows);
+                       P.mfw, P.mgw, P.nzw, pairs, W.Zt, P.upd_rows,
+                       W.cnt + (size_t)step * P.npairs * 4);
     prof_mark(K_UPDATE, false, s);
 }
 

@@ -156,13 +156,18 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner(
 // Grid (row ranges of the rows of Fw, Gw and Zw in sequence, pairs); each workgroup owns
 // 4 * rows_per_wave consecutive rows, its waves taking 16-row tiles in turn.
 // ------------------------------------------------------------------------
+// A pair whose inner solve left Z_tilde = I (its counter word 3, written by
+// the inner solver) is skipped (Section 2.5): every workgroup of the pair
+// returns at once.
 template <int W2>
 __global__ __launch_bounds__(256) void k_update(double *__restrict__ Fw, double *__restrict__ Gw,
                                                 double *__restrict__ Zw, int64_t mfw,
                                                 int64_t mgw, int64_t nzw,
                                                 const int *__restrict__ pairs,
-                                                const double *__restrict__ Zt, int rows_per_wave)
+                                                const double *__restrict__ Zt, int rows_per_wave,
+                                                const unsigned long long *__restrict__ scnt)
 {
+    if (scnt[(size_t)blockIdx.y * 4 + 3]) return;
     // The rows of F, G and Z (each padded to a multiple of 64) are taken as
     // one sequence and cut into equal ranges of 4 * rows_per_wave; a range
     // that reaches the end of one matrix continues in the next (a 16-row
@@ -363,14 +368,15 @@ __global__ __launch_bounds__(256) void k_sweep_totals(const unsigned long long *
                                                       int noffd, const int *__restrict__ status,
                                                       unsigned long long *__restrict__ tot)
 {
-    __shared__ unsigned long long s3[3][256];
+    __shared__ unsigned long long s3[4][256];
     __shared__ double so[256];
     const int t = threadIdx.x;
-    unsigned long long a = 0, b = 0, c = 0;
+    unsigned long long a = 0, b = 0, c = 0, d = 0;
     for (int i = t; i < n; i += 256) {
         a += cnt[4 * (size_t)i];
         b += cnt[4 * (size_t)i + 1];
         c += cnt[4 * (size_t)i + 2];
+        d += cnt[4 * (size_t)i + 3];
     }
     double m = 0.0;
     if (offd)
@@ -378,6 +384,7 @@ __global__ __launch_bounds__(256) void k_sweep_totals(const unsigned long long *
     s3[0][t] = a;
     s3[1][t] = b;
     s3[2][t] = c;
+    s3[3][t] = d;
     so[t] = m;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
@@ -385,6 +392,7 @@ __global__ __launch_bounds__(256) void k_sweep_totals(const unsigned long long *
             s3[0][t] += s3[0][t + h];
             s3[1][t] += s3[1][t + h];
             s3[2][t] += s3[2][t + h];
+            s3[3][t] += s3[3][t + h];
             so[t] = fmax(so[t], so[t + h]);
         }
         __syncthreads();
@@ -396,6 +404,7 @@ __global__ __launch_bounds__(256) void k_sweep_totals(const unsigned long long *
         tot[TOT_OFFD] = __builtin_bit_cast(unsigned long long, so[0]);
         tot[TOT_FLAGS] = (unsigned long long)(unsigned)status[ST_FLAGS];
         tot[TOT_FAILPAIR] = (unsigned long long)(unsigned)status[ST_FAILPAIR];
+        tot[TOT_SKIP] = s3[3][0];
     }
 }
 
@@ -494,7 +503,8 @@ static void step_impl(const Plan &P, const Ptrs &W, int step, const hz_params &p
     const int nt = (int)((P.mfw + P.mgw + P.nzw + rpt - 1) / rpt);
     prof_mark(K_UPDATE, true, s);
     hipLaunchKernelGGL(k_update<W2>, dim3(nt, P.npairs), dim3(256), 0, s, W.Fw, W.Gw, W.Zw,
-                       P.mfw, P.mgw, P.nzw, pairs, W.Zt, P.upd_rows);
+                       P.mfw, P.mgw, P.nzw, pairs, W.Zt, P.upd_rows,
+                       W.cnt + (size_t)step * P.npairs * 4);
     prof_mark(K_UPDATE, false, s);
 }
 

@@ -79,3 +79,45 @@ def test_config4_mixed_vs_oracle_golden():
     em = max_rel(rm["sigma"], gold)
     print(f"config4 mixed: fp32 sweeps={rm['sweeps_fp32']} fp64 sweeps={rm['sweeps']} err={em:.2e}")
     assert rm["status"] == 0 and em < SIG_TOL
+    assert len(rm["fp32_offdiag"]) == min(32, rm["sweeps_fp32"])
+    assert rm["fp32_offdiag"][-1] == rm["last_offdiag"]
+    rp = _run(F, G, w=32, tol=tol, inner_max_sweeps=1)
+    ep = max_rel(rp["sigma"], gold)
+    print(f"config4 plain: fp64 sweeps={rp['sweeps']} err={ep:.2e}")
+    assert rp["status"] == 0 and ep < SIG_TOL
+
+
+@pytest.mark.parametrize("seed", [700, 701])
+def test_mixed_fp32_indefinite_gram_restarts_in_fp64(seed):
+    """A pair whose prescaled F has kappa(F^T F) near 1e9: the FP32 pivot
+    Gram (FP32 rounding noise about 1e-7 of its norm) is not positive
+    definite, the FP64 one is.  The FP32 phase must end at its first
+    Cholesky failure and the FP64 restart and sweeps must reach the
+    oracle's sigma, as the plain FP64 solver does."""
+    import oracle
+    F, G, s_true = gi.custom_pair(192, 160, 64, kappa=10.0, sig_lo=1e-4, sig_hi=1e2, seed=seed)
+    tol = 64 * EPS
+    o = oracle.gsvd(F, G, ordering=1, tol=tol, threads=4)
+    rp = _run(F, G, w=32, tol=tol)
+    rm = _run(F, G, w=32, tol=tol, mixed=True)
+    ep, em = max_rel(rp["sigma"], o["sigma"]), max_rel(rm["sigma"], o["sigma"])
+    print(f"seed {seed}: plain err={ep:.2e}; mixed fp32 sweeps={rm['sweeps_fp32']} "
+          f"restart={rm['fp32_chol_restarts']} fp64 sweeps={rm['sweeps']} err={em:.2e}")
+    assert rp["status"] == 0 and ep < SIG_TOL
+    assert rm["status"] == 0 and rm["fp32_chol_restarts"] == 1 and rm["sweeps_fp32"] == 1
+    assert em < SIG_TOL
+    assert_contract(F, G, rm["U"], rm["V"], rm["Z"], rm["sigma_f"], rm["sigma_g"], rm["sigma"],
+                    tol_res=1e-12, tol_orth=1e-12)
+
+
+def test_mixed_offdiag_history():
+    """One off-diagonal measure per FP32 sweep; the phase ends on the sweep
+    whose measure falls below the switch (or at the cap)."""
+    F, G, _ = gi.custom_pair(400, 300, 96, kappa=1e2, seed=41)
+    r = _run(F, G, w=16, mixed=True, tol=96 * EPS)
+    h = r["fp32_offdiag"]
+    print("fp32 off-diagonal per sweep:", " ".join(f"{x:.1e}" for x in h))
+    assert r["status"] == 0 and len(h) == r["sweeps_fp32"] >= 1
+    assert h[-1] == r["last_offdiag"]
+    assert all(x >= 1e-5 for x in h[:-1])
+    assert h[-1] < 1e-5 or r["sweeps_fp32"] == 20

@@ -246,3 +246,64 @@ def test_device_2x2_invariants():
     one = hz.eval_2x2(torch.tensor([[3.0, 1.0, 0.0, 0.0]], dtype=torch.float64,
                                    device="cuda")).cpu().numpy()[0]
     assert one[0] == 1.0 and one[3] == 1.0 and one[1] == 0.0 and one[2] == 0.0
+
+
+def test_call_timing_fills_phase_times_and_keeps_bits():
+    """hz_params.timing = 1 times the Gram, inner-solve and update launches of
+    this call (direct launches); the result is bitwise the one of the
+    graph-replayed call without timing."""
+    F, G, _ = gi.custom_pair(600, 500, 192, kappa=1e2, seed=61)
+    a = _run(F, G, w=32, tol=192 * EPS)
+    b = _run(F, G, w=32, tol=192 * EPS, timing=1)
+    t = b["times_ms"]
+    print("per-call ms:", {k: round(v, 3) for k, v in t.items()})
+    assert a["status"] == 0 and b["status"] == 0
+    assert t["gram"] > 0 and t["inner"] > 0 and t["update"] > 0 and t["other"] >= 0
+    assert all(v == 0.0 for v in a["times_ms"].values())
+    assert _digest(a) == _digest(b)
+
+
+def test_sweep_graph_cached_across_calls_with_one_workspace():
+    """Calls that reuse a workspace replay a cached sweep graph; a different
+    problem in the same workspace gets its own graph, and returning to the
+    first problem reproduces its bits."""
+    import oracle
+    hz = _hz()
+    FA, GA, _ = gi.custom_pair(300, 260, 96, kappa=1e2, seed=62)
+    FB, GB, _ = gi.custom_pair(200, 220, 64, kappa=30.0, seed=63)
+    work = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+
+    def run(F, G):
+        r = hz.gsvd(torch.from_numpy(np.asfortranarray(F)).cuda(),
+                    torch.from_numpy(np.asfortranarray(G)).cuda(), w=16, workspace=work)
+        torch.cuda.synchronize()
+        return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in r.items()}
+
+    a1, b1, a2, b2 = run(FA, GA), run(FB, GB), run(FA, GA), run(FB, GB)
+    assert _digest(a1) == _digest(a2) and _digest(b1) == _digest(b2)
+    assert a1["status"] == 0 and b1["status"] == 0
+    assert max_rel(b1["sigma"], _oracle(FB, GB)["sigma"]) < SIG_TOL
+    assert max_rel(a1["sigma"], _oracle(FA, GA)["sigma"]) < SIG_TOL
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_identity_blocks_skip_their_update(cplx):
+    """A pair that is already a GSVD (orthogonal columns of F with descending
+    norms, orthonormal G): no pivot pair is transformed or swapped, every
+    Z_tilde is I and every block update is skipped (Section 2.5); the
+    result is still the exact GSVD."""
+    rng = np.random.default_rng(64)
+    m, n = 160, 64
+    shape = (m, 2 * n)
+    M = rng.standard_normal(shape) + (1j * rng.standard_normal(shape) if cplx else 0)
+    Q, _ = np.linalg.qr(M)
+    sig = np.geomspace(50.0, 0.02, n)
+    F = np.asfortranarray(Q[:, :n] * sig)
+    G = np.asfortranarray(Q[:, n:])
+    r = _run(F, G, w=16, tol=n * EPS)
+    steps, pairs = n // 16, n // 32
+    print(f"sweeps={r['sweeps']} skipped={r['updates_skipped']} of {r['sweeps'] * steps * pairs}")
+    assert r["status"] == 0 and r["sweeps"] == 1 and r["rot_total"] == 0
+    assert r["updates_skipped"] == r["sweeps"] * steps * pairs
+    assert max_rel(r["sigma"], sig) < 1e-13
+    _check(F, G, r)
