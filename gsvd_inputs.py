@@ -30,8 +30,17 @@ workloads listed in ``CONFIGS``.
 from __future__ import annotations
 
 import dataclasses
+import os
 
-import numpy as np
+# numpy's QR and SVD run in OpenBLAS, which picks its kernels by CPU model;
+# kernels of different families round differently, so the same seed would
+# give pairs that differ in the last bits from one host to another.  One
+# fixed family (AVX2 "Haswell", present on every x86-64 host used here)
+# makes the pairs bitwise the same everywhere.  It takes effect only if
+# numpy was not imported before this module; blas_coretype() tells.
+os.environ.setdefault("OPENBLAS_CORETYPE", "Haswell")
+
+import numpy as np  # noqa: E402
 
 SEED_BASE = 190900101
 
@@ -82,9 +91,29 @@ def _conditioned(rng, n: int, kappa: float, is_complex: bool) -> np.ndarray:
     return (p * s[np.newaxis, :]) @ qh
 
 
+# OpenBLAS splits a factorization's work by its thread count, which changes
+# the rounding; the draws run with a fixed count (every host used has at
+# least this many cores).
+BLAS_THREADS = 4
+
+
+def _blas_threads():
+    try:
+        from threadpoolctl import threadpool_limits
+        return threadpool_limits(limits=BLAS_THREADS, user_api="blas")
+    except ImportError:      # pragma: no cover - threadpoolctl is part of the image
+        import contextlib
+        return contextlib.nullcontext()
+
+
 def make_pair(spec: PairSpec, rng: np.random.Generator):
     """Draw one pair.  Returns (F, G, sigma_desc) with F, G Fortran-ordered
     (column-major) and sigma the prescribed values sorted descending."""
+    with _blas_threads():
+        return _make_pair(spec, rng)
+
+
+def _make_pair(spec: PairSpec, rng: np.random.Generator):
     u = _orthonormal(rng, spec.m_f, spec.n, spec.is_complex)
     v = _orthonormal(rng, spec.m_g, spec.n, spec.is_complex)
     x = _conditioned(rng, spec.n, spec.kappa, spec.is_complex)
@@ -128,3 +157,17 @@ def make_batch(count=None, seed=5, n_lo=None, n_hi=None):
         spec = PairSpec(m_f, m_g, n, kappa, c["sig_lo"], c["sig_hi"])
         out.append(make_pair(spec, rng))
     return out
+
+
+def blas_coretype():
+    """The OpenBLAS kernel family numpy runs on in this process (None if it
+    cannot be read); the seeded pairs are host-independent under
+    "Haswell"."""
+    try:
+        import threadpoolctl
+        for d in threadpoolctl.threadpool_info():
+            if d.get("internal_api") == "openblas":
+                return d.get("architecture")
+    except Exception:
+        pass
+    return None

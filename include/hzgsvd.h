@@ -45,8 +45,10 @@
  *   HZ_ENOCONV    max_sweeps reached; outputs are valid but not converged
  *   HZ_ECHOL      a pivot Gram block was not numerically positive definite
  *                 (input not of full column rank, or too ill-conditioned for
- *                 Gram + Cholesky); info->failed_pair names the block pair;
- *                 outputs are not meaningful
+ *                 Gram + Cholesky): a Cholesky pivot of the 2w x 2w block was
+ *                 not above 2w * DBL_EPSILON times that column's diagonal
+ *                 entry; info->failed_pair names the block pair; outputs are
+ *                 not meaningful
  *   HZ_ENONFINITE a NaN or infinity was found in the input or arose; outputs
  *                 are not meaningful
  *   HZ_EHIP       a HIP runtime call failed

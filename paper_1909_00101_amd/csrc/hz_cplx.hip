@@ -229,12 +229,15 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
             d2 a[W2];
 #pragma unroll
             for (int k = 0; k < W2; ++k) a[k] = M[k * LDI + i];
+            const double d0 = M[i * LDI + i][0];   // column i's diagonal before the factorization
             bool ok = true;
 #pragma unroll
             for (int j = 0; j < W2; ++j) {
                 const double p0 = readlane_d(a[j][0], j), p1 = readlane_d(a[j][0], 32 + j);
+                const double q0 = readlane_d(d0, j), q1 = readlane_d(d0, 32 + j);
                 const double piv = mat ? p1 : p0;
-                ok = ok && (piv > 0.0) && (piv < INFINITY);
+                // numerically positive definite: pivots above W2 * eps times the diagonal
+                ok = ok && (piv > W2 * 2.220446049250313e-16 * (mat ? q1 : q0)) && (piv < INFINITY);
                 const double inv = rsqrt_nr(piv);
                 d2 l = (i > j) ? a[j] * inv : d2{0.0, 0.0};
                 if (i == j) l = d2{piv * inv, 0.0};

@@ -18,6 +18,13 @@ template <int W2, bool DB = false> constexpr int gram_lds()
     return (DB ? 2 : 1) * W2 * 66 > W2 * (W2 + 2) ? (DB ? 2 : 1) * W2 * 66 : W2 * (W2 + 2);
 }
 template <int W2> constexpr int update_lds() { return W2 * (W2 + 1); }
+
+// A pivot Gram block counts as numerically positive definite when every
+// Cholesky pivot exceeds W2 * eps (eps = 2^-52) times that column's diagonal
+// entry before the factorization: a smaller pivot is at the level of the
+// factorization's own rounding errors (an exactly rank-deficient block, e.g.
+// two equal columns, leaves pivots of either sign of about that size).
+template <int W2> constexpr double PIV_REL() { return W2 * 2.220446049250313e-16; }
 template <int W2> constexpr int inner_lds()
 {
     return 3 * W2 * (W2 + 2) + 128 + W2 * W2 / 4 + (3 * (W2 / 2) + 1) / 2 + 2;
@@ -202,6 +209,8 @@ __device__ __forceinline__ void inner_solve(
         if (wave < 2) {
             double *M = wave ? sG : sF;
             bool ok = true;
+            // lane j holds column j's diagonal before the factorization
+            const double d0 = (lane < W2) ? M[lane * LDI + lane] : 0.0;
 #pragma unroll
             for (int kb = 0; kb < NBK; ++kb) {
                 const int c0 = 16 * kb, row = c0 + lane;
@@ -212,7 +221,7 @@ __device__ __forceinline__ void inner_solve(
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const double piv = readlane_d(pv[j], j);
-                    ok = ok && (piv > 0.0) && (piv < INFINITY);
+                    ok = ok && (piv > PIV_REL<W2>() * readlane_d(d0, c0 + j)) && (piv < INFINITY);
                     const double inv = rsqrt_nr(piv);
                     const double l = (lane >= j) ? pv[j] * inv : 0.0;
                     pv[j] = l;
@@ -267,17 +276,21 @@ __device__ __forceinline__ void inner_solve(
             double a[W2];
 #pragma unroll
             for (int k = 0; k < W2; ++k) a[k] = M[k * LDI + i];
+            const double d0 = M[i * LDI + i];    // column i's diagonal before the factorization
             bool ok = true;
 #pragma unroll
             for (int j = 0; j < W2; ++j) {
-                double piv;
+                double piv, dj;
                 if (two) {
                     piv = readlane_d(a[j], j);
+                    dj = readlane_d(d0, j);
                 } else {
                     const double p0 = readlane_d(a[j], j), p1 = readlane_d(a[j], 32 + j);
+                    const double q0 = readlane_d(d0, j), q1 = readlane_d(d0, 32 + j);
                     piv = mat ? p1 : p0;
+                    dj = mat ? q1 : q0;
                 }
-                ok = ok && (piv > 0.0) && (piv < INFINITY);
+                ok = ok && (piv > PIV_REL<W2>() * dj) && (piv < INFINITY);
                 const double inv = rsqrt_nr(piv);
                 const double l = (i >= j) ? a[j] * inv : 0.0;
                 a[j] = l;

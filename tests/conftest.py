@@ -1,7 +1,11 @@
 import os
 import sys
 
-import pytest
+# Before numpy loads: the seeded pairs are drawn with one fixed OpenBLAS
+# kernel family, so they are bitwise the same on every host.
+os.environ.setdefault("OPENBLAS_CORETYPE", "Haswell")
+
+import pytest  # noqa: E402
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:

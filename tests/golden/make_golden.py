@@ -9,6 +9,8 @@ import os
 import sys
 import time
 
+os.environ.setdefault("OPENBLAS_CORETYPE", "Haswell")   # host-independent pairs
+
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -36,6 +38,7 @@ def main(configs):
             tol=tol, sweeps=r["sweeps"], converged=r["converged"], rot_all=r["rot_all"],
             rot_big=r["rot_big"], seconds=round(dt, 2), threads=threads,
             max_rel_err_vs_prescribed=float(np.max(np.abs(r["sigma"] - s_true) / s_true)),
+            blas_coretype=gi.blas_coretype(),
             sigma=[float(x) for x in r["sigma"]],
         )
         path = os.path.join(HERE, "oracle_config%d.json" % k)
