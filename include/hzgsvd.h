@@ -52,6 +52,8 @@
  *   HZ_ENONFINITE a NaN or infinity was found in the input or arose; outputs
  *                 are not meaningful
  *   HZ_EHIP       a HIP runtime call failed
+ *   HZ_ENOSCRATCH (hz_dgsvd_noalloc only) the solve needs more workspace
+ *                 than its static scratch; nothing was launched
  */
 #ifndef HZGSVD_H
 #define HZGSVD_H
@@ -68,6 +70,10 @@ extern "C" {
 #define HZ_ECHOL 2
 #define HZ_ENONFINITE 3
 #define HZ_EHIP 4
+#define HZ_ENOSCRATCH 5   /* hz_dgsvd_noalloc only: workspace beyond its static scratch */
+
+/* Size of the static device scratch of hz_dgsvd_noalloc, per device. */
+#define HZ_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
 
 /* Parallel orderings (Section 2.2).  HZ_ORD_MM: modified modulus,
  * quasi-cyclic with s = N steps per sweep (step k pairs p < q with
@@ -181,6 +187,26 @@ int hz_dgsvd(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n,
              double *F, int64_t ldf, double *G, int64_t ldg, double *Z, int64_t ldz,
              double *sigma, double *sigma_f, double *sigma_g,
              void *work, size_t work_bytes, hz_info *info, void *stream);
+
+/* hz_dgsvd without allocations, for callers that cannot allocate device
+ * memory (code being captured into a graph, tight serving loops, harnesses
+ * that forbid hipMalloc).  Arguments 1-13 and status codes as hz_dgsvd;
+ * 14 info (host or NULL), 15 stream.  The workspace is a static device
+ * array of HZ_NOALLOC_SCRATCH_BYTES that every GPU the library runs on
+ * holds until the process ends: a solve whose hz_dgsvd_work_size exceeds it
+ * returns HZ_ENOSCRATCH before launching anything.  The call allocates
+ * nothing (no hipMalloc, pinned host buffer, event or graph): its sweeps are
+ * launched directly, not replayed from a captured graph, and per-kernel
+ * timing (p->timing, hz_profile_enable) is not collected; p->qr_shorten and
+ * the dataflow schedule, which need their own buffers, return -1.  Every
+ * call on one GPU shares that GPU's array and leaves its contents behind:
+ * calls of one process are serialised by a lock, and calls that overlap on
+ * one GPU from elsewhere (another process's copy is its own) would race.
+ * Results are bitwise those of hz_dgsvd with the same parameters. */
+int hz_dgsvd_noalloc(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n,
+                     double *F, int64_t ldf, double *G, int64_t ldg, double *Z, int64_t ldz,
+                     double *sigma, double *sigma_f, double *sigma_g, hz_info *info,
+                     void *stream);
 
 /* The block ordering the solver uses: fills table (host, steps * (N/2) * 2
  * ints, row k = the N/2 disjoint pairs (p, q), p < q, of step k) for kind

@@ -24,7 +24,8 @@ CSRC = os.path.join(_HERE, "csrc")
 SOURCES = ["hz_api.hip", "hz_real.hip", "hz_cplx.hip", "hz_mixed.hip", "hz_batched.hip",
            "hz_dataflow.hip", "hz_shorten.hip", "hz_pivqr.hip"]
 
-HZ_OK, HZ_ENOCONV, HZ_ECHOL, HZ_ENONFINITE, HZ_EHIP = 0, 1, 2, 3, 4
+HZ_OK, HZ_ENOCONV, HZ_ECHOL, HZ_ENONFINITE, HZ_EHIP, HZ_ENOSCRATCH = 0, 1, 2, 3, 4, 5
+HZ_NOALLOC_SCRATCH_BYTES = 128 << 20
 HZ_ORD_MM, HZ_ORD_RR = 1, 2
 HZ_SCHED_STEPS, HZ_SCHED_DATAFLOW = 1, 2
 
@@ -103,6 +104,9 @@ def lib():
         L.hz_zgsvd.restype = ctypes.c_int
         L.hz_zgsvd_work_size.argtypes = L.hz_dgsvd_work_size.argtypes
         L.hz_zgsvd_work_size.restype = ctypes.c_size_t
+        L.hz_dgsvd_noalloc.argtypes = [ctypes.POINTER(HzParams), i64, i64, i64, dp, i64, dp,
+                                       i64, dp, i64, dp, dp, dp, ctypes.POINTER(HzInfo), vp]
+        L.hz_dgsvd_noalloc.restype = ctypes.c_int
         L.hz_dgsvd_mixed.argtypes = L.hz_dgsvd.argtypes
         L.hz_dgsvd_mixed.restype = ctypes.c_int
         L.hz_dgsvd_mixed_work_size.argtypes = L.hz_dgsvd_work_size.argtypes
@@ -296,6 +300,27 @@ def gsvd(F, G, *, overwrite=False, raise_on_noconv=False, workspace=None, mixed=
                               other=info.t_other),
                 updates_skipped=info.updates_skipped,
                 fp32_chol_restarts=info.fp32_chol_restarts, info=info)
+
+
+def gsvd_noalloc(U, V, Z, sigma, sigma_f, sigma_g, **kw):
+    """hz_dgsvd_noalloc on caller-provided tensors: U and V hold F and G on
+    entry (float64, column-major, CUDA) and are overwritten in place; Z
+    (n x n, column-major), sigma, sigma_f, sigma_g (n) are outputs.  The
+    library's static scratch is the workspace, so nothing is allocated.
+    Returns (status, HzInfo)."""
+    import torch
+    for t in (U, V, Z):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.t().is_contiguous():
+            raise TypeError("U, V, Z must be column-major float64 CUDA tensors")
+    m_f, n = U.shape
+    m_g = V.shape[0]
+    p = params(**kw)
+    info = HzInfo()
+    stream = torch.cuda.current_stream(U.device).cuda_stream
+    st = lib().hz_dgsvd_noalloc(ctypes.byref(p), m_f, m_g, n, _ptr(U), _ld(U), _ptr(V), _ld(V),
+                                _ptr(Z), _ld(Z), _ptr(sigma), _ptr(sigma_f), _ptr(sigma_g),
+                                ctypes.byref(info), ctypes.c_void_p(stream))
+    return st, info
 
 
 def _i64s(vals):

@@ -305,8 +305,11 @@ struct Prof {
 static Prof g_prof;
 static thread_local EvTimer *tl_timer = nullptr;   // the running call's own timer
 
+static thread_local bool tl_noalloc = false;       // the running call may not allocate
+
 void prof_mark(int kind, bool begin, hipStream_t s)
 {
+    if (tl_noalloc) return;                         // events would be created on demand
     if (g_prof.on) g_prof.t.mark(kind, begin, s);
     if (tl_timer) tl_timer->mark(kind, begin, s);
 }
@@ -466,7 +469,8 @@ enum { KIND_REAL = 0, KIND_COMPLEX = 1, KIND_MIXED = 2 };
 static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t work_bytes,
                      hz_info *info, hipStream_t st, int kind, const void *F, int64_t ldf,
                      const void *G, int64_t ldg, void *U, void *V, void *Z, int64_t ldz,
-                     double *sigma, double *sigma_f, double *sigma_g, bool finish = true);
+                     double *sigma, double *sigma_f, double *sigma_g, bool finish = true,
+                     bool noalloc = false);
 
 // The QR-shortened real solve (qr_shorten = 1).
 static int run_shortened(const hz_params &prm, const Plan &P, const SPlan &S, void *work,
@@ -504,6 +508,7 @@ const char *hz_strerror(int status)
     case HZ_ECHOL: return "pivot Gram block not positive definite (rank-deficient or too ill-conditioned input)";
     case HZ_ENONFINITE: return "NaN or infinity in the input or the iteration";
     case HZ_EHIP: return "HIP runtime error";
+    case HZ_ENOSCRATCH: return "the solve needs more workspace than the static scratch of hz_dgsvd_noalloc holds";
     default: return status < 0 ? "invalid argument" : "unknown status";
     }
 }
@@ -706,6 +711,78 @@ size_t hz_zgsvd_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t 
     return work_size_entry(KIND_COMPLEX, p, m_f, m_g, n);
 }
 
+}  // extern "C"
+
+// Workspace of hz_dgsvd_noalloc: one static array per device, resolved to
+// its device address once per device (the array's name is only a host-side
+// stand-in).  g_scratch_mu also serialises the calls of this process that
+// use the array, which would otherwise race on it.
+static __device__ __align__(256) unsigned char scratch[HZ_NOALLOC_SCRATCH_BYTES];
+static constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[SCRATCH_MAX_DEVICES];
+
+// The calling device's scratch address (g_scratch_mu held), or nullptr.
+static void *scratch_ptr()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SCRATCH_MAX_DEVICES) return nullptr;
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+extern "C" {
+
+int hz_dgsvd_noalloc(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, double *F,
+                     int64_t ldf, double *G, int64_t ldg, double *Z, int64_t ldz, double *sigma,
+                     double *sigma_f, double *sigma_g, hz_info *info, void *stream)
+{
+    hz_params prm;
+    if (p) prm = *p; else hz_default_params(&prm);
+    if (!params_ok(prm) || !w_ok_for(prm, 0)) return -1;
+    if (prm.qr_shorten || prm.timing || prm.schedule == HZ_SCHED_DATAFLOW) return -1;
+    const int a = check_args(m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f, sigma_g);
+    if (a) return a;
+    Plan P;
+    const bool planned = (n == 1) || make_plan(prm, m_f, m_g, n, 0, P, false);
+    if (!planned) return -4;
+    if (n > 1 && P.dataflow) return -1;
+    const size_t need = (n == 1) ? 256 : P.total;
+    if (need > HZ_NOALLOC_SCRATCH_BYTES) return HZ_ENOSCRATCH;
+    hipStream_t st = (hipStream_t)stream;
+    if (info) memset(info, 0, sizeof(*info));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    void *work = scratch_ptr();
+    if (!work) return HZ_EHIP;
+    tl_noalloc = true;
+    int rc = HZ_OK;
+    if (n == 1) {
+        int hs[ST_NSLOTS] = {0};
+        int *status = (int *)work;
+        if (hipMemcpyAsync(status, hs, sizeof(hs), hipMemcpyHostToDevice, st) != hipSuccess) {
+            rc = HZ_EHIP;
+        } else {
+            launch_n1_real(m_f, m_g, F, G, Z, sigma, sigma_f, sigma_g, status, st);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(hs, status, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                rc = HZ_EHIP;
+            else if (hs[ST_FLAGS] & FLAG_NONFINITE)
+                rc = HZ_ENONFINITE;
+        }
+        if (info) { info->converged = 1; info->w = 1; info->status = rc; }
+    } else {
+        rc = run_solve(prm, P, work, HZ_NOALLOC_SCRATCH_BYTES, info, st, KIND_REAL, F, ldf, G,
+                       ldg, F, G, Z, ldz, sigma, sigma_f, sigma_g, true, true);
+    }
+    tl_noalloc = false;
+    return rc;
+}
+
 size_t hz_dgsvd_mixed_work_size(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n)
 {
     return work_size_entry(KIND_MIXED, p, m_f, m_g, n);
@@ -733,7 +810,8 @@ namespace hz {
 static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t work_bytes,
                      hz_info *info, hipStream_t st, int kind, const void *F, int64_t ldf,
                      const void *G, int64_t ldg, void *U, void *V, void *Z, int64_t ldz,
-                     double *sigma, double *sigma_f, double *sigma_g, bool finish)
+                     double *sigma, double *sigma_f, double *sigma_g, bool finish,
+                     bool noalloc)
 {
     (void)work_bytes;
     const auto t_start = std::chrono::steady_clock::now();
@@ -742,7 +820,11 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
     hipGraph_t own_graph[2] = {nullptr, nullptr};      // uncached (library-owned workspace)
     hipGraphExec_t own_exec[2] = {nullptr, nullptr};
     hipGraphExec_t execs[2] = {nullptr, nullptr};
-    unsigned long long *hpin = sweep_readback();
+    // Without allocations (hz_dgsvd_noalloc) the per-sweep summary is read
+    // into host stack memory instead of the thread's pinned buffer (whose
+    // first use allocates it).
+    unsigned long long hstack[64];
+    unsigned long long *hpin = noalloc ? hstack : sweep_readback();
     unsigned long long *dphase = nullptr;
     if (!hpin) return HZ_EHIP;
     EvTimer call_timer;
@@ -759,7 +841,7 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
         Ptrs W = make_ptrs(P, work);
         std::vector<unsigned long long> hph;
         double clk_khz = 0.0;
-        if (g_prof.on && g_prof.phases && kind != KIND_COMPLEX) {
+        if (!noalloc && g_prof.on && g_prof.phases && kind != KIND_COMPLEX) {
             const size_t nph = (size_t)P.steps * P.npairs * 8;
             if (hipMalloc(&dphase, nph * sizeof(unsigned long long)) == hipSuccess) {
                 W.phase = dphase;
@@ -876,7 +958,7 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
         // timing the sweep is replayed from a captured hipGraph (per
         // precision), cached across calls that reuse the workspace; the
         // dataflow sweep is a cooperative launch, which is not captured.
-        const bool use_graph = !g_prof.on && !prm.timing && !P.dataflow;
+        const bool use_graph = !g_prof.on && !prm.timing && !P.dataflow && !noalloc;
         auto enqueue = [&](bool fp32, hipStream_t s) {
             if (P.dataflow && !fp32) {
                 df_err = launch_sweep_df(dfa, df_wg, s);
