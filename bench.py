@@ -340,7 +340,7 @@ def batched_vs_plain(tune_cache=None, reps=3, oracle_sample=16):
     S = [s for _, _, s in pairs]
     kw = dict(inner_max_sweeps=1)
     if tune_cache is not None:
-        kw, _ = hz.tune_batched(D, cache=tune_cache)
+        kw, _ = hz.tune_batched(D, cache=tune_cache, inner_ordering=0)
     works = []
     for f, g in W:
         p = hz.params(**kw)

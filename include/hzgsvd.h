@@ -81,6 +81,17 @@ extern "C" {
  * HZ_ORD_RR: round robin, cyclic with s = N - 1 steps. */
 #define HZ_ORD_MM 1
 #define HZ_ORD_RR 2
+/* HZ_ORD_RING (inner_ordering of the real solvers only): a cyclic ordering
+ * of the 2w columns of a pivot block built for the inner solver's data
+ * movement, level by level.  The columns form blocks of size 2h (h = w,
+ * w/2, ..., 1); in a block, column u of the first half meets every column
+ * of the second half once, keeping its place while the others come to it
+ * (h steps).  Level by level that is w + w/2 + ... + 1 = 2w - 1 steps of w
+ * disjoint pairs, every pair once (Section 2.2's conditions on a parallel
+ * ordering).  The order of the second half's columns within a level follows
+ * the solver's lane groups (sets of min(h, 64/inner_lanes) columns visited
+ * by the groups of one wave in xor order), so it depends on inner_lanes. */
+#define HZ_ORD_RING 3
 
 /* hz_params.schedule */
 #define HZ_SCHED_STEPS 1
@@ -97,7 +108,8 @@ typedef struct hz_params {
                              complex pairs the squared norms a_ii, a_jj by the appendix's
                              simpler procedure (a_ij, b_ij ordinary) */
     int ordering;         /* outer block ordering, HZ_ORD_MM (default) or HZ_ORD_RR */
-    int inner_ordering;   /* pointwise ordering inside a block pair (default HZ_ORD_RR) */
+    int inner_ordering;   /* pointwise ordering inside a block pair: HZ_ORD_RR (default),
+                             HZ_ORD_MM or HZ_ORD_RING (real solvers, per-step schedule) */
     int w;                /* block-column width: 0 = default, else 8, 16 or 32 */
     int inner_max_sweeps; /* inner sweeps per block step: 30 = FB (default), 1 = BO */
     int max_sweeps;       /* outer sweep cap (default 30, Algorithm 1) */
@@ -214,6 +226,17 @@ int hz_dgsvd_noalloc(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n,
  * number of steps (N or N - 1), or -1 for a bad kind or N.  table may be
  * NULL to query the step count. */
 int hz_ordering(int kind, int N, int *table);
+
+/* The ring ordering (HZ_ORD_RING) of the inner solver on a pivot block of
+ * N = 2w columns (4 <= N <= 64, a power of two) with `lanes` lanes per
+ * column pair (4, 8 or 16; N/2 * lanes >= 64): fills table (host,
+ * (N-1) * (N/2) * 2 ints, row k = the pair (i, j), i < j, that lane group g
+ * of the solver takes in step k, for g = 0 .. N/2-1; lane groups 64/lanes
+ * at a time form one wave) and sync (host, N-1 ints: 1 where the solver
+ * synchronises its whole workgroup after step k, 0 where only the wave's
+ * own program order separates step k from step k+1).  Either may be NULL.
+ * Returns N - 1, or -1 for bad arguments. */
+int hz_ring_ordering(int N, int lanes, int *table, int *sync);
 
 /* Diagnostic: the task list of one sweep of the dataflow schedule
  * (HZ_SCHED_DATAFLOW) for these sizes and parameters (w must be 32).

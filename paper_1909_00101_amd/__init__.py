@@ -26,7 +26,7 @@ SOURCES = ["hz_api.hip", "hz_real.hip", "hz_cplx.hip", "hz_mixed.hip", "hz_batch
 
 HZ_OK, HZ_ENOCONV, HZ_ECHOL, HZ_ENONFINITE, HZ_EHIP, HZ_ENOSCRATCH = 0, 1, 2, 3, 4, 5
 HZ_NOALLOC_SCRATCH_BYTES = 128 << 20
-HZ_ORD_MM, HZ_ORD_RR = 1, 2
+HZ_ORD_MM, HZ_ORD_RR, HZ_ORD_RING = 1, 2, 3
 HZ_SCHED_STEPS, HZ_SCHED_DATAFLOW = 1, 2
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -119,6 +119,9 @@ def lib():
         L.hz_eval_2x2.restype = ctypes.c_int
         L.hz_eval_mul_rd.argtypes = [i64, vp, vp, vp, vp, vp]
         L.hz_eval_mul_rd.restype = ctypes.c_int
+        L.hz_ring_ordering.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int)]
+        L.hz_ring_ordering.restype = ctypes.c_int
         L.hz_ordering.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.hz_ordering.restype = ctypes.c_int
         L.hz_profile_enable.argtypes = [ctypes.c_int]

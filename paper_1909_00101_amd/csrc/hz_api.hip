@@ -73,7 +73,10 @@ static int params_ok(const hz_params &p)
     if (p.variant != 0 && p.variant != 1 && p.variant != 4 && p.variant != 5) return 0;
     if (p.schedule != 0 && p.schedule != HZ_SCHED_STEPS && p.schedule != HZ_SCHED_DATAFLOW) return 0;
     if (p.ordering != HZ_ORD_MM && p.ordering != HZ_ORD_RR) return 0;
-    if (p.inner_ordering != HZ_ORD_MM && p.inner_ordering != HZ_ORD_RR) return 0;
+    if (p.inner_ordering != HZ_ORD_MM && p.inner_ordering != HZ_ORD_RR &&
+        p.inner_ordering != HZ_ORD_RING)
+        return 0;
+    if (p.inner_ordering == HZ_ORD_RING && p.schedule == HZ_SCHED_DATAFLOW) return 0;
     if (p.w != 0 && p.w != 8 && p.w != 16 && p.w != 32) return 0;
     if (p.inner_max_sweeps < 1 || p.max_sweeps < 1) return 0;
     if (p.inner_lanes != 0 && p.inner_lanes != 4 && p.inner_lanes != 8 && p.inner_lanes != 16)
@@ -96,7 +99,15 @@ static int default_w(int64_t n, int is_complex)
 // complex 32x32 tiles in LDS).
 static int w_ok_for(const hz_params &p, int is_complex)
 {
+    if (is_complex && p.inner_ordering == HZ_ORD_RING) return 0;   // real solvers only
     return !is_complex || p.w == 0 || p.w == 8 || p.w == 16;
+}
+
+// The table the inner solver reads for a table ordering (the ring ordering
+// is generated inside the solver; a round-robin table fills its slot).
+static int inner_table_kind(int inner_ordering)
+{
+    return inner_ordering == HZ_ORD_RING ? HZ_ORD_RR : inner_ordering;
 }
 
 static bool make_plan(const hz_params &prm, int64_t mf, int64_t mg, int64_t n, int is_complex,
@@ -545,6 +556,31 @@ int hz_ordering(int kind, int N, int *table)
     return steps;
 }
 
+int hz_ring_ordering(int N, int lanes, int *table, int *sync)
+{
+    if (N < 4 || N > 64 || (N & (N - 1)) || (lanes != 4 && lanes != 8 && lanes != 16)) return -1;
+    const int W = N / 2, gw = 64 / lanes, steps = N - 1;
+    if (W * lanes < 64) return -1;               // the solver's workgroup is at least one wave
+    if (!table && !sync) return steps;
+    int st = 0;
+    for (int h = W; h >= 1; h >>= 1) {
+        const int nset = h >= gw ? h / gw : 1, ssz = h >= gw ? gw : h;
+        for (int p = 0; p < nset; ++p)
+            for (int t = 0; t < ssz; ++t, ++st) {
+                for (int g = 0; g < W; ++g) {
+                    const int blk = g / h, u = g % h;
+                    if (table) {
+                        table[((size_t)st * W + g) * 2] = blk * 2 * h + u;
+                        table[((size_t)st * W + g) * 2 + 1] =
+                            blk * 2 * h + h + ring_col(ssz, nset, u / ssz, u % ssz, p, t);
+                    }
+                }
+                if (sync) sync[st] = (t + 1 == ssz) ? 1 : 0;
+            }
+    }
+    return steps;
+}
+
 int hz_dataflow_tasks(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, int *tasks,
                       int *parents, int *info)
 {
@@ -856,7 +892,7 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
         std::vector<int> otab;
         std::vector<int16_t> itab;
         build_ordering<int>(prm.ordering, P.nblk, otab);
-        build_ordering<int16_t>(prm.inner_ordering, P.W2, itab);
+        build_ordering<int16_t>(inner_table_kind(prm.inner_ordering), P.W2, itab);
         const int hs0[ST_NSLOTS] = {0, INT_MAX, 0, 0};
         int hs[ST_NSLOTS] = {0, INT_MAX, 0, 0};
         uint64_t tot_all = 0, tot_big = 0, tot_isw = 0, tot_skip = 0;
@@ -999,6 +1035,7 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
             key_add(key, tol);
             key_add(key, P);
             key_add(key, prm.variant);
+            key_add(key, prm.inner_ordering);   // the ring and round-robin plans are alike
             key_add(key, prm.inner_max_sweeps);
             key_add(key, prm.sort);
             key_add(key, prm.pivot_qr);
@@ -1385,7 +1422,7 @@ static int run_batched(const hz_params &prm, int batch, const int64_t *mf, const
         int *hst = (int *)(hm + L.o_pstatus);
         {
             std::vector<int16_t> it;
-            build_ordering<int16_t>(prm.inner_ordering, L.W2, it);
+            build_ordering<int16_t>(inner_table_kind(prm.inner_ordering), L.W2, it);
             memcpy(hm + L.o_itab, it.data(), it.size() * sizeof(int16_t));
             for (size_t t = 0; t < L.otab_nblk.size(); ++t) {
                 std::vector<int> ot;
@@ -1715,7 +1752,7 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
     if (a) return a;
     if (!best) return -10;
     hipStream_t st = (hipStream_t)stream;
-    const uint64_t key = tune_key(tune_iord ? "dgsvd_iord" : "dgsvd", base, 1, &m_f, &m_g, &n);
+    const uint64_t key = tune_key(tune_iord ? "dgsvd_iord3" : "dgsvd", base, 1, &m_f, &m_g, &n);
     hz_params cur = base;
     double ms = 0.0;
     if (cache_lookup(cache_path, key, cur, ms)) {
@@ -1777,7 +1814,10 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
     if (!base.inner_lanes) cur.inner_lanes = 0;
     std::vector<std::vector<int>> axes;
     std::vector<int *> fields;
-    if (tune_iord) { axes.push_back({HZ_ORD_RR, HZ_ORD_MM}); fields.push_back(&cur.inner_ordering); }
+    if (tune_iord) {
+        axes.push_back({HZ_ORD_RR, HZ_ORD_MM, HZ_ORD_RING});
+        fields.push_back(&cur.inner_ordering);
+    }
     axes.push_back({1, base.inner_max_sweeps});
     fields.push_back(&cur.inner_max_sweeps);
     if (!base.w) { axes.push_back({8, 16, 32}); fields.push_back(&cur.w); }
@@ -1801,9 +1841,12 @@ int hz_dgsvd_batched_tune(const hz_params *p, int batch, const int64_t *m_f, con
 {
     hz_params base;
     if (p) base = *p; else hz_default_params(&base);
-    // ordering 0 asks the tuner to choose between modified modulus and round robin
+    // ordering 0 asks the tuner to choose between modified modulus and round robin,
+    // inner_ordering 0 the ordering inside a block pair
     const bool tune_ord = (base.ordering == 0);
     if (tune_ord) base.ordering = HZ_ORD_MM;
+    const bool tune_iord = (base.inner_ordering == 0);
+    if (tune_iord) base.inner_ordering = HZ_ORD_RR;
     if (!params_ok(base) || base.qr_shorten || base.pivot_qr) return -1;
     if (batch < 1 || batch > 65535) return -2;
     if (!m_f) return -3;
@@ -1821,8 +1864,10 @@ int hz_dgsvd_batched_tune(const hz_params *p, int batch, const int64_t *m_f, con
     }
     if (!best) return -11;
     hipStream_t st = (hipStream_t)stream;
-    const uint64_t key = tune_key(tune_ord ? "dgsvd_batched_ord" : "dgsvd_batched", base, batch,
-                                  m_f, m_g, n);
+    const uint64_t key = tune_key(tune_iord ? (tune_ord ? "dgsvd_batched_ord_iord3"
+                                                        : "dgsvd_batched_iord3")
+                                            : (tune_ord ? "dgsvd_batched_ord" : "dgsvd_batched"),
+                                  base, batch, m_f, m_g, n);
     hz_params cur = base;
     double ms = 0.0;
     if (cache_lookup(cache_path, key, cur, ms)) {
@@ -1859,6 +1904,10 @@ int hz_dgsvd_batched_tune(const hz_params *p, int batch, const int64_t *m_f, con
     if (!base.w) { axes.push_back({8, 16, 32}); fields.push_back(&cur.w); }
     if (!base.inner_lanes) { axes.push_back({4, 8, 16}); fields.push_back(&cur.inner_lanes); }
     if (tune_ord) { axes.push_back({HZ_ORD_MM, HZ_ORD_RR}); fields.push_back(&cur.ordering); }
+    if (tune_iord) {
+        axes.push_back({HZ_ORD_RR, HZ_ORD_MM, HZ_ORD_RING});
+        fields.push_back(&cur.inner_ordering);
+    }
     ms = coordinate_search(cur, axes, fields, solve);
     if (herr) return HZ_EHIP;
     if (ms < 0.0) return HZ_ENOCONV;

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void kb_gram(const BProb *__restrict__ probs,
                    P.gram + ((size_t)tk.y * 2 + mat) * (W2 * W2), tile);
 }
 
-template <int W2, int LP>
+template <int W2, int LP, bool RING>
 __global__ __launch_bounds__((W2 / 2) * LP) void kb_inner(
     const BProb *__restrict__ probs, const int2 *__restrict__ tasks, const int *__restrict__ active,
     int step, const int16_t *__restrict__ itab, int isteps, int inner_max, int sort, int variant,
@@ -73,7 +73,7 @@ __global__ __launch_bounds__((W2 / 2) * LP) void kb_inner(
     const BProb &P = probs[tk.x];
     const double *pa = P.gram + (size_t)tk.y * 2 * (W2 * W2);
     __shared__ __attribute__((aligned(16))) double lds[inner_lds<W2>()];
-    inner_solve<W2, LP>(pa, pa + W2 * W2, 1, 0, itab, isteps, inner_max, P.tol, sort, variant,
+    inner_solve<W2, LP, RING>(pa, pa + W2 * W2, 1, 0, itab, isteps, inner_max, P.tol, sort, variant,
                         P.Zt + (size_t)tk.y * (W2 * W2), c,
                         pstatus + (size_t)tk.x * ST_NSLOTS, step * 65536 + tk.y, nullptr, lds);
     __syncthreads();
@@ -231,23 +231,26 @@ static void stepb_impl(const BPlan &B, int k, const hz_params &prm, hipStream_t 
     hipLaunchKernelGGL(kb_gram<W2>, dim3(nt, 2), dim3(256), 0, s, B.probs, tasks, B.active, k);
     prof_mark(K_GRAM, false, s);
     prof_mark(K_INNER, true, s);
-    if constexpr (W2 == 16) {
-        hipLaunchKernelGGL((kb_inner<W2, 8>), dim3(nt), dim3((W2 / 2) * 8), 0, s, B.probs, tasks,
-                           B.active, k, B.itab, B.isteps, prm.inner_max_sweeps, prm.sort, prm.variant,
-                           B.pcnt, B.pstatus);
+    const bool ring = (prm.inner_ordering == HZ_ORD_RING);
+    const int lp = (W2 == 16) ? 8 : (B.inner_lp == 4 || B.inner_lp == 16 ? B.inner_lp : 8);
+    auto go = [&](auto kern, int l) {
+        hipLaunchKernelGGL(kern, dim3(nt), dim3((W2 / 2) * l), 0, s, B.probs, tasks, B.active, k,
+                           B.itab, B.isteps, prm.inner_max_sweeps, prm.sort, prm.variant, B.pcnt,
+                           B.pstatus);
+    };
+    if (lp == 4) {
+        if constexpr (W2 != 16) {
+            if (ring) go(kb_inner<W2, 4, true>, 4);
+            else go(kb_inner<W2, 4, false>, 4);
+        }
+    } else if (lp == 16) {
+        if constexpr (W2 != 16) {
+            if (ring) go(kb_inner<W2, 16, true>, 16);
+            else go(kb_inner<W2, 16, false>, 16);
+        }
     } else {
-        if (B.inner_lp == 4)
-            hipLaunchKernelGGL((kb_inner<W2, 4>), dim3(nt), dim3((W2 / 2) * 4), 0, s, B.probs,
-                               tasks, B.active, k, B.itab, B.isteps, prm.inner_max_sweeps,
-                               prm.sort, prm.variant, B.pcnt, B.pstatus);
-        else if (B.inner_lp == 16)
-            hipLaunchKernelGGL((kb_inner<W2, 16>), dim3(nt), dim3((W2 / 2) * 16), 0, s, B.probs,
-                               tasks, B.active, k, B.itab, B.isteps, prm.inner_max_sweeps,
-                               prm.sort, prm.variant, B.pcnt, B.pstatus);
-        else
-            hipLaunchKernelGGL((kb_inner<W2, 8>), dim3(nt), dim3((W2 / 2) * 8), 0, s, B.probs,
-                               tasks, B.active, k, B.itab, B.isteps, prm.inner_max_sweeps,
-                               prm.sort, prm.variant, B.pcnt, B.pstatus);
+        if (ring) go(kb_inner<W2, 8, true>, 8);
+        else go(kb_inner<W2, 8, false>, 8);
     }
     prof_mark(K_INNER, false, s);
     prof_mark(K_UPDATE, true, s);

@@ -88,6 +88,19 @@ struct BPlan {
 };
 
 // status[] slots written by kernels (integer atomics only)
+// Ring ordering inside a pivot block (HZ_ORD_RING), shared by the inner
+// solver and the host-side table of hz_ring_ordering.  At the level of
+// blocks of size 2h, group u of a block keeps its column u and meets column
+// h + ring_col(...) of the block in sub-step t of phase p, where the second
+// half is cut into nset = max(h / gw, 1) sets of ssz = min(h, gw) columns
+// (gw = lane groups per wave), wave ow = u / ssz of the block takes set
+// (ow + p) mod nset and group gi = u mod ssz of it column gi xor t of the
+// set.  h, gw, ssz and nset are powers of two.
+__host__ __device__ inline int ring_col(int ssz, int nset, int ow, int gi, int p, int t)
+{
+    return ssz * ((ow + p) & (nset - 1)) + (gi ^ t);
+}
+
 enum { ST_FLAGS = 0, ST_FAILPAIR = 1, ST_NSLOTS = 4 };
 enum { FLAG_NONFINITE = 1, FLAG_CHOL = 2, FLAG_STALL = 4 };
 

@@ -131,6 +131,100 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
             if ((e % W2) / 16 >= (e / W2) / 16) out[e] = tile[(e / W2) * LDSUM + e % W2];
 }
 
+// The four pivot entries of a column pair held as RPL rows per lane by
+// groups of LP lanes, summed over the group (every lane gets the sums):
+// a_ii = f_i^T f_i, a_jj = f_j^T f_j, a_ij = f_i^T f_j, b_ij = g_i^T g_j
+// (b_ii = b_jj = 1 after the prescaling, Section 2.1).  Odd variants use the
+// enhanced dot products of Appendix A.
+template <int LP, int RPL>
+__device__ __forceinline__ void pair_dots(const double (&fi)[RPL], const double (&fj)[RPL],
+                                          const double (&gi)[RPL], const double (&gj)[RPL],
+                                          int variant, double &aii, double &ajj, double &aij,
+                                          double &bij)
+{
+    aii = 0.0; ajj = 0.0; aij = 0.0; bij = 0.0;
+    if (variant & 1) {
+        // the rounded-down products and their errors are summed apart
+        double ei = 0.0, ej = 0.0, eij = 0.0, eb = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            edot_acc(fi[r], fi[r], aii, ei);
+            edot_acc(fj[r], fj[r], ajj, ej);
+            edot_acc(fi[r], fj[r], aij, eij);
+            edot_acc(gi[r], gj[r], bij, eb);
+        }
+        aii = dpp_group_sum<LP>(aii) + dpp_group_sum<LP>(ei);
+        ajj = dpp_group_sum<LP>(ajj) + dpp_group_sum<LP>(ej);
+        aij = dpp_group_sum<LP>(aij) + dpp_group_sum<LP>(eij);
+        bij = dpp_group_sum<LP>(bij) + dpp_group_sum<LP>(eb);
+    } else {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            aii = fma(fi[r], fi[r], aii);
+            ajj = fma(fj[r], fj[r], ajj);
+            aij = fma(fi[r], fj[r], aij);
+            bij = fma(gi[r], gj[r], bij);
+        }
+        aii = dpp_group_sum<LP>(aii);
+        ajj = dpp_group_sum<LP>(ajj);
+        aij = dpp_group_sum<LP>(aij);
+        bij = dpp_group_sum<LP>(bij);
+    }
+}
+
+// One pointwise step of the inner solver on the pivot entries of column
+// pair (i, j), i < j (Section 2.1): the relative orthogonality test, the 2x2
+// transformation Z' (real case, Section 2.1.2), its classification (big
+// unless criterion C1, or C2 for variants 4 and 5, says small, Section 2.5)
+// and the sorting heuristic (swap the two columns when the transformed
+// a''_11 < a''_22, or when an orthogonal pair has a_ii < a_jj).  Returns
+// whether [f_i f_j] (and g, z) change: z11, z21, z12, z22 is then the 2x2
+// matrix to postmultiply them by, swap included.
+__device__ __forceinline__ bool pair_transform(double aii, double ajj, double aij, double bij,
+                                               double tol, double tol2, int sort, int variant,
+                                               double &z11, double &z21, double &z12,
+                                               double &z22, unsigned &sw_all, unsigned &sw_big)
+{
+    z11 = 1.0; z21 = 0.0; z12 = 0.0; z22 = 1.0;
+    bool swap;
+    const bool orth = (aij * aij < aii * ajj * tol2) && (fabs(bij) < tol);
+    if (orth) {
+        swap = sort && (aii < ajj);
+    } else {
+        bool c2small;
+        hz_real_2x2_fast(aii, ajj, aij, bij, z11, z21, z12, z22, c2small);
+        sw_all += 1;
+        // small: criterion C1 (variants 0, 1) or C2 (variants 4, 5), Section 2.5
+        if ((variant & 4) ? !c2small : !(z11 == 1.0 && z22 == 1.0)) sw_big += 1;
+        swap = false;
+        if (sort) {
+            const double a11 = fma(z11 * z11, aii, fma(2.0 * z11 * z21, aij, z21 * z21 * ajj));
+            const double a22 = fma(z12 * z12, aii, fma(2.0 * z22 * z12, aij, z22 * z22 * ajj));
+            swap = a11 < a22;
+        }
+    }
+    if (swap) {
+        double t;
+        t = z11; z11 = z12; z12 = t;
+        t = z21; z21 = z22; z22 = t;
+    }
+    return !orth || swap;
+}
+
+// [x_i x_j] <- [x_i x_j] [[z11, z12], [z21, z22]] on RPL rows per lane.
+template <int RPL>
+__device__ __forceinline__ void rotate_rows(double (&xi)[RPL], double (&xj)[RPL], double z11,
+                                            double z21, double z12, double z22)
+{
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const double ni = fma(xj[r], z21, xi[r] * z11);
+        const double nj = fma(xi[r], z12, xj[r] * z22);
+        xi[r] = ni;
+        xj[r] = nj;
+    }
+}
+
 // Device body: the workgroup (NT threads) solves the block pair whose Gram
 // blocks are pa (F) and pb (G) (column-major W2 x W2, lower triangles),
 // writes Z_tilde to zt, the counters (transformations, big ones, inner
@@ -141,7 +235,7 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
 // which only renormalizes columns that already have ||f_j||^2 + ||g_j||^2 =
 // 1 up to rounding; it is then set to I exactly and myc[3] = 1, so the
 // block update may be skipped (Section 2.5).
-template <int W2, int LP>
+template <int W2, int LP, bool RING = false>
 __device__ __forceinline__ void inner_solve(
     const double *__restrict__ pa, const double *__restrict__ pb, int nsplit, size_t sstride,
     const int16_t *__restrict__ itab, int isteps, int inner_max, double tol, int sort, int variant,
@@ -181,7 +275,8 @@ __device__ __forceinline__ void inner_solve(
             *(d2 *)(sF + col * LDI + row) = a;
             *(d2 *)(sG + col * LDI + row) = b;
         }
-        for (int e = tid; e < isteps * W * 2; e += NT) stab[e] = itab[e];
+        if (!RING)
+            for (int e = tid; e < isteps * W * 2; e += NT) stab[e] = itab[e];
         if (tid == 0) s_fail = 0;
     }
     __syncthreads();
@@ -331,6 +426,11 @@ __device__ __forceinline__ void inner_solve(
     }
 
     const int grp = tid / LP, gl = tid % LP, r0 = gl * RPL;
+    // Row k (0 <= k < RPL) of a lane's share of a column: RPL consecutive
+    // rows for the table orderings; for the ring ordering pairs of rows
+    // 2 LP apart, so that the 16-byte accesses of a group's lanes are
+    // contiguous in LDS.
+    auto RI = [&](int k) { return RING ? (k >> 1) * 2 * LP + 2 * gl + (k & 1) : r0 + k; };
     // 3. prescale the factor pair: columns 2*grp and 2*grp+1 per group.
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -338,16 +438,16 @@ __device__ __forceinline__ void inner_solve(
         double s = 0.0;
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
-            const double g = sG[c * LDI + r0 + r];
+            const double g = sG[c * LDI + RI(r)];
             s = fma(g, g, s);
         }
         s = dpp_group_sum<LP>(s);
         const double d = rsqrt_nr(s);
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
-            sF[c * LDI + r0 + r] *= d;
-            sG[c * LDI + r0 + r] *= d;
-            sZ[c * LDI + r0 + r] = (r0 + r == c) ? d : 0.0;
+            sF[c * LDI + RI(r)] *= d;
+            sG[c * LDI + RI(r)] *= d;
+            sZ[c * LDI + RI(r)] = (RI(r) == c) ? d : 0.0;
         }
     }
     __syncthreads();
@@ -357,102 +457,98 @@ __device__ __forceinline__ void inner_solve(
     const double tol2 = tol * tol;
     unsigned my_all = 0, my_big = 0, my_chg = 0;
     int nsw = 0;
+    auto load = [&](const double *M, int c, double (&x)[RPL]) {
+#pragma unroll
+        for (int r = 0; r < RPL; r += 2) {
+            const d2 v = *(const d2 *)(M + c * LDI + RI(r));
+            x[r] = v[0];
+            x[r + 1] = v[1];
+        }
+    };
+    auto store = [&](double *M, int c, const double (&x)[RPL]) {
+#pragma unroll
+        for (int r = 0; r < RPL; r += 2) *(d2 *)(M + c * LDI + RI(r)) = d2{x[r], x[r + 1]};
+    };
     for (int sw = 0; sw < inner_max; ++sw) {
         unsigned sw_all = 0, sw_big = 0;
         ++nsw;
-        for (int st = 0; st < isteps; ++st) {
-            const int ci = stab[(st * W + grp) * 2], cj = stab[(st * W + grp) * 2 + 1];
-            double fi[RPL], fj[RPL], gi[RPL], gj[RPL], zi[RPL], zj[RPL];
-#pragma unroll
-            for (int r = 0; r < RPL; r += 2) {
-                const d2 a0 = *(const d2 *)(sF + ci * LDI + r0 + r);
-                const d2 a1 = *(const d2 *)(sF + cj * LDI + r0 + r);
-                const d2 b0 = *(const d2 *)(sG + ci * LDI + r0 + r);
-                const d2 b1 = *(const d2 *)(sG + cj * LDI + r0 + r);
-                const d2 c0 = *(const d2 *)(sZ + ci * LDI + r0 + r);
-                const d2 c1 = *(const d2 *)(sZ + cj * LDI + r0 + r);
-                fi[r] = a0[0]; fi[r + 1] = a0[1];
-                fj[r] = a1[0]; fj[r + 1] = a1[1];
-                gi[r] = b0[0]; gi[r + 1] = b0[1];
-                gj[r] = b1[0]; gj[r + 1] = b1[1];
-                zi[r] = c0[0]; zi[r + 1] = c0[1];
-                zj[r] = c1[0]; zj[r + 1] = c1[1];
-            }
-            double aii = 0.0, ajj = 0.0, aij = 0.0, bij = 0.0;
-            if (variant & 1) {
-                // enhanced dot products (variants 1 and 5, Appendix A): the
-                // rounded-down products and their errors are summed apart
-                double ei = 0.0, ej = 0.0, eij = 0.0, eb = 0.0;
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) {
-                    edot_acc(fi[r], fi[r], aii, ei);
-                    edot_acc(fj[r], fj[r], ajj, ej);
-                    edot_acc(fi[r], fj[r], aij, eij);
-                    edot_acc(gi[r], gj[r], bij, eb);
-                }
-                aii = dpp_group_sum<LP>(aii) + dpp_group_sum<LP>(ei);
-                ajj = dpp_group_sum<LP>(ajj) + dpp_group_sum<LP>(ej);
-                aij = dpp_group_sum<LP>(aij) + dpp_group_sum<LP>(eij);
-                bij = dpp_group_sum<LP>(bij) + dpp_group_sum<LP>(eb);
-            } else {
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) {
-                    aii = fma(fi[r], fi[r], aii);
-                    ajj = fma(fj[r], fj[r], ajj);
-                    aij = fma(fi[r], fj[r], aij);
-                    bij = fma(gi[r], gj[r], bij);
-                }
-                aii = dpp_group_sum<LP>(aii);
-                ajj = dpp_group_sum<LP>(ajj);
-                aij = dpp_group_sum<LP>(aij);
-                bij = dpp_group_sum<LP>(bij);
-            }
-            double z11 = 1.0, z21 = 0.0, z12 = 0.0, z22 = 1.0;
-            bool swap;
-            const bool orth = (aij * aij < aii * ajj * tol2) && (fabs(bij) < tol);
-            if (orth) {
-                swap = sort && (aii < ajj);
-            } else {
-                bool c2small;
-                hz_real_2x2_fast(aii, ajj, aij, bij, z11, z21, z12, z22, c2small);
-                sw_all += 1;
-                // small: criterion C1 (variants 0, 1) or C2 (variants 4, 5), Section 2.5
-                if ((variant & 4) ? !c2small : !(z11 == 1.0 && z22 == 1.0)) sw_big += 1;
-                swap = false;
-                if (sort) {
-                    const double a11 = fma(z11 * z11, aii, fma(2.0 * z11 * z21, aij, z21 * z21 * ajj));
-                    const double a22 = fma(z12 * z12, aii, fma(2.0 * z22 * z12, aij, z22 * z22 * ajj));
-                    swap = a11 < a22;
-                }
-            }
-            if (swap) {
-                double t;
-                t = z11; z11 = z12; z12 = t;
-                t = z21; z21 = z22; z22 = t;
-            }
-            if (!orth || swap) {
-                my_chg = 1;
-#pragma unroll
-                for (int r = 0; r < RPL; r += 2) {
-                    d2 nfi, nfj, ngi, ngj, nzi, nzj;
-#pragma unroll
-                    for (int u = 0; u < 2; ++u) {
-                        nfi[u] = fma(fj[r + u], z21, fi[r + u] * z11);
-                        nfj[u] = fma(fi[r + u], z12, fj[r + u] * z22);
-                        ngi[u] = fma(gj[r + u], z21, gi[r + u] * z11);
-                        ngj[u] = fma(gi[r + u], z12, gj[r + u] * z22);
-                        nzi[u] = fma(zj[r + u], z21, zi[r + u] * z11);
-                        nzj[u] = fma(zi[r + u], z12, zj[r + u] * z22);
+        if constexpr (RING) {
+            // Ring ordering, level by level: the columns form blocks of size
+            // 2h (h = W, W/2, ..., 1); group u of a block keeps column u of
+            // the block's first half in registers for the whole level and
+            // meets every column of the second half once.  The second half
+            // is cut into sets of G = min(h, groups per wave) columns; in
+            // phase p wave o of the block takes set (o + p) mod (h / G), and
+            // in its sub-step t group g of the wave takes column g xor t of
+            // that set.  A set stays inside one wave for a phase, so the
+            // columns move between sub-steps through LDS in the wave's own
+            // program order; only between phases and levels does the whole
+            // workgroup synchronise.
+            constexpr int GW = 64 / LP;             // groups per wave
+            for (int h = W; h >= 1; h >>= 1) {
+                const int blk = grp / h, u = grp % h;
+                const int ci = blk * 2 * h + u;
+                const int nset = (h >= GW) ? h / GW : 1, ssz = (h >= GW) ? GW : h;
+                const int ow = u / ssz, gw = u % ssz;
+                double fi[RPL], gi[RPL], zi[RPL];
+                load(sF, ci, fi);
+                load(sG, ci, gi);
+                load(sZ, ci, zi);
+                for (int p = 0; p < nset; ++p) {
+                    for (int t = 0; t < ssz; ++t) {
+                        const int cj = blk * 2 * h + h + ring_col(ssz, nset, ow, gw, p, t);
+                        double fj[RPL], gj[RPL], zj[RPL];
+                        load(sF, cj, fj);
+                        load(sG, cj, gj);
+                        load(sZ, cj, zj);
+                        double aii, ajj, aij, bij, z11, z21, z12, z22;
+                        pair_dots<LP, RPL>(fi, fj, gi, gj, variant, aii, ajj, aij, bij);
+                        if (pair_transform(aii, ajj, aij, bij, tol, tol2, sort, variant, z11, z21,
+                                           z12, z22, sw_all, sw_big)) {
+                            my_chg = 1;
+                            rotate_rows<RPL>(fi, fj, z11, z21, z12, z22);
+                            rotate_rows<RPL>(gi, gj, z11, z21, z12, z22);
+                            rotate_rows<RPL>(zi, zj, z11, z21, z12, z22);
+                            store(sF, cj, fj);
+                            store(sG, cj, gj);
+                            store(sZ, cj, zj);
+                        }
+                        if (t + 1 < ssz) wave_fence();
                     }
-                    *(d2 *)(sF + ci * LDI + r0 + r) = nfi;
-                    *(d2 *)(sF + cj * LDI + r0 + r) = nfj;
-                    *(d2 *)(sG + ci * LDI + r0 + r) = ngi;
-                    *(d2 *)(sG + cj * LDI + r0 + r) = ngj;
-                    *(d2 *)(sZ + ci * LDI + r0 + r) = nzi;
-                    *(d2 *)(sZ + cj * LDI + r0 + r) = nzj;
+                    __syncthreads();
                 }
+                store(sF, ci, fi);
+                store(sG, ci, gi);
+                store(sZ, ci, zi);
+                __syncthreads();
             }
-            __syncthreads();
+        } else {
+            for (int st = 0; st < isteps; ++st) {
+                const int ci = stab[(st * W + grp) * 2], cj = stab[(st * W + grp) * 2 + 1];
+                double fi[RPL], fj[RPL], gi[RPL], gj[RPL], zi[RPL], zj[RPL];
+                load(sF, ci, fi);
+                load(sF, cj, fj);
+                load(sG, ci, gi);
+                load(sG, cj, gj);
+                load(sZ, ci, zi);
+                load(sZ, cj, zj);
+                double aii, ajj, aij, bij, z11, z21, z12, z22;
+                pair_dots<LP, RPL>(fi, fj, gi, gj, variant, aii, ajj, aij, bij);
+                if (pair_transform(aii, ajj, aij, bij, tol, tol2, sort, variant, z11, z21, z12,
+                                   z22, sw_all, sw_big)) {
+                    my_chg = 1;
+                    rotate_rows<RPL>(fi, fj, z11, z21, z12, z22);
+                    rotate_rows<RPL>(gi, gj, z11, z21, z12, z22);
+                    rotate_rows<RPL>(zi, zj, z11, z21, z12, z22);
+                    store(sF, ci, fi);
+                    store(sF, cj, fj);
+                    store(sG, ci, gi);
+                    store(sG, cj, gj);
+                    store(sZ, ci, zi);
+                    store(sZ, cj, zj);
+                }
+                __syncthreads();
+            }
         }
         my_all += sw_all;
         my_big += sw_big;
@@ -470,20 +566,20 @@ __device__ __forceinline__ void inner_solve(
         const int c = 2 * grp + h;
         if (nchg == 0) {
 #pragma unroll
-            for (int r = 0; r < RPL; ++r) zt[c * W2 + r0 + r] = (r0 + r == c) ? 1.0 : 0.0;
+            for (int r = 0; r < RPL; ++r) zt[c * W2 + RI(r)] = (RI(r) == c) ? 1.0 : 0.0;
             continue;
         }
         double s = 0.0;
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
-            const double f = sF[c * LDI + r0 + r], g = sG[c * LDI + r0 + r];
+            const double f = sF[c * LDI + RI(r)], g = sG[c * LDI + RI(r)];
             s = fma(f, f, s);
             s = fma(g, g, s);
         }
         s = dpp_group_sum<LP>(s);
         const double th = rsqrt_nr(s);
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) zt[c * W2 + r0 + r] = sZ[c * LDI + r0 + r] * th;
+        for (int r = 0; r < RPL; ++r) zt[c * W2 + RI(r)] = sZ[c * LDI + RI(r)] * th;
     }
     // counters: the groups' totals summed in group order
     if (gl == 0) {

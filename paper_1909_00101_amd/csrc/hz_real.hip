@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_gram_sum(const double *__restrict__ par
 //  5. Z_tilde = Z_hat Theta, Theta_jj = (||f_hat_j||^2+||g_hat_j||^2)^-1/2.
 // Counters per (step, pair): transformations, big ones, inner sweeps run.
 // ------------------------------------------------------------------------
-template <int W2, int LP>
+template <int W2, int LP, bool RING>
 __global__ __launch_bounds__((W2 / 2) * LP) void k_inner(
     const double *__restrict__ gram, int nsplit, int npairs, int step,
     const int16_t *__restrict__ itab, int isteps, int inner_max, double tol, int sort, int variant,
@@ -136,7 +136,7 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner(
     const int ns = nsplit > 0 ? nsplit : 1;   // nsplit 0: one triangular factor per matrix
     const double *pa = gram + (size_t)(pr * 2) * ns * (W2 * W2);
     __shared__ __attribute__((aligned(16))) double lds[inner_lds<W2>()];
-    inner_solve<W2, LP>(pa, pa + (size_t)ns * (W2 * W2), nsplit, W2 * W2, itab, isteps,
+    inner_solve<W2, LP, RING>(pa, pa + (size_t)ns * (W2 * W2), nsplit, W2 * W2, itab, isteps,
                         inner_max, tol, sort, variant,
                         Zt + (size_t)pr * (W2 * W2), cnt + ((size_t)step * npairs + pr) * 4,
                         status, step * 65536 + pr,
@@ -424,32 +424,36 @@ void launch_prescale_real(const Plan &P, const Ptrs &W, const double *F, int64_t
                        ldg, P.nw, P.mfw, P.mgw, P.nzw, W.Fw, W.Gw, W.Zw, W.status);
 }
 
+template <int W2, int LP, bool RING>
+static void inner_launch(const Plan &P, const Ptrs &W, int step, const hz_params &prm,
+                         double tol, const double *src, int ns, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_inner<W2, LP, RING>), dim3(P.npairs), dim3((W2 / 2) * LP), 0, s, src,
+                       ns, P.npairs, step, W.itab, P.isteps, prm.inner_max_sweeps, tol, prm.sort,
+                       prm.variant, W.Zt, W.cnt, W.status, W.phase);
+}
+
 template <int W2>
 static void inner_impl(const Plan &P, const Ptrs &W, int step, const hz_params &prm, double tol,
                        bool partials, hipStream_t s)
 {
     const double *src = partials ? W.part : W.gram;
     const int ns = partials ? P.splits : (prm.pivot_qr ? 0 : 1);
+    const bool ring = (prm.inner_ordering == HZ_ORD_RING);
     if constexpr (W2 == 16) {
-        hipLaunchKernelGGL((k_inner<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s, src, ns,
-                           P.npairs, step, W.itab, P.isteps, prm.inner_max_sweeps, tol, prm.sort,
-                           prm.variant, W.Zt, W.cnt, W.status, W.phase);
+        if (ring) inner_launch<W2, 8, true>(P, W, step, prm, tol, src, ns, s);
+        else inner_launch<W2, 8, false>(P, W, step, prm, tol, src, ns, s);
     } else {
-        if (P.inner_lp == 4)
-            hipLaunchKernelGGL((k_inner<W2, 4>), dim3(P.npairs), dim3((W2 / 2) * 4), 0, s,
-                               src, ns, P.npairs, step, W.itab, P.isteps,
-                               prm.inner_max_sweeps, tol, prm.sort, prm.variant, W.Zt, W.cnt, W.status,
-                               W.phase);
-        else if (P.inner_lp == 8)
-            hipLaunchKernelGGL((k_inner<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s,
-                               src, ns, P.npairs, step, W.itab, P.isteps,
-                               prm.inner_max_sweeps, tol, prm.sort, prm.variant, W.Zt, W.cnt, W.status,
-                               W.phase);
-        else
-            hipLaunchKernelGGL((k_inner<W2, 16>), dim3(P.npairs), dim3((W2 / 2) * 16), 0, s,
-                               src, ns, P.npairs, step, W.itab, P.isteps,
-                               prm.inner_max_sweeps, tol, prm.sort, prm.variant, W.Zt, W.cnt, W.status,
-                               W.phase);
+        if (P.inner_lp == 4) {
+            if (ring) inner_launch<W2, 4, true>(P, W, step, prm, tol, src, ns, s);
+            else inner_launch<W2, 4, false>(P, W, step, prm, tol, src, ns, s);
+        } else if (P.inner_lp == 8) {
+            if (ring) inner_launch<W2, 8, true>(P, W, step, prm, tol, src, ns, s);
+            else inner_launch<W2, 8, false>(P, W, step, prm, tol, src, ns, s);
+        } else {
+            if (ring) inner_launch<W2, 16, true>(P, W, step, prm, tol, src, ns, s);
+            else inner_launch<W2, 16, false>(P, W, step, prm, tol, src, ns, s);
+        }
     }
 }
 

@@ -127,6 +127,54 @@ def test_library_orderings(hz, N):
     assert hz.lib().hz_ordering(5, 8, None) == -1
 
 
+@pytest.mark.parametrize("N,lanes", [(16, 8), (32, 4), (32, 8), (32, 16), (64, 4), (64, 8),
+                                     (64, 16)])
+def test_ring_ordering(hz, N, lanes):
+    """The inner solver's ring ordering: N - 1 steps of N/2 disjoint pairs
+    (i < j) covering every pair once (a cyclic parallel ordering); within a
+    level a lane group keeps its first column; and the schedule is free of
+    races: where the solver does not synchronise its workgroup after a
+    step, every column a group touches in the next step was last touched by
+    a group of the same wave."""
+    L = hz.lib()
+    steps = L.hz_ring_ordering(N, lanes, None, None)
+    assert steps == N - 1
+    t = (ctypes.c_int * (steps * N))()
+    sy = (ctypes.c_int * steps)()
+    assert L.hz_ring_ordering(N, lanes, t, sy) == steps
+    tab = np.array(t).reshape(steps, N // 2, 2)
+    sync = list(sy)
+    seen = set()
+    for step in tab:
+        assert sorted(step.reshape(-1).tolist()) == list(range(N))
+        for i, j in step:
+            assert i < j and (i, j) not in seen
+            seen.add((i, j))
+    assert len(seen) == N * (N - 1) // 2
+    gw = 64 // lanes
+    last = {}                      # column -> (wave of the group that last touched it, synced since)
+    for k, step in enumerate(tab):
+        for g, (i, j) in enumerate(step):
+            for c in (i, j):
+                if c in last:
+                    wave, synced = last[c]
+                    assert synced or wave == g // gw, (k, g, c)
+        for g, (i, j) in enumerate(step):
+            last[i] = (g // gw, False)
+            last[j] = (g // gw, False)
+        if sync[k]:
+            last = {c: (wv, True) for c, (wv, _) in last.items()}
+    assert sync[-1] == 1
+    # the first column of a group stays for a whole level (levels of N/2, N/4, ... steps)
+    k0, h = 0, N // 2
+    while h >= 1:
+        for g in range(N // 2):
+            assert len({int(tab[k, g, 0]) for k in range(k0, k0 + h)}) == 1
+        k0, h = k0 + h, h // 2
+    assert L.hz_ring_ordering(48, 8, None, None) == -1
+    assert L.hz_ring_ordering(16, 2, None, None) == -1
+
+
 def test_product_path_does_not_reach_the_oracle():
     pkg = os.path.join(ROOT, "paper_1909_00101_amd")
     for dirpath, _, files in os.walk(pkg):

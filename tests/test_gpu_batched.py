@@ -67,10 +67,11 @@ def _small_batch():
     return pairs
 
 
-@pytest.mark.parametrize("w,lanes", [(8, 0), (16, 0), (16, 4)])
-def test_small_batch_vs_oracle(w, lanes):
+@pytest.mark.parametrize("w,lanes,iord", [(8, 0, 2), (16, 0, 2), (16, 4, 2), (8, 0, 3),
+                                           (16, 8, 3), (16, 16, 3)])
+def test_small_batch_vs_oracle(w, lanes, iord):
     pairs = _small_batch()
-    st, res = _run_batch(pairs, w=w, inner_lanes=lanes)
+    st, res = _run_batch(pairs, w=w, inner_lanes=lanes, inner_ordering=iord)
     assert st == 0, [r["status"] for r in res]
     worst = 0.0
     for i, ((F, G, s_true), r) in enumerate(zip(pairs, res)):
@@ -85,13 +86,13 @@ def test_small_batch_vs_oracle(w, lanes):
     print(f"w={w}: {len(pairs)} pairs, worst err vs oracle {worst:.2e}")
 
 
-@pytest.mark.parametrize("w", [8, 16, 32])
-def test_batched_equals_single_pair_bitwise(w):
+@pytest.mark.parametrize("w,iord", [(8, 2), (16, 2), (32, 2), (16, 3), (32, 3)])
+def test_batched_equals_single_pair_bitwise(w, iord):
     pairs = gi.make_batch(count=9, seed=21, n_lo=2, n_hi=100)
-    st, res = _run_batch(pairs, w=w)
+    st, res = _run_batch(pairs, w=w, inner_ordering=iord)
     assert st == 0
     for i, ((F, G, _), r) in enumerate(zip(pairs, res)):
-        s = _run_single(F, G, w=w, gram_splits=1)
+        s = _run_single(F, G, w=w, gram_splits=1, inner_ordering=iord)
         assert r["sweeps"] == s["sweeps"], (i, r["sweeps"], s["sweeps"])
         assert r["rot_total"] == s["rot_total"] and r["rot_big"] == s["rot_big"], i
         for k in ("sigma", "sigma_f", "sigma_g", "U", "V", "Z"):

@@ -46,10 +46,11 @@ def test_mixed_parity(shape):
                     tol_res=1e-12, tol_orth=1e-12)
 
 
-def test_mixed_matches_plain():
+@pytest.mark.parametrize("iord", [2, 3], ids=["innerRR", "ring"])
+def test_mixed_matches_plain(iord):
     F, G, _ = gi.custom_pair(1024, 768, 256, kappa=1e2, seed=31)
-    a = _run(F, G, w=16, tol=256 * EPS)
-    b = _run(F, G, w=16, tol=256 * EPS, mixed=True)
+    a = _run(F, G, w=16, tol=256 * EPS, inner_ordering=iord)
+    b = _run(F, G, w=16, tol=256 * EPS, mixed=True, inner_ordering=iord)
     assert a["status"] == 0 and b["status"] == 0
     assert max_rel(b["sigma"], a["sigma"]) < SIG_TOL
 

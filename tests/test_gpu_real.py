@@ -105,9 +105,18 @@ def test_n1_closed_form():
 @pytest.mark.parametrize("kw", [dict(ordering=2), dict(inner_ordering=1),
                                 dict(inner_max_sweeps=1), dict(sort=0),
                                 dict(w=16, inner_lanes=4), dict(w=32, inner_lanes=4),
-                                dict(w=32, inner_lanes=8)],
+                                dict(w=32, inner_lanes=8),
+                                dict(inner_ordering=3), dict(inner_ordering=3, inner_max_sweeps=1),
+                                dict(w=16, inner_ordering=3, inner_lanes=4),
+                                dict(w=16, inner_ordering=3, inner_lanes=16),
+                                dict(w=32, inner_ordering=3),
+                                dict(w=32, inner_ordering=3, inner_lanes=4),
+                                dict(w=32, inner_ordering=3, inner_lanes=8, sort=0),
+                                dict(w=32, inner_ordering=3, variant=5)],
                          ids=["outerRR", "innerMM", "BO", "nosort", "w16lanes4", "w32lanes4",
-                              "w32lanes8"])
+                              "w32lanes8", "ring", "ringBO", "ringw16lanes4", "ringw16lanes16",
+                              "ringw32", "ringw32lanes4", "ringw32lanes8nosort",
+                              "ringw32variant5"])
 def test_variants_parity(kw):
     F, G, _ = gi.custom_pair(200, 180, 64, kappa=1e2, seed=77)
     o = _oracle(F, G)
@@ -116,6 +125,41 @@ def test_variants_parity(kw):
     assert r["status"] == 0
     assert max_rel(r["sigma"], o["sigma"]) < SIG_TOL
     _check(F, G, r)
+
+
+RING_SHAPES = [
+    # m_f, m_g, n, w, kappa, inner sweeps
+    (300, 280, 64, 32, 1e2, 30),   # one pivot block: the solve is one full-block inner solve
+    (130, 129, 37, 8, 30.0, 1),   # ragged n: bordering columns inside the pivot blocks
+    (700, 520, 256, 32, 1e2, 1),
+    (400, 300, 100, 32, 1e2, 30),
+    (333, 65, 65, 16, 50.0, 1),
+]
+
+
+@pytest.mark.parametrize("shape", RING_SHAPES, ids=lambda s: "x".join(map(str, s[:4])) +
+                         f"-is{s[5]}")
+def test_ring_inner_ordering_parity(shape):
+    """The ring ordering inside the pivot blocks (HZ_ORD_RING): sigma within
+    the parity tolerance of the oracle (which runs its own ordering), the
+    prescribed sigma, and the GSVD contract."""
+    m_f, m_g, n, w, kappa, isw = shape
+    F, G, s_true = gi.custom_pair(m_f, m_g, n, kappa=kappa, seed=3 * n + w)
+    o = _oracle(F, G, ordering=1, threads=4)
+    r = _run(F, G, w=w, inner_ordering=3, inner_max_sweeps=isw)
+    err = max_rel(r["sigma"], o["sigma"])
+    print(f"ring {shape}: sweeps={r['sweeps']} status={r['status']} err={err:.2e}")
+    assert r["status"] == 0 and r["converged"]
+    assert err < SIG_TOL
+    assert max_rel(r["sigma"], s_true) < 1e-11
+    _check(F, G, r)
+
+
+def test_ring_bitwise_reruns():
+    F, G, _ = gi.custom_pair(512, 384, 192, kappa=1e2, seed=6)
+    digests = {_digest(_run(F, G, w=32, inner_ordering=3, inner_max_sweeps=1))
+               for _ in range(3)}
+    assert len(digests) == 1
 
 
 def _digest(r):
@@ -175,7 +219,8 @@ def test_sweep_cap():
 @pytest.mark.parametrize("launch", [
     {},
     dict(inner_ordering=1, inner_max_sweeps=1, gram_splits=8, update_rows=48, inner_lanes=16),
-], ids=["defaults", "bench_tuned"])
+    dict(inner_ordering=3, inner_max_sweeps=1, gram_splits=8, update_rows=48, inner_lanes=16),
+], ids=["defaults", "bench_tuned", "ring"])
 def test_config2_full_size_vs_oracle_golden(launch):
     """The 4096x1024 workload (w = 32, modified modulus, tol = 1024 eps), with
     the library's default launch and with the launch the benchmark times
@@ -284,6 +329,28 @@ def test_sweep_graph_cached_across_calls_with_one_workspace():
     assert a1["status"] == 0 and b1["status"] == 0
     assert max_rel(b1["sigma"], _oracle(FB, GB)["sigma"]) < SIG_TOL
     assert max_rel(a1["sigma"], _oracle(FA, GA)["sigma"]) < SIG_TOL
+
+
+def test_graph_cache_keys_the_inner_ordering():
+    """Round-robin and ring plans of one shape are alike in everything but
+    the inner ordering: a call with the ring ordering in a workspace whose
+    round-robin sweep graph is cached must not replay that graph."""
+    hz = _hz()
+    F, G, _ = gi.custom_pair(300, 260, 96, kappa=1e2, seed=65)
+    work = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+
+    def run(iord, wk):
+        r = hz.gsvd(torch.from_numpy(np.asfortranarray(F)).cuda(),
+                    torch.from_numpy(np.asfortranarray(G)).cuda(), w=16, inner_ordering=iord,
+                    workspace=wk)
+        torch.cuda.synchronize()
+        return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in r.items()}
+
+    rr = run(2, work)
+    ring = run(3, work)
+    fresh = run(3, torch.empty(64 << 20, dtype=torch.uint8, device="cuda"))
+    assert _digest(ring) == _digest(fresh)
+    assert ring["rot_total"] != rr["rot_total"] or _digest(ring) != _digest(rr)
 
 
 @pytest.mark.parametrize("cplx", [False, True])
