@@ -96,6 +96,7 @@ extern "C" {
 /* hz_params.schedule */
 #define HZ_SCHED_STEPS 1
 #define HZ_SCHED_DATAFLOW 2
+#define HZ_SCHED_PERSISTENT 3
 
 typedef struct hz_params {
     int variant;          /* Table 1, prescaled: 0 = small transformations by criterion
@@ -130,7 +131,15 @@ typedef struct hz_params {
     int schedule;         /* real FP64 path: 0 = default, HZ_SCHED_STEPS = one launch per
                              phase and block step, HZ_SCHED_DATAFLOW = one persistent
                              launch per sweep whose workgroups take Gram, inner-solve and
-                             update tasks from a dependency-ordered queue (w = 32 only) */
+                             update tasks from a dependency-ordered queue (w = 32 only).
+                             hz_dgsvd_batched: 0 = HZ_SCHED_PERSISTENT where it applies
+                             (w = 16 or 32), else HZ_SCHED_STEPS; HZ_SCHED_PERSISTENT =
+                             one launch for all sweeps of all pairs, whose workgroups take
+                             whole block-pair tasks (Gram, inner solve, update) from a
+                             queue ordered by the pairs' steps, each pair deciding its own
+                             convergence on the device (inner_lanes is then 16 for w = 16,
+                             8 or 16 for w = 32); HZ_SCHED_STEPS = launches per block step
+                             and a host check after every sweep */
     int qr_shorten;       /* hz_dgsvd, hz_zgsvd, hz_dgsvd_mixed: 1 = shorten the pair first
                              (Section 2, before the prescaling): F P1 = Q_F R_F and
                              (G P1) P2 = Q_G R_G with column pivoting, the sweeps run on the

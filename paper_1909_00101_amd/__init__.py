@@ -27,7 +27,7 @@ SOURCES = ["hz_api.hip", "hz_real.hip", "hz_cplx.hip", "hz_mixed.hip", "hz_batch
 HZ_OK, HZ_ENOCONV, HZ_ECHOL, HZ_ENONFINITE, HZ_EHIP, HZ_ENOSCRATCH = 0, 1, 2, 3, 4, 5
 HZ_NOALLOC_SCRATCH_BYTES = 128 << 20
 HZ_ORD_MM, HZ_ORD_RR, HZ_ORD_RING = 1, 2, 3
-HZ_SCHED_STEPS, HZ_SCHED_DATAFLOW = 1, 2
+HZ_SCHED_STEPS, HZ_SCHED_DATAFLOW, HZ_SCHED_PERSISTENT = 1, 2, 3
 
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -71,7 +71,9 @@ static int build_ordering(int kind, int N, std::vector<T> &tab)
 static int params_ok(const hz_params &p)
 {
     if (p.variant != 0 && p.variant != 1 && p.variant != 4 && p.variant != 5) return 0;
-    if (p.schedule != 0 && p.schedule != HZ_SCHED_STEPS && p.schedule != HZ_SCHED_DATAFLOW) return 0;
+    if (p.schedule != 0 && p.schedule != HZ_SCHED_STEPS && p.schedule != HZ_SCHED_DATAFLOW &&
+        p.schedule != HZ_SCHED_PERSISTENT)
+        return 0;
     if (p.ordering != HZ_ORD_MM && p.ordering != HZ_ORD_RR) return 0;
     if (p.inner_ordering != HZ_ORD_MM && p.inner_ordering != HZ_ORD_RR &&
         p.inner_ordering != HZ_ORD_RING)
@@ -651,6 +653,7 @@ static int solve_entry(int kind, const hz_params *p, int64_t m_f, int64_t m_g, i
     hz_params prm;
     if (p) prm = *p; else hz_default_params(&prm);
     if (!params_ok(prm) || !w_ok_for(prm, is_complex)) return -1;
+    if (prm.schedule == HZ_SCHED_PERSISTENT) return -1;   // the batched form's schedule
     if (kind == KIND_MIXED && (prm.max_fp32_sweeps < 0 || !(prm.mixed_switch >= 0.0))) return -1;
     if (prm.qr_shorten && n > 1 && !shorten_cpt(n)) return -1;
     if (prm.pivot_qr && kind == KIND_MIXED) return -1;
@@ -1254,9 +1257,11 @@ namespace hz {
 // arrays follow, each 256-byte aligned.
 struct BLayout {
     int w = 0, W2 = 0, isteps = 0, inner_lp = 0, kmax = 0;
-    int64_t max_nw = 0;
+    int persistent = 0;                  // one launch for all sweeps (kb_persist)
+    int64_t max_nw = 0, nptask = 0;
     size_t o_probs = 0, o_tasks = 0, o_itab = 0, o_active = 0, o_pinfo = 0, o_pstatus = 0,
            o_nactive = 0, o_pcnt = 0, o_ptot = 0, meta = 0, total = 0;
+    size_t o_ptask = 0, o_qhead = 0, o_pdone = 0, o_pfin = 0, o_psw = 0;
     std::vector<Plan> plan;              // per pair (n >= 2)
     std::vector<size_t> pair_off;        // per pair: start of its arrays
     std::vector<int> order;              // pairs by decreasing work
@@ -1290,6 +1295,13 @@ static bool plan_batched(const hz_params &prm, int batch, const int64_t *mf, con
     L.isteps = (prm.inner_ordering == HZ_ORD_MM) ? L.W2 : L.W2 - 1;
     L.inner_lp = prm.inner_lanes ? prm.inner_lanes : (L.W2 == 64 ? 16 : 8);
     if (L.W2 == 16) L.inner_lp = 8;
+    // The persistent schedule (default where it applies) runs a task's
+    // inner solve with the whole workgroup of at least four waves: 2w = 64
+    // with 8 or 16 lanes per column pair, 2w = 32 with 16.
+    const bool can_persist = L.W2 == 64 || L.W2 == 32;
+    if (prm.schedule == HZ_SCHED_PERSISTENT && !can_persist) return false;
+    L.persistent = can_persist && (prm.schedule == 0 || prm.schedule == HZ_SCHED_PERSISTENT);
+    if (L.persistent) L.inner_lp = (L.W2 == 32) ? 16 : (L.inner_lp == 16 ? 16 : 8);
     L.plan.assign(batch, Plan{});
     std::vector<int64_t> work(batch, 0);
     for (int i = 0; i < batch; ++i) {
@@ -1333,6 +1345,24 @@ static bool plan_batched(const hz_params &prm, int batch, const int64_t *mf, con
     L.o_nactive = o; o = align256(o + sizeof(int) * 4);
     L.o_pcnt = o; o = align256(o + sizeof(unsigned long long) * 4 * (size_t)batch);
     L.o_ptot = o; o = align256(o + sizeof(unsigned long long) * 4 * (size_t)batch);
+    if (L.persistent) {
+        // tasks of every round of every pair up to the sweep cap; the
+        // packing holds rounds below 2^19 and block pairs below 4096
+        int64_t nt = 0;
+        for (int i = 0; i < batch; ++i) {
+            if (n[i] < 2) continue;
+            const Plan &P = L.plan[i];
+            if (P.npairs > 4095 || (int64_t)prm.max_sweeps * P.steps >= (1 << 19)) return false;
+            nt += (int64_t)prm.max_sweeps * P.steps * P.npairs;
+        }
+        if (nt > (1 << 26)) return false;
+        L.nptask = nt;
+        L.o_ptask = o; o = align256(o + sizeof(int2) * (size_t)(nt > 0 ? nt : 1));
+        L.o_qhead = o; o = align256(o + sizeof(int) * 4);
+        L.o_pdone = o; o = align256(o + sizeof(unsigned) * (size_t)batch);
+        L.o_pfin = o; o = align256(o + sizeof(int) * (size_t)batch);
+        L.o_psw = o; o = align256(o + sizeof(unsigned long long) * 3 * (size_t)batch * prm.max_sweeps);
+    }
     L.meta = o;
     L.pair_off.assign(batch, 0);
     for (int i = 0; i < batch; ++i) {
@@ -1412,6 +1442,12 @@ static int run_batched(const hz_params &prm, int batch, const int64_t *mf, const
         B.nactive = (int *)(base + L.o_nactive);
         B.pcnt = (unsigned long long *)(base + L.o_pcnt);
         B.ptot = (unsigned long long *)(base + L.o_ptot);
+        B.ptask = (int2 *)(base + L.o_ptask);
+        B.nptask = (int)L.nptask;
+        B.qhead = (int *)(base + L.o_qhead);
+        B.pdone = (unsigned *)(base + L.o_pdone);
+        B.pfin = (int *)(base + L.o_pfin);
+        B.psw = (unsigned long long *)(base + L.o_psw);
         B.total = L.total;
 
         // host staging of the metadata region
@@ -1481,6 +1517,20 @@ static int run_batched(const hz_params &prm, int batch, const int64_t *mf, const
                 for (int l = 0; l < L.plan[i].npairs; ++l) ht[c++] = make_int2(i, l);
             }
         }
+        if (L.persistent) {
+            // rounds r = sweep * steps + step of every pair, round by round,
+            // largest pairs first within a round
+            int2 *pt = (int2 *)(hm + L.o_ptask);
+            int64_t c = 0, rmax = 0;
+            for (int i = 0; i < batch; ++i)
+                if (n[i] >= 2) rmax = std::max<int64_t>(rmax, (int64_t)prm.max_sweeps * L.plan[i].steps);
+            for (int64_t r = 0; r < rmax; ++r)
+                for (int i : L.order) {
+                    if (n[i] < 2 || r >= (int64_t)prm.max_sweeps * L.plan[i].steps) continue;
+                    for (int l = 0; l < L.plan[i].npairs; ++l)
+                        pt[c++] = make_int2(i, (int)((r << 12) | l));
+                }
+        }
         HZ_CHECK(hipMemcpyAsync(base, hm, L.meta, hipMemcpyHostToDevice, st));
         for (int i = 0; i < batch && finish; ++i) {
             if (n[i] != 1) continue;
@@ -1491,7 +1541,29 @@ static int run_batched(const hz_params &prm, int batch, const int64_t *mf, const
         HZ_CHECK(hipGetLastError());
 
         const bool use_graph = !g_prof.on;
-        if (use_graph && L.kmax > 0) {
+        if (L.persistent && L.kmax > 0) {
+            // one launch for all sweeps (captured and replayed once, like a
+            // sweep of the per-step schedule), then the counter totals
+            if (use_graph) {
+                hipStream_t cs = capture_stream();
+                if (!cs) { rc = HZ_EHIP; goto done; }
+                HZ_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+                const hipError_t le = launchb_persistent(B, prm, cs);
+                hipGraph_t g = nullptr;
+                const hipError_t ce = hipStreamEndCapture(cs, &g);
+                graph = g;
+                HZ_CHECK(le);
+                HZ_CHECK(ce);
+                HZ_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+                HZ_CHECK(hipGraphLaunch(exec, st));
+            } else {
+                prof_mark(K_OTHER, true, st);
+                HZ_CHECK(launchb_persistent(B, prm, st));
+                prof_mark(K_OTHER, false, st);
+            }
+            sweeps = prm.max_sweeps;
+        }
+        if (use_graph && L.kmax > 0 && !L.persistent) {
             hipStream_t cs = capture_stream();
             if (!cs) { rc = HZ_EHIP; goto done; }
             HZ_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
@@ -1499,7 +1571,7 @@ static int run_batched(const hz_params &prm, int batch, const int64_t *mf, const
             HZ_CHECK(hipStreamEndCapture(cs, &graph));
             HZ_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
         }
-        for (int sw = 0; sw < prm.max_sweeps && L.kmax > 0; ++sw) {
+        for (int sw = 0; sw < prm.max_sweeps && L.kmax > 0 && !L.persistent; ++sw) {
             if (use_graph) HZ_CHECK(hipGraphLaunch(exec, st));
             else launchb_sweep(B, prm, st);
             HZ_CHECK(hipGetLastError());
@@ -1523,7 +1595,8 @@ static int run_batched(const hz_params &prm, int batch, const int64_t *mf, const
             const int fl = hstat[(size_t)i * ST_NSLOTS + ST_FLAGS];
             const bool conv = (n[i] == 1) || hinfo[(size_t)i * 4 + 1];
             int prc = HZ_OK, sev = 0;
-            if (fl & FLAG_NONFINITE) { prc = HZ_ENONFINITE; sev = 3; }
+            if (fl & FLAG_STALL) { prc = HZ_EHIP; sev = 4; }
+            else if (fl & FLAG_NONFINITE) { prc = HZ_ENONFINITE; sev = 3; }
             else if (fl & FLAG_CHOL) { prc = HZ_ECHOL; sev = 2; }
             else if (!conv) { prc = HZ_ENOCONV; sev = 1; }
             worst = sev > worst ? sev : worst;
@@ -1540,7 +1613,8 @@ static int run_batched(const hz_params &prm, int batch, const int64_t *mf, const
                 f.status = prc;
             }
         }
-        rc = worst == 3 ? HZ_ENONFINITE : worst == 2 ? HZ_ECHOL : worst == 1 ? HZ_ENOCONV : HZ_OK;
+        rc = worst == 4 ? HZ_EHIP : worst == 3 ? HZ_ENONFINITE : worst == 2 ? HZ_ECHOL
+           : worst == 1 ? HZ_ENOCONV : HZ_OK;
     }
 done:
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -1581,7 +1655,8 @@ int hz_dgsvd_batched(const hz_params *p, int batch, const int64_t *m_f, const in
 {
     hz_params prm;
     if (p) prm = *p; else hz_default_params(&prm);
-    if (!params_ok(prm) || prm.qr_shorten || prm.pivot_qr) return -1;
+    if (!params_ok(prm) || prm.qr_shorten || prm.pivot_qr || prm.schedule == HZ_SCHED_DATAFLOW)
+        return -1;
     const int a = check_batched(batch, m_f, m_g, n, F, ldf, G, ldg, Z, ldz, sigma, sigma_f,
                                 sigma_g);
     if (a) return a;
@@ -1864,9 +1939,10 @@ int hz_dgsvd_batched_tune(const hz_params *p, int batch, const int64_t *m_f, con
     }
     if (!best) return -11;
     hipStream_t st = (hipStream_t)stream;
-    const uint64_t key = tune_key(tune_iord ? (tune_ord ? "dgsvd_batched_ord_iord3"
-                                                        : "dgsvd_batched_iord3")
-                                            : (tune_ord ? "dgsvd_batched_ord" : "dgsvd_batched"),
+    const uint64_t key = tune_key(tune_iord ? (tune_ord ? "dgsvd_batched_ord_iord3_persist"
+                                                        : "dgsvd_batched_iord3_persist")
+                                            : (tune_ord ? "dgsvd_batched_ord_persist"
+                                                        : "dgsvd_batched_persist"),
                                   base, batch, m_f, m_g, n);
     hz_params cur = base;
     double ms = 0.0;

@@ -213,6 +213,184 @@ __global__ __launch_bounds__(256) void kb_scatter(const BProb *__restrict__ prob
     }
 }
 
+// ------------------------------------------------------------ persistent
+// One launch for all sweeps of all pairs.  A task is one block pair of one
+// step of one pair: its Gram blocks, inner solve and block update, with the
+// device bodies and the operation order of kb_gram, kb_inner and kb_update
+// (so the results are bitwise those of the per-step schedule).  Workgroups
+// claim tasks from a list ordered by the pair's round r = sweep * steps +
+// step (largest pairs first within a round) with one atomic counter; a
+// task of round r of pair i first waits until all tasks of the pair's
+// earlier rounds are done (pdone[i] = r * npairs).  Only tasks that have
+// been claimed are waited on, and a workgroup claims only while it runs, so
+// every wait ends whether or not the whole grid is resident.  At the first
+// step of a sweep the pair's previous sweep is complete: without a big
+// transformation in it (Section 2.5), or with a failure flag, the pair is
+// finished and its remaining tasks are skipped.  Data written by a task are
+// published with a device-scope release before the counter is raised and
+// read after a device-scope acquire.  A wait that exceeds spin_limit polls
+// sets FLAG_STALL on the pair and skips, so the kernel always ends.
+template <int W2, int LP, bool RING>
+__global__ __launch_bounds__((W2 / 2) * LP) void kb_persist(
+    const BProb *__restrict__ probs, const int2 *__restrict__ tasks, int ntasks,
+    int *__restrict__ qhead, unsigned *__restrict__ pdone, int *__restrict__ pfin,
+    unsigned long long *__restrict__ psw, int max_sweeps, const int16_t *__restrict__ itab,
+    int isteps, int inner_max, int sort, int variant, int *__restrict__ pstatus,
+    unsigned spin_limit)
+{
+    constexpr int NT = (W2 / 2) * LP;
+    static_assert(NT >= 256 && NT % 64 == 0, "a persistent workgroup has at least four waves");
+    constexpr int L1 = gram_lds<W2>(), L2 = inner_lds<W2>(), L3 = update_lds<W2>();
+    constexpr int LDSN = (L1 > L2 ? (L1 > L3 ? L1 : L3) : (L2 > L3 ? L2 : L3));
+    __shared__ __attribute__((aligned(16))) double lds[LDSN];
+    __shared__ unsigned long long c[4];
+    __shared__ int s_task, s_skip;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // Claiming, waiting and deciding run on all lanes of wave 0 with every
+    // value read made wave-uniform (readfirstlane), so that every branch of
+    // the task loop is uniform: a loop exit taken by one lane alone would
+    // let the compiler split the wave between loop levels.
+    const bool claimer = __builtin_amdgcn_readfirstlane(tid >> 6) == 0;
+    for (;;) {
+        if (claimer) {
+            int t = 0;
+            if (lane == 0) t = atomicAdd(qhead, 1);
+            t = __builtin_amdgcn_readfirstlane(t);
+            int skip = 0;
+            if (t < ntasks) {
+                const int2 tk = tasks[t];
+                const int i = __builtin_amdgcn_readfirstlane(tk.x);
+                const int r = __builtin_amdgcn_readfirstlane(tk.y) >> 12;
+                const BProb &P = probs[i];
+                const int steps = __builtin_amdgcn_readfirstlane(P.steps);
+                const unsigned need = (unsigned)r * (unsigned)__builtin_amdgcn_readfirstlane(P.npairs);
+                const int sw = r / steps, k = r % steps;
+                int *const st = pstatus + (size_t)i * ST_NSLOTS;
+                unsigned spins = 0;
+                for (;;) {
+                    const int fin = __builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(pfin + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    if (fin) {
+                        skip = 1;
+                        break;
+                    }
+                    const unsigned d = __builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(pdone + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    if (d >= need) break;
+                    if (++spins > spin_limit) {
+                        if (lane == 0) {
+                            atomicOr(st + ST_FLAGS, FLAG_STALL);
+                            __hip_atomic_store(pfin + i, 1, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                        skip = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                if (!skip && k == 0 && sw > 0) {
+                    // the pair's previous sweep is complete (Section 2.5 stopping rule)
+                    const int big = __builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(psw + ((size_t)i * max_sweeps + sw - 1) * 3 + 1,
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0ull
+                            ? 1 : 0);
+                    const int fl = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                        st + ST_FLAGS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    if (fl != 0 || big == 0) {
+                        if (lane == 0)
+                            __hip_atomic_store(pfin + i, 1, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        skip = 1;
+                    }
+                }
+            }
+            if (lane == 0) {
+                s_task = t;
+                s_skip = skip;
+            }
+        }
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(s_task);
+        if (t >= ntasks) break;
+        if (__builtin_amdgcn_readfirstlane(s_skip)) continue;
+        const int2 tk = tasks[t];
+        const int i = __builtin_amdgcn_readfirstlane(tk.x);
+        const int r = __builtin_amdgcn_readfirstlane(tk.y) >> 12;
+        const int l = __builtin_amdgcn_readfirstlane(tk.y) & 4095;
+        const BProb &P = probs[i];
+        const int steps = __builtin_amdgcn_readfirstlane(P.steps);
+        const int sw = r / steps, k = r % steps;
+        int *const st = pstatus + (size_t)i * ST_NSLOTS;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int *pr = P.otab + ((size_t)k * P.npairs + l) * 2;
+        double *const gm = P.gram + (size_t)l * 2 * (W2 * W2);
+        gram_block<W2, 4>(P.Fw, P.mfw, pr[0], pr[1], 0, P.mfw / 64, gm, lds);
+        __syncthreads();
+        gram_block<W2, 4>(P.Gw, P.mgw, pr[0], pr[1], 0, P.mgw / 64, gm + W2 * W2, lds);
+        __syncthreads();
+        double *const zt = P.Zt + (size_t)l * (W2 * W2);
+        inner_solve<W2, LP, RING>(gm, gm + W2 * W2, 1, 0, itab, isteps, inner_max, P.tol, sort,
+                                  variant, zt, c, st, k * 65536 + l, nullptr, lds);
+        __syncthreads();
+        const bool ident = __builtin_amdgcn_readfirstlane(c[3] != 0 ? 1 : 0) != 0;
+        if (tid == 0) {
+            unsigned long long *q = psw + ((size_t)i * max_sweeps + sw) * 3;
+            atomicAdd(q + 0, c[0]);
+            atomicAdd(q + 1, c[1]);
+            atomicAdd(q + 2, c[2]);
+        }
+        if (!ident) {
+            // Z_tilde = I leaves the block columns as they are (Section 2.5)
+            update_rows<W2, NT / 64>(P.Fw, P.mfw, pr[0], pr[1], 0, P.mfw, zt, lds);
+            __syncthreads();
+            update_rows<W2, NT / 64>(P.Gw, P.mgw, pr[0], pr[1], 0, P.mgw, zt, lds);
+            __syncthreads();
+            update_rows<W2, NT / 64>(P.Zw, P.nzw, pr[0], pr[1], 0, P.nzw, zt, lds);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            atomicAdd(pdone + i, 1u);
+        }
+    }
+}
+
+// After the persistent launch: per pair the sweeps run (a sweep follows
+// one with a big transformation and no failure flag, up to max_sweeps),
+// whether the last one had no big transformation, and the counter totals
+// over them -- what kb_converge records sweep by sweep.
+__global__ __launch_bounds__(256) void kb_persist_totals(const BProb *__restrict__ probs,
+                                                         int batch, int max_sweeps,
+                                                         const unsigned long long *__restrict__ psw,
+                                                         const int *__restrict__ pstatus,
+                                                         int *__restrict__ pinfo,
+                                                         unsigned long long *__restrict__ ptot)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= batch || probs[i].n < 2) return;
+    const int fl = pstatus[(size_t)i * ST_NSLOTS + ST_FLAGS];
+    unsigned long long a = 0, b = 0, q = 0;
+    int sw = 0, conv = 0;
+    while (sw < max_sweeps) {
+        const unsigned long long *c = psw + ((size_t)i * max_sweeps + sw) * 3;
+        a += c[0];
+        b += c[1];
+        q += c[2];
+        ++sw;
+        if (fl) break;
+        if (c[1] == 0) {
+            conv = 1;
+            break;
+        }
+    }
+    pinfo[(size_t)i * 4] = sw;
+    pinfo[(size_t)i * 4 + 1] = conv;
+    ptot[(size_t)i * 4] = a;
+    ptot[(size_t)i * 4 + 1] = b;
+    ptot[(size_t)i * 4 + 2] = q;
+}
+
 // ------------------------------------------------------------------ launchers
 
 void launchb_prescale(const BPlan &B, hipStream_t s)
@@ -269,6 +447,41 @@ void launchb_sweep(const BPlan &B, const hz_params &prm, hipStream_t s)
     }
     hipLaunchKernelGGL(kb_converge, dim3(1), dim3(256), 0, s, B.batch, prm.max_sweeps, B.active,
                        B.pcnt, B.ptot, B.pinfo, B.pstatus, B.nactive);
+}
+
+template <int W2, int LP, bool RING>
+static hipError_t persist_launch(const BPlan &B, const hz_params &prm, hipStream_t s)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kb_persist<W2, LP, RING>,
+                                                         (W2 / 2) * LP, 0);
+    if (e != hipSuccess) return e;
+    const int grid = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+    hipLaunchKernelGGL((kb_persist<W2, LP, RING>), dim3(grid), dim3((W2 / 2) * LP), 0, s,
+                       B.probs, B.ptask, B.nptask, B.qhead, B.pdone, B.pfin, B.psw,
+                       prm.max_sweeps, B.itab, B.isteps, prm.inner_max_sweeps, prm.sort,
+                       prm.variant, B.pstatus, 1u << 22);
+    return hipGetLastError();
+}
+
+// The persistent schedule: all sweeps in one launch, then the counter totals.
+hipError_t launchb_persistent(const BPlan &B, const hz_params &prm, hipStream_t s)
+{
+    const bool ring = (prm.inner_ordering == HZ_ORD_RING);
+    hipError_t e = hipErrorInvalidValue;
+    if (B.W2 == 64 && B.inner_lp == 16)
+        e = ring ? persist_launch<64, 16, true>(B, prm, s) : persist_launch<64, 16, false>(B, prm, s);
+    else if (B.W2 == 64 && B.inner_lp == 8)
+        e = ring ? persist_launch<64, 8, true>(B, prm, s) : persist_launch<64, 8, false>(B, prm, s);
+    else if (B.W2 == 32 && B.inner_lp == 16)
+        e = ring ? persist_launch<32, 16, true>(B, prm, s) : persist_launch<32, 16, false>(B, prm, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kb_persist_totals, dim3((B.batch + 255) / 256), dim3(256), 0, s, B.probs,
+                       B.batch, prm.max_sweeps, B.psw, B.pstatus, B.pinfo, B.ptot);
+    return hipGetLastError();
 }
 
 void launchb_finish(const BPlan &B, hipStream_t s)

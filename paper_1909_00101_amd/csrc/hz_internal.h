@@ -84,6 +84,13 @@ struct BPlan {
     int16_t *itab;
     int *active, *pinfo, *pstatus, *nactive;
     unsigned long long *pcnt, *ptot;
+    // persistent schedule: task list (pair, round << 12 | block pair), queue
+    // head, per pair tasks done and finished flag, per (pair, sweep) counters
+    int2 *ptask;
+    int nptask;
+    int *qhead, *pfin;
+    unsigned *pdone;
+    unsigned long long *psw;
     size_t total;
 };
 
@@ -172,6 +179,7 @@ hipError_t df_occupancy(int *per_cu);   // resident sweep workgroups per compute
 void launchb_prescale(const BPlan &B, hipStream_t s);
 void launchb_sweep(const BPlan &B, const hz_params &prm, hipStream_t s);
 void launchb_finish(const BPlan &B, hipStream_t s);
+hipError_t launchb_persistent(const BPlan &B, const hz_params &prm, hipStream_t s);
 
 // launchers (mixed precision), hz_mixed.hip
 void launch_prescale_mixed(const Plan &P, const Ptrs &W, const double *F, int64_t ldf,

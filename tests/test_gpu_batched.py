@@ -86,13 +86,17 @@ def test_small_batch_vs_oracle(w, lanes, iord):
     print(f"w={w}: {len(pairs)} pairs, worst err vs oracle {worst:.2e}")
 
 
-@pytest.mark.parametrize("w,iord", [(8, 2), (16, 2), (32, 2), (16, 3), (32, 3)])
-def test_batched_equals_single_pair_bitwise(w, iord):
+@pytest.mark.parametrize("w,iord,lanes,sched", [(8, 2, 8, 1), (16, 2, 16, 0), (32, 2, 16, 0),
+                                                (16, 3, 16, 0), (32, 3, 8, 0), (16, 3, 8, 1)])
+def test_batched_equals_single_pair_bitwise(w, iord, lanes, sched):
+    """Every pair of a batch, per-step (sched 1) or persistent (default
+    where w is 16 or 32), bitwise equal to the single-pair solver with the
+    same block width, ordering and lanes (one Gram split)."""
     pairs = gi.make_batch(count=9, seed=21, n_lo=2, n_hi=100)
-    st, res = _run_batch(pairs, w=w, inner_ordering=iord)
+    st, res = _run_batch(pairs, w=w, inner_ordering=iord, inner_lanes=lanes, schedule=sched)
     assert st == 0
     for i, ((F, G, _), r) in enumerate(zip(pairs, res)):
-        s = _run_single(F, G, w=w, gram_splits=1, inner_ordering=iord)
+        s = _run_single(F, G, w=w, gram_splits=1, inner_ordering=iord, inner_lanes=lanes)
         assert r["sweeps"] == s["sweeps"], (i, r["sweeps"], s["sweeps"])
         assert r["rot_total"] == s["rot_total"] and r["rot_big"] == s["rot_big"], i
         for k in ("sigma", "sigma_f", "sigma_g", "U", "V", "Z"):
@@ -115,12 +119,52 @@ def test_failures_stay_with_their_pair():
         _check(F, G, res[i])
 
 
-def test_sweep_cap_per_pair():
+def test_persistent_failures_stay_with_their_pair():
+    """The persistent schedule: a non-finite pair and a rank-deficient pair
+    stop with their own status while the other pairs of the launch converge
+    to oracle parity."""
+    hz = _hz()
+    pairs = [list(p) for p in gi.make_batch(count=6, seed=32, n_lo=40, n_hi=120)]
+    pairs[1][0][3, 1] = np.nan
+    pairs[4][1][:, 5] = pairs[4][1][:, 4]
+    st, res = _run_batch(pairs, w=16, schedule=3)
+    assert st == hz.HZ_ENONFINITE
+    assert res[1]["status"] == hz.HZ_ENONFINITE
+    assert res[4]["status"] == hz.HZ_ECHOL
+    for i in (0, 2, 3, 5):
+        F, G, _ = pairs[i]
+        assert res[i]["status"] == 0 and res[i]["converged"]
+        assert max_rel(res[i]["sigma"], _oracle(F, G)["sigma"]) < SIG_TOL
+        _check(F, G, res[i])
+
+
+@pytest.mark.parametrize("w,sched", [(8, 1), (16, 3), (32, 3)])
+def test_sweep_cap_per_pair(w, sched):
     hz = _hz()
     pairs = gi.make_batch(count=4, seed=41, n_lo=30, n_hi=60)
-    st, res = _run_batch(pairs, w=8, max_sweeps=1)
+    st, res = _run_batch(pairs, w=w, max_sweeps=1, schedule=sched)
     assert st == hz.HZ_ENOCONV
     assert all(r["status"] == hz.HZ_ENOCONV and r["sweeps"] == 1 for r in res)
+    st, res = _run_batch(pairs, w=w, max_sweeps=3, schedule=sched)
+    assert all(r["sweeps"] == 3 or (r["status"] == 0 and r["sweeps"] < 3) for r in res)
+
+
+@pytest.mark.parametrize("w,lanes,iord", [(16, 16, 2), (16, 16, 3), (32, 8, 3), (32, 16, 1)])
+def test_persistent_equals_per_step_bitwise(w, lanes, iord):
+    """One persistent launch for all sweeps gives bitwise the results, the
+    sweep counts and the counters of the per-step schedule with its host
+    check after every sweep."""
+    pairs = gi.make_batch(count=24, seed=23, n_lo=2, n_hi=200)
+    kw = dict(w=w, inner_lanes=lanes, inner_ordering=iord)
+    st1, a = _run_batch(pairs, schedule=1, **kw)
+    st3, b = _run_batch(pairs, schedule=3, **kw)
+    assert st1 == st3 == 0
+    for i, (ra, rb) in enumerate(zip(a, b)):
+        assert ra["sweeps"] == rb["sweeps"], (i, ra["sweeps"], rb["sweeps"])
+        assert ra["rot_total"] == rb["rot_total"] and ra["rot_big"] == rb["rot_big"], i
+        assert ra["inner_sweeps"] == rb["inner_sweeps"], i
+        for k in ("sigma", "sigma_f", "sigma_g", "U", "V", "Z"):
+            assert np.array_equal(ra[k], rb[k]), (i, k)
 
 
 def test_bitwise_reruns():
