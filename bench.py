@@ -233,7 +233,8 @@ def _form_entry(name, r, dt, spec_mnw, err_ref, s_true, esz=8, cmul=1, timing=No
 
 def mixed_vs_plain(reps=2):
     """hz_dgsvd_mixed against hz_dgsvd on the seeded 8192 x 2048 pair (w = 32,
-    one inner sweep, tol = n eps, the same launch parameters for both, the
+    ring ordering inside the blocks with 8 lanes per column pair, one inner
+    sweep, tol = n eps, the same launch parameters for both, the
     switch to FP64 at the default off-diagonal measure 1e-5), and both again
     on the QR-shortened pair (qr_shorten = 1); all restore the pair from
     device copies inside the timed call (two 128 MiB copies).  Errors are
@@ -248,7 +249,7 @@ def mixed_vs_plain(reps=2):
     F0, G0 = torch.from_numpy(F).to(dev), torch.from_numpy(G).to(dev)
     Fw, Gw = F0.clone(), G0.clone()
     kw = dict(w=32, inner_max_sweeps=1, tol=spec.n * np.finfo(np.float64).eps, gram_splits=8,
-              update_rows=64)
+              update_rows=64, inner_ordering=hz.HZ_ORD_RING, inner_lanes=8)
     work = torch.empty(4 << 30, dtype=torch.uint8, device=dev)
     res = {}
     mnw = (spec.m_f, spec.m_g, spec.n, 32)
@@ -273,6 +274,7 @@ def mixed_vs_plain(reps=2):
     del F0, G0, Fw, Gw, work
     torch.cuda.empty_cache()
     return dict(workload=f"seeded {spec.m_f}x{spec.n} real pair, kappa(X)=1e2, w=32, "
+                         f"ring ordering inside the blocks with 8 lanes per column pair, "
                          f"one inner sweep, tol=n*eps, 8 Gram splits, 64 update rows per wave",
                 speedup=round(res["plain"]["ms"] / res["mixed"]["ms"], 3),
                 speedup_shortened=round(res["plain"]["ms"] / res["plain_shortened"]["ms"], 3),
@@ -282,7 +284,8 @@ def mixed_vs_plain(reps=2):
 
 def complex_shortened_vs_plain(reps=2):
     """hz_zgsvd on the seeded complex 3072x1024 / 2048x1024 pair (kappa(X) =
-    50, w = 16, modified-modulus outer and inner orderings, one inner sweep,
+    50, w = 16, modified-modulus outer ordering, ring ordering inside the
+    blocks, one inner sweep,
     tol = n eps) plain and QR-shortened; both restore the pair from device
     copies inside the timed call.  Complex work counts a complex
     multiply-add as 8 real flops and 16 bytes per element."""
@@ -295,7 +298,7 @@ def complex_shortened_vs_plain(reps=2):
     dev = torch.device("cuda:0")
     F0, G0 = torch.from_numpy(F).to(dev), torch.from_numpy(G).to(dev)
     Fw, Gw = F0.clone(), G0.clone()
-    kw = dict(w=16, ordering=hz.HZ_ORD_MM, inner_ordering=hz.HZ_ORD_MM, inner_max_sweeps=1,
+    kw = dict(w=16, ordering=hz.HZ_ORD_MM, inner_ordering=hz.HZ_ORD_RING, inner_max_sweeps=1,
               tol=spec.n * np.finfo(np.float64).eps)
     work = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
     res = {}
@@ -315,7 +318,8 @@ def complex_shortened_vs_plain(reps=2):
     del F0, G0, Fw, Gw, work
     torch.cuda.empty_cache()
     return dict(workload=f"seeded complex {spec.m_f}x{spec.n} / {spec.m_g}x{spec.n} pair, "
-                         "kappa(X)=50, w=16, MM outer and inner orderings, one inner sweep, "
+                         "kappa(X)=50, w=16, MM outer ordering, ring inside the blocks, "
+                         "one inner sweep, "
                          "tol=n*eps",
                 speedup=round(res["plain"]["ms"] / res["shortened"]["ms"], 3), **res)
 

@@ -81,7 +81,7 @@ extern "C" {
  * HZ_ORD_RR: round robin, cyclic with s = N - 1 steps. */
 #define HZ_ORD_MM 1
 #define HZ_ORD_RR 2
-/* HZ_ORD_RING (inner_ordering of the real solvers only): a cyclic ordering
+/* HZ_ORD_RING (inner_ordering only): a cyclic ordering
  * of the 2w columns of a pivot block built for the inner solver's data
  * movement, level by level.  The columns form blocks of size 2h (h = w,
  * w/2, ..., 1); in a block, column u of the first half meets every column
@@ -110,7 +110,7 @@ typedef struct hz_params {
                              simpler procedure (a_ij, b_ij ordinary) */
     int ordering;         /* outer block ordering, HZ_ORD_MM (default) or HZ_ORD_RR */
     int inner_ordering;   /* pointwise ordering inside a block pair: HZ_ORD_RR (default),
-                             HZ_ORD_MM or HZ_ORD_RING (real solvers, per-step schedule) */
+                             HZ_ORD_MM or HZ_ORD_RING (not with the dataflow schedule) */
     int w;                /* block-column width: 0 = default, else 8, 16 or 32 */
     int inner_max_sweeps; /* inner sweeps per block step: 30 = FB (default), 1 = BO */
     int max_sweeps;       /* outer sweep cap (default 30, Algorithm 1) */

@@ -101,7 +101,6 @@ static int default_w(int64_t n, int is_complex)
 // complex 32x32 tiles in LDS).
 static int w_ok_for(const hz_params &p, int is_complex)
 {
-    if (is_complex && p.inner_ordering == HZ_ORD_RING) return 0;   // real solvers only
     return !is_complex || p.w == 0 || p.w == 8 || p.w == 16;
 }
 

@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void k_gram_sum_z(const d2 *__restrict__ part,
 // pointwise method (Section 2.1.1), Theta rescale (Section 2.4).  Layout and
 // phases as the real k_inner; columns of F_hat, G_hat, Z_hat are
 // interleaved complex in LDS.
-template <int W2, int LP>
+template <int W2, int LP, bool RING>
 __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
     const d2 *__restrict__ gram, int factors, int npairs, int step,
     const int16_t *__restrict__ itab, int isteps, int inner_max, double tol, int sort, int variant,
@@ -303,18 +303,13 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
     for (int sw = 0; sw < inner_max; ++sw) {
         unsigned sw_all = 0, sw_big = 0;
         ++nsw;
-        for (int st = 0; st < isteps; ++st) {
-            const int ci = stab[(st * W + grp) * 2], cj = stab[(st * W + grp) * 2 + 1];
-            d2 fi[RPL], fj[RPL], gi[RPL], gj[RPL], zi[RPL], zj[RPL];
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) {
-                fi[r] = sF[ci * LDI + r0 + r];
-                fj[r] = sF[cj * LDI + r0 + r];
-                gi[r] = sG[ci * LDI + r0 + r];
-                gj[r] = sG[cj * LDI + r0 + r];
-                zi[r] = sZ[ci * LDI + r0 + r];
-                zj[r] = sZ[cj * LDI + r0 + r];
-            }
+        // One pointwise step on column pair (i, j), i < j, held in registers:
+        // the complex pivot entries, the orthogonality test, the 2x2
+        // transformation of Section 2.1.1, criterion C1 (C2), the sorting
+        // swap, and [y_i y_j] <- [y_i y_j] Z' applied to the arrays.  Returns
+        // whether the columns changed.
+        auto pair_step = [&](d2 (&fi)[RPL], d2 (&fj)[RPL], d2 (&gi)[RPL], d2 (&gj)[RPL],
+                             d2 (&zi)[RPL], d2 (&zj)[RPL]) -> bool {
             double aii = 0.0, ajj = 0.0, ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
             if (variant & 1) {
                 // variants 1 and 5: squared norms by the enhanced procedure
@@ -369,33 +364,89 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
                     swap = a11 < a22;
                 }
             }
-            if (!orth || swap) {
-                my_chg = 1;
-                // [y_i y_j] <- [y_i y_j] Z (z11, z22 real), then the sorting swap
-                auto rot = [&](const d2 yi, const d2 yj, d2 &oi, d2 &oj) {
-                    d2 a, b;
-                    a[0] = fma(yi[0], z11, fma(yj[0], z21r, -yj[1] * z21i));
-                    a[1] = fma(yi[1], z11, fma(yj[0], z21i, yj[1] * z21r));
-                    b[0] = fma(yj[0], z22, fma(yi[0], z12r, -yi[1] * z12i));
-                    b[1] = fma(yj[1], z22, fma(yi[0], z12i, yi[1] * z12r));
-                    oi = swap ? b : a;
-                    oj = swap ? a : b;
-                };
+            if (!(!orth || swap)) return false;
+            my_chg = 1;
+            // [y_i y_j] <- [y_i y_j] Z (z11, z22 real), then the sorting swap
+            auto rot = [&](d2 &yi, d2 &yj) {
+                d2 a, b;
+                a[0] = fma(yi[0], z11, fma(yj[0], z21r, -yj[1] * z21i));
+                a[1] = fma(yi[1], z11, fma(yj[0], z21i, yj[1] * z21r));
+                b[0] = fma(yj[0], z22, fma(yi[0], z12r, -yi[1] * z12i));
+                b[1] = fma(yj[1], z22, fma(yi[0], z12i, yi[1] * z12r));
+                yi = swap ? b : a;
+                yj = swap ? a : b;
+            };
 #pragma unroll
-                for (int r = 0; r < RPL; ++r) {
-                    d2 oi, oj;
-                    rot(fi[r], fj[r], oi, oj);
-                    sF[ci * LDI + r0 + r] = oi;
-                    sF[cj * LDI + r0 + r] = oj;
-                    rot(gi[r], gj[r], oi, oj);
-                    sG[ci * LDI + r0 + r] = oi;
-                    sG[cj * LDI + r0 + r] = oj;
-                    rot(zi[r], zj[r], oi, oj);
-                    sZ[ci * LDI + r0 + r] = oi;
-                    sZ[cj * LDI + r0 + r] = oj;
-                }
+            for (int r = 0; r < RPL; ++r) {
+                rot(fi[r], fj[r]);
+                rot(gi[r], gj[r]);
+                rot(zi[r], zj[r]);
             }
-            __syncthreads();
+            return true;
+        };
+        auto load = [&](const d2 *M, int c, d2 (&x)[RPL]) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) x[r] = M[c * LDI + r0 + r];
+        };
+        auto store = [&](d2 *M, int c, const d2 (&x)[RPL]) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) M[c * LDI + r0 + r] = x[r];
+        };
+        if constexpr (RING) {
+            // the ring ordering of the real solver (HZ_ORD_RING): the first
+            // column of a pair stays in registers for a level, the second
+            // half of the block is visited in-wave between phase barriers
+            constexpr int GW = 64 / LP;
+            for (int h = W; h >= 1; h >>= 1) {
+                const int blk = grp / h, u = grp % h;
+                const int ci = blk * 2 * h + u;
+                const int nset = (h >= GW) ? h / GW : 1, ssz = (h >= GW) ? GW : h;
+                const int ow = u / ssz, gw = u % ssz;
+                d2 fi[RPL], gi[RPL], zi[RPL];
+                load(sF, ci, fi);
+                load(sG, ci, gi);
+                load(sZ, ci, zi);
+                for (int p = 0; p < nset; ++p) {
+                    for (int t = 0; t < ssz; ++t) {
+                        const int cj = blk * 2 * h + h + ring_col(ssz, nset, ow, gw, p, t);
+                        d2 fj[RPL], gj[RPL], zj[RPL];
+                        load(sF, cj, fj);
+                        load(sG, cj, gj);
+                        load(sZ, cj, zj);
+                        if (pair_step(fi, fj, gi, gj, zi, zj)) {
+                            store(sF, cj, fj);
+                            store(sG, cj, gj);
+                            store(sZ, cj, zj);
+                        }
+                        if (t + 1 < ssz) wave_fence();
+                    }
+                    __syncthreads();
+                }
+                store(sF, ci, fi);
+                store(sG, ci, gi);
+                store(sZ, ci, zi);
+                __syncthreads();
+            }
+        } else {
+            for (int st = 0; st < isteps; ++st) {
+                const int ci = stab[(st * W + grp) * 2], cj = stab[(st * W + grp) * 2 + 1];
+                d2 fi[RPL], fj[RPL], gi[RPL], gj[RPL], zi[RPL], zj[RPL];
+                load(sF, ci, fi);
+                load(sF, cj, fj);
+                load(sG, ci, gi);
+                load(sG, cj, gj);
+                load(sZ, ci, zi);
+                load(sZ, cj, zj);
+                if (pair_step(fi, fj, gi, gj, zi, zj)) {
+                    store(sF, ci, fi);
+                    store(sF, cj, fj);
+                    store(sG, ci, gi);
+                    store(sG, cj, gj);
+                    store(sZ, ci, zi);
+                    store(sZ, cj, zj);
+                }
+                __syncthreads();
+            }
         }
         my_all += sw_all;
         my_big += sw_big;
@@ -652,22 +703,18 @@ static void step_impl_z(const Plan &P, const Ptrs &W, int step, const hz_params 
     }
     prof_mark(K_GRAM, false, s);
     prof_mark(K_INNER, true, s);
-    if constexpr (W2 == 32) {
-        if (P.inner_lp == 16)
-            hipLaunchKernelGGL((k_inner_z<W2, 16>), dim3(P.npairs), dim3((W2 / 2) * 16), 0, s,
-                               (const d2 *)W.gram, fac, P.npairs, step, W.itab, P.isteps,
-                               prm.inner_max_sweeps, tol, prm.sort, prm.variant, (d2 *)W.Zt, W.cnt,
-                               W.status);
-        else
-            hipLaunchKernelGGL((k_inner_z<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s,
-                               (const d2 *)W.gram, fac, P.npairs, step, W.itab, P.isteps,
-                               prm.inner_max_sweeps, tol, prm.sort, prm.variant, (d2 *)W.Zt, W.cnt,
-                               W.status);
+    const bool ring = (prm.inner_ordering == HZ_ORD_RING);
+    auto go = [&](auto kern, int lp) {
+        hipLaunchKernelGGL(kern, dim3(P.npairs), dim3((W2 / 2) * lp), 0, s, (const d2 *)W.gram,
+                           fac, P.npairs, step, W.itab, P.isteps, prm.inner_max_sweeps, tol,
+                           prm.sort, prm.variant, (d2 *)W.Zt, W.cnt, W.status);
+    };
+    if (W2 == 32 && P.inner_lp == 16) {
+        if (ring) go(k_inner_z<W2, 16, true>, 16);
+        else go(k_inner_z<W2, 16, false>, 16);
     } else {
-        hipLaunchKernelGGL((k_inner_z<W2, 8>), dim3(P.npairs), dim3((W2 / 2) * 8), 0, s,
-                           (const d2 *)W.gram, fac, P.npairs, step, W.itab, P.isteps,
-                           prm.inner_max_sweeps, tol, prm.sort, prm.variant, (d2 *)W.Zt, W.cnt,
-                               W.status);
+        if (ring) go(k_inner_z<W2, 8, true>, 8);
+        else go(k_inner_z<W2, 8, false>, 8);
     }
     prof_mark(K_INNER, false, s);
     const int64_t rpt = 4 * (int64_t)P.upd_rows;

@@ -75,11 +75,12 @@ def test_device_complex_2x2_invariants():
 @pytest.mark.parametrize("shape", [(40, 36, 24, 8), (70, 50, 37, 8), (200, 150, 96, 16),
                                    (300, 256, 160, 16), (64, 64, 2, 8)],
                          ids=lambda s: "x".join(map(str, s)))
-def test_complex_parity(shape):
+@pytest.mark.parametrize("iord", [2, 3], ids=["innerRR", "ring"])
+def test_complex_parity(shape, iord):
     m_f, m_g, n, w = shape
     F, G, s_true = gi.custom_pair(m_f, m_g, n, kappa=50.0, is_complex=True, seed=n + 3)
     o = _oracle(F, G, ordering=1, threads=4)
-    r = _run(F, G, w=w)
+    r = _run(F, G, w=w, inner_ordering=iord)
     err = max_rel(r["sigma"], o["sigma"])
     print(f"{shape}: sweeps={r['sweeps']} status={r['status']} err={err:.2e}")
     assert r["status"] == 0
@@ -102,7 +103,9 @@ def test_complex_n1():
 def test_complex_bo_and_rr():
     F, G, _ = gi.custom_pair(180, 160, 64, kappa=50.0, is_complex=True, seed=12)
     o = _oracle(F, G)
-    for kw in (dict(inner_max_sweeps=1), dict(ordering=2), dict(inner_lanes=16)):
+    for kw in (dict(inner_max_sweeps=1), dict(ordering=2), dict(inner_lanes=16),
+               dict(inner_ordering=3, inner_max_sweeps=1),
+               dict(inner_ordering=3, inner_lanes=16), dict(inner_ordering=3, variant=5)):
         r = _run(F, G, w=16, **kw)
         assert r["status"] == 0
         assert max_rel(r["sigma"], o["sigma"]) < SIG_TOL
@@ -128,16 +131,18 @@ def test_complex_rejects_w32():
         _run(F, G, w=32)
 
 
-def test_config3_full_size_vs_oracle_golden():
-    """The complex 3072x1024 / 2048x1024 workload (w = 16, modified modulus,
-    tol = 1024 eps) against the oracle's sigma for the same seeded pair."""
+@pytest.mark.parametrize("iord", [2, 3], ids=["innerRR", "ring"])
+def test_config3_full_size_vs_oracle_golden(iord):
+    """The complex 3072x1024 / 2048x1024 workload (w = 16, tol = 1024 eps,
+    round-robin or ring ordering inside the blocks) against the oracle's
+    sigma for the same seeded pair."""
     path = os.path.join(os.path.dirname(__file__), "golden", "oracle_config3.json")
     gold = json.load(open(path))
     F, G, s_true = gi.config_pair(3)
     hz = _hz()
     dF = torch.from_numpy(F).cuda()
     dG = torch.from_numpy(G).cuda()
-    r = hz.gsvd(dF, dG, w=16, tol=1024 * EPS, inner_max_sweeps=1)
+    r = hz.gsvd(dF, dG, w=16, tol=1024 * EPS, inner_max_sweeps=1, inner_ordering=iord)
     torch.cuda.synchronize()
     s = r["sigma"].cpu().numpy()
     err = max_rel(s, np.array(gold["sigma"]))

@@ -69,13 +69,22 @@ def test_shortened_parity(shape, w):
 
 def test_shortened_headline_shape():
     """F, G 4096 x 1024 with w = 32, modified modulus, tol = 1024 eps, the
-    launch of the plain path's headline workload: sigma against the known
-    generalized singular values of the generator and the contract."""
+    launch of the plain path's headline workload: sigma against the oracle's
+    sigma for the same seeded pair (tests/golden/oracle_config2.json, written
+    by tests/golden/make_golden.py from the oracle alone), against the known
+    generalized singular values of the generator, and the contract."""
+    import json
+    import os
+    gold = np.array(json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                                 "oracle_config2.json")))["sigma"])
     F, G, s_true = gi.config_pair(2)
     print("shortened 4096x1024 w=32", flush=True)
     r = _run(F, G, w=32, ordering=_hz().HZ_ORD_MM, tol=1024 * EPS)
-    print(f"  sweeps={r['sweeps']} err_vs_truth={max_rel(r['sigma'], s_true):.2e}")
+    err = max_rel(r["sigma"], gold)
+    print(f"  sweeps={r['sweeps']} err_vs_oracle={err:.2e} "
+          f"err_vs_truth={max_rel(r['sigma'], s_true):.2e}")
     assert r["status"] == 0 and r["converged"]
+    assert err < SIG_TOL
     assert max_rel(r["sigma"], s_true) < SIG_TOL
     assert_contract(F, G, r["U"], r["V"], r["Z"], r["sigma_f"], r["sigma_g"], r["sigma"],
                     tol_res=1e-12, tol_orth=1e-12)
