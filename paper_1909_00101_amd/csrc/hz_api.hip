@@ -525,7 +525,7 @@ const char *hz_strerror(int status)
     }
 }
 
-const char *hz_version(void) { return "hzgsvd 0.1 (gfx950)"; }
+const char *hz_version(void) { return "hzgsvd 0.2 (gfx950)"; }
 
 int hz_eval_2x2(int64_t count, const double *in, double *out, void *stream)
 {

@@ -59,13 +59,14 @@ __global__ __launch_bounds__(256) void k_gram_z(const d2 *__restrict__ Fw,
                                                 int64_t mgw, const int *__restrict__ pairs,
                                                 int splits, d2 *__restrict__ part)
 {
-    // LDR: row stride of the summed tile (padded so that the 16 lanes of a
-    // tile row fall in distinct LDS banks); it fits in the staging arrays.
+    // LDR: row stride of the two regions that take the waves' partial
+    // tiles (padded so that the 16 lanes of a tile row fall in distinct LDS
+    // banks); the staging arrays hold them once the chunks are done.
     constexpr int W = W2 / 2, NB = W2 / 16, LDT = 66, NLD = W2 / 4, LDR = W2 + 2;
     constexpr int NT = NB * (NB + 1) / 2;
-    static_assert(LDR <= LDT, "summed tile exceeds the staging arrays");
-    __shared__ __attribute__((aligned(16))) double tre[W2 * LDT];
-    __shared__ __attribute__((aligned(16))) double tim[W2 * LDT];
+    constexpr int LEN = W2 * LDT > 2 * W2 * LDR ? W2 * LDT : 2 * W2 * LDR;
+    __shared__ __attribute__((aligned(16))) double tre[LEN];
+    __shared__ __attribute__((aligned(16))) double tim[LEN];
     const int split = blockIdx.x, pr = blockIdx.y, mat = blockIdx.z;
     const d2 *Y = mat ? Gw : Fw;
     const int64_t m = mat ? mgw : mfw;
@@ -127,31 +128,57 @@ __global__ __launch_bounds__(256) void k_gram_z(const d2 *__restrict__ Fw,
                 }
         }
     }
-    for (int wv = 0; wv < 4; ++wv) {
-        __syncthreads();
-        if (wave == wv) {
-            int t = 0;
+    // The waves' partial tiles summed pairwise, (w0 + w1) + (w2 + w3), as
+    // for the real Gram: waves 1 and 3 leave theirs in two regions, wave 2
+    // adds its own into the second, wave 0 adds both and stores the lower
+    // tiles (entry (16a + 4r + l/16, 16b + l%16) of tile (a, b) in lane l).
+    auto at = [&](int reg, int a, int b, int r) {
+        return reg * W2 * LDR + (16 * b + (lane & 15)) * LDR + 16 * a + 4 * r + (lane >> 4);
+    };
+    __syncthreads();
+    if (wave == 1 || wave == 3) {
+        int t = 0;
 #pragma unroll
-            for (int a = 0; a < NB; ++a)
+        for (int a = 0; a < NB; ++a)
 #pragma unroll
-                for (int b = 0; b <= a; ++b, ++t)
+            for (int b = 0; b <= a; ++b, ++t)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int gi = 16 * a + 4 * r + (lane >> 4), gj = 16 * b + (lane & 15);
-                        double *dr = tre + gj * LDR + gi, *di = tim + gj * LDR + gi;
-                        *dr = (wv == 0) ? accr[t][r] : *dr + accr[t][r];
-                        *di = (wv == 0) ? acci[t][r] : *di + acci[t][r];
-                    }
-        }
+                for (int r = 0; r < 4; ++r) {
+                    tre[at(wave >> 1, a, b, r)] = accr[t][r];
+                    tim[at(wave >> 1, a, b, r)] = acci[t][r];
+                }
     }
     __syncthreads();
-    d2 *out = part + ((size_t)(pr * 2 + mat) * splits + split) * (W2 * W2);
-    for (int e = tid; e < W2 * W2; e += 256) {
-        const int o = (e / W2) * LDR + e % W2;
-        out[e] = d2{tre[o], tim[o]};
+    if (wave == 2) {
+        int t = 0;
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b, ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    tre[at(1, a, b, r)] = accr[t][r] + tre[at(1, a, b, r)];
+                    tim[at(1, a, b, r)] = acci[t][r] + tim[at(1, a, b, r)];
+                }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        d2 *out = part + ((size_t)(pr * 2 + mat) * splits + split) * (W2 * W2);
+        int t = 0;
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b, ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    out[(16 * b + (lane & 15)) * W2 + 16 * a + 4 * r + (lane >> 4)] =
+                        d2{(accr[t][r] + tre[at(0, a, b, r)]) + tre[at(1, a, b, r)],
+                           (acci[t][r] + tim[at(0, a, b, r)]) + tim[at(1, a, b, r)]};
     }
 }
 
+// Sum of the split partials in split order (fixed association); the upper
+// tiles, which no kernel forms, are written as zeros.
 template <int W2>
 __global__ __launch_bounds__(256) void k_gram_sum_z(const d2 *__restrict__ part, int splits,
                                                     d2 *__restrict__ gram)
@@ -160,6 +187,10 @@ __global__ __launch_bounds__(256) void k_gram_sum_z(const d2 *__restrict__ part,
     const int pm = blockIdx.y;
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= W2 * W2) return;
+    if ((e % W2) / 16 < (e / W2) / 16) {       // upper tiles: not formed, left at zero
+        gram[(size_t)pm * (W2 * W2) + e] = d2{0.0, 0.0};
+        return;
+    }
     const d2 *src = part + (size_t)pm * splits * (W2 * W2) + e;
     d2 v[MAXS];
 #pragma unroll

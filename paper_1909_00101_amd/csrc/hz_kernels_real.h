@@ -10,12 +10,12 @@ namespace hz {
 
 // LDS (doubles) each body needs; the caller provides it, so one kernel can
 // run several bodies over a single allocation.
-// (gram: 64-row chunks of W2 columns with stride 66, then the waves'
-// partial blocks summed with stride W2 + 2, which puts the 16 lanes of a
-// tile row in distinct banks)
+// (gram: 64-row chunks of W2 columns with stride 66, then two regions for
+// the waves' partial blocks with stride W2 + 2, which puts the 16 lanes of
+// a tile row in distinct banks)
 template <int W2, bool DB = false> constexpr int gram_lds()
 {
-    return (DB ? 2 : 1) * W2 * 66 > W2 * (W2 + 2) ? (DB ? 2 : 1) * W2 * 66 : W2 * (W2 + 2);
+    return (DB ? 2 : 1) * W2 * 66 > 2 * W2 * (W2 + 2) ? (DB ? 2 : 1) * W2 * 66 : 2 * W2 * (W2 + 2);
 }
 template <int W2> constexpr int update_lds() { return W2 * (W2 + 1); }
 
@@ -35,10 +35,10 @@ template <int W2> constexpr int inner_lds()
 // (column-major W2 x W2, lower tiles).  Each chunk is staged in LDS (tile,
 // gram_lds<W2, DB>() doubles; with DB two tiles taken in turn) with the
 // next two prefetched into registers; wave
-// w takes the k-steps w, w + NW, ... of every chunk, and the waves' partial
-// tiles are summed in wave order.  Further waves of a larger workgroup only
-// take part in the barriers, so the sums do not depend on the workgroup
-// size.
+// w takes the k-steps w, w + NW, ... of every chunk, and the four waves'
+// partial tiles are summed as (w0 + w1) + (w2 + w3).  Further waves of a
+// larger workgroup only take part in the barriers, so the sums do not
+// depend on the workgroup size.
 template <int W2, int NW, bool DB = false>
 __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t m, int p, int q,
                                            int64_t c0, int64_t c1, double *__restrict__ out,
@@ -106,29 +106,50 @@ __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t
         chunk(bufa, c, 0);
         if (c + 1 < c1) chunk(bufb, c + 1, 1);
     }
-    // Sum the waves' partial tiles in wave order (tile reused, ld W2 + 2).
+    // Sum the waves' partial tiles pairwise, (w0 + w1) + (w2 + w3): waves 1
+    // and 3 leave theirs in two LDS regions (tile reused, ld W2 + 2), wave 2
+    // adds its own into the second, and wave 0 adds both regions to its own
+    // and stores the lower tiles straight from its registers.  Element r of
+    // tile (a, b) in lane l is entry (16a + 4r + l/16, 16b + l%16).
+    static_assert(NW == 4, "pairwise sum of four waves' partial tiles");
     constexpr int LDSUM = W2 + 2;
-    for (int wv = 0; wv < NW; ++wv) {
-        __syncthreads();
-        if (wave == wv) {
-            int t = 0;
+    double *const R0 = tile, *const R1 = tile + W2 * LDSUM;
+    auto at = [&](int a, int b, int r) {
+        return (16 * b + (lane & 15)) * LDSUM + 16 * a + 4 * r + (lane >> 4);
+    };
+    __syncthreads();                     // every wave is done with the chunk tiles
+    if (wave == 1 || wave == 3) {
+        double *const R = (wave == 1) ? R0 : R1;
+        int t = 0;
 #pragma unroll
-            for (int a = 0; a < NB; ++a)
+        for (int a = 0; a < NB; ++a)
 #pragma unroll
-                for (int b = 0; b <= a; ++b, ++t)
+            for (int b = 0; b <= a; ++b, ++t)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int gi = 16 * a + 4 * r + (lane >> 4), gj = 16 * b + (lane & 15);
-                        double *dst = tile + gj * LDSUM + gi;
-                        *dst = (wv == 0) ? acc[t][r] : *dst + acc[t][r];
-                    }
-        }
+                for (int r = 0; r < 4; ++r) R[at(a, b, r)] = acc[t][r];
     }
     __syncthreads();
-    // Only lower-triangle tiles are meaningful and written.
-    if (act)
-        for (int e = tid; e < W2 * W2; e += NT)
-            if ((e % W2) / 16 >= (e / W2) / 16) out[e] = tile[(e / W2) * LDSUM + e % W2];
+    if (wave == 2) {
+        int t = 0;
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b, ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) R1[at(a, b, r)] = acc[t][r] + R1[at(a, b, r)];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        int t = 0;
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b, ++t)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    out[(16 * b + (lane & 15)) * W2 + 16 * a + 4 * r + (lane >> 4)] =
+                        (acc[t][r] + R0[at(a, b, r)]) + R1[at(a, b, r)];
+    }
 }
 
 // The four pivot entries of a column pair held as RPL rows per lane by
@@ -503,6 +524,11 @@ __device__ __forceinline__ void inner_solve(
                         load(sZ, cj, zj);
                         double aii, ajj, aij, bij, z11, z21, z12, z22;
                         pair_dots<LP, RPL>(fi, fj, gi, gj, variant, aii, ajj, aij, bij);
+                        // Every group applies its 2x2 matrix, the identity when
+                        // its pair is left alone (which reproduces the columns,
+                        // a negative zero possibly turned positive): with one
+                        // path through the step the columns stay in their
+                        // registers, where a branch costs a copy of each.
                         if (pair_transform(aii, ajj, aij, bij, tol, tol2, sort, variant, z11, z21,
                                            z12, z22, sw_all, sw_big)) {
                             my_chg = 1;

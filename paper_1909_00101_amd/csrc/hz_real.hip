@@ -59,8 +59,8 @@ __global__ __launch_bounds__(256) void k_prescale_copy(
 // alternating LDS tiles, the next two chunks in flight in registers) into
 // the lower-triangle 16x16 tiles
 // of a W2 x W2 partial Gram (the inner solver reads only the lower
-// triangle); the four waves take interleaved k-steps and are summed in LDS
-// in wave order.  k_gram_sum then adds the split partials in split order:
+// triangle); the four waves take interleaved k-steps and are summed as
+// (w0 + w1) + (w2 + w3).  k_gram_sum then adds the split partials in split order:
 // no floating-point atomics, so the result is reproducible bit for bit.
 // ------------------------------------------------------------------------
 template <int W2>
