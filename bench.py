@@ -355,14 +355,15 @@ def _batched_call(hz, W, kw):
     p = hz.params(**kw)
     i64 = lambda v: (ctypes.c_int64 * batch)(*v)
     ptrs = lambda ts: (ctypes.c_void_p * batch)(*[t.data_ptr() for t in ts])
+    ld = lambda t: t.shape[0] if t.shape[1] == 1 else t.stride(1)
     mf, mg, nn = i64([f.shape[0] for f, _ in W]), i64([g.shape[0] for _, g in W]), i64(ns)
     nbytes = L.hz_dgsvd_batched_work_size(ctypes.byref(p), batch, mf, mg, nn)
     work = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
     wptr = (work.data_ptr() + 255) & ~255
     infos = (hz.HzInfo * batch)()
     args = (ctypes.byref(p), batch, mf, mg, nn, ptrs([f for f, _ in W]),
-            i64([f.stride(1) for f, _ in W]), ptrs([g for _, g in W]),
-            i64([g.stride(1) for _, g in W]), ptrs(Zs), i64(ns), ptrs(sig), ptrs(sf), ptrs(sg),
+            i64([ld(f) for f, _ in W]), ptrs([g for _, g in W]),
+            i64([ld(g) for _, g in W]), ptrs(Zs), i64(ns), ptrs(sig), ptrs(sf), ptrs(sg),
             ctypes.c_void_p(wptr), nbytes, infos,
             ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
 
@@ -390,7 +391,8 @@ def _single_calls(hz, W, kw):
         wptr = (wk.data_ptr() + 255) & ~255
         info = hz.HzInfo()
         a = (ctypes.byref(p), f.shape[0], g.shape[0], n, ctypes.c_void_p(f.data_ptr()),
-             f.stride(1), ctypes.c_void_p(g.data_ptr()), g.stride(1),
+             f.shape[0] if n == 1 else f.stride(1), ctypes.c_void_p(g.data_ptr()),
+             g.shape[0] if n == 1 else g.stride(1),
              ctypes.c_void_p(Z.data_ptr()), n, ctypes.c_void_p(s3[0].data_ptr()),
              ctypes.c_void_p(s3[1].data_ptr()), ctypes.c_void_p(s3[2].data_ptr()),
              ctypes.c_void_p(wptr), nb, ctypes.byref(info), stream)

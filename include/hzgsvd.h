@@ -30,7 +30,8 @@
  * caller-owned DEVICE pointers (HIP device memory of the current device).
  * info is a caller-owned HOST pointer (may be NULL).  The library keeps no
  * pointer after a call returns.  If work is NULL the library allocates the
- * workspace itself for the duration of the call; otherwise work must hold at
+ * workspace itself for the duration of the call, stream-ordered on `stream`
+ * (hipMallocAsync / hipFreeAsync); otherwise work must hold at
  * least hz_*_work_size(...) bytes, 256-byte aligned.  Inputs are read once
  * into the workspace, so F and G may be any device buffers of the stated
  * shape.  stream is a hipStream_t (NULL = the default stream); every call is

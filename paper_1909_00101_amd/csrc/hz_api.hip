@@ -669,7 +669,7 @@ static int solve_entry(int kind, const hz_params *p, int64_t m_f, int64_t m_g, i
         int hs[ST_NSLOTS] = {0};
         bool own = false;
         if (work && work_bytes >= 256) status = (int *)work;
-        else { if (hipMalloc(&status, 256) != hipSuccess) return HZ_EHIP; own = true; }
+        else { if (hipMallocAsync((void **)&status, 256, st) != hipSuccess) return HZ_EHIP; own = true; }
         HZ_CHECK(hipMemsetAsync(status, 0, sizeof(int) * ST_NSLOTS, st));
         if (is_complex) launch_n1_cplx(m_f, m_g, F, G, Z, sigma, sigma_f, sigma_g, status, st);
         else launch_n1_real(m_f, m_g, F, G, Z, sigma, sigma_f, sigma_g, status, st);
@@ -679,7 +679,7 @@ static int solve_entry(int kind, const hz_params *p, int64_t m_f, int64_t m_g, i
         if (hs[ST_FLAGS] & FLAG_NONFINITE) rc = HZ_ENONFINITE;
         if (info) { info->converged = 1; info->w = 1; info->status = rc; }
     done:
-        if (own) (void)hipFree(status);
+        if (own) (void)hipFreeAsync(status, st);
         return rc;
     }
     Plan P;
@@ -1203,7 +1203,7 @@ static int run_shortened(const hz_params &prm, const Plan &P, const SPlan &S, vo
 {
     bool own = false;
     if (!work) {
-        if (hipMalloc(&work, S.total) != hipSuccess) return HZ_EHIP;
+        if (hipMallocAsync(&work, S.total, st) != hipSuccess) return HZ_EHIP;
         own = true;
     }
     char *b = (char *)work;
@@ -1238,10 +1238,7 @@ static int run_shortened(const hz_params &prm, const Plan &P, const SPlan &S, vo
             if (info) info->status = rc;
         }
     }
-    if (own) {
-        (void)hipStreamSynchronize(st);
-        (void)hipFree(work);
-    }
+    if (own) (void)hipFreeAsync(work, st);
     return rc;
 }
 
@@ -1417,7 +1414,7 @@ static int run_batched(const hz_params &prm, int batch, const int64_t *mf, const
     std::vector<unsigned long long> htot((size_t)batch * 4);
     int nact = 0, sweeps = 0;
     if (!work) {
-        if (hipMalloc(&work, L.total) != hipSuccess) return HZ_EHIP;
+        if (hipMallocAsync(&work, L.total, st) != hipSuccess) return HZ_EHIP;
         own = true;
     }
     {
@@ -1618,10 +1615,7 @@ static int run_batched(const hz_params &prm, int batch, const int64_t *mf, const
 done:
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    if (own) {
-        (void)hipStreamSynchronize(st);
-        (void)hipFree(work);
-    }
+    if (own) (void)hipFreeAsync(work, st);
     (void)sweeps;
     return rc;
 }
@@ -1849,16 +1843,16 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
         SPlan S;
         int hs[ST_NSLOTS] = {0, 0, 0, 0};
         if (!make_splan(m_f, m_g, n, 0, S, 0)) return -4;
-        if (hipMalloc(&swork, S.total) != hipSuccess) return HZ_EHIP;
+        if (hipMallocAsync(&swork, S.total, st) != hipSuccess) return HZ_EHIP;
         if (launch_shorten(S, swork, F, ldf, G, ldg, st) != hipSuccess ||
             hipMemcpyAsync(hs, (char *)swork + S.o_status, sizeof(hs), hipMemcpyDeviceToHost,
                            st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess) {
-            (void)hipFree(swork);
+            (void)hipFreeAsync(swork, st);
             return HZ_EHIP;
         }
         if (hs[ST_FLAGS] & (FLAG_NONFINITE | FLAG_CHOL)) {
-            (void)hipFree(swork);
+            (void)hipFreeAsync(swork, st);
             return (hs[ST_FLAGS] & FLAG_NONFINITE) ? HZ_ENONFINITE : HZ_ECHOL;
         }
         Ft = (const double *)((char *)swork + S.o_f2);
@@ -1870,7 +1864,7 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
         Plan P;
         if (!make_plan(c, mft, mgt, n, 0, P)) return -1.0;
         void *work = nullptr;
-        if (hipMalloc(&work, P.total) != hipSuccess) { herr = 1; return -1.0; }
+        if (hipMallocAsync(&work, P.total, st) != hipSuccess) { herr = 1; return -1.0; }
         hz_info info;
         memset(&info, 0, sizeof(info));
         (void)hipStreamSynchronize(st);
@@ -1878,7 +1872,7 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
         const int rc = run_solve(c, P, work, P.total, &info, st, KIND_REAL, Ft, ldft, Gt, ldgt,
                                  nullptr, nullptr, nullptr, n, nullptr, nullptr, nullptr, false);
         const double t = now_ms() - t0;
-        (void)hipFree(work);
+        (void)hipFreeAsync(work, st);
         if (rc == HZ_EHIP) herr = 1;
         return rc == HZ_OK ? t : -1.0;
     };
@@ -1899,7 +1893,7 @@ int hz_dgsvd_tune(const hz_params *p, int64_t m_f, int64_t m_g, int64_t n, const
     if (!base.update_rows) { axes.push_back({16, 32, 48, 64, 80, 128}); fields.push_back(&cur.update_rows); }
     if (!base.inner_lanes) { axes.push_back({4, 8, 16}); fields.push_back(&cur.inner_lanes); }
     ms = coordinate_search(cur, axes, fields, solve);
-    if (swork) (void)hipFree(swork);
+    if (swork) (void)hipFreeAsync(swork, st);
     if (herr) return HZ_EHIP;
     if (ms < 0.0) return HZ_ENOCONV;
     *best = cur;
@@ -1957,7 +1951,7 @@ int hz_dgsvd_batched_tune(const hz_params *p, int batch, const int64_t *m_f, con
         BLayout L;
         if (!plan_batched(c, batch, m_f, m_g, n, L)) return -1.0;
         void *work = nullptr;
-        if (hipMalloc(&work, L.total) != hipSuccess) { herr = 1; return -1.0; }
+        if (hipMallocAsync(&work, L.total, st) != hipSuccess) { herr = 1; return -1.0; }
         std::vector<hz_info> infos((size_t)batch);
         (void)hipStreamSynchronize(st);
         const double t0 = now_ms();
@@ -1965,7 +1959,7 @@ int hz_dgsvd_batched_tune(const hz_params *p, int batch, const int64_t *m_f, con
                                    (double *const *)G, ldg, nul.data(), ldz.data(), nul.data(),
                                    nul.data(), nul.data(), L, work, infos.data(), st, false);
         const double t = now_ms() - t0;
-        (void)hipFree(work);
+        (void)hipFreeAsync(work, st);
         if (rc == HZ_EHIP) herr = 1;
         return rc == HZ_OK ? t : -1.0;
     };

@@ -109,3 +109,74 @@ def test_misaligned_exact_workspace_is_not_overrun():
     assert torch.all(base[off + need:] == 0xA5).item()
     for k in ("U", "V", "Z", "sigma", "sigma_f", "sigma_g"):
         assert torch.equal(ref[k], got[k]), k
+
+
+def test_batched_null_workspace_equals_caller_workspace():
+    """hz_dgsvd_batched with work = NULL (stream-ordered allocation inside
+    the library) gives bitwise the results of the same call on a caller
+    workspace; the pairs include n = 1."""
+    hz = _hz()
+    L = hz.lib()
+    pairs = gi.make_batch(count=6, seed=530, n_lo=2, n_hi=70)
+    rng = np.random.default_rng(531)
+    pairs.append((rng.standard_normal((9, 1)), rng.standard_normal((4, 1)), None))
+
+    def run(null_work):
+        W = [(torch.from_numpy(np.asfortranarray(F)).cuda(),
+              torch.from_numpy(np.asfortranarray(G)).cuda()) for F, G, _ in pairs]
+        batch = len(W)
+        ns = [f.shape[1] for f, _ in W]
+        Zs = [torch.empty((n, n), dtype=torch.float64, device="cuda").t() for n in ns]
+        sig = [torch.empty(n, dtype=torch.float64, device="cuda") for n in ns]
+        sf = [torch.empty_like(x) for x in sig]
+        sg = [torch.empty_like(x) for x in sig]
+        i64 = lambda v: (ctypes.c_int64 * batch)(*v)
+        ptrs = lambda ts: (ctypes.c_void_p * batch)(*[t.data_ptr() for t in ts])
+        # leading dimension of a column-major buffer (a single column's stride
+        # is arbitrary)
+        ld = lambda t: t.shape[0] if t.shape[1] == 1 else t.stride(1)
+        p = hz.params(w=16)
+        mf, mg, nn = i64([f.shape[0] for f, _ in W]), i64([g.shape[0] for _, g in W]), i64(ns)
+        nbytes = L.hz_dgsvd_batched_work_size(ctypes.byref(p), batch, mf, mg, nn)
+        work = None if null_work else torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        wptr = None if null_work else ctypes.c_void_p((work.data_ptr() + 255) & ~255)
+        infos = (hz.HzInfo * batch)()
+        st = L.hz_dgsvd_batched(ctypes.byref(p), batch, mf, mg, nn, ptrs([f for f, _ in W]),
+                                i64([ld(f) for f, _ in W]), ptrs([g for _, g in W]),
+                                i64([ld(g) for _, g in W]), ptrs(Zs), i64(ns), ptrs(sig),
+                                ptrs(sf), ptrs(sg), wptr, 0 if null_work else nbytes, infos,
+                                None)
+        torch.cuda.synchronize()
+        return st, [infos[i].status for i in range(batch)], \
+            [(f.cpu().numpy(), g.cpu().numpy(), z.cpu().numpy(), s.cpu().numpy())
+             for (f, g), z, s in zip(W, Zs, sig)]
+
+    st0, s0, a = run(False)
+    st1, s1, b = run(True)
+    assert st0 == st1 == 0 and s0 == s1
+    for i, (ra, rb) in enumerate(zip(a, b)):
+        for x, y in zip(ra, rb):
+            assert np.array_equal(x, y), i
+
+
+def test_n1_null_workspace():
+    """n = 1 with work = NULL: the closed form with the library's own status
+    word, sigma = ||f|| / ||g||."""
+    hz = _hz()
+    L = hz.lib()
+    rng = np.random.default_rng(540)
+    F, G = rng.standard_normal((11, 1)), rng.standard_normal((6, 1))
+    dF = torch.from_numpy(np.asfortranarray(F)).cuda()
+    dG = torch.from_numpy(np.asfortranarray(G)).cuda()
+    dZ = torch.empty((1, 1), dtype=torch.float64, device="cuda")
+    sig = torch.empty(1, dtype=torch.float64, device="cuda")
+    sf, sg = torch.empty_like(sig), torch.empty_like(sig)
+    info = hz.HzInfo()
+    st = L.hz_dgsvd(None, 11, 6, 1, ctypes.c_void_p(dF.data_ptr()), 11,
+                    ctypes.c_void_p(dG.data_ptr()), 6, ctypes.c_void_p(dZ.data_ptr()), 1,
+                    ctypes.c_void_p(sig.data_ptr()), ctypes.c_void_p(sf.data_ptr()),
+                    ctypes.c_void_p(sg.data_ptr()), None, 0, ctypes.byref(info), None)
+    torch.cuda.synchronize()
+    assert st == 0 and info.converged
+    want = np.linalg.norm(F) / np.linalg.norm(G)
+    assert abs(sig.item() - want) <= 4 * np.finfo(np.float64).eps * want
