@@ -325,8 +325,13 @@ __device__ __forceinline__ void inner_solve(
         if (wave < 2) {
             double *M = wave ? sG : sF;
             bool ok = true;
-            // lane j holds column j's diagonal before the factorization
-            const double d0 = (lane < W2) ? M[lane * LDI + lane] : 0.0;
+            // lane j (< 16) holds the diagonals of columns 16 kb + j before
+            // the factorization; it tests the pivot of that column itself
+            // once the panel is factored
+            double d0[NBK];
+#pragma unroll
+            for (int kb = 0; kb < NBK; ++kb)
+                d0[kb] = (lane < 16) ? M[(16 * kb + lane) * LDI + 16 * kb + lane] : 1.0;
 #pragma unroll
             for (int kb = 0; kb < NBK; ++kb) {
                 const int c0 = 16 * kb, row = c0 + lane;
@@ -334,16 +339,18 @@ __device__ __forceinline__ void inner_solve(
                 double pv[16];
 #pragma unroll
                 for (int t = 0; t < 16; ++t) pv[t] = live ? M[(c0 + t) * LDI + row] : 0.0;
+                double own = 1.0;           // lane j: the pivot of column c0 + j
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
                     const double piv = readlane_d(pv[j], j);
-                    ok = ok && (piv > PIV_REL<W2>() * readlane_d(d0, c0 + j)) && (piv < INFINITY);
+                    if (lane == j) own = pv[j];
                     const double inv = rsqrt_nr(piv);
                     const double l = (lane >= j) ? pv[j] * inv : 0.0;
                     pv[j] = l;
 #pragma unroll
                     for (int t = j + 1; t < 16; ++t) pv[t] = fma(-l, readlane_d(l, t), pv[t]);
                 }
+                if (lane < 16) ok = ok && (own > PIV_REL<W2>() * d0[kb]) && (own < INFINITY);
                 if (live) {
 #pragma unroll
                     for (int t = 0; t < 16; ++t) M[(c0 + t) * LDI + row] = pv[t];
