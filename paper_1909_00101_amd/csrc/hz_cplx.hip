@@ -261,14 +261,12 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
 #pragma unroll
             for (int k = 0; k < W2; ++k) a[k] = M[k * LDI + i];
             const double d0 = M[i * LDI + i][0];   // column i's diagonal before the factorization
-            bool ok = true;
+            double own = 1.0;                        // the pivot of column i, kept by lane i
 #pragma unroll
             for (int j = 0; j < W2; ++j) {
                 const double p0 = readlane_d(a[j][0], j), p1 = readlane_d(a[j][0], 32 + j);
-                const double q0 = readlane_d(d0, j), q1 = readlane_d(d0, 32 + j);
                 const double piv = mat ? p1 : p0;
-                // numerically positive definite: pivots above W2 * eps times the diagonal
-                ok = ok && (piv > W2 * 2.220446049250313e-16 * (mat ? q1 : q0)) && (piv < INFINITY);
+                if (i == j) own = a[j][0];
                 const double inv = rsqrt_nr(piv);
                 d2 l = (i > j) ? a[j] * inv : d2{0.0, 0.0};
                 if (i == j) l = d2{piv * inv, 0.0};
@@ -288,7 +286,9 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
 #pragma unroll
             for (int k = 0; k < W2; ++k)
                 M[i * LDI + k] = (k <= i) ? d2{a[k][0], -a[k][1]} : d2{0.0, 0.0};
-            if (!ok) s_fail = 1;
+            // numerically positive definite: every pivot above W2 * eps times
+            // its column's diagonal, each tested by the lane that holds it
+            if (!((own > W2 * 2.220446049250313e-16 * d0) && (own < INFINITY))) s_fail = 1;
         }
     }
     __syncthreads();

@@ -400,20 +400,17 @@ __device__ __forceinline__ void inner_solve(
 #pragma unroll
             for (int k = 0; k < W2; ++k) a[k] = M[k * LDI + i];
             const double d0 = M[i * LDI + i];    // column i's diagonal before the factorization
-            bool ok = true;
+            double own = 1.0;                      // the pivot of column i, kept by lane i
 #pragma unroll
             for (int j = 0; j < W2; ++j) {
-                double piv, dj;
+                double piv;
                 if (two) {
                     piv = readlane_d(a[j], j);
-                    dj = readlane_d(d0, j);
                 } else {
                     const double p0 = readlane_d(a[j], j), p1 = readlane_d(a[j], 32 + j);
-                    const double q0 = readlane_d(d0, j), q1 = readlane_d(d0, 32 + j);
                     piv = mat ? p1 : p0;
-                    dj = mat ? q1 : q0;
                 }
-                ok = ok && (piv > PIV_REL<W2>() * dj) && (piv < INFINITY);
+                if (i == j) own = a[j];
                 const double inv = rsqrt_nr(piv);
                 const double l = (i >= j) ? a[j] * inv : 0.0;
                 a[j] = l;
@@ -435,7 +432,7 @@ __device__ __forceinline__ void inner_solve(
             // F_hat = L^T: column i of F_hat is row i of L.
 #pragma unroll
             for (int k = 0; k < W2; ++k) M[i * LDI + k] = (k <= i) ? a[k] : 0.0;
-            if (!ok) s_fail = 1;
+            if (!((own > PIV_REL<W2>() * d0) && (own < INFINITY))) s_fail = 1;
         }
     }
     __syncthreads();
