@@ -218,15 +218,17 @@ def test_sweep_cap():
 
 @pytest.mark.parametrize("launch", [
     {},
+    dict(inner_ordering=3, inner_max_sweeps=1, gram_splits=8, update_rows=48, inner_lanes=8),
     dict(inner_ordering=1, inner_max_sweeps=1, gram_splits=8, update_rows=48, inner_lanes=16),
-    dict(inner_ordering=3, inner_max_sweeps=1, gram_splits=8, update_rows=48, inner_lanes=16),
-], ids=["defaults", "bench_tuned", "ring"])
+    dict(inner_ordering=3, inner_max_sweeps=1, gram_splits=16, update_rows=48, inner_lanes=16),
+], ids=["defaults", "bench_tuned", "mm_inner_16_lanes", "ring_16_lanes"])
 def test_config2_full_size_vs_oracle_golden(launch):
     """The 4096x1024 workload (w = 32, modified modulus, tol = 1024 eps), with
-    the library's default launch and with the launch the benchmark times
-    (modified modulus inside the blocks, one inner sweep, 8 Gram splits, 48
-    update rows per wave, 16 inner lanes), against the oracle's sigma for the
-    same seeded pair (tests/golden/oracle_config2.json, written by
+    the library's default launch, with the launch the benchmark times (the
+    autotuner's choice on MI355X: ring ordering inside the blocks, one inner
+    sweep, 8 lanes per column pair, 8 Gram splits, 48 update rows per wave)
+    and with two other launches, against the oracle's sigma for the same
+    seeded pair (tests/golden/oracle_config2.json, written by
     tests/golden/make_golden.py from the oracle alone), plus the contract
     residuals of the GPU outputs computed on the GPU."""
     import json
