@@ -160,3 +160,21 @@ def test_config3_full_size_vs_oracle_golden(iord):
     vv = torch.linalg.norm(V.conj().T @ V - eye) / n
     assert float(fz) < 1e-12 and float(gz) < 1e-12, (float(fz), float(gz))
     assert float(uu) < 1e-12 and float(vv) < 1e-12, (float(uu), float(vv))
+
+
+@pytest.mark.parametrize("w", [8, 16])
+def test_complex_rank_deficient_reports_cholesky_failure(w):
+    """Two equal columns of the complex G (one a complex multiple of the
+    other would do as well): the Hermitian Cholesky of their pivot block
+    meets a pivot at rounding level, which the lane holding it reports, and
+    the solve stops with HZ_ECHOL."""
+    hz = _hz()
+    F, G, _ = gi.custom_pair(120, 90, 48, kappa=10.0, is_complex=True, seed=95)
+    G[:, 13] = G[:, 12] * np.exp(0.3j)
+    dF = torch.from_numpy(np.asfortranarray(F)).cuda()
+    dG = torch.from_numpy(np.asfortranarray(G)).cuda()
+    print(f"complex rank deficiency, w={w}", flush=True)
+    with pytest.raises(hz.GsvdError) as e:
+        hz.gsvd(dF, dG, w=w)
+    assert e.value.status == hz.HZ_ECHOL
+    assert e.value.info.failed_pair >= 0

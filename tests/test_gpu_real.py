@@ -185,6 +185,21 @@ def test_rank_deficient_reports_cholesky_failure():
     assert e.value.info.failed_pair >= 0
 
 
+def test_rank_deficiency_in_a_later_cholesky_panel():
+    """2w = 64: two equal columns of G in the middle of a block (columns 20
+    and 21 of block 1), so the failing pivot of its pivot block pair lies in
+    the second or the fourth 16-column panel of the blocked Cholesky, where
+    the lane holding it tests it against that panel's diagonal."""
+    hz = _hz()
+    F, G, _ = gi.custom_pair(300, 300, 128, seed=94)
+    G[:, 32 + 21] = G[:, 32 + 20]
+    print("rank deficiency in a later panel, w=32", flush=True)
+    with pytest.raises(hz.GsvdError) as e:
+        _run(F, G, w=32)
+    assert e.value.status == hz.HZ_ECHOL
+    assert e.value.info.failed_pair >= 0
+
+
 def test_exact_zero_pivot_in_blocked_cholesky():
     """2w = 64 (the blocked Cholesky): columns 0 and 1 of G both equal e_0,
     so their prescale factor is 1, their Gram entries exactly 1 and the
