@@ -17,6 +17,10 @@ only the dominant kernel's launches with HIP events on the solve's stream,
 which gives that kernel's average launch time for the roofline entry
 (algorithmic bytes or flops per launch over it).
 
+A further untimed solve stamps the device wall clock at the inner solver's
+phase boundaries (`inner_phases_us`: Gram load, Cholesky, factor prescale,
+inner sweeps, Theta rescale; mean per launch and pivot pair).
+
 Prints one JSON line: solves/s, the split, the roofline entry, the CPU
 oracle timed on one complete solve of the same pair on the host cores, and
 (unless --no-forms) the QR-shortened, mixed-precision, complex and batched
@@ -665,6 +669,16 @@ def main():
     L.hz_profile_read(ms, cnt, 4)
     L.hz_profile_enable(0)
     t_launch = ms[kind_index[dom]] / max(1, cnt[kind_index[dom]]) * 1e-3
+    # ---- the inner solver's phases: one more solve with the device wall
+    # clock stamped at the phase boundaries (mean per launch and pivot pair)
+    L.hz_profile_enable(2)
+    solve()
+    torch.cuda.synchronize()
+    ph = (ctypes.c_double * 5)()
+    L.hz_profile_read_phases(ph, 5)
+    L.hz_profile_enable(0)
+    inner_phases = {k: round(v, 2) for k, v in
+                    zip(("load", "cholesky", "prescale", "sweeps", "theta"), ph)}
 
     w = args.w
     gram, upd = algorithmic(spec.m_f, spec.m_g, spec.n, w)
@@ -697,8 +711,9 @@ def main():
                         unit="TFLOP/s", frac=round(achieved / FP64_MFMA_PEAK_TFS, 4),
                         traffic=None)
     lp = kw.get("inner_lanes") or (16 if w == 32 else 8)
+    ring = "true" if kw.get("inner_ordering") == hz.HZ_ORD_RING else "false"
     names = {"gram": [f"hz::k_gram<{2 * w}>", f"hz::k_gram_sum<{2 * w}>"],
-             "inner": [f"hz::k_inner<{2 * w},{lp}>"],
+             "inner": [f"hz::k_inner<{2 * w},{lp},{ring}>"],
              "update": [f"hz::k_update<{2 * w}>"]}
     traffic = measured_traffic()
     tr = {k: (sum(traffic[n] for n in v) if all(n in traffic for n in v) else None)
@@ -737,7 +752,7 @@ def main():
                fp64_mfma_util_solve=round(mfma_util, 4),
                hbm_frac_solve=round(sbytes * solves_per_s / (HBM_PEAK_GBS * 1e9), 4),
                kernel_time_split=split, split_ms={k: round(v, 2) for k, v in split_ms.items()},
-               kernels=per_kernel, roofline=roof)
+               kernels=per_kernel, inner_phases_us=inner_phases, roofline=roof)
     if not args.no_forms:
         out["transfer_inclusive"] = transfer_inclusive(F, G, Fw, Gw, work, kw)
         out["forms"] = dict(
