@@ -879,7 +879,7 @@ static int run_solve(const hz_params &prm, const Plan &P, void *work, size_t wor
         Ptrs W = make_ptrs(P, work);
         std::vector<unsigned long long> hph;
         double clk_khz = 0.0;
-        if (!noalloc && g_prof.on && g_prof.phases && kind != KIND_COMPLEX) {
+        if (!noalloc && g_prof.on && g_prof.phases) {
             const size_t nph = (size_t)P.steps * P.npairs * 8;
             if (hipMalloc(&dphase, nph * sizeof(unsigned long long)) == hipSuccess) {
                 W.phase = dphase;

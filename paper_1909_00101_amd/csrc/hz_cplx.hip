@@ -212,7 +212,8 @@ template <int W2, int LP, bool RING>
 __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
     const d2 *__restrict__ gram, int factors, int npairs, int step,
     const int16_t *__restrict__ itab, int isteps, int inner_max, double tol, int sort, int variant,
-    d2 *__restrict__ Zt, unsigned long long *__restrict__ cnt, int *__restrict__ status)
+    d2 *__restrict__ Zt, unsigned long long *__restrict__ cnt, int *__restrict__ status,
+    unsigned long long *__restrict__ phase)
 {
     constexpr int W = W2 / 2;
     constexpr int NT = W * LP;
@@ -229,6 +230,10 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
 
     const int pr = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     unsigned long long *myc = cnt + ((size_t)step * npairs + pr) * 4;
+    // with `phase`, the wall clock at the boundaries of the phases (load,
+    // Cholesky, prescale, inner sweeps, Theta and store)
+    unsigned long long *const ph = phase ? phase + ((size_t)step * npairs + pr) * 8 : nullptr;
+    if (ph && tid == 0) ph[0] = wall_clock64();
     {
         const d2 *pa = gram + (size_t)(pr * 2) * (W2 * W2);
         const d2 *pb = pa + (W2 * W2);
@@ -241,6 +246,7 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
         if (tid == 0) s_fail = 0;
     }
     __syncthreads();
+    if (ph && tid == 0) ph[1] = wall_clock64();
 
     // Hermitian Cholesky, lane = row, A in lanes 0..31 and B in 32..63 of wave 0.
     // With `factors` the blocks are already the upper triangular factors (QR
@@ -292,6 +298,7 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
         }
     }
     __syncthreads();
+    if (ph && tid == 0) ph[2] = wall_clock64();
     if (s_fail) {
         d2 *zt = Zt + (size_t)pr * (W2 * W2);
         for (int e = tid; e < W2 * W2; e += NT)
@@ -327,6 +334,7 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
         }
     }
     __syncthreads();
+    if (ph && tid == 0) ph[3] = wall_clock64();
 
     const double tol2 = tol * tol;
     unsigned my_all = 0, my_big = 0, my_chg = 0;
@@ -485,6 +493,7 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
         if (any == 0) break;
     }
 
+    if (ph && tid == 0) ph[4] = wall_clock64();
     // Z_tilde = Z_hat Theta, or exactly I when nothing was transformed or
     // swapped (the block update is then skipped, Section 2.5)
     d2 *zt = Zt + (size_t)pr * (W2 * W2);
@@ -525,6 +534,7 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
         myc[1] = tb;
         myc[2] = (unsigned long long)nsw;
         myc[3] = (nchg == 0) ? 1ull : 0ull;
+        if (ph) ph[5] = wall_clock64();
     }
 }
 
@@ -738,7 +748,7 @@ static void step_impl_z(const Plan &P, const Ptrs &W, int step, const hz_params 
     auto go = [&](auto kern, int lp) {
         hipLaunchKernelGGL(kern, dim3(P.npairs), dim3((W2 / 2) * lp), 0, s, (const d2 *)W.gram,
                            fac, P.npairs, step, W.itab, P.isteps, prm.inner_max_sweeps, tol,
-                           prm.sort, prm.variant, (d2 *)W.Zt, W.cnt, W.status);
+                           prm.sort, prm.variant, (d2 *)W.Zt, W.cnt, W.status, W.phase);
     };
     if (W2 == 32 && P.inner_lp == 16) {
         if (ring) go(k_inner_z<W2, 16, true>, 16);
