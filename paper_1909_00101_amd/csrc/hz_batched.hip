@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void kb_gram(const BProb *__restrict__ probs,
     const int *pr = P.otab + ((size_t)step * P.npairs + tk.y) * 2;
     const int64_t m = mat ? P.mgw : P.mfw;
     __shared__ __attribute__((aligned(16))) double tile[gram_lds<W2>()];
-    gram_block<W2, 4>(mat ? P.Gw : P.Fw, m, pr[0], pr[1], 0, m / 64,
+    gram_block<W2>(mat ? P.Gw : P.Fw, m, pr[0], pr[1], 0, m / 64,
                    P.gram + ((size_t)tk.y * 2 + mat) * (W2 * W2), tile);
 }
 
@@ -325,9 +325,9 @@ __global__ __launch_bounds__((W2 / 2) * LP) void kb_persist(
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const int *pr = P.otab + ((size_t)k * P.npairs + l) * 2;
         double *const gm = P.gram + (size_t)l * 2 * (W2 * W2);
-        gram_block<W2, 4>(P.Fw, P.mfw, pr[0], pr[1], 0, P.mfw / 64, gm, lds);
+        gram_block<W2>(P.Fw, P.mfw, pr[0], pr[1], 0, P.mfw / 64, gm, lds);
         __syncthreads();
-        gram_block<W2, 4>(P.Gw, P.mgw, pr[0], pr[1], 0, P.mgw / 64, gm + W2 * W2, lds);
+        gram_block<W2>(P.Gw, P.mgw, pr[0], pr[1], 0, P.mgw / 64, gm + W2 * W2, lds);
         __syncthreads();
         double *const zt = P.Zt + (size_t)l * (W2 * W2);
         inner_solve<W2, LP, RING>(gm, gm + W2 * W2, 1, 0, itab, isteps, inner_max, P.tol, sort,

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(DF_NT) void k_sweep_df(DFArgs A)
             const int mat = sub / S, sp = sub % S;
             const int64_t m = mat ? A.mgw : A.mfw;
             const int64_t nch = m / 64;
-            gram_block<W2, 4>(mat ? A.Gw : A.Fw, m, pr[0], pr[1], nch * sp / S,
+            gram_block<W2>(mat ? A.Gw : A.Fw, m, pr[0], pr[1], nch * sp / S,
                               nch * (sp + 1) / S,
                               A.part + ((kl * 2 + mat) * S + sp) * W2SQ, lds);
             sig = gram_done + kl;

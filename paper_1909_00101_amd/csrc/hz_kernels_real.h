@@ -10,13 +10,9 @@ namespace hz {
 
 // LDS (doubles) each body needs; the caller provides it, so one kernel can
 // run several bodies over a single allocation.
-// (gram: 64-row chunks of W2 columns with stride 66, then two regions for
-// the waves' partial blocks with stride W2 + 2, which puts the 16 lanes of
-// a tile row in distinct banks)
-template <int W2, bool DB = false> constexpr int gram_lds()
-{
-    return (DB ? 2 : 1) * W2 * 66 > 2 * W2 * (W2 + 2) ? (DB ? 2 : 1) * W2 * 66 : 2 * W2 * (W2 + 2);
-}
+// (gram: two regions for the waves' partial blocks with stride W2 + 2,
+// which puts the 16 lanes of a tile row in distinct banks)
+template <int W2> constexpr int gram_lds() { return 2 * W2 * (W2 + 2); }
 template <int W2> constexpr int update_lds() { return W2 * (W2 + 1); }
 
 // A pivot Gram block counts as numerically positive definite when every
@@ -30,94 +26,88 @@ template <int W2> constexpr int inner_lds()
     return 3 * W2 * (W2 + 2) + 128 + W2 * W2 / 4 + (3 * (W2 / 2) + 1) / 2 + 2;
 }
 
-// Device body: NW waves form the Gram block of the block-column pair (p, q)
-// of Y (m rows, ld m) over the 64-row chunks [c0, c1) and write it to out
-// (column-major W2 x W2, lower tiles).  Each chunk is staged in LDS (tile,
-// gram_lds<W2, DB>() doubles; with DB two tiles taken in turn) with the
-// next two prefetched into registers; wave
-// w takes the k-steps w, w + NW, ... of every chunk, and the four waves'
-// partial tiles are summed as (w0 + w1) + (w2 + w3).  Further waves of a
-// larger workgroup only take part in the barriers, so the sums do not
-// depend on the workgroup size.
-template <int W2, int NW, bool DB = false>
+// Device body: four waves form the Gram block of the block-column pair
+// (p, q) of Y (m rows, ld m) over the 64-row chunks [c0, c1) and write it to
+// out (column-major W2 x W2, lower tiles).  The MFMA operands come straight
+// from global memory, no LDS in the loop: for X^T X both operands of a
+// product hold the same kind of value (lane l: row k of the chunk's slab,
+// column l % 16 of a 16-column tile), and which rows feed which k-step is
+// free, so wave w takes rows 16w .. 16w + 15 of every chunk and lane group
+// g = l / 16 loads rows 2g, 2g + 1 of each 8-row half as one 16-byte load:
+// a column's 64 bytes are contiguous per load and every 128-byte line is
+// used whole by one wave.  A wave's k-steps are, per chunk, rows
+// 16w + 8h + 2g + j for (h, j) = (0,0), (0,1), (1,0), (1,1); the four
+// waves' partial tiles are summed as (w0 + w1) + (w2 + w3) (tile, gram_lds
+// doubles).  Further waves of a larger workgroup only take part in the
+// barriers, so the sums do not depend on the workgroup size.
+template <int W2>
 __device__ __forceinline__ void gram_block(const double *__restrict__ Y, int64_t m, int p, int q,
                                            int64_t c0, int64_t c1, double *__restrict__ out,
                                            double *__restrict__ tile)
 {
-    constexpr int W = W2 / 2, NB = W2 / 16, LDT = 66, NT = 64 * NW;
-    constexpr int CPP = NT / 32;             // columns loaded per pass (32 lanes per column)
-    constexpr int NLD = W2 / CPP;            // columns per thread
-    constexpr int NTL = NB * (NB + 1) / 2;   // lower-triangle tiles
-    static_assert(W2 % CPP == 0 && 16 % NW == 0, "bad Gram geometry");
+    constexpr int W = W2 / 2, NB = W2 / 16, NTL = NB * (NB + 1) / 2, PF = 2;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const bool act = tid < NT;
-    const int lrow = 2 * (tid & 31), lcol = (tid >> 5) % CPP;
 
     d4 acc[NTL];
 #pragma unroll
     for (int t = 0; t < NTL; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-
-    const double *colp[NLD];
+    const double *colp[NB];
 #pragma unroll
-    for (int t = 0; t < NLD; ++t) {
-        const int cc = lcol + CPP * t;
+    for (int a = 0; a < NB; ++a) {
+        const int cc = 16 * a + (lane & 15);
         const int gc = (cc < W) ? p * W + cc : q * W + (cc - W);
-        colp[t] = Y + (int64_t)gc * m + lrow;
+        colp[a] = Y + (int64_t)gc * m + 16 * wave + 2 * (lane >> 4);
     }
-    // Two chunks in flight: while chunk c is staged and multiplied, the loads
-    // of chunk c + 1 are outstanding, and chunk c + 2's go out as soon as
-    // c's registers are free.  The chunks are still accumulated in order.
-    d2 bufa[NLD], bufb[NLD];
-    auto load = [&](d2 (&b)[NLD], int64_t c) {
+    d2 buf[PF][NB][2];
+    auto load = [&](d2 (&b)[NB][2], int64_t c) {
 #pragma unroll
-        for (int t = 0; t < NLD; ++t) b[t] = *(const d2 *)(colp[t] + c * 64);
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) b[a][h] = *(const d2 *)(colp[a] + c * 64 + 8 * h);
     };
-    // With DB the chunks alternate between two LDS tiles: the tile chunk c
-    // writes was last read for chunk c - 2, before chunk c - 1's barrier,
-    // so one barrier per chunk suffices.
-    auto chunk = [&](d2 (&b)[NLD], int64_t c, int slot) {
-        double *const tl = tile + (DB ? slot * W2 * LDT : 0);
-        if (!DB) __syncthreads();
-        if (act) {
+    auto mul = [&](const d2 (&b)[NB][2]) {
 #pragma unroll
-            for (int t = 0; t < NLD; ++t) *(d2 *)(tl + (lcol + CPP * t) * LDT + lrow) = b[t];
-        }
-        __syncthreads();
-        if (act) {
-            if (c + 2 < c1) load(b, c + 2);
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int s = 0; s < 16 / NW; ++s) {
-                const int ks = wave + NW * s;
-                double fr[NB];
-#pragma unroll
-                for (int b2 = 0; b2 < NB; ++b2)
-                    fr[b2] = tl[(16 * b2 + (lane & 15)) * LDT + 4 * ks + (lane >> 4)];
+            for (int j = 0; j < 2; ++j) {
                 int t = 0;
 #pragma unroll
                 for (int a = 0; a < NB; ++a)
 #pragma unroll
-                    for (int b2 = 0; b2 <= a; ++b2, ++t) acc[t] = mfma16(fr[a], fr[b2], acc[t]);
+                    for (int b2 = 0; b2 <= a; ++b2, ++t)
+                        acc[t] = mfma16(b[a][h][j], b[b2][h][j], acc[t]);
+            }
+    };
+    // PF chunks in flight.  The main loop has no branch, so each chunk's
+    // products wait only for that chunk's loads (a branch there made the
+    // compiler wait for all of them); loads past the range are clamped to
+    // its last chunk and left unused, and the remainder follows the loop.
+    if (wave < 4 && c0 < c1) {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) load(buf[i], c0 + i < c1 ? c0 + i : c1 - 1);
+        int64_t c = c0;
+        for (; c + PF <= c1; c += PF) {
+#pragma unroll
+            for (int i = 0; i < PF; ++i) {
+                mul(buf[i]);
+                load(buf[i], c + i + PF < c1 ? c + i + PF : c1 - 1);
             }
         }
-    };
-    if (act && c0 < c1) load(bufa, c0);
-    if (act && c0 + 1 < c1) load(bufb, c0 + 1);
-    for (int64_t c = c0; c < c1; c += 2) {
-        chunk(bufa, c, 0);
-        if (c + 1 < c1) chunk(bufb, c + 1, 1);
+#pragma unroll
+        for (int i = 0; i < PF - 1; ++i)
+            if (c + i < c1) mul(buf[i]);
     }
     // Sum the waves' partial tiles pairwise, (w0 + w1) + (w2 + w3): waves 1
     // and 3 leave theirs in two LDS regions (tile reused, ld W2 + 2), wave 2
     // adds its own into the second, and wave 0 adds both regions to its own
     // and stores the lower tiles straight from its registers.  Element r of
     // tile (a, b) in lane l is entry (16a + 4r + l/16, 16b + l%16).
-    static_assert(NW == 4, "pairwise sum of four waves' partial tiles");
     constexpr int LDSUM = W2 + 2;
     double *const R0 = tile, *const R1 = tile + W2 * LDSUM;
     auto at = [&](int a, int b, int r) {
         return (16 * b + (lane & 15)) * LDSUM + 16 * a + 4 * r + (lane >> 4);
     };
-    __syncthreads();                     // every wave is done with the chunk tiles
+    __syncthreads();                     // the caller's previous use of tile is over
     if (wave == 1 || wave == 3) {
         double *const R = (wave == 1) ? R0 : R1;
         int t = 0;

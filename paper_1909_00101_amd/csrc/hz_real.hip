@@ -55,12 +55,11 @@ __global__ __launch_bounds__(256) void k_prescale_copy(
 // ------------------------------------------------------------------------
 // Pivot Gram blocks (paper: Section 2.3, A_hat = [F_p F_q]^T [F_p F_q] and
 // B_hat likewise).  FP64 MFMA 16x16x4.  Grid (splits, pairs, 2): each
-// workgroup sums the rows of its split (64-row chunks staged in two
-// alternating LDS tiles, the next two chunks in flight in registers) into
-// the lower-triangle 16x16 tiles
-// of a W2 x W2 partial Gram (the inner solver reads only the lower
-// triangle); the four waves take interleaved k-steps and are summed as
-// (w0 + w1) + (w2 + w3).  k_gram_sum then adds the split partials in split order:
+// workgroup sums the rows of its split (64-row chunks loaded straight into
+// the MFMA operand registers, two chunks in flight) into the lower-triangle
+// 16x16 tiles of a W2 x W2 partial Gram (the inner solver reads only the
+// lower triangle); each of the four waves takes a 16-row slab of every
+// chunk, and their partials are summed as (w0 + w1) + (w2 + w3).  k_gram_sum then adds the split partials in split order:
 // no floating-point atomics, so the result is reproducible bit for bit.
 // ------------------------------------------------------------------------
 template <int W2>
@@ -72,8 +71,8 @@ __global__ __launch_bounds__(256) void k_gram(const double *__restrict__ Fw,
     const int split = blockIdx.x, pr = blockIdx.y, mat = blockIdx.z;
     const int64_t m = mat ? mgw : mfw;
     const int64_t nch = m / 64;
-    __shared__ __attribute__((aligned(16))) double tile[gram_lds<W2, true>()];
-    gram_block<W2, 4, true>(mat ? Gw : Fw, m, pairs[2 * pr], pairs[2 * pr + 1], nch * split / splits,
+    __shared__ __attribute__((aligned(16))) double tile[gram_lds<W2>()];
+    gram_block<W2>(mat ? Gw : Fw, m, pairs[2 * pr], pairs[2 * pr + 1], nch * split / splits,
                    nch * (split + 1) / splits,
                    part + ((size_t)(pr * 2 + mat) * splits + split) * (W2 * W2), tile);
 }
