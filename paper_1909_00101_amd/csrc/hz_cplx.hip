@@ -53,6 +53,11 @@ __global__ __launch_bounds__(256) void k_prescale_copy_z(
 // Hermitian pivot Gram blocks A_hat = X^H X (Section 2.3, ZHERK-like),
 // lower-triangle 16x16 tiles, split-K partials (interleaved complex,
 // column-major W2 x W2).  Re = Xr^T Xr + Xi^T Xi, Im = Xr^T Xi - Xi^T Xr.
+// The MFMA operands come straight from memory: wave w takes rows
+// 16w .. 16w + 15 of every 64-row chunk, its k-step s rows 16w + 4s + g
+// (g = lane / 16), one 16-byte complex element per lane, so a column's
+// 64 bytes are contiguous per load; two chunks in flight, with a
+// branch-free main loop as in the real Gram.
 template <int W2>
 __global__ __launch_bounds__(256) void k_gram_z(const d2 *__restrict__ Fw,
                                                 const d2 *__restrict__ Gw, int64_t mfw,
@@ -61,12 +66,11 @@ __global__ __launch_bounds__(256) void k_gram_z(const d2 *__restrict__ Fw,
 {
     // LDR: row stride of the two regions that take the waves' partial
     // tiles (padded so that the 16 lanes of a tile row fall in distinct LDS
-    // banks); the staging arrays hold them once the chunks are done.
-    constexpr int W = W2 / 2, NB = W2 / 16, LDT = 66, NLD = W2 / 4, LDR = W2 + 2;
+    // banks).
+    constexpr int W = W2 / 2, NB = W2 / 16, LDR = W2 + 2, PF = 2;
     constexpr int NT = NB * (NB + 1) / 2;
-    constexpr int LEN = W2 * LDT > 2 * W2 * LDR ? W2 * LDT : 2 * W2 * LDR;
-    __shared__ __attribute__((aligned(16))) double tre[LEN];
-    __shared__ __attribute__((aligned(16))) double tim[LEN];
+    __shared__ __attribute__((aligned(16))) double tre[2 * W2 * LDR];
+    __shared__ __attribute__((aligned(16))) double tim[2 * W2 * LDR];
     const int split = blockIdx.x, pr = blockIdx.y, mat = blockIdx.z;
     const d2 *Y = mat ? Gw : Fw;
     const int64_t m = mat ? mgw : mfw;
@@ -74,7 +78,6 @@ __global__ __launch_bounds__(256) void k_gram_z(const d2 *__restrict__ Fw,
     const int64_t nch = m / 64;
     const int64_t c0 = nch * split / splits, c1 = nch * (split + 1) / splits;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lrow = tid & 63, lcol = tid >> 6;
 
     d4 accr[NT], acci[NT];
 #pragma unroll
@@ -82,51 +85,49 @@ __global__ __launch_bounds__(256) void k_gram_z(const d2 *__restrict__ Fw,
         accr[t] = d4{0.0, 0.0, 0.0, 0.0};
         acci[t] = d4{0.0, 0.0, 0.0, 0.0};
     }
-    const d2 *colp[NLD];
+    const d2 *colp[NB];
 #pragma unroll
-    for (int t = 0; t < NLD; ++t) {
-        const int cc = lcol + 4 * t;
+    for (int a = 0; a < NB; ++a) {
+        const int cc = 16 * a + (lane & 15);
         const int gc = (cc < W) ? p * W + cc : q * W + (cc - W);
-        colp[t] = Y + (int64_t)gc * m + lrow;
+        colp[a] = Y + (int64_t)gc * m + 16 * wave + (lane >> 4);
     }
-    d2 buf[NLD];
-    if (c0 < c1) {
+    d2 buf[PF][NB][4];
+    auto load = [&](d2 (&b)[NB][4], int64_t c) {
 #pragma unroll
-        for (int t = 0; t < NLD; ++t) buf[t] = colp[t][c0 * 64];
-    }
-    for (int64_t c = c0; c < c1; ++c) {
-        __syncthreads();
+        for (int a = 0; a < NB; ++a)
 #pragma unroll
-        for (int t = 0; t < NLD; ++t) {
-            tre[(lcol + 4 * t) * LDT + lrow] = buf[t][0];
-            tim[(lcol + 4 * t) * LDT + lrow] = buf[t][1];
-        }
-        __syncthreads();
-        if (c + 1 < c1) {
-#pragma unroll
-            for (int t = 0; t < NLD; ++t) buf[t] = colp[t][(c + 1) * 64];
-        }
+            for (int s = 0; s < 4; ++s) b[a][s] = colp[a][c * 64 + 4 * s];
+    };
+    auto mul = [&](const d2 (&b)[NB][4]) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int ks = wave + 4 * s;
-            double fr[NB], fi[NB];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const int o = (16 * b + (lane & 15)) * LDT + 4 * ks + (lane >> 4);
-                fr[b] = tre[o];
-                fi[b] = tim[o];
-            }
             int t = 0;
 #pragma unroll
             for (int a = 0; a < NB; ++a)
 #pragma unroll
-                for (int b = 0; b <= a; ++b, ++t) {
-                    accr[t] = mfma16(fr[a], fr[b], accr[t]);
-                    accr[t] = mfma16(fi[a], fi[b], accr[t]);
-                    acci[t] = mfma16(fr[a], fi[b], acci[t]);
-                    acci[t] = mfma16(-fi[a], fr[b], acci[t]);
+                for (int bb = 0; bb <= a; ++bb, ++t) {
+                    accr[t] = mfma16(b[a][s][0], b[bb][s][0], accr[t]);
+                    accr[t] = mfma16(b[a][s][1], b[bb][s][1], accr[t]);
+                    acci[t] = mfma16(b[a][s][0], b[bb][s][1], acci[t]);
+                    acci[t] = mfma16(-b[a][s][1], b[bb][s][0], acci[t]);
                 }
         }
+    };
+    if (c0 < c1) {
+#pragma unroll
+        for (int i = 0; i < PF; ++i) load(buf[i], c0 + i < c1 ? c0 + i : c1 - 1);
+        int64_t c = c0;
+        for (; c + PF <= c1; c += PF) {
+#pragma unroll
+            for (int i = 0; i < PF; ++i) {
+                mul(buf[i]);
+                load(buf[i], c + i + PF < c1 ? c + i + PF : c1 - 1);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PF - 1; ++i)
+            if (c + i < c1) mul(buf[i]);
     }
     // The waves' partial tiles summed pairwise, (w0 + w1) + (w2 + w3), as
     // for the real Gram: waves 1 and 3 leave theirs in two regions, wave 2
