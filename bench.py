@@ -23,8 +23,9 @@ inner sweeps, Theta rescale; mean per launch and pivot pair).
 
 Prints one JSON line: solves/s, the split, the roofline entry, the CPU
 oracle timed on one complete solve of the same pair on the host cores, and
-(unless --no-forms) the QR-shortened, mixed-precision, complex and batched
-forms, each with absolute times, its fraction of the FP64 MFMA and HBM
+(unless --no-forms) the QR-shortened (beside it the solve with QR pivot
+factors, whose roofline counts Householder flops in place of the Gram's),
+mixed-precision, complex and batched forms, each with absolute times, its fraction of the FP64 MFMA and HBM
 rooflines from the algorithmic work of the sweeps it executed, and its
 error against the oracle's sigma for the same seeded pair.
 """
@@ -499,7 +500,8 @@ def qr_shortened_vs_plain(F0, G0, s_true, tol, plain_kw, tune_cache=None, reps=3
     m_f, n = F0.shape
     m_g = G0.shape[0]
     res = {}
-    for name, kw in (("plain", plain_kw), ("shortened", skw)):
+    for name, kw in (("plain", plain_kw), ("shortened", skw),
+                     ("pivot_qr", dict(plain_kw, pivot_qr=1))):
         def run(**extra):
             Fw.copy_(F0)
             Gw.copy_(G0)
@@ -510,7 +512,15 @@ def qr_shortened_vs_plain(F0, G0, s_true, tol, plain_kw, tune_cache=None, reps=3
         tr = run(timing=1)["times_ms"]
         w = kw["w"]
         m_eff = (n, n) if name == "shortened" else (m_f, m_g)
-        res[name] = _form_entry(name, r, dt, (*m_eff, n, w), gold, s_true, timing=tr)
+        ef = 0.0
+        if name == "pivot_qr":
+            # Householder QR of every m x 2w block pair (leading term
+            # 2 (2w)^2 m per matrix) in place of its Gram (2w (2w + 1) m)
+            steps = nw_of(n, w) // w
+            ef = (r["sweeps"] * steps * (nw_of(n, w) // (2 * w)) * (m_f + m_g)
+                  * 2 * w * (2 * w - 1))
+        res[name] = _form_entry(name, r, dt, (*m_eff, n, w), gold, s_true, timing=tr,
+                                extra_flops=ef)
         res[name]["params"] = {k: kw[k] for k in ("w", "inner_ordering", "inner_max_sweeps",
                                                   "inner_lanes", "gram_splits", "update_rows")
                                if k in kw}
@@ -518,7 +528,7 @@ def qr_shortened_vs_plain(F0, G0, s_true, tol, plain_kw, tune_cache=None, reps=3
     torch.cuda.empty_cache()
     return dict(workload="the headline pair (seeded 4096x1024, kappa(X)=1e2), MM ordering, "
                          "tol=1024*eps", speedup=round(res["plain"]["ms"] / res["shortened"]["ms"], 3),
-                **res)
+                pivot_qr_over_plain=round(res["pivot_qr"]["ms"] / res["plain"]["ms"], 3), **res)
 
 
 def transfer_inclusive(F, G, Fw, Gw, work, kw, reps=3):
