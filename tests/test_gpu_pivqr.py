@@ -53,6 +53,26 @@ def test_qr_factors_parity(shape, w):
                     tol_res=1e-12, tol_orth=1e-12)
 
 
+@pytest.mark.parametrize("shape,w", [((4700, 300, 128), 32), ((300, 4700, 96), 16)])
+def test_qr_factors_three_tree_levels(shape, w):
+    """The taller matrix takes three levels of the QR tree (4700 rows: 10
+    nodes of 512 rows, then 2, then 1) while the other has one node from the
+    start and is carried through the later levels as one triangle stacked on
+    zeros (its factorization must come out unchanged)."""
+    import oracle
+    m_f, m_g, n = shape
+    F, G, s_true = gi.custom_pair(m_f, m_g, n, kappa=1e2, seed=930 + n)
+    print(f"pivot_qr three tree levels {shape} w={w}", flush=True)
+    r = _run(F, G, w=w, pivot_qr=1, ordering=_hz().HZ_ORD_MM)
+    assert r["status"] == 0 and r["converged"]
+    o = oracle.gsvd(F, G, ordering=oracle.ORD_MM, threads=4)
+    print(f"  sweeps {r['sweeps']} err {max_rel(r['sigma'], o['sigma']):.2e}")
+    assert max_rel(r["sigma"], o["sigma"]) < SIG_TOL
+    assert max_rel(r["sigma"], s_true) < SIG_TOL
+    assert_contract(F, G, r["U"], r["V"], r["Z"], r["sigma_f"], r["sigma_g"], r["sigma"],
+                    tol_res=1e-12, tol_orth=1e-12)
+
+
 def _ill_pair(n):
     F, G, s_true = gi.custom_pair(3 * n, 2 * n, n, kappa=10.0, sig_lo=1e-9, sig_hi=1e2,
                                   seed=910 + n)
@@ -117,10 +137,12 @@ def test_qr_factors_with_shortening():
 
 
 @pytest.mark.parametrize("shape,w", [((64, 48, 32), 8), ((300, 200, 100), 16),
-                                     ((129, 100, 64), 16), ((40, 40, 40), 8)])
+                                     ((129, 100, 64), 16), ((40, 40, 40), 8),
+                                     ((4700, 260, 64), 16)])
 def test_qr_factors_complex_parity(shape, w):
     """Complex pairs: Householder reflectors with complex tau and a real
-    diagonal in R, which the complex inner solver takes as its factor."""
+    diagonal in R, which the complex inner solver takes as its factor (the
+    4700-row F takes three levels of the QR tree)."""
     import oracle
     m_f, m_g, n = shape
     F, G, s_true = gi.custom_pair(m_f, m_g, n, kappa=50.0, is_complex=True, seed=930 + n)
