@@ -43,12 +43,35 @@ struct QRLevel {
 constexpr int QR_ROWS = 512;   // rows of a node
 constexpr int QR_FAN = 8;      // triangles combined by a node of a further level
 
-// Sum over the 64 lanes of a wave in a fixed order (16-lane rows by DPP,
-// then the four row sums as (r0 + r1) + (r2 + r3)); every lane gets it.
+// v_permlane32_swap / v_permlane16_swap with one register as both
+// operands: the two results summed give, in every lane, the sum of its own
+// value and the one 32 lanes (or one 16-lane row) away, in the same operand
+// order in both lanes of a pair.
+__device__ __forceinline__ double swap_sum32(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    const double a = __builtin_bit_cast(double, ((long long)hi[0] << 32) | lo[0]);
+    const double c = __builtin_bit_cast(double, ((long long)hi[1] << 32) | lo[1]);
+    return a + c;
+}
+__device__ __forceinline__ double swap_sum16(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    const double a = __builtin_bit_cast(double, ((long long)hi[0] << 32) | lo[0]);
+    const double c = __builtin_bit_cast(double, ((long long)hi[1] << 32) | lo[1]);
+    return a + c;
+}
+
+// Sum over the 64 lanes of a wave in a fixed order, every lane getting the
+// same bits: the 16-lane rows by DPP (S0 .. S3), then (S0 + S2) + (S1 + S3)
+// by the two lane swaps.
 __device__ __forceinline__ double wave_total(double v)
 {
-    v = dpp_group_sum<16>(v);
-    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+    return swap_sum16(swap_sum32(dpp_group_sum<16>(v)));
 }
 
 // A workgroup of 16 waves factors one node.  Wave g owns the C = W2 / 16
