@@ -236,12 +236,23 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
     unsigned long long *const ph = phase ? phase + ((size_t)step * npairs + pr) * 8 : nullptr;
     if (ph && tid == 0) ph[0] = wall_clock64();
     {
+        // every load of a thread issued before the first store, so the
+        // phase costs one memory latency
         const d2 *pa = gram + (size_t)(pr * 2) * (W2 * W2);
         const d2 *pb = pa + (W2 * W2);
-        for (int e = tid; e < W2 * W2; e += NT) {
-            const int col = e / W2, row = e % W2;
-            sF[col * LDI + row] = pa[e];
-            sG[col * LDI + row] = pb[e];
+        constexpr int NIT = (W2 * W2) / NT;
+        static_assert(NIT * NT == W2 * W2, "Gram load geometry");
+        d2 va[NIT], vb[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            va[it] = pa[tid + NT * it];
+            vb[it] = pb[tid + NT * it];
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int e = tid + NT * it, col = e / W2, row = e % W2;
+            sF[col * LDI + row] = va[it];
+            sG[col * LDI + row] = vb[it];
         }
         for (int e = tid; e < isteps * W * 2; e += NT) stab[e] = itab[e];
         if (tid == 0) s_fail = 0;

@@ -273,10 +273,34 @@ __device__ __forceinline__ void inner_solve(
     // blocks arrive as nsplit row-split partials (stride sstride), added in
     // split order; with nsplit 0 they are the upper triangular factors
     // themselves (QR of the block-column pairs).
-    {
+    if (nsplit <= 1) {
+        // one summed block (or a factor): every load of a thread issued
+        // before the first store, so the phase costs one memory latency
+        constexpr int NIT = (W2 * W2) / (2 * NT);
+        static_assert(NIT * 2 * NT == W2 * W2, "Gram load geometry");
+        d2 va[NIT], vb[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int e = 2 * tid + 2 * NT * it;
+            // upper tiles of a Gram are never read (zeros go to LDS); a factor
+            // (nsplit 0) is upper
+            const bool skip = nsplit > 0 && (e / W2) / 16 > (e % W2) / 16;
+            va[it] = skip ? d2{0.0, 0.0} : *(const d2 *)(pa + e);
+            vb[it] = skip ? d2{0.0, 0.0} : *(const d2 *)(pb + e);
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int e = 2 * tid + 2 * NT * it, col = e / W2, row = e % W2;
+            *(d2 *)(sF + col * LDI + row) = va[it];
+            *(d2 *)(sG + col * LDI + row) = vb[it];
+        }
+        if (!RING)
+            for (int e = tid; e < isteps * W * 2; e += NT) stab[e] = itab[e];
+        if (tid == 0) s_fail = 0;
+    } else {
         for (int e = 2 * tid; e < W2 * W2; e += 2 * NT) {
-            // upper tiles of a Gram are never read; a factor (nsplit 0) is upper
-            if (nsplit > 0 && (e / W2) / 16 > (e % W2) / 16) continue;
+            // upper tiles of a Gram are never read
+            if ((e / W2) / 16 > (e % W2) / 16) continue;
             d2 a = *(const d2 *)(pa + e), b = *(const d2 *)(pb + e);
             for (int sp = 1; sp < nsplit; ++sp) {
                 a += *(const d2 *)(pa + sp * sstride + e);
