@@ -570,7 +570,19 @@ __global__ __launch_bounds__(256) void k_update_z(d2 *__restrict__ Fw, d2 *__res
     const int p = pairs[2 * pr], q = pairs[2 * pr + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const d2 *zt = Zt + (size_t)pr * (W2 * W2);
-    for (int e = tid; e < W2 * W2; e += 256) sz[(e / W2) * LDZ + (e % W2)] = zt[e];
+    {
+        // every load of a thread issued before the first store
+        constexpr int NZ = (W2 * W2) / 256;
+        static_assert(NZ * 256 == W2 * W2, "Z_tilde staging geometry");
+        d2 zv[NZ];
+#pragma unroll
+        for (int it = 0; it < NZ; ++it) zv[it] = zt[tid + 256 * it];
+#pragma unroll
+        for (int it = 0; it < NZ; ++it) {
+            const int e = tid + 256 * it;
+            sz[(e / W2) * LDZ + (e % W2)] = zv[it];
+        }
+    }
     const int64_t span = 4 * (int64_t)rows_per_wave;
     const int64_t vb = (int64_t)blockIdx.x * span, total = mfw + mgw + nzw;
     const int64_t ve = (vb + span < total) ? vb + span : total;

@@ -659,7 +659,22 @@ __device__ __forceinline__ void update_row_seq(Locate locate, int p, int q, int6
 {
     constexpr int W = W2 / 2, NB = W2 / 16, KS = W2 / 4, LDZ = W2 + 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < W2 * W2; e += 64 * NW) sz[(e / W2) * LDZ + (e % W2)] = zt[e];
+    constexpr int NTH = 64 * NW;
+    if constexpr ((W2 * W2) % NTH == 0) {
+        // every load of a thread issued before the first store: one memory
+        // latency before the rows can start instead of one per element
+        constexpr int NZ = (W2 * W2) / NTH;
+        double zv[NZ];
+#pragma unroll
+        for (int it = 0; it < NZ; ++it) zv[it] = zt[tid + NTH * it];
+#pragma unroll
+        for (int it = 0; it < NZ; ++it) {
+            const int e = tid + NTH * it;
+            sz[(e / W2) * LDZ + (e % W2)] = zv[it];
+        }
+    } else {
+        for (int e = tid; e < W2 * W2; e += NTH) sz[(e / W2) * LDZ + (e % W2)] = zt[e];
+    }
     __syncthreads();
     // Lane (i, k) = (lane % 16, lane / 16).  Columns 0..W-1 of the pair are
     // block column p, W..2W-1 block column q; every k-step's column offset

@@ -161,7 +161,19 @@ __global__ __launch_bounds__(256) void k_update32(float *__restrict__ Fs, float 
     const int p = pairs[2 * pr], q = pairs[2 * pr + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double *zt = Zt + (size_t)pr * (W2 * W2);
-    for (int e = tid; e < W2 * W2; e += 256) sz[(e / W2) * LDZ + (e % W2)] = (float)zt[e];
+    {
+        // every load of a thread issued before the first store
+        constexpr int NZ = (W2 * W2) / 256;
+        static_assert(NZ * 256 == W2 * W2, "Z_tilde staging geometry");
+        double zv[NZ];
+#pragma unroll
+        for (int it = 0; it < NZ; ++it) zv[it] = zt[tid + 256 * it];
+#pragma unroll
+        for (int it = 0; it < NZ; ++it) {
+            const int e = tid + 256 * it;
+            sz[(e / W2) * LDZ + (e % W2)] = (float)zv[it];
+        }
+    }
     // The rows of F, G and Z (each a multiple of 64) are taken as one
     // sequence cut into workgroup ranges of 4 * rows_per_wave rows (a
     // multiple of 64); a 32-row tile never straddles two matrices, and its
