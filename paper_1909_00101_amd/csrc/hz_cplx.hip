@@ -254,7 +254,7 @@ __global__ __launch_bounds__((W2 / 2) * LP) void k_inner_z(
             sF[col * LDI + row] = va[it];
             sG[col * LDI + row] = vb[it];
         }
-        for (int e = tid; e < isteps * W * 2; e += NT) stab[e] = itab[e];
+        if (!RING) copy_table<NT>(stab, itab, isteps * W * 2);   // the ring needs no table
         if (tid == 0) s_fail = 0;
     }
     __syncthreads();

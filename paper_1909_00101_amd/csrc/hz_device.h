@@ -68,6 +68,24 @@ __device__ __forceinline__ double readlane_d(double v, int l)
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
+// Copy n int16 entries (the inner ordering table) from global memory to
+// LDS with a workgroup of NT threads, four loads of a thread in flight
+// before its stores.
+template <int NT>
+__device__ __forceinline__ void copy_table(int16_t *__restrict__ dst, const int16_t *__restrict__ src,
+                                           int n)
+{
+    const int tid = threadIdx.x;
+    for (int e0 = tid; e0 < n; e0 += 4 * NT) {
+        int16_t v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = (e0 + k * NT < n) ? src[e0 + k * NT] : (int16_t)0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (e0 + k * NT < n) dst[e0 + k * NT] = v[k];
+    }
+}
+
 // Reciprocal square root from the hardware estimate y0 = v_rsq_f64(x)
 // (relative error e0 about 2^-22) refined by one third-order step
 // y = y0 (1 + e/2 + 3e^2/8), e = 1 - x y0^2, which leaves O(e0^3) -- below

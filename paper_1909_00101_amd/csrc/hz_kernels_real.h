@@ -294,8 +294,7 @@ __device__ __forceinline__ void inner_solve(
             *(d2 *)(sF + col * LDI + row) = va[it];
             *(d2 *)(sG + col * LDI + row) = vb[it];
         }
-        if (!RING)
-            for (int e = tid; e < isteps * W * 2; e += NT) stab[e] = itab[e];
+        if (!RING) copy_table<NT>(stab, itab, isteps * W * 2);
         if (tid == 0) s_fail = 0;
     } else {
         for (int e = 2 * tid; e < W2 * W2; e += 2 * NT) {
@@ -310,8 +309,7 @@ __device__ __forceinline__ void inner_solve(
             *(d2 *)(sF + col * LDI + row) = a;
             *(d2 *)(sG + col * LDI + row) = b;
         }
-        if (!RING)
-            for (int e = tid; e < isteps * W * 2; e += NT) stab[e] = itab[e];
+        if (!RING) copy_table<NT>(stab, itab, isteps * W * 2);
         if (tid == 0) s_fail = 0;
     }
     __syncthreads();

@@ -251,10 +251,18 @@ __global__ __launch_bounds__(256) void k_offdiag(const double *__restrict__ gram
     for (int i = tid; i < W2; i += 256) dg[i] = A[i * W2 + i];
     __syncthreads();
     double mx = 0.0;
-    for (int e = tid; e < W2 * W2; e += 256) {
-        const int col = e / W2, row = e % W2;
+    // every load of a thread issued before the first use (the upper
+    // entries are loaded and left unused)
+    constexpr int NIT = (W2 * W2) / 256;
+    static_assert(NIT * 256 == W2 * W2, "off-diagonal geometry");
+    double av[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) av[it] = A[tid + 256 * it];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int e = tid + 256 * it, col = e / W2, row = e % W2;
         if (row > col) {
-            const double v = fabs(A[e]) / sqrt(dg[row] * dg[col]);
+            const double v = fabs(av[it]) / sqrt(dg[row] * dg[col]);
             mx = (v > mx) ? v : mx;
         }
     }
